@@ -1,0 +1,231 @@
+"""Throughput of the per-pixel chain statistics + regional reconstruction filter path on one
+MI355X, at 1920x1080 with 64 spp (fp32 RGB radiance + albedo/normal/depth features), 11x11
+window (radius 5), 20x20 region grid.
+
+One step = the whole hot path over one frame already resident in HBM:
+  stats_accumulate -> filter_forward -> loss_seed (MSE vs a 4096-spp reference) ->
+  filter_backward (gradients for every radiance sample and every region parameter).
+`value` is filtered Mpixel/s of that fwd+bwd step; the forward-only rate (stats + filter)
+is reported beside it. Inputs are synthetic and seeded (synth/), generated on the GPU
+before timing.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+W_DEFAULT, H_DEFAULT, S_DEFAULT, R_DEFAULT, N_DEFAULT = 1920, 1080, 64, 5, 20
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--width", type=int, default=W_DEFAULT)
+    p.add_argument("--height", type=int, default=H_DEFAULT)
+    p.add_argument("--spp", type=int, default=S_DEFAULT)
+    p.add_argument("--radius", type=int, default=R_DEFAULT)
+    p.add_argument("--regions", type=int, default=N_DEFAULT)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-rows", type=int, default=0, help="rows of the frame the oracle times (0 = auto)")
+    p.add_argument("--traffic", type=str, default="", help="JSON file with rocprofv3 HBM byte counts")
+    return p.parse_args()
+
+
+def stats_bytes(P, S, feat_bytes=4):
+    # every sample read once (3 radiance fp32 + 7 features) + 23 fp32 output planes
+    return P * S * (3 * 4 + 7 * feat_bytes) + P * 23 * 4
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this path has no multi-GPU form in this build "
+              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2402_08273_amd import _abi, ops
+    from synth import gpu as sgpu
+    from synth import make_lambda
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    W, H, S, r, N = args.width, args.height, args.spp, args.radius, args.regions
+    P = W * H
+
+    # ---- inputs (untimed): seeded synthetic frame, reference, lambda table
+    rad, feat = sgpu.make_frame(W, H, S, seed=2, frame=0)
+    ref = sgpu.make_reference(W, H, seed=1002, frame=0, spp=4096)
+    lam = torch.from_numpy(make_lambda(N, seed=99)).to(dev)
+    torch.cuda.synchronize()
+
+    # ---- outputs and descriptors (built once; the timed loop only launches)
+    f32 = dict(device=dev, dtype=torch.float32)
+    mean, var, tau = (torch.empty((3, H, W), **f32) for _ in range(3))
+    fmean, fvar = torch.empty((7, H, W), **f32), torch.empty((7, H, W), **f32)
+    out, U, G = (torch.empty((3, H, W), **f32) for _ in range(3))
+    grad_lam = torch.zeros(N * N, **f32)
+    loss = torch.zeros(1, device=dev, dtype=torch.float64)
+    st_out = ops.Stats(mean, var, tau, None, fmean, fvar)
+    fs, _ = ops.stats_frame(rad, feat, 8, st_out, with_lag_corr=False)
+    ff = ops.filter_frame(mean, lam, r, N)
+    ff.out, ff.S = out.data_ptr(), S
+    ff.reference, ff.loss, ff.grad_out = ref.data_ptr(), loss.data_ptr(), U.data_ptr()
+    ff.grad_radiance, ff.grad_lambda = G.data_ptr(), grad_lam.data_ptr()
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    tabs = (_abi.RamltFrame * 1)(fs)
+    tabf = (_abi.RamltFrame * 1)(ff)
+    lib = _abi.load()
+
+    def call(fn, tab):
+        st = fn(tab, None, 1, None, 0, sh)
+        if st != 0:
+            raise RuntimeError(_abi.last_error())
+
+    def step(timing=None):
+        if timing is not None:
+            timing[0].record(stream)
+        call(lib.stats_accumulate, tabs)
+        if timing is not None:
+            timing[1].record(stream)
+        call(lib.filter_forward, tabf)
+        if timing is not None:
+            timing[2].record(stream)
+        grad_lam.zero_()
+        loss.zero_()
+        call(lib.loss_seed, tabf)
+        call(lib.filter_backward, tabf)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---- timed region: K whole steps; per-launch stats/forward durations from HIP events
+    # recorded on the launch stream inside the same region
+    marks = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for k in range(args.steps):
+        step(marks[k])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    stats_ms = float(np.mean([m[0].elapsed_time(m[1]) for m in marks]))
+    fwd_ms = float(np.mean([m[0].elapsed_time(m[2]) for m in marks]))
+
+    # forward-only rate (stats + filter), timed separately
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for _ in range(args.steps):
+        call(lib.stats_accumulate, tabs)
+        call(lib.filter_forward, tabf)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    fwd_only_ms = t_start.elapsed_time(t_end) / args.steps
+
+    sb = stats_bytes(P, S)
+    achieved = sb / (stats_ms * 1e-3) / 1e9
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        traffic = json.load(open(args.traffic)).get("stats_accumulate_bytes")
+
+    result = {
+        "metric": "Mpixel/s filtered (fwd, fwd+bwd) at 1080p 64spp; % of HBM roofline",
+        "value": round(P / (ms_step * 1e-3) / 1e6, 2),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 in, f64 stats accumulate, f32 filter",
+        "data": "synthetic (seeded scene: ramp + hard edge + disc, per-pixel noise U[0.02,0.5], 0.1% lognormal "
+                "fireflies; 4096-spp seeded reference)",
+        "config": {"workload": f"stats+filter fwd+bwd, {W}x{H}, {S} spp, fp32 radiance+features, "
+                               f"{2 * r + 1}x{2 * r + 1} window, {N}x{N} regions",
+                   "width": W, "height": H, "spp": S, "radius": r, "regions": N, "max_lag": 8},
+        "fwd_mpx_s": round(P / (fwd_only_ms * 1e-3) / 1e6, 2),
+        "fwd_ms": round(fwd_only_ms, 4),
+        "stats_ms": round(stats_ms, 4),
+        "filter_forward_ms": round(fwd_ms - stats_ms, 4),
+        "roofline": {
+            "kernel": "stats_accumulate",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes": sb,
+        },
+        "step_algorithmic_gbs": round((sb + P * (24 + 36 + 48)) / (ms_step * 1e-3) / 1e9, 1),
+    }
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(rad, feat, ref, lam, W, H, S, r, N, args.cpu_rows)
+
+    print(json.dumps(result), flush=True)
+
+
+def _oracle_chain(rad_b, feat_b, ref_b, lam_h, S, r, N):
+    import oracle
+
+    st = oracle.stats_accumulate(rad_b, feat_b, 8)
+    out, _ = oracle.filter_forward(st["mean"], lam_h, N, r)
+    _, U = oracle.mse_loss_seed(out, ref_b)
+    oracle.filter_backward(U, st["mean"], out, lam_h, N, r, -30.0, S)
+
+
+def cpu_baseline(rad, feat, ref, lam, W, H, S, r, N, rows, target_s=15.0):
+    """The FP64 oracle, as it stands, on a band of rows of the same frame (same chain:
+    stats -> filter -> loss seed -> adjoint), timed on the host. Rate in Mpixel/s. The
+    band height is chosen from a 16-row probe so the timed run takes about target_s."""
+    lam_h = lam.cpu().numpy()
+
+    def band(n):
+        sl = slice(0, n)
+        return rad[:, :, sl].cpu().numpy(), feat[:, :, sl].cpu().numpy(), ref[:, sl].cpu().numpy()
+
+    if not rows:
+        probe = min(16, H)
+        t0 = time.perf_counter()
+        _oracle_chain(*band(probe), lam_h, S, r, N)
+        per_row = (time.perf_counter() - t0) / probe
+        rows = int(max(probe, min(H, target_s / max(per_row, 1e-6))))
+    data = band(rows)
+    t0 = time.perf_counter()
+    _oracle_chain(*data, lam_h, S, r, N)
+    dt = time.perf_counter() - t0
+    px = W * rows
+    return {
+        "value": round(px / dt / 1e6, 5),
+        "unit": "Mpixel/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"rows 0..{rows - 1} of the {W}x{H} frame ({px} px, {S} spp, features), full "
+                  f"stats+filter+loss+adjoint chain in numpy fp64 on one thread, {dt:.2f} s",
+        "seconds": round(dt, 3),
+    }
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,162 @@
+/*
+ * ramlt.h -- per-pixel Monte Carlo chain statistics and the regional reconstruction
+ * filter, with its adjoint, on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow "Regional Adaptive Metropolis Light Transport" (Otsu et al.):
+ *
+ *   stats_accumulate  Appendix A: per-pixel estimator mean, sample variance, lag
+ *                     autocorrelations rho_k and autocorrelation time
+ *                     tau = 1 + 2 sum_k rho_k of each pixel's sample sequence
+ *                     (buffer order is the sequence); feature planes get mean and variance.
+ *   filter_forward    Sec. 3.1 eq. path_integral: the pixel reconstruction filter h_j
+ *                     applied to the per-pixel means, as a normalised Gaussian over the
+ *                     (2r+1)^2 window, clipped at the border, whose width
+ *                     sigma_k = sqrt(exp(lambda_k)) (Sec. 5.3) is looked up from the
+ *                     region of the output pixel on the N x N screen grid
+ *                     (Sec. 5.2 state-dependent parameters, Sec. 6.1 grid partition).
+ *   loss_seed         MSE against a reference image, L = sum (out - R)^2 / (3P), and its
+ *                     gradient U = 2 (out - R) / (3P). (Not in the paper; drives the adjoint.)
+ *   filter_backward   The exact adjoint of filter_forward composed with the per-pixel mean:
+ *                     dL/dg for every radiance sample and dL/dlambda_k per region, with the
+ *                     window weights recomputed from lambda.
+ *
+ * Conventions shared by every entry point
+ *   - All pointers inside ramlt_frame are DEVICE pointers into memory the caller owns
+ *     (e.g. allocated by PyTorch). The library allocates nothing, never synchronises,
+ *     never copies between host and device, keeps no pointer after returning, and only
+ *     enqueues work on `stream` (a hipStream_t; NULL = the null stream).
+ *   - frames_host is a HOST array of n_frames descriptors. It is read for validation and
+ *     launch sizing only. With n_frames == 1, frames_dev may be NULL. With n_frames > 1
+ *     frames_dev must be a device-resident copy of the same array (built once by the
+ *     caller, e.g. before graph capture); kernels read descriptors from it and process
+ *     all frames in one persistent launch per radius.
+ *   - Sample planes are laid out [c][s][y][x] with x contiguous; stride_c, stride_s,
+ *     stride_y are element strides (radiance and features each have their own).
+ *     Per-pixel planes (mean, var, tau, out, reference, grad_out, grad_radiance,
+ *     feat_*) are dense [c][H][W]; lag_corr is dense [3][K_L][H][W].
+ *   - Return value: a RAMLT_* status. On failure nothing has been enqueued (validation
+ *     runs entirely on the host before any launch) except for RAMLT_EHIP, which reports
+ *     a failed HIP call; ramlt_last_error() then holds a message (thread-local).
+ *   - NaN or Inf inputs propagate to the outputs; they never abort a call.
+ */
+#ifndef RAMLT_H
+#define RAMLT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum ramlt_status {
+  RAMLT_OK = 0,
+  RAMLT_EINVAL = 1,       /* bad argument: null required pointer, size, radius, lag, ... */
+  RAMLT_EUNSUPPORTED = 2, /* unknown dtype, non-gfx950 device, plane too large          */
+  RAMLT_EWORKSPACE = 3,   /* workspace missing or smaller than ramlt_workspace_size()    */
+  RAMLT_EHIP = 4          /* a HIP runtime call or kernel launch failed                   */
+};
+
+enum ramlt_feature_dtype { RAMLT_F32 = 0, RAMLT_F16 = 1 };
+
+enum ramlt_op {
+  RAMLT_OP_STATS = 0,
+  RAMLT_OP_FILTER_FORWARD = 1,
+  RAMLT_OP_LOSS_SEED = 2,
+  RAMLT_OP_FILTER_BACKWARD = 3
+};
+
+#define RAMLT_N_RADIANCE 3
+#define RAMLT_N_FEATURES 7
+#define RAMLT_MAX_RADIUS 15
+#define RAMLT_MAX_LAG 32
+#define RAMLT_MAX_FRAMES 4096
+#define RAMLT_MAX_PLANE_ELEMS (1LL << 30) /* (H-1)*stride_y + W must not exceed this */
+
+/* One frame of render buffers and its outputs. Fields an operation does not use are
+ * ignored by it (they may be NULL/0). "in" = read, "out" = written, "acc" = accumulated (+=). */
+typedef struct ramlt_frame {
+  int32_t W, H;           /* image size, >= 1                                          */
+  int32_t S;              /* samples per pixel, >= 1                                   */
+  int32_t max_lag;        /* stats: 0..RAMLT_MAX_LAG; K_L = min(max_lag, S - 1)         */
+
+  /* stats, in: radiance samples g[3][S][H][W] (fp32)                                  */
+  const float *radiance;
+  int64_t rad_stride_c, rad_stride_s, rad_stride_y;
+
+  /* stats, in: feature samples f[7][S][H][W] (albedo rgb, normal xyz, depth), or NULL */
+  const void *features;
+  int64_t feat_stride_c, feat_stride_s, feat_stride_y;
+  int32_t feat_dtype;     /* RAMLT_F32 or RAMLT_F16                                    */
+  int32_t flags;          /* reserved, must be 0                                        */
+
+  /* stats, out: [3][H][W] each; lag_corr [3][K_L][H][W] or NULL                       */
+  float *mean, *var, *tau, *lag_corr;
+  /* stats, out: [7][H][W] each; required iff features != NULL                          */
+  float *feat_mean, *feat_var;
+
+  /* filter parameters: lambda[n_regions * n_regions], row-major (ky, kx), in           */
+  const float *lambda;
+  int32_t n_regions;      /* grid size N >= 1 (the paper's N_top = 20)                  */
+  int32_t radius;         /* window radius r, 0..RAMLT_MAX_RADIUS; K = 2r + 1           */
+  float lambda_min;       /* lower clamp of lambda (the paper uses -30); finite         */
+  int32_t _reserved0;
+
+  /* filter_forward: in = mean; out = filtered image [3][H][W]                          */
+  float *out;
+  /* loss_seed: in = out, reference [3][H][W]; out = grad_out; acc = *loss (fp64)       */
+  const float *reference;
+  double *loss;           /* may be NULL                                               */
+  /* filter_backward: in = grad_out U = dL/dout, mean, out                               */
+  float *grad_out;
+  /* filter_backward, out: G [3][H][W], dL/dg[c][s][y][x] = G[c][y][x] for every s       */
+  float *grad_radiance;
+  /* filter_backward, acc: dL/dlambda [n_regions^2] (caller zeroes); may be NULL         */
+  float *grad_lambda;
+} ramlt_frame;
+
+/* Appendix A per-pixel statistics (mean = the estimator of I_j, Sec. 3.2; variance;
+ * rho_k = C_k / M2 with C_k = sum_{s<S-k} (g_s - mean)(g_{s+k} - mean); tau; features:
+ * mean and variance). Accumulation is in fp64. var = M2 / (S - 1), 0 for S = 1. A pixel
+ * whose samples are all equal gets rho_k = 0 and tau = 1. Requires per frame: radiance,
+ * mean, var, tau; features => feat_mean, feat_var. Workspace: see ramlt_workspace_size. */
+int stats_accumulate(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
+                     int32_t n_frames, void *workspace, size_t ws_bytes, void *stream);
+
+/* Sec. 3.1 reconstruction filter with per-region width (Sec. 5.2-5.3, 6.1):
+ *   k(x,y) = floor((2y+1)N/(2H)) * N + floor((2x+1)N/(2W)),
+ *   h_jp = exp(-(dx^2+dy^2) / (2 exp(max(lambda_k(j), lambda_min)))),
+ *   out_j = sum_{p in window(j), inside} h_jp mean_p / sum h_jp   (fp32).
+ * Requires per frame: mean, lambda, out, n_regions >= 1, 0 <= radius <= 15. */
+int filter_forward(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
+                   int32_t n_frames, void *workspace, size_t ws_bytes, void *stream);
+
+/* grad_out = 2 (out - reference) / (3 W H); *loss += sum (out - reference)^2 / (3 W H)
+ * (fp64 accumulation; summed over frames in a batch). Requires: out, reference, grad_out. */
+int loss_seed(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
+              int32_t n_frames, void *workspace, size_t ws_bytes, void *stream);
+
+/* Adjoint of filter_forward o per-pixel mean, for U = grad_out:
+ *   grad_radiance_p = (1/S) sum_{j : p in window(j)} U_j h_jp / D_j,
+ *   grad_lambda_k  += sum_{k(j)=k} sum_c U_jc sum_p h'_jp (mean_pc - out_jc) / D_j,
+ *   h'_jp = h_jp (dx^2+dy^2) / (2 sigma^2) if lambda_k >= lambda_min else 0.
+ * Requires: grad_out, mean, out, lambda, grad_radiance; grad_lambda may be NULL. The
+ * lambda sums use float atomics, so their rounding order is not deterministic. */
+int filter_backward(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
+                    int32_t n_frames, void *workspace, size_t ws_bytes, void *stream);
+
+/* Bytes of device workspace `op` needs for these frames (0 if none). Workspace is
+ * caller-owned, 256-byte aligned, and may be reused across calls on one stream. */
+size_t ramlt_workspace_size(const ramlt_frame *frames_host, int32_t n_frames, int32_t op);
+
+/* Message for the last non-zero status returned on this thread ("" if none). */
+const char *ramlt_last_error(void);
+
+/* ABI version: sizeof(ramlt_frame) in the high 16 bits, revision in the low 16. */
+int32_t ramlt_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAMLT_H */

@@ -1,0 +1,168 @@
+"""ctypes binding of ``include/ramlt.h`` (argument marshalling only).
+
+The entry points keep the C names: :func:`stats_accumulate`, :func:`filter_forward`,
+:func:`loss_seed`, :func:`filter_backward`, :func:`workspace_size`, :func:`last_error`.
+Each takes a sequence of :class:`RamltFrame` descriptors holding device pointers, an
+optional device copy of that table, an optional workspace pointer and a stream handle,
+and raises :class:`RamltError` on a non-zero status.
+"""
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libramlt.so")
+
+RAMLT_OK = 0
+RAMLT_EINVAL = 1
+RAMLT_EUNSUPPORTED = 2
+RAMLT_EWORKSPACE = 3
+RAMLT_EHIP = 4
+
+RAMLT_F32 = 0
+RAMLT_F16 = 1
+
+OP_STATS = 0
+OP_FILTER_FORWARD = 1
+OP_LOSS_SEED = 2
+OP_FILTER_BACKWARD = 3
+
+MAX_RADIUS = 15
+MAX_LAG = 32
+MAX_FRAMES = 4096
+
+EXPORTED = (
+    "stats_accumulate",
+    "filter_forward",
+    "loss_seed",
+    "filter_backward",
+    "ramlt_workspace_size",
+    "ramlt_last_error",
+    "ramlt_abi_version",
+)
+
+
+class RamltFrame(ctypes.Structure):
+    """Mirror of ``ramlt_frame``; every pointer field is a device address (int)."""
+
+    _fields_ = [
+        ("W", ctypes.c_int32),
+        ("H", ctypes.c_int32),
+        ("S", ctypes.c_int32),
+        ("max_lag", ctypes.c_int32),
+        ("radiance", ctypes.c_void_p),
+        ("rad_stride_c", ctypes.c_int64),
+        ("rad_stride_s", ctypes.c_int64),
+        ("rad_stride_y", ctypes.c_int64),
+        ("features", ctypes.c_void_p),
+        ("feat_stride_c", ctypes.c_int64),
+        ("feat_stride_s", ctypes.c_int64),
+        ("feat_stride_y", ctypes.c_int64),
+        ("feat_dtype", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("mean", ctypes.c_void_p),
+        ("var", ctypes.c_void_p),
+        ("tau", ctypes.c_void_p),
+        ("lag_corr", ctypes.c_void_p),
+        ("feat_mean", ctypes.c_void_p),
+        ("feat_var", ctypes.c_void_p),
+        ("lambda_", ctypes.c_void_p),
+        ("n_regions", ctypes.c_int32),
+        ("radius", ctypes.c_int32),
+        ("lambda_min", ctypes.c_float),
+        ("_reserved0", ctypes.c_int32),
+        ("out", ctypes.c_void_p),
+        ("reference", ctypes.c_void_p),
+        ("loss", ctypes.c_void_p),
+        ("grad_out", ctypes.c_void_p),
+        ("grad_radiance", ctypes.c_void_p),
+        ("grad_lambda", ctypes.c_void_p),
+    ]
+
+
+class RamltError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"ramlt status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load ``libramlt.so`` (built in-tree). Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2402_08273_amd.build` "
+            "(there is no fallback implementation)"
+        )
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = [ctypes.POINTER(RamltFrame), ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+           ctypes.c_size_t, ctypes.c_void_p]
+    for name in ("stats_accumulate", "filter_forward", "loss_seed", "filter_backward"):
+        fn = getattr(lib, name)
+        fn.argtypes = sig
+        fn.restype = ctypes.c_int
+    lib.ramlt_workspace_size.argtypes = [ctypes.POINTER(RamltFrame), ctypes.c_int32, ctypes.c_int32]
+    lib.ramlt_workspace_size.restype = ctypes.c_size_t
+    lib.ramlt_last_error.argtypes = []
+    lib.ramlt_last_error.restype = ctypes.c_char_p
+    lib.ramlt_abi_version.argtypes = []
+    lib.ramlt_abi_version.restype = ctypes.c_int32
+    if (lib.ramlt_abi_version() >> 16) != ctypes.sizeof(RamltFrame):
+        raise RuntimeError("ramlt_frame layout mismatch between libramlt.so and the binding")
+    _lib = lib
+    return lib
+
+
+def _table(frames):
+    if isinstance(frames, RamltFrame):
+        frames = [frames]
+    n = len(frames)
+    arr = (RamltFrame * n)(*frames)
+    return arr, n
+
+
+def _call(name, frames, frames_dev=None, workspace=None, ws_bytes=0, stream=None):
+    lib = load()
+    arr, n = _table(frames)
+    st = getattr(lib, name)(arr, frames_dev, n, workspace, ws_bytes, stream)
+    if st != RAMLT_OK:
+        raise RamltError(st, lib.ramlt_last_error().decode())
+    return st
+
+
+def stats_accumulate(frames, frames_dev=None, workspace=None, ws_bytes=0, stream=None):
+    return _call("stats_accumulate", frames, frames_dev, workspace, ws_bytes, stream)
+
+
+def filter_forward(frames, frames_dev=None, workspace=None, ws_bytes=0, stream=None):
+    return _call("filter_forward", frames, frames_dev, workspace, ws_bytes, stream)
+
+
+def loss_seed(frames, frames_dev=None, workspace=None, ws_bytes=0, stream=None):
+    return _call("loss_seed", frames, frames_dev, workspace, ws_bytes, stream)
+
+
+def filter_backward(frames, frames_dev=None, workspace=None, ws_bytes=0, stream=None):
+    return _call("filter_backward", frames, frames_dev, workspace, ws_bytes, stream)
+
+
+def workspace_size(frames, op):
+    lib = load()
+    arr, n = _table(frames)
+    return int(lib.ramlt_workspace_size(arr, n, op))
+
+
+def last_error():
+    return load().ramlt_last_error().decode()
+
+
+def status_of(name, frames, frames_dev=None, workspace=None, ws_bytes=0, stream=None):
+    """Raw status code of an entry point (no exception); used by host-validation tests."""
+    lib = load()
+    arr, n = _table(frames)
+    return getattr(lib, name)(arr, frames_dev, n, workspace, ws_bytes, stream)

@@ -1,0 +1,232 @@
+// C ABI of the ramlt library: host-side validation, device check, dispatch.
+//
+// Every argument check runs on the host before anything is enqueued, so each error
+// status can be produced without a GPU. Only after validation does the library touch
+// the HIP runtime (device query, launches).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+#define REQUIRE_PTR(i, f, field, align)                                                        \
+  do {                                                                                         \
+    if ((f).field == nullptr) return fail(RAMLT_EINVAL, "frame %d: " #field " is NULL", (i));  \
+    if (!aligned((f).field, (align)))                                                          \
+      return fail(RAMLT_EINVAL, "frame %d: " #field " is not %d-byte aligned", (i), (int)(align)); \
+  } while (0)
+
+#define OPTIONAL_PTR(i, f, field, align)                                                       \
+  do {                                                                                         \
+    if ((f).field != nullptr && !aligned((f).field, (align)))                                  \
+      return fail(RAMLT_EINVAL, "frame %d: " #field " is not %d-byte aligned", (i), (int)(align)); \
+  } while (0)
+
+int check_plane_layout(int i, const char *what, int W, int H, int64_t sc, int64_t ss, int64_t sy) {
+  if (sc < 1 || ss < 1 || sy < W)
+    return fail(RAMLT_EINVAL, "frame %d: %s strides must satisfy stride_c >= 1, stride_s >= 1, stride_y >= W",
+                i, what);
+  const long long extent = (long long)(H - 1) * sy + W;
+  if (extent > RAMLT_MAX_PLANE_ELEMS)
+    return fail(RAMLT_EUNSUPPORTED, "frame %d: %s plane extent %lld exceeds %lld elements", i, what, extent,
+                (long long)RAMLT_MAX_PLANE_ELEMS);
+  return RAMLT_OK;
+}
+
+int check_common(const ramlt_frame *fh, const ramlt_frame *fd, int32_t n) {
+  if (fh == nullptr) return fail(RAMLT_EINVAL, "frames_host is NULL");
+  if (n < 1 || n > RAMLT_MAX_FRAMES) return fail(RAMLT_EINVAL, "n_frames %d outside 1..%d", n, RAMLT_MAX_FRAMES);
+  if (n > 1 && fd == nullptr) return fail(RAMLT_EINVAL, "n_frames > 1 needs the device copy frames_dev");
+  if (fd != nullptr && !aligned(fd, 8)) return fail(RAMLT_EINVAL, "frames_dev is not 8-byte aligned");
+  for (int i = 0; i < n; ++i) {
+    const ramlt_frame &f = fh[i];
+    if (f.W < 1 || f.H < 1) return fail(RAMLT_EINVAL, "frame %d: W and H must be >= 1 (got %d x %d)", i, f.W, f.H);
+    if ((long long)f.W * f.H > RAMLT_MAX_PLANE_ELEMS)
+      return fail(RAMLT_EUNSUPPORTED, "frame %d: W*H exceeds %lld", i, (long long)RAMLT_MAX_PLANE_ELEMS);
+    if (f.flags != 0) return fail(RAMLT_EINVAL, "frame %d: flags must be 0", i);
+  }
+  return RAMLT_OK;
+}
+
+int check_filter_params(int i, const ramlt_frame &f) {
+  if (f.n_regions < 1 || f.n_regions > 4096)
+    return fail(RAMLT_EINVAL, "frame %d: n_regions %d outside 1..4096", i, f.n_regions);
+  if (f.radius < 0 || f.radius > RAMLT_MAX_RADIUS)
+    return fail(RAMLT_EINVAL, "frame %d: radius %d outside 0..%d", i, f.radius, RAMLT_MAX_RADIUS);
+  if (!std::isfinite(f.lambda_min)) return fail(RAMLT_EINVAL, "frame %d: lambda_min is not finite", i);
+  REQUIRE_PTR(i, f, lambda, 4);
+  return RAMLT_OK;
+}
+
+int validate_stats(const ramlt_frame &f, int i) {
+  if (f.S < 1) return fail(RAMLT_EINVAL, "frame %d: S must be >= 1 (got %d)", i, f.S);
+  if (f.max_lag < 0 || f.max_lag > RAMLT_MAX_LAG)
+    return fail(RAMLT_EINVAL, "frame %d: max_lag %d outside 0..%d", i, f.max_lag, RAMLT_MAX_LAG);
+  REQUIRE_PTR(i, f, radiance, 4);
+  int r = check_plane_layout(i, "radiance", f.W, f.H, f.rad_stride_c, f.rad_stride_s, f.rad_stride_y);
+  if (r) return r;
+  REQUIRE_PTR(i, f, mean, 4);
+  REQUIRE_PTR(i, f, var, 4);
+  REQUIRE_PTR(i, f, tau, 4);
+  OPTIONAL_PTR(i, f, lag_corr, 4);
+  if (f.features != nullptr) {
+    if (f.feat_dtype != RAMLT_F32 && f.feat_dtype != RAMLT_F16)
+      return fail(RAMLT_EUNSUPPORTED, "frame %d: feat_dtype %d is not RAMLT_F32 or RAMLT_F16", i, f.feat_dtype);
+    if (!aligned(f.features, f.feat_dtype == RAMLT_F16 ? 2 : 4))
+      return fail(RAMLT_EINVAL, "frame %d: features pointer misaligned for its dtype", i);
+    r = check_plane_layout(i, "features", f.W, f.H, f.feat_stride_c, f.feat_stride_s, f.feat_stride_y);
+    if (r) return r;
+    REQUIRE_PTR(i, f, feat_mean, 4);
+    REQUIRE_PTR(i, f, feat_var, 4);
+  }
+  return RAMLT_OK;
+}
+
+int validate_forward(const ramlt_frame &f, int i) {
+  int r = check_filter_params(i, f);
+  if (r) return r;
+  REQUIRE_PTR(i, f, mean, 4);
+  REQUIRE_PTR(i, f, out, 4);
+  return RAMLT_OK;
+}
+
+int validate_loss(const ramlt_frame &f, int i) {
+  REQUIRE_PTR(i, f, out, 4);
+  REQUIRE_PTR(i, f, reference, 4);
+  REQUIRE_PTR(i, f, grad_out, 4);
+  OPTIONAL_PTR(i, f, loss, 8);
+  return RAMLT_OK;
+}
+
+int validate_backward(const ramlt_frame &f, int i) {
+  if (f.S < 1) return fail(RAMLT_EINVAL, "frame %d: S must be >= 1 (got %d)", i, f.S);
+  int r = check_filter_params(i, f);
+  if (r) return r;
+  REQUIRE_PTR(i, f, grad_out, 4);
+  REQUIRE_PTR(i, f, mean, 4);
+  REQUIRE_PTR(i, f, out, 4);
+  REQUIRE_PTR(i, f, grad_radiance, 4);
+  OPTIONAL_PTR(i, f, grad_lambda, 4);
+  return RAMLT_OK;
+}
+
+// gfx950 check, once per device.
+constexpr int kMaxDevices = 64;
+std::once_flag g_dev_once[kMaxDevices];
+int g_dev_status[kMaxDevices];
+char g_dev_arch[kMaxDevices][64];
+
+int check_device() {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(RAMLT_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(RAMLT_EUNSUPPORTED, "device index %d out of range", dev);
+  std::call_once(g_dev_once[dev], [dev] {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      g_dev_status[dev] = RAMLT_EHIP;
+      std::snprintf(g_dev_arch[dev], sizeof(g_dev_arch[dev]), "unknown");
+      return;
+    }
+    std::snprintf(g_dev_arch[dev], sizeof(g_dev_arch[dev]), "%s", prop.gcnArchName);
+    g_dev_status[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? RAMLT_OK : RAMLT_EUNSUPPORTED;
+  });
+  if (g_dev_status[dev] == RAMLT_EHIP) return fail(RAMLT_EHIP, "hipGetDeviceProperties failed on device %d", dev);
+  if (g_dev_status[dev] != RAMLT_OK)
+    return fail(RAMLT_EUNSUPPORTED, "device %d is %s; this library is built for gfx950 only", dev, g_dev_arch[dev]);
+  return RAMLT_OK;
+}
+
+typedef int (*Validator)(const ramlt_frame &, int);
+typedef hipError_t (*Launcher)(const ramlt_frame *, const ramlt_frame *, int, void *, hipStream_t);
+
+int run_op(int op, const char *name, Validator v, Launcher l, const ramlt_frame *fh, const ramlt_frame *fd,
+           int32_t n, void *ws, size_t ws_bytes, void *stream) {
+  int r = check_common(fh, fd, n);
+  if (r) return r;
+  for (int i = 0; i < n; ++i) {
+    r = v(fh[i], i);
+    if (r) return r;
+  }
+  const size_t need = ramlt::workspace_bytes(fh, n, op);
+  if (need > 0) {
+    if (ws == nullptr || ws_bytes < need)
+      return fail(RAMLT_EWORKSPACE, "%s needs %zu bytes of workspace, got %zu", name, need,
+                  ws == nullptr ? (size_t)0 : ws_bytes);
+    if (!aligned(ws, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
+  }
+  r = check_device();
+  if (r) return r;
+  const hipError_t e = l(fh, fd, n, ws, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RAMLT_EHIP, "%s: %s", name, hipGetErrorString(e));
+  g_last_error.clear();
+  return RAMLT_OK;
+}
+
+}  // namespace
+
+namespace ramlt {
+size_t workspace_bytes(const ramlt_frame *fh, int n, int op) {
+  (void)fh;
+  (void)n;
+  (void)op;
+  return 0;
+}
+}  // namespace ramlt
+
+extern "C" {
+
+int stats_accumulate(const ramlt_frame *frames_host, const ramlt_frame *frames_dev, int32_t n_frames,
+                     void *workspace, size_t ws_bytes, void *stream) {
+  return run_op(RAMLT_OP_STATS, "stats_accumulate", validate_stats, ramlt::launch_stats, frames_host, frames_dev,
+                n_frames, workspace, ws_bytes, stream);
+}
+
+int filter_forward(const ramlt_frame *frames_host, const ramlt_frame *frames_dev, int32_t n_frames,
+                   void *workspace, size_t ws_bytes, void *stream) {
+  return run_op(RAMLT_OP_FILTER_FORWARD, "filter_forward", validate_forward, ramlt::launch_filter_forward,
+                frames_host, frames_dev, n_frames, workspace, ws_bytes, stream);
+}
+
+int loss_seed(const ramlt_frame *frames_host, const ramlt_frame *frames_dev, int32_t n_frames, void *workspace,
+              size_t ws_bytes, void *stream) {
+  return run_op(RAMLT_OP_LOSS_SEED, "loss_seed", validate_loss, ramlt::launch_loss_seed, frames_host, frames_dev,
+                n_frames, workspace, ws_bytes, stream);
+}
+
+int filter_backward(const ramlt_frame *frames_host, const ramlt_frame *frames_dev, int32_t n_frames,
+                    void *workspace, size_t ws_bytes, void *stream) {
+  return run_op(RAMLT_OP_FILTER_BACKWARD, "filter_backward", validate_backward, ramlt::launch_filter_backward,
+                frames_host, frames_dev, n_frames, workspace, ws_bytes, stream);
+}
+
+size_t ramlt_workspace_size(const ramlt_frame *frames_host, int32_t n_frames, int32_t op) {
+  if (frames_host == nullptr || n_frames < 1 || n_frames > RAMLT_MAX_FRAMES) return 0;
+  return ramlt::workspace_bytes(frames_host, n_frames, op);
+}
+
+const char *ramlt_last_error(void) { return g_last_error.c_str(); }
+
+int32_t ramlt_abi_version(void) { return (int32_t)((sizeof(ramlt_frame) << 16) | 1); }
+
+}  // extern "C"

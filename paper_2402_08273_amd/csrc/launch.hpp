@@ -1,0 +1,20 @@
+// Host-side launchers of the ramlt kernels. Arguments are already validated by the
+// C-ABI layer (abi.hip); these only size grids and enqueue on the given stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ramlt.h"
+
+namespace ramlt {
+
+// fh: host descriptors; fd: device copy (may be null when n == 1); ws: workspace.
+hipError_t launch_stats(const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws, hipStream_t st);
+hipError_t launch_filter_forward(const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws,
+                                 hipStream_t st);
+hipError_t launch_loss_seed(const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws, hipStream_t st);
+hipError_t launch_filter_backward(const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws,
+                                  hipStream_t st);
+size_t workspace_bytes(const ramlt_frame *fh, int n, int op);
+
+}  // namespace ramlt

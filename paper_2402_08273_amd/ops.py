@@ -1,0 +1,189 @@
+"""PyTorch-facing wrappers around the C ABI: device memory and streams come from torch,
+every computation runs in the HIP kernels of ``libramlt.so``.
+
+All tensors must be CUDA (HIP) tensors on the current device. Sample planes are
+``[C, S, H, W]`` views with unit x stride (any other strides); per-pixel planes are dense
+``[C, H, W]`` float32.
+"""
+
+from typing import NamedTuple, Optional
+
+import torch
+
+from . import _abi
+from ._abi import RamltFrame
+
+LAMBDA_MIN_DEFAULT = -30.0
+N_REGIONS_DEFAULT = 20
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _check_samples(t, name, channels, dtypes):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dim() != 4 or t.shape[0] != channels:
+        raise ValueError(f"{name} must be [{channels}, S, H, W], got {tuple(t.shape)}")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name} dtype {t.dtype} not in {dtypes}")
+    if t.stride(3) != 1:
+        raise ValueError(f"{name} must have unit x stride")
+
+
+def _check_plane(t, name, channels=3):
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous() or t.dim() != 3 or t.shape[0] != channels:
+        raise ValueError(f"{name} must be a contiguous float32 device tensor [{channels}, H, W]")
+
+
+class Stats(NamedTuple):
+    mean: torch.Tensor
+    var: torch.Tensor
+    tau: torch.Tensor
+    lag_corr: Optional[torch.Tensor]
+    feat_mean: Optional[torch.Tensor]
+    feat_var: Optional[torch.Tensor]
+
+
+def stats_frame(radiance, features=None, max_lag=8, out: Optional[Stats] = None, with_lag_corr=True):
+    """Descriptor + output tensors for :func:`stats` (allocates outputs unless given)."""
+    _check_samples(radiance, "radiance", 3, (torch.float32,))
+    _, S, H, W = radiance.shape
+    dev = radiance.device
+    K_L = min(int(max_lag), S - 1)
+    if out is None:
+        mk = lambda c: torch.empty((c, H, W), device=dev, dtype=torch.float32)  # noqa: E731
+        out = Stats(
+            mk(3), mk(3), mk(3),
+            torch.empty((3, K_L, H, W), device=dev, dtype=torch.float32) if with_lag_corr else None,
+            mk(7) if features is not None else None,
+            mk(7) if features is not None else None,
+        )
+    f = RamltFrame()
+    f.W, f.H, f.S, f.max_lag = W, H, S, int(max_lag)
+    f.radiance = radiance.data_ptr()
+    f.rad_stride_c, f.rad_stride_s, f.rad_stride_y = radiance.stride(0), radiance.stride(1), radiance.stride(2)
+    if features is not None:
+        _check_samples(features, "features", 7, (torch.float32, torch.float16))
+        if features.shape[1:] != radiance.shape[1:]:
+            raise ValueError("features and radiance must have the same S, H, W")
+        f.features = features.data_ptr()
+        f.feat_stride_c, f.feat_stride_s, f.feat_stride_y = features.stride(0), features.stride(1), features.stride(2)
+        f.feat_dtype = _abi.RAMLT_F16 if features.dtype == torch.float16 else _abi.RAMLT_F32
+        f.feat_mean, f.feat_var = _ptr(out.feat_mean), _ptr(out.feat_var)
+    f.mean, f.var, f.tau = _ptr(out.mean), _ptr(out.var), _ptr(out.tau)
+    f.lag_corr = _ptr(out.lag_corr)
+    return f, out
+
+
+def stats(radiance, features=None, max_lag=8, with_lag_corr=True, out: Optional[Stats] = None) -> Stats:
+    """Per-pixel Appendix A statistics of radiance (and feature) sample planes."""
+    f, out = stats_frame(radiance, features, max_lag, out, with_lag_corr)
+    _abi.stats_accumulate([f], stream=_stream())
+    return out
+
+
+def filter_frame(mean, lam, radius, n_regions=None, lambda_min=LAMBDA_MIN_DEFAULT):
+    _check_plane(mean, "mean")
+    if n_regions is None:
+        n_regions = int(round(lam.numel() ** 0.5))
+    if lam.dtype != torch.float32 or not lam.is_cuda or lam.numel() != n_regions * n_regions or not lam.is_contiguous():
+        raise ValueError("lam must be a contiguous float32 device tensor with n_regions**2 entries")
+    f = RamltFrame()
+    f.W, f.H = mean.shape[2], mean.shape[1]
+    f.mean = mean.data_ptr()
+    f.lambda_ = lam.data_ptr()
+    f.n_regions = int(n_regions)
+    f.radius = int(radius)
+    f.lambda_min = float(lambda_min)
+    return f
+
+
+def filter_forward(mean, lam, radius, n_regions=None, lambda_min=LAMBDA_MIN_DEFAULT, out=None):
+    """Regional reconstruction filter of per-pixel means -> [3, H, W]."""
+    f = filter_frame(mean, lam, radius, n_regions, lambda_min)
+    if out is None:
+        out = torch.empty_like(mean)
+    f.out = out.data_ptr()
+    _abi.filter_forward([f], stream=_stream())
+    return out
+
+
+def loss_seed(out, reference, grad_out=None, loss=None):
+    """MSE loss (accumulated into a float64 [1] tensor) and its gradient w.r.t. ``out``."""
+    _check_plane(out, "out")
+    _check_plane(reference, "reference")
+    if grad_out is None:
+        grad_out = torch.empty_like(out)
+    if loss is None:
+        loss = torch.zeros(1, device=out.device, dtype=torch.float64)
+    f = RamltFrame()
+    f.W, f.H = out.shape[2], out.shape[1]
+    f.out, f.reference, f.grad_out, f.loss = out.data_ptr(), reference.data_ptr(), grad_out.data_ptr(), loss.data_ptr()
+    _abi.loss_seed([f], stream=_stream())
+    return loss, grad_out
+
+
+def filter_backward(grad_out, mean, out, lam, radius, S, n_regions=None, lambda_min=LAMBDA_MIN_DEFAULT,
+                    want_grad_lambda=True, grad_radiance=None, grad_lambda=None):
+    """Adjoint of the filter: (G [3,H,W] = dL/dg for every sample, dL/dlambda [N*N])."""
+    f = filter_frame(mean, lam, radius, n_regions, lambda_min)
+    _check_plane(grad_out, "grad_out")
+    _check_plane(out, "out")
+    f.S = int(S)
+    if grad_radiance is None:
+        grad_radiance = torch.empty_like(mean)
+    if want_grad_lambda and grad_lambda is None:
+        grad_lambda = torch.zeros_like(lam)
+    f.grad_out, f.out = grad_out.data_ptr(), out.data_ptr()
+    f.grad_radiance = grad_radiance.data_ptr()
+    f.grad_lambda = _ptr(grad_lambda) if want_grad_lambda else None
+    _abi.filter_backward([f], stream=_stream())
+    return grad_radiance, grad_lambda
+
+
+class RegionalFilter(torch.autograd.Function):
+    """out = filter(mean over samples of radiance; lambda). Differentiable in radiance and
+    lambda; the statistics outputs and features carry no gradient.
+
+    ``RegionalFilter.apply(radiance, features, lam, radius, n_regions, lambda_min, max_lag)``
+    """
+
+    @staticmethod
+    def forward(ctx, radiance, features, lam, radius, n_regions=None, lambda_min=LAMBDA_MIN_DEFAULT, max_lag=8):
+        st = stats(radiance, features, max_lag)
+        out = filter_forward(st.mean, lam, radius, n_regions, lambda_min)
+        ctx.save_for_backward(st.mean, out, lam)
+        ctx.cfg = (int(radius), n_regions, float(lambda_min), radiance.shape)
+        ctx.mark_non_differentiable()
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        mean, out, lam = ctx.saved_tensors
+        radius, n_regions, lambda_min, shape = ctx.cfg
+        G, gl = filter_backward(grad_out.contiguous(), mean, out, lam, radius, shape[1], n_regions, lambda_min,
+                                want_grad_lambda=ctx.needs_input_grad[2])
+        g_rad = G.unsqueeze(1).expand(shape) if ctx.needs_input_grad[0] else None
+        return g_rad, None, gl, None, None, None, None
+
+
+class MSELoss(torch.autograd.Function):
+    """L = mean((out - reference)^2) in float64, with the gradient formed by the loss_seed
+    kernel during the forward pass."""
+
+    @staticmethod
+    def forward(ctx, out, reference):
+        loss, grad = loss_seed(out.contiguous(), reference.contiguous())
+        ctx.save_for_backward(grad)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return grad * g.to(grad.dtype), None

@@ -74,7 +74,8 @@ def make_frame(W, H, S, seed, frame=0, noise=NOISE_UNIFORM, sigma=0.1, firefly_p
         g, f = _sample_values(W, H, s, fk, sig, firefly_p)
         rad[:, s] = g.astype(np.float32)
         if with_features:
-            feat[:, s] = f.astype(feature_dtype)
+            # fp16 storage rounds through fp32 (the GPU generator does the same)
+            feat[:, s] = f.astype(np.float32).astype(feature_dtype)
     return rad, feat
 
 

@@ -1,0 +1,181 @@
+"""Host-side ABI checks that need no GPU: the library loads, exports every symbol that
+include/ramlt.h declares, and returns the documented status for every invalid argument
+before touching the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2402_08273_amd import _abi
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "ramlt.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _abi.load()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "defined")))
+
+
+def test_header_declarations_are_exported(lib):
+    names = _declared_functions()
+    assert set(names) == set(_abi.EXPORTED)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_layout_matches_header(lib):
+    assert lib.ramlt_abi_version() >> 16 == ctypes.sizeof(_abi.RamltFrame)
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct ramlt_frame"):text.index("} ramlt_frame;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl or decl.startswith("typedef"):
+            if "{" in decl:
+                decl = decl.split("{", 1)[1].strip()
+            else:
+                continue
+        if not decl:
+            continue
+        names = decl.replace("*", " ").split()[-1:]
+        head, _, tail = decl.rpartition(" ")
+        parts = [p.strip().lstrip("*") for p in decl.split(",")]
+        first = parts[0].replace("*", " ").split()[-1]
+        fields.append(first)
+        fields.extend(p.strip().lstrip("*").strip() for p in parts[1:])
+    py = [f[0] for f in _abi.RamltFrame._fields_]
+    py = ["lambda" if f == "lambda_" else f for f in py]
+    assert fields == py
+
+
+def _valid_stats_frame():
+    f = _abi.RamltFrame()
+    f.W, f.H, f.S, f.max_lag = 8, 4, 16, 8
+    f.radiance = 0x10000
+    f.rad_stride_c, f.rad_stride_s, f.rad_stride_y = 16 * 32, 32, 8
+    f.mean, f.var, f.tau = 0x20000, 0x30000, 0x40000
+    return f
+
+
+def _valid_filter_frame():
+    f = _abi.RamltFrame()
+    f.W, f.H, f.S = 8, 4, 4
+    f.mean, f.out, f.lambda_ = 0x20000, 0x50000, 0x60000
+    f.n_regions, f.radius, f.lambda_min = 2, 3, -30.0
+    f.grad_out, f.grad_radiance, f.grad_lambda = 0x70000, 0x80000, 0x90000
+    f.reference, f.loss = 0xA0000, 0xB0000
+    return f
+
+
+def _status(name, frames, **kw):
+    return _abi.status_of(name, frames, **kw)
+
+
+def test_valid_arguments_reach_the_device_check(lib):
+    # No GPU here: a fully valid call gets past validation and fails at hipGetDevice.
+    for name, f in [("stats_accumulate", _valid_stats_frame()), ("filter_forward", _valid_filter_frame()),
+                    ("loss_seed", _valid_filter_frame()), ("filter_backward", _valid_filter_frame())]:
+        st = _status(name, [f])
+        assert st in (_abi.RAMLT_EHIP, _abi.RAMLT_OK), (name, st, _abi.last_error())
+
+
+@pytest.mark.parametrize(
+    "mutate,code",
+    [
+        (lambda f: setattr(f, "W", 0), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "H", -1), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "S", 0), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "max_lag", 33), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "max_lag", -1), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "radiance", None), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "radiance", 0x10002), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "mean", None), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "var", None), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "tau", 0x40001), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "lag_corr", 0x40003), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "rad_stride_y", 7), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "rad_stride_s", 0), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "flags", 1), _abi.RAMLT_EINVAL),
+        (lambda f: (setattr(f, "H", 1 << 16), setattr(f, "rad_stride_y", 1 << 15)), _abi.RAMLT_EUNSUPPORTED),
+        (lambda f: (setattr(f, "features", 0x100000), setattr(f, "feat_dtype", 7),
+                    setattr(f, "feat_stride_c", 512), setattr(f, "feat_stride_s", 32),
+                    setattr(f, "feat_stride_y", 8), setattr(f, "feat_mean", 0x1000),
+                    setattr(f, "feat_var", 0x2000)), _abi.RAMLT_EUNSUPPORTED),
+        (lambda f: (setattr(f, "features", 0x100000), setattr(f, "feat_dtype", 1),
+                    setattr(f, "feat_stride_c", 512), setattr(f, "feat_stride_s", 32),
+                    setattr(f, "feat_stride_y", 8)), _abi.RAMLT_EINVAL),  # feat_mean missing
+        (lambda f: (setattr(f, "features", 0x100001), setattr(f, "feat_dtype", 1)), _abi.RAMLT_EINVAL),
+    ],
+)
+def test_stats_validation_errors(lib, mutate, code):
+    f = _valid_stats_frame()
+    mutate(f)
+    assert _status("stats_accumulate", [f]) == code
+    assert _abi.last_error() != ""
+
+
+@pytest.mark.parametrize("name", ["filter_forward", "filter_backward"])
+@pytest.mark.parametrize(
+    "mutate",
+    [
+        lambda f: setattr(f, "radius", 16),
+        lambda f: setattr(f, "radius", -1),
+        lambda f: setattr(f, "n_regions", 0),
+        lambda f: setattr(f, "lambda_min", float("nan")),
+        lambda f: setattr(f, "lambda_min", float("-inf")),
+        lambda f: setattr(f, "lambda_", None),
+        lambda f: setattr(f, "mean", None),
+        lambda f: setattr(f, "out", 0x50002),
+    ],
+)
+def test_filter_validation_errors(lib, name, mutate):
+    f = _valid_filter_frame()
+    mutate(f)
+    assert _status(name, [f]) == _abi.RAMLT_EINVAL
+
+
+@pytest.mark.parametrize("field", ["grad_out", "grad_radiance"])
+def test_backward_requires_gradient_buffers(lib, field):
+    f = _valid_filter_frame()
+    setattr(f, field, None)
+    assert _status("filter_backward", [f]) == _abi.RAMLT_EINVAL
+    f = _valid_filter_frame()
+    f.S = 0
+    assert _status("filter_backward", [f]) == _abi.RAMLT_EINVAL
+
+
+@pytest.mark.parametrize("field", ["out", "reference", "grad_out"])
+def test_loss_seed_requires_buffers(lib, field):
+    f = _valid_filter_frame()
+    setattr(f, field, None)
+    assert _status("loss_seed", [f]) == _abi.RAMLT_EINVAL
+    f = _valid_filter_frame()
+    f.loss = 0xB0004  # fp64 accumulator must be 8-byte aligned
+    assert _status("loss_seed", [f]) == _abi.RAMLT_EINVAL
+
+
+def test_table_errors(lib):
+    lib_ = _abi.load()
+    sig_null = lib_.stats_accumulate(None, None, 1, None, 0, None)
+    assert sig_null == _abi.RAMLT_EINVAL
+    f = _valid_stats_frame()
+    assert _status("stats_accumulate", [f, f]) == _abi.RAMLT_EINVAL  # n > 1 needs frames_dev
+    arr = (_abi.RamltFrame * 1)(f)
+    assert lib_.stats_accumulate(arr, None, 0, None, 0, None) == _abi.RAMLT_EINVAL
+    assert lib_.stats_accumulate(arr, None, _abi.MAX_FRAMES + 1, None, 0, None) == _abi.RAMLT_EINVAL
+
+
+def test_workspace_size_is_safe_on_bad_input(lib):
+    assert lib.ramlt_workspace_size(None, 1, 0) == 0
+    arr = (_abi.RamltFrame * 1)(_valid_stats_frame())
+    assert lib.ramlt_workspace_size(arr, 0, 0) == 0
