@@ -39,7 +39,22 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-rows", type=int, default=0, help="rows of the frame the oracle times (0 = auto)")
     p.add_argument("--traffic", type=str, default="", help="JSON file with rocprofv3 HBM byte counts")
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                   help="only run a plain device-to-device copy of MIB MiB (counter calibration) and exit")
     return p.parse_args()
+
+
+def calibrate_copy(mib):
+    """A plain copy kernel of known size, for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, device="cuda:0", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}), flush=True)
 
 
 def stats_bytes(P, S, feat_bytes=4):
@@ -53,6 +68,9 @@ def main():
         print("bench.py runs on exactly one GPU: this path has no multi-GPU form in this build "
               "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
 
     import numpy as np
     import torch
@@ -83,12 +101,16 @@ def main():
     fs, _ = ops.stats_frame(rad, feat, 8, st_out, with_lag_corr=False)
     ff = ops.filter_frame(mean, lam, r, N)
     ff.out, ff.S = out.data_ptr(), S
-    ff.reference, ff.loss, ff.grad_out = ref.data_ptr(), loss.data_ptr(), U.data_ptr()
+    ff.reference, ff.loss = ref.data_ptr(), loss.data_ptr()
     ff.grad_radiance, ff.grad_lambda = G.data_ptr(), grad_lam.data_ptr()
+    # fused: the MSE seed is formed inside the adjoint (grad_out NULL)
+    fu = _abi.RamltFrame.from_buffer_copy(ff)
+    fu.grad_out = U.data_ptr()  # unfused variant: loss_seed writes U, the adjoint reads it
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
     tabs = (_abi.RamltFrame * 1)(fs)
     tabf = (_abi.RamltFrame * 1)(ff)
+    tabu = (_abi.RamltFrame * 1)(fu)
     lib = _abi.load()
 
     def call(fn, tab):
@@ -96,7 +118,7 @@ def main():
         if st != 0:
             raise RuntimeError(_abi.last_error())
 
-    def step(timing=None):
+    def step(timing=None, fused=True):
         if timing is not None:
             timing[0].record(stream)
         call(lib.stats_accumulate, tabs)
@@ -107,8 +129,11 @@ def main():
             timing[2].record(stream)
         grad_lam.zero_()
         loss.zero_()
-        call(lib.loss_seed, tabf)
-        call(lib.filter_backward, tabf)
+        if fused:
+            call(lib.filter_backward, tabf)
+        else:
+            call(lib.loss_seed, tabu)
+            call(lib.filter_backward, tabu)
 
     for _ in range(args.warmup):
         step()
@@ -129,6 +154,15 @@ def main():
     ms_step = ms_total / args.steps
     stats_ms = float(np.mean([m[0].elapsed_time(m[1]) for m in marks]))
     fwd_ms = float(np.mean([m[0].elapsed_time(m[2]) for m in marks]))
+
+    # unfused step (separate loss_seed kernel writing U), timed separately
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for _ in range(args.steps):
+        step(fused=False)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    unfused_ms = t_start.elapsed_time(t_end) / args.steps
 
     # forward-only rate (stats + filter), timed separately
     torch.cuda.synchronize()
@@ -164,6 +198,7 @@ def main():
                                f"{2 * r + 1}x{2 * r + 1} window, {N}x{N} regions",
                    "width": W, "height": H, "spp": S, "radius": r, "regions": N, "max_lag": 8},
         "fwd_mpx_s": round(P / (fwd_only_ms * 1e-3) / 1e6, 2),
+        "unfused_fwd_bwd_mpx_s": round(P / (unfused_ms * 1e-3) / 1e6, 2),
         "fwd_ms": round(fwd_only_ms, 4),
         "stats_ms": round(stats_ms, 4),
         "filter_forward_ms": round(fwd_ms - stats_ms, 4),
@@ -177,7 +212,10 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes": sb,
         },
-        "step_algorithmic_gbs": round((sb + P * (24 + 36 + 48)) / (ms_step * 1e-3) / 1e9, 1),
+        # whole step: stats + filter (mean re-read, out write) + fused adjoint (mean, out,
+        # reference read; G write) = 5.549 GB + 48 B/px at this size
+        "step_algorithmic_gbs": round((sb + P * (24 + 48)) / (ms_step * 1e-3) / 1e9, 1),
+        "step_hbm_frac": round((sb + P * (24 + 48)) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
 
     if not args.no_cpu_baseline:

@@ -71,7 +71,8 @@ enum ramlt_op {
 #define RAMLT_MAX_RADIUS 15
 #define RAMLT_MAX_LAG 32
 #define RAMLT_MAX_FRAMES 4096
-#define RAMLT_MAX_PLANE_ELEMS (1LL << 30) /* (H-1)*stride_y + W must not exceed this */
+#define RAMLT_MAX_PLANE_ELEMS (1LL << 30) /* (H-1)*stride_y + W and W*H must not exceed this */
+#define RAMLT_MAX_SIDE 65536               /* W and H must not exceed this               */
 
 /* One frame of render buffers and its outputs. Fields an operation does not use are
  * ignored by it (they may be NULL/0). "in" = read, "out" = written, "acc" = accumulated (+=). */
@@ -140,8 +141,11 @@ int loss_seed(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
  *   grad_radiance_p = (1/S) sum_{j : p in window(j)} U_j h_jp / D_j,
  *   grad_lambda_k  += sum_{k(j)=k} sum_c U_jc sum_p h'_jp (mean_pc - out_jc) / D_j,
  *   h'_jp = h_jp (dx^2+dy^2) / (2 sigma^2) if lambda_k >= lambda_min else 0.
- * Requires: grad_out, mean, out, lambda, grad_radiance; grad_lambda may be NULL. The
- * lambda sums use float atomics, so their rounding order is not deterministic. */
+ * Requires: mean, out, lambda, grad_radiance, and either grad_out, or (grad_out NULL)
+ * reference: then U = 2 (out - reference) / (3 W H) is formed inside the kernel (the
+ * loss seed fused into the adjoint, nothing written to grad_out) and *loss, if not
+ * NULL, accumulates the MSE as loss_seed would. grad_lambda may be NULL. The lambda and
+ * loss sums use atomics, so their rounding order is not deterministic. */
 int filter_backward(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
                     int32_t n_frames, void *workspace, size_t ws_bytes, void *stream);
 

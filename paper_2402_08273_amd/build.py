@@ -11,7 +11,7 @@ PKG_DIR = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG_DIR)
 CSRC = os.path.join(PKG_DIR, "csrc")
 LIB = os.path.join(PKG_DIR, "libramlt.so")
-SOURCES = ["abi.hip", "stats.hip", "filter.hip"]
+SOURCES = ["abi.hip", "batch.hip", "stats.hip", "filter.hip"]
 ARCH = "gfx950"
 
 

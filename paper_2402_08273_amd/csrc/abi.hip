@@ -61,6 +61,8 @@ int check_common(const ramlt_frame *fh, const ramlt_frame *fd, int32_t n) {
   for (int i = 0; i < n; ++i) {
     const ramlt_frame &f = fh[i];
     if (f.W < 1 || f.H < 1) return fail(RAMLT_EINVAL, "frame %d: W and H must be >= 1 (got %d x %d)", i, f.W, f.H);
+    if (f.W > RAMLT_MAX_SIDE || f.H > RAMLT_MAX_SIDE)
+      return fail(RAMLT_EUNSUPPORTED, "frame %d: W and H must be <= %d (got %d x %d)", i, RAMLT_MAX_SIDE, f.W, f.H);
     if ((long long)f.W * f.H > RAMLT_MAX_PLANE_ELEMS)
       return fail(RAMLT_EUNSUPPORTED, "frame %d: W*H exceeds %lld", i, (long long)RAMLT_MAX_PLANE_ELEMS);
     if (f.flags != 0) return fail(RAMLT_EINVAL, "frame %d: flags must be 0", i);
@@ -122,7 +124,13 @@ int validate_backward(const ramlt_frame &f, int i) {
   if (f.S < 1) return fail(RAMLT_EINVAL, "frame %d: S must be >= 1 (got %d)", i, f.S);
   int r = check_filter_params(i, f);
   if (r) return r;
-  REQUIRE_PTR(i, f, grad_out, 4);
+  if (f.grad_out == nullptr && f.reference == nullptr)
+    return fail(RAMLT_EINVAL, "frame %d: filter_backward needs grad_out, or reference for the fused MSE seed", i);
+  OPTIONAL_PTR(i, f, grad_out, 4);
+  if (f.grad_out == nullptr) {
+    REQUIRE_PTR(i, f, reference, 4);
+    OPTIONAL_PTR(i, f, loss, 8);
+  }
   REQUIRE_PTR(i, f, mean, 4);
   REQUIRE_PTR(i, f, out, 4);
   REQUIRE_PTR(i, f, grad_radiance, 4);
@@ -184,15 +192,6 @@ int run_op(int op, const char *name, Validator v, Launcher l, const ramlt_frame 
 }
 
 }  // namespace
-
-namespace ramlt {
-size_t workspace_bytes(const ramlt_frame *fh, int n, int op) {
-  (void)fh;
-  (void)n;
-  (void)op;
-  return 0;
-}
-}  // namespace ramlt
 
 extern "C" {
 

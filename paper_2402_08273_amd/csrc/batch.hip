@@ -1,0 +1,100 @@
+// Device-side planning of batched launches.
+//
+// For a batch of frames the plan kernel computes each frame's tile count, orders frames
+// by per-tile cost (samples per pixel for the statistics pass; uniform otherwise),
+// largest first, so that the costliest tiles are popped first and the tail of the
+// persistent launch is made of cheap tiles (longest-processing-time-first), and writes
+// the exclusive prefix of tile counts in that order. Everything stays on the device and
+// in stream order, so a batch can be captured in a graph.
+#include <mutex>
+#include <unordered_map>
+
+#include "batch.hpp"
+
+namespace ramlt {
+
+namespace {
+
+constexpr int kPlanBlock = 256;
+
+__device__ long long tiles_of(const ramlt_frame &f, int op, int radius_sel) {
+  const long long P = (long long)f.W * f.H;
+  switch (op) {
+    case RAMLT_OP_STATS:
+      return (P + kStatsTilePixels - 1) / kStatsTilePixels;
+    case RAMLT_OP_LOSS_SEED:
+      return (P + kLossTilePixels - 1) / kLossTilePixels;
+    default:
+      if (radius_sel >= 0 && f.radius != radius_sel) return 0;
+      return (long long)((f.W + kFilterTileW - 1) / kFilterTileW) * ((f.H + kFilterTileH - 1) / kFilterTileH);
+  }
+}
+
+__device__ long long cost_of(const ramlt_frame &f, int op) { return op == RAMLT_OP_STATS ? f.S : 1; }
+
+__global__ __launch_bounds__(kPlanBlock) void plan_kernel(const ramlt_frame *__restrict__ frames, int n, int op,
+                                                          int radius_sel, BatchPlan *plan) {
+  int *order = plan_order(plan);
+  long long *prefix = plan_prefix(plan, n);
+  // rank = number of frames that go before frame i (higher cost, or equal cost and
+  // lower index)
+  for (int i = threadIdx.x; i < n; i += kPlanBlock) {
+    const long long ci = cost_of(frames[i], op);
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const long long cj = cost_of(frames[j], op);
+      rank += (cj > ci) || (cj == ci && j < i);
+    }
+    order[rank] = i;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long acc = 0;
+    for (int q = 0; q < n; ++q) {
+      prefix[q] = acc;
+      acc += tiles_of(frames[order[q]], op, radius_sel);
+    }
+    prefix[n] = acc;
+    plan->n_frames = n;
+    plan->total_tiles = (unsigned long long)acc;
+    plan->next_tile = 0ULL;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_plan(const ramlt_frame *frames_dev, int n, int op, int radius_sel, BatchPlan *plan,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, st, frames_dev, n, op, radius_sel, plan);
+  return hipGetLastError();
+}
+
+int persistent_grid(const void *kernel, int block) {
+  static std::mutex mu;
+  static std::unordered_map<const void *, int> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const void *key = (const void *)((const char *)kernel + dev);  // per device
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+  const int grid = per_cu * cus;
+  cache[key] = grid;
+  return grid;
+}
+
+int distinct_radii(const ramlt_frame *fh, int n, int *radii) {
+  bool seen[RAMLT_MAX_RADIUS + 1] = {};
+  for (int i = 0; i < n; ++i)
+    if (fh[i].radius >= 0 && fh[i].radius <= RAMLT_MAX_RADIUS) seen[fh[i].radius] = true;
+  int k = 0;
+  for (int r = 0; r <= RAMLT_MAX_RADIUS; ++r)
+    if (seen[r]) radii[k++] = r;
+  return k;
+}
+
+}  // namespace ramlt

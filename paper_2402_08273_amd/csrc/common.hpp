@@ -39,8 +39,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Batched-launch bookkeeping kept in the caller's workspace. The plan kernel fills it at
 // the start of every batched launch (stream-ordered, so it is safe under graph capture).
 struct BatchPlan {
-  unsigned int next_tile;   // work counter popped by persistent workgroups
-  unsigned int pad0;
+  unsigned long long next_tile;  // work counter popped by persistent workgroups
   unsigned long long total_tiles;
   int n_frames;
   int pad1[11];

@@ -5,13 +5,29 @@
 // whose width sigma_k = sqrt(exp(lambda_k)) (Sec. 5.3) comes from the screen-grid region
 // of the output pixel (Sec. 5.2, Sec. 6.1).
 //
-// Design: 32 x 8 output tiles, one thread per output pixel. The tile plus an R-pixel
-// halo of per-pixel values is staged in LDS as float4 (one 16-byte LDS read per tap).
-// Out-of-image halo entries are zero, so clipped taps contribute nothing and the
-// normaliser D_j = (sum of in-image 1-D weights along x) * (same along y) is formed in
-// closed form. Taps are summed row by row, then the row sums are combined, which keeps
-// the fp32 rounding error near 2(2R+1) ulp. The radius R is a template parameter so the
-// window loops unroll and the 1-D weights stay in registers.
+// Tiling. Output tiles are at most 32 x 8 pixels and, when the regions are large enough
+// (>= 16 px wide and >= 4 px tall), never straddle a region boundary: tile columns and
+// rows are laid out inside each region column / row. Every output pixel of such a tile
+// shares one sigma, so the forward filter and the lambda gather are separable (a pass
+// over rows, then over columns) and the 1-D weights w(d) = exp(-d^2 / (2 sigma^2)) are
+// computed once per thread. Smaller regions use plain 32 x 8 tiles and a direct (2R+1)^2
+// gather with per-pixel weights.
+//
+// The tile plus an R-pixel halo of per-pixel values is staged in LDS as float4 (one
+// 16-byte LDS read per tap). Out-of-image halo entries are zero, so clipped taps
+// contribute nothing and the normaliser D_j = (sum of in-image 1-D weights along x) *
+// (same along y) is formed in closed form. Sums are formed row by row, then over rows,
+// which keeps the fp32 rounding error near 2(2R+1) ulp.
+//
+// Adjoint. G_p = (1/S) sum_j U_j h_jp / D_j weights each SOURCE j with its own sigma.
+// Sources of a tile's window lie in at most three region columns (the tile's and its two
+// neighbours); G is accumulated as a sum over those columns of separable convolutions of
+// the masked field a_j = U_j / (S D_j), with row weights taken from each source row's
+// region. With the fused loss seed (reference given, grad_out NULL), U_j = 2 (out_j - R_j)
+// / (3P) is formed on the fly and the loss is accumulated per tile in fp64.
+#include <type_traits>
+
+#include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -19,11 +35,70 @@ namespace ramlt {
 
 namespace {
 
-constexpr int kTX = 32;
-constexpr int kTY = 8;
+constexpr int kTX = kFilterTileW;
+constexpr int kTY = kFilterTileH;
 constexpr int kFilterBlock = kTX * kTY;
 constexpr float kLog2e = 1.4426950408889634f;
 
+// ------------------------------------------------------------------------ tiling
+struct Rect {
+  int x0, y0, x1, y1;  // outputs [x0, x1) x [y0, y1)
+};
+
+// First coordinate (of n) whose cell floor((2c + 1) N / (2n)) is >= k. Every region is
+// at most ceil(n / N) wide. 32-bit arithmetic: n <= 65536 and N <= 4096 (validated).
+__host__ __device__ inline int region_start(int k, int n, int N) {
+  if (k <= 0) return 0;
+  if (k >= N) return n;
+  // (2c + 1) N >= 2 k n  <=>  c >= (2 k n - N) / (2 N)
+  const int num = 2 * k * n - N;
+  const int c = num <= 0 ? 0 : (int)(((unsigned)num + 2u * (unsigned)N - 1u) / (2u * (unsigned)N));
+  return c > n ? n : c;
+}
+
+__host__ __device__ inline bool aligned_tiling(const ramlt_frame &f) {
+  return f.W >= 16 * f.n_regions && f.H >= 4 * f.n_regions;
+}
+
+// Tiles per region along an axis when aligned (some may be empty), else 0.
+__host__ __device__ inline int tiles_per_region(int n, int N, int T) { return ((n + N - 1) / N + T - 1) / T; }
+
+__host__ __device__ inline int tiles_along(int n, int N, int T, bool aligned) {
+  return aligned ? N * tiles_per_region(n, N, T) : (n + T - 1) / T;
+}
+
+// Interval [lo, hi) of the idx-th tile along an axis (possibly empty when aligned).
+__device__ inline void tile_span(int idx, int n, int N, int T, bool aligned, int *lo, int *hi) {
+  if (!aligned) {
+    *lo = idx * T;
+    *hi = min(n, *lo + T);
+    return;
+  }
+  const int tpr = tiles_per_region(n, N, T);
+  const int k = idx / tpr;
+  const int i = idx - k * tpr;
+  const int a = region_start(k, n, N), b = region_start(k + 1, n, N);
+  *lo = min(a + i * T, b);
+  *hi = min(b, a + (i + 1) * T);
+}
+
+__device__ inline Rect tile_rect(const ramlt_frame &f, long long t) {
+  const bool al = aligned_tiling(f);
+  const int ntx = tiles_along(f.W, f.n_regions, kTX, al);
+  Rect r;
+  tile_span((int)(t % ntx), f.W, f.n_regions, kTX, al, &r.x0, &r.x1);
+  tile_span((int)(t / ntx), f.H, f.n_regions, kTY, al, &r.y0, &r.y1);
+  return r;
+}
+
+__device__ __forceinline__ int cell_x(int x, const ramlt_frame &f) {
+  return (int)(((unsigned)(2 * x + 1) * (unsigned)f.n_regions) / (2u * (unsigned)f.W));
+}
+__device__ __forceinline__ int cell_y(int y, const ramlt_frame &f) {
+  return (int)(((unsigned)(2 * y + 1) * (unsigned)f.n_regions) / (2u * (unsigned)f.H));
+}
+
+// ------------------------------------------------------------------------ weights
 template <int R>
 __device__ __forceinline__ void gauss_weights(float beta, float (&w)[R + 1]) {
   w[0] = 1.0f;
@@ -45,45 +120,89 @@ __device__ __forceinline__ float clipped_sum(const float (&w)[R + 1], int c, int
   return s;
 }
 
-__device__ __forceinline__ int tiles_x(int W) { return (W + kTX - 1) / kTX; }
-__device__ __forceinline__ int tiles_y(int H) { return (H + kTY - 1) / kTY; }
-
-// ------------------------------------------------------------------------ forward
-template <int R>
-__device__ __forceinline__ void forward_tile(const ramlt_frame &f, int x0, int y0, float4 *lds) {
+// Stage a float4 per halo pixel of the tile at (x0, y0): value(gx, gy) inside the image,
+// zero outside.
+template <int R, typename F>
+__device__ __forceinline__ void stage_halo(const ramlt_frame &f, int x0, int y0, float4 *lds, F value) {
   constexpr int HX = kTX + 2 * R;
   constexpr int HY = kTY + 2 * R;
-  const int W = f.W, H = f.H;
-  const long long P = (long long)W * H;
-  const float *__restrict__ mean = f.mean;
   for (int i = threadIdx.x; i < HX * HY; i += kFilterBlock) {
     const int hy = i / HX;
     const int hx = i - hy * HX;
     const int gx = x0 - R + hx;
     const int gy = y0 - R + hy;
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-      const long long o = (long long)gy * W + gx;
-      v.x = mean[o];
-      v.y = mean[P + o];
-      v.z = mean[2 * P + o];
-    }
+    if (gx >= 0 && gx < f.W && gy >= 0 && gy < f.H) v = value(gx, gy);
     lds[i] = v;
   }
+}
+
+__device__ __forceinline__ float4 load3(const float *p, long long P, long long o) {
+  return make_float4(p[o], p[P + o], p[2 * P + o], 0.f);
+}
+
+// ------------------------------------------------------------------------ forward
+template <int R>
+__device__ __forceinline__ void forward_tile(const ramlt_frame &f, const Rect &r, float4 *stage, float4 *hbuf) {
+  constexpr int HX = kTX + 2 * R;
+  constexpr int HY = kTY + 2 * R;
+  const long long P = (long long)f.W * f.H;
+  stage_halo<R>(f, r.x0, r.y0, stage, [&](int gx, int gy) { return load3(f.mean, P, (long long)gy * f.W + gx); });
   __syncthreads();
   const int tx = threadIdx.x % kTX;
   const int ty = threadIdx.x / kTX;
-  const int x = x0 + tx;
-  const int y = y0 + ty;
-  if (x < W && y < H) {
-    const int k = region_of(x, y, W, H, f.n_regions);
+  const int x = r.x0 + tx;
+  const int y = r.y0 + ty;
+  const bool inside = x < r.x1 && y < r.y1;
+  const bool uniform = region_of(r.x0, r.y0, f.W, f.H, f.n_regions) ==
+                       region_of(r.x1 - 1, r.y1 - 1, f.W, f.H, f.n_regions);
+  if (uniform) {
+    // one sigma for the whole tile: rows, then columns
+    const float beta = half_inv_var(f.lambda[region_of(r.x0, r.y0, f.W, f.H, f.n_regions)], f.lambda_min);
+    float w[R + 1];
+    gauss_weights<R>(beta, w);
+    for (int i = threadIdx.x; i < HY * kTX; i += kFilterBlock) {
+      const int hy = i / kTX;
+      const int hx = i - hy * kTX;
+      const float4 *row = stage + hy * HX + hx + R;
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int dx = -R; dx <= R; ++dx) {
+        const float4 m = row[dx];
+        const float ww = w[dx < 0 ? -dx : dx];
+        a.x = fmaf(ww, m.x, a.x);
+        a.y = fmaf(ww, m.y, a.y);
+        a.z = fmaf(ww, m.z, a.z);
+      }
+      hbuf[i] = a;
+    }
+    __syncthreads();
+    if (inside) {
+      float ax = 0.f, ay = 0.f, az = 0.f;
+#pragma unroll
+      for (int dy = -R; dy <= R; ++dy) {
+        const float4 h = hbuf[(ty + R + dy) * kTX + tx];
+        const float wy = w[dy < 0 ? -dy : dy];
+        ax = fmaf(wy, h.x, ax);
+        ay = fmaf(wy, h.y, ay);
+        az = fmaf(wy, h.z, az);
+      }
+      const float D = clipped_sum<R, 0>(w, x, f.W) * clipped_sum<R, 0>(w, y, f.H);
+      const long long o = (long long)y * f.W + x;
+      f.out[o] = ax / D;
+      f.out[P + o] = ay / D;
+      f.out[2 * P + o] = az / D;
+    }
+  } else if (inside) {
+    // per-pixel sigma: direct (2R+1)^2 gather
+    const int k = region_of(x, y, f.W, f.H, f.n_regions);
     const float beta = half_inv_var(f.lambda[k], f.lambda_min);
     float w[R + 1];
     gauss_weights<R>(beta, w);
     float ax = 0.f, ay = 0.f, az = 0.f;
 #pragma unroll
     for (int dy = -R; dy <= R; ++dy) {
-      const float4 *row = lds + (ty + R + dy) * HX + tx + R;
+      const float4 *row = stage + (ty + R + dy) * HX + tx + R;
       float rx = 0.f, ry = 0.f, rz = 0.f;
 #pragma unroll
       for (int dx = -R; dx <= R; ++dx) {
@@ -98,234 +217,465 @@ __device__ __forceinline__ void forward_tile(const ramlt_frame &f, int x0, int y
       ay = fmaf(wy, ry, ay);
       az = fmaf(wy, rz, az);
     }
-    const float D = clipped_sum<R, 0>(w, x, W) * clipped_sum<R, 0>(w, y, H);
-    const long long o = (long long)y * W + x;
+    const float D = clipped_sum<R, 0>(w, x, f.W) * clipped_sum<R, 0>(w, y, f.H);
+    const long long o = (long long)y * f.W + x;
     f.out[o] = ax / D;
     f.out[P + o] = ay / D;
     f.out[2 * P + o] = az / D;
   }
 }
 
-template <int R>
-__global__ __launch_bounds__(kFilterBlock) void forward_kernel(const ramlt_frame f) {
-  __shared__ float4 lds[(kTX + 2 * R) * (kTY + 2 * R)];
-  const int ntx = tiles_x(f.W);
-  const int t = blockIdx.x;
-  forward_tile<R>(f, (t % ntx) * kTX, (t / ntx) * kTY, lds);
-}
-
 // ------------------------------------------------------------------------ loss seed
 constexpr int kLossBlock = 256;
 
-__global__ __launch_bounds__(kLossBlock) void loss_seed_kernel(const ramlt_frame f) {
-  const long long n = 3LL * f.W * f.H;
-  const float scale = (float)(2.0 / (double)n);
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+// grad_out and the loss for pixels [p0, p0 + npix) of a frame (all three planes).
+__device__ __forceinline__ void loss_range(const ramlt_frame &f, long long p0, long long npix, double *red) {
+  const long long P = (long long)f.W * f.H;
+  const float scale = (float)(2.0 / (3.0 * (double)P));
   double acc = 0.0;
-  for (long long i = (long long)blockIdx.x * kLossBlock + threadIdx.x; i < n;
-       i += (long long)gridDim.x * kLossBlock) {
-    const float d = f.out[i] - f.reference[i];
-    f.grad_out[i] = d * scale;
-    acc = fma((double)d, (double)d, acc);
+  for (long long i = threadIdx.x; i < npix; i += kLossBlock) {
+    const long long o = p0 + i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float d = f.out[c * P + o] - f.reference[c * P + o];
+      f.grad_out[c * P + o] = d * scale;
+      acc = fma((double)d, (double)d, acc);
+    }
   }
   if (f.loss) {
-    __shared__ double part[kLossBlock / kWave];
-    acc = wave_sum(acc);
-    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-#pragma unroll
-      for (int i = 0; i < kLossBlock / kWave; ++i) s += part[i];
-      unsafeAtomicAdd(f.loss, s / (double)n);
-    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) unsafeAtomicAdd(f.loss, s / (3.0 * (double)P));
   }
 }
 
 // ------------------------------------------------------------------------ backward
-// Per tile: stage a_j = U_j / (S D_j) with beta_j * log2(e) (float4) and mean_j (float4)
-// over tile + halo; then for each pixel p of the tile
-//   G_p = sum_{e in window} a_{p+e} exp2(-|e|^2 beta'_{p+e})        (transpose gather)
-// and for each output pixel j of the tile
-//   dL/dlam_k(j) += beta_j sum_c U_jc (N2_jc - out_jc H2_j) / D_j,
-//   N2 = sum_p h_jp d^2 mean_p,  H2 = sum_p h_jp d^2  (h' = h d^2 beta).
+// Segmented wave reduction keyed by region, then one float atomic per (wave, region).
+__device__ __forceinline__ void reduce_lambda(float *grad_lambda, int key, float contrib) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (;;) {
+    const unsigned long long pending = __ballot(key >= 0);
+    if (pending == 0ULL) break;
+    const int lead = __ffsll((long long)pending) - 1;
+    const int kk = __shfl(key, lead, kWave);
+    float v = (key == kk) ? contrib : 0.f;
+    v = wave_sum(v);
+    if (lane == lead) unsafeAtomicAdd(grad_lambda + kk, v);
+    if (key == kk) key = -1;
+  }
+}
+
+// Per-tile adjoint. LDS: stage (HX*HY float4), hb1/hb2 (HY*kTX float4 each), tab (weights
+// of up to 3x3 regions around the tile), rows (row slots of the halo), red (reductions).
 template <int R>
-__device__ __forceinline__ void backward_tile(const ramlt_frame &f, int x0, int y0, float4 *la,
-                                              float4 *lm) {
+__device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &r, float4 *stage, float4 *hb1,
+                                              float4 *hb2, float *tab, int *rows, double *red) {
   constexpr int HX = kTX + 2 * R;
   constexpr int HY = kTY + 2 * R;
   const int W = f.W, H = f.H, N = f.n_regions;
   const long long P = (long long)W * H;
+  const bool fused = f.grad_out == nullptr;
+  const float useed = (float)(2.0 / (3.0 * (double)P));
   const float invS = 1.0f / (float)f.S;
-  for (int i = threadIdx.x; i < HX * HY; i += kFilterBlock) {
-    const int hy = i / HX;
-    const int hx = i - hy * HX;
-    const int gx = x0 - R + hx;
-    const int gy = y0 - R + hy;
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-      const long long o = (long long)gy * W + gx;
-      const int k = region_of(gx, gy, W, H, N);
-      const float beta = half_inv_var(f.lambda[k], f.lambda_min);
-      float w[R + 1];
-      gauss_weights<R>(beta, w);
-      const float D = clipped_sum<R, 0>(w, gx, W) * clipped_sum<R, 0>(w, gy, H);
-      const float s = invS / D;
-      a = make_float4(f.grad_out[o] * s, f.grad_out[P + o] * s, f.grad_out[2 * P + o] * s, beta * kLog2e);
-      m = make_float4(f.mean[o], f.mean[P + o], f.mean[2 * P + o], 0.f);
-    }
-    la[i] = a;
-    lm[i] = m;
-  }
-  __syncthreads();
   const int tx = threadIdx.x % kTX;
   const int ty = threadIdx.x / kTX;
-  const int x = x0 + tx;
-  const int y = y0 + ty;
-  const bool inside = x < W && y < H;
-  int key = -1;
-  float contrib = 0.f;
-  if (inside) {
-    float gx = 0.f, gy = 0.f, gz = 0.f;
+  const int x = r.x0 + tx;
+  const int y = r.y0 + ty;
+  const bool inside = x < r.x1 && y < r.y1;
+  const long long o = (long long)y * W + x;
+
+  // Region columns / rows reachable from the tile's window.
+  const int gx_lo = max(r.x0 - R, 0), gx_hi = min(r.x0 + kTX + R, W) - 1;
+  const int gy_lo = max(r.y0 - R, 0), gy_hi = min(r.y0 + kTY + R, H) - 1;
+  const int kx_lo = cell_x(gx_lo, f), nsx = cell_x(gx_hi, f) - kx_lo + 1;
+  const int ky_lo = cell_y(gy_lo, f), nsy = cell_y(gy_hi, f) - ky_lo + 1;
+  const bool sep = nsx <= 3 && nsy <= 3;  // block-uniform
+
+  // U_j of an in-image pixel (given, or from the fused MSE seed)
+  auto U_at = [&](long long q) -> float4 {
+    if (fused) {
+      return make_float4(useed * (f.out[q] - f.reference[q]), useed * (f.out[P + q] - f.reference[P + q]),
+                         useed * (f.out[2 * P + q] - f.reference[2 * P + q]), 0.f);
+    }
+    return load3(f.grad_out, P, q);
+  };
+
+  // ---- stage a_j = U_j / (S D_j) and the source's region-column slot (or beta' for the
+  // direct path) over tile + halo
+  stage_halo<R>(f, r.x0, r.y0, stage, [&](int gx, int gy) {
+    const long long q = (long long)gy * W + gx;
+    const float beta = half_inv_var(f.lambda[region_of(gx, gy, W, H, N)], f.lambda_min);
+    float w[R + 1];
+    gauss_weights<R>(beta, w);
+    const float s = invS / (clipped_sum<R, 0>(w, gx, W) * clipped_sum<R, 0>(w, gy, H));
+    const float4 u = U_at(q);
+    const float tag = sep ? (float)(cell_x(gx, f) - kx_lo) : beta * kLog2e;
+    return make_float4(u.x * s, u.y * s, u.z * s, tag);
+  });
+  if (sep) {
+    // weights of the (<= 3 x 3) regions around the tile, and row slots of the halo
+    for (int i = threadIdx.x; i < 9 * (R + 1); i += kFilterBlock) {
+      const int d = i % (R + 1), s = i / (R + 1);
+      const int sx = s % 3, sy = s / 3;
+      const int kx = min(kx_lo + sx, N - 1), ky = min(ky_lo + sy, N - 1);
+      const float beta = half_inv_var(f.lambda[ky * N + kx], f.lambda_min);
+      tab[i] = d == 0 ? 1.0f : expf(-(float)(d * d) * beta);
+    }
+    for (int i = threadIdx.x; i < HY; i += kFilterBlock) {
+      const int gy = min(max(r.y0 - R + i, 0), H - 1);
+      rows[i] = cell_y(gy, f) - ky_lo;
+    }
+  }
+  __syncthreads();
+
+  // ---- G_p = sum_e a_{p+e} h(e; sigma of p+e)
+  float gx_ = 0.f, gy_ = 0.f, gz_ = 0.f;
+  if (sep) {
+    for (int sx = 0; sx < nsx; ++sx) {
+      // rows: H_sx(hy, x) = sum_dx w_(sx, row)(|dx|) a(hy, x + dx) [source column in slot sx]
+      for (int i = threadIdx.x; i < HY * kTX; i += kFilterBlock) {
+        const int hy = i / kTX;
+        const int hx = i - hy * kTX;
+        const float *wt = tab + (rows[hy] * 3 + sx) * (R + 1);
+        float w[R + 1];
+#pragma unroll
+        for (int d = 0; d <= R; ++d) w[d] = wt[d];
+        const float4 *src = stage + hy * HX + hx + R;
+        const float fsx = (float)sx;
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx) {
+          const float4 v = src[dx];
+          const float ww = v.w == fsx ? w[dx < 0 ? -dx : dx] : 0.f;
+          a.x = fmaf(ww, v.x, a.x);
+          a.y = fmaf(ww, v.y, a.y);
+          a.z = fmaf(ww, v.z, a.z);
+        }
+        hb1[i] = a;
+      }
+      __syncthreads();
+      if (inside) {
+#pragma unroll
+        for (int dy = -R; dy <= R; ++dy) {
+          const int hy = ty + R + dy;
+          const float wy = tab[(rows[hy] * 3 + sx) * (R + 1) + (dy < 0 ? -dy : dy)];
+          const float4 h = hb1[hy * kTX + tx];
+          gx_ = fmaf(wy, h.x, gx_);
+          gy_ = fmaf(wy, h.y, gy_);
+          gz_ = fmaf(wy, h.z, gz_);
+        }
+      }
+      __syncthreads();
+    }
+  } else if (inside) {
 #pragma unroll
     for (int dy = -R; dy <= R; ++dy) {
-      const float4 *row = la + (ty + R + dy) * HX + tx + R;
+      const float4 *row = stage + (ty + R + dy) * HX + tx + R;
 #pragma unroll
       for (int dx = -R; dx <= R; ++dx) {
         const float4 a = row[dx];
         const float h = __builtin_amdgcn_exp2f(-(float)(dx * dx + dy * dy) * a.w);
-        gx = fmaf(h, a.x, gx);
-        gy = fmaf(h, a.y, gy);
-        gz = fmaf(h, a.z, gz);
+        gx_ = fmaf(h, a.x, gx_);
+        gy_ = fmaf(h, a.y, gy_);
+        gz_ = fmaf(h, a.z, gz_);
       }
     }
-    const long long o = (long long)y * W + x;
-    f.grad_radiance[o] = gx;
-    f.grad_radiance[P + o] = gy;
-    f.grad_radiance[2 * P + o] = gz;
+  }
+  if (inside) {
+    f.grad_radiance[o] = gx_;
+    f.grad_radiance[P + o] = gy_;
+    f.grad_radiance[2 * P + o] = gz_;
+  }
 
-    if (f.grad_lambda) {
-      const int k = region_of(x, y, W, H, N);
-      const float lam = f.lambda[k];
-      key = k;
-      if (lam >= f.lambda_min) {
-        const float beta = half_inv_var(lam, f.lambda_min);
-        float w[R + 1], wd2[R + 1];
-        gauss_weights<R>(beta, w);
+  // ---- loss value of the tile's pixels (fused seed)
+  if (fused && f.loss) {
+    double acc = 0.0;
+    if (inside) {
 #pragma unroll
-        for (int d = 0; d <= R; ++d) wd2[d] = w[d] * (float)(d * d);
-        float nx = 0.f, ny = 0.f, nz = 0.f;
-#pragma unroll
-        for (int dy = -R; dy <= R; ++dy) {
-          const float4 *row = lm + (ty + R + dy) * HX + tx + R;
-          float r1x = 0.f, r1y = 0.f, r1z = 0.f, r2x = 0.f, r2y = 0.f, r2z = 0.f;
-#pragma unroll
-          for (int dx = -R; dx <= R; ++dx) {
-            const float4 m = row[dx];
-            const int ax = dx < 0 ? -dx : dx;
-            r1x = fmaf(w[ax], m.x, r1x);
-            r1y = fmaf(w[ax], m.y, r1y);
-            r1z = fmaf(w[ax], m.z, r1z);
-            r2x = fmaf(wd2[ax], m.x, r2x);
-            r2y = fmaf(wd2[ax], m.y, r2y);
-            r2z = fmaf(wd2[ax], m.z, r2z);
-          }
-          const int ay = dy < 0 ? -dy : dy;
-          nx = fmaf(w[ay], r2x, fmaf(wd2[ay], r1x, nx));
-          ny = fmaf(w[ay], r2y, fmaf(wd2[ay], r1y, ny));
-          nz = fmaf(w[ay], r2z, fmaf(wd2[ay], r1z, nz));
-        }
-        const float sx0 = clipped_sum<R, 0>(w, x, W), sy0 = clipped_sum<R, 0>(w, y, H);
-        const float sx2 = clipped_sum<R, 2>(w, x, W), sy2 = clipped_sum<R, 2>(w, y, H);
-        const float H2 = sx2 * sy0 + sx0 * sy2;
-        const float D = sx0 * sy0;
-        const float t = f.grad_out[o] * (nx - f.out[o] * H2) + f.grad_out[P + o] * (ny - f.out[P + o] * H2) +
-                        f.grad_out[2 * P + o] * (nz - f.out[2 * P + o] * H2);
-        contrib = beta * t / D;
+      for (int c = 0; c < 3; ++c) {
+        const float d = f.out[c * P + o] - f.reference[c * P + o];
+        acc = fma((double)d, (double)d, acc);
       }
     }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) unsafeAtomicAdd(f.loss, s / (3.0 * (double)P));
   }
-  if (f.grad_lambda) {
-    // Segmented wave reduction keyed by region, then one float atomic per (wave, region).
-    const int lane = threadIdx.x & (kWave - 1);
-    for (;;) {
-      const unsigned long long pending = __ballot(key >= 0);
-      if (pending == 0ULL) break;
-      const int lead = __ffsll((long long)pending) - 1;
-      const int kk = __shfl(key, lead, kWave);
-      float v = (key == kk) ? contrib : 0.f;
-      v = wave_sum(v);
-      if (lane == lead) unsafeAtomicAdd(f.grad_lambda + kk, v);
-      if (key == kk) key = -1;
+
+  // ---- dL/dlambda_k(j) += beta_j sum_c U_jc (N2_jc - out_jc H2_j) / D_j
+  if (!f.grad_lambda) return;
+  __syncthreads();  // stage is rewritten below
+  stage_halo<R>(f, r.x0, r.y0, stage, [&](int gx, int gy) { return load3(f.mean, P, (long long)gy * W + gx); });
+  __syncthreads();
+  const bool uniform = region_of(r.x0, r.y0, W, H, N) == region_of(r.x1 - 1, r.y1 - 1, W, H, N);
+  const int k_own = inside ? region_of(x, y, W, H, N) : region_of(r.x0, r.y0, W, H, N);
+  const float lam = f.lambda[k_own];
+  const bool live = lam >= f.lambda_min;
+  const float beta = half_inv_var(lam, f.lambda_min);
+  float w[R + 1], wd2[R + 1];
+  gauss_weights<R>(beta, w);
+#pragma unroll
+  for (int d = 0; d <= R; ++d) wd2[d] = w[d] * (float)(d * d);
+  float nx = 0.f, ny = 0.f, nz = 0.f;
+  if (uniform) {
+    if (live) {
+      for (int i = threadIdx.x; i < HY * kTX; i += kFilterBlock) {
+        const int hy = i / kTX;
+        const int hx = i - hy * kTX;
+        const float4 *row = stage + hy * HX + hx + R;
+        float4 a1 = make_float4(0.f, 0.f, 0.f, 0.f), a2 = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx) {
+          const float4 m = row[dx];
+          const int ax = dx < 0 ? -dx : dx;
+          a1.x = fmaf(w[ax], m.x, a1.x);
+          a1.y = fmaf(w[ax], m.y, a1.y);
+          a1.z = fmaf(w[ax], m.z, a1.z);
+          a2.x = fmaf(wd2[ax], m.x, a2.x);
+          a2.y = fmaf(wd2[ax], m.y, a2.y);
+          a2.z = fmaf(wd2[ax], m.z, a2.z);
+        }
+        hb1[i] = a1;
+        hb2[i] = a2;
+      }
+    }
+    __syncthreads();
+    if (inside && live) {
+#pragma unroll
+      for (int dy = -R; dy <= R; ++dy) {
+        const int ay = dy < 0 ? -dy : dy;
+        const float4 h1 = hb1[(ty + R + dy) * kTX + tx];
+        const float4 h2 = hb2[(ty + R + dy) * kTX + tx];
+        nx = fmaf(w[ay], h2.x, fmaf(wd2[ay], h1.x, nx));
+        ny = fmaf(w[ay], h2.y, fmaf(wd2[ay], h1.y, ny));
+        nz = fmaf(w[ay], h2.z, fmaf(wd2[ay], h1.z, nz));
+      }
+    }
+  } else if (inside && live) {
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy) {
+      const float4 *row = stage + (ty + R + dy) * HX + tx + R;
+      float r1x = 0.f, r1y = 0.f, r1z = 0.f, r2x = 0.f, r2y = 0.f, r2z = 0.f;
+#pragma unroll
+      for (int dx = -R; dx <= R; ++dx) {
+        const float4 m = row[dx];
+        const int ax = dx < 0 ? -dx : dx;
+        r1x = fmaf(w[ax], m.x, r1x);
+        r1y = fmaf(w[ax], m.y, r1y);
+        r1z = fmaf(w[ax], m.z, r1z);
+        r2x = fmaf(wd2[ax], m.x, r2x);
+        r2y = fmaf(wd2[ax], m.y, r2y);
+        r2z = fmaf(wd2[ax], m.z, r2z);
+      }
+      const int ay = dy < 0 ? -dy : dy;
+      nx = fmaf(w[ay], r2x, fmaf(wd2[ay], r1x, nx));
+      ny = fmaf(w[ay], r2y, fmaf(wd2[ay], r1y, ny));
+      nz = fmaf(w[ay], r2z, fmaf(wd2[ay], r1z, nz));
     }
   }
+  float contrib = 0.f;
+  if (inside && live) {
+    const float sx0 = clipped_sum<R, 0>(w, x, W), sy0 = clipped_sum<R, 0>(w, y, H);
+    const float sx2 = clipped_sum<R, 2>(w, x, W), sy2 = clipped_sum<R, 2>(w, y, H);
+    const float H2 = sx2 * sy0 + sx0 * sy2;
+    const float D = sx0 * sy0;
+    const float4 u = U_at(o);
+    const float t = u.x * (nx - f.out[o] * H2) + u.y * (ny - f.out[P + o] * H2) + u.z * (nz - f.out[2 * P + o] * H2);
+    contrib = beta * t / D;
+  }
+  reduce_lambda(f.grad_lambda, inside ? k_own : -1, contrib);
+}
+
+// ------------------------------------------------------------------------ kernels
+// XCD-aware order for single-frame grids: consecutive workgroup ids land on different
+// XCDs, so give each XCD a contiguous band of tiles (its halos overlap in that XCD's L2).
+__device__ __forceinline__ long long xcd_tile(unsigned b, unsigned nblocks) {
+  const unsigned per = (nblocks + 7) / 8;
+  return (long long)(b & 7) * per + (b >> 3);
 }
 
 template <int R>
-__global__ __launch_bounds__(kFilterBlock) void backward_kernel(const ramlt_frame f) {
-  __shared__ float4 la[(kTX + 2 * R) * (kTY + 2 * R)];
-  __shared__ float4 lm[(kTX + 2 * R) * (kTY + 2 * R)];
-  const int ntx = tiles_x(f.W);
-  const int t = blockIdx.x;
-  backward_tile<R>(f, (t % ntx) * kTX, (t / ntx) * kTY, la, lm);
+struct FwdLds {
+  float4 stage[(kTX + 2 * R) * (kTY + 2 * R)];
+  float4 hb1[(kTY + 2 * R) * kTX];
+};
+
+template <int R>
+struct BwdLds {
+  float4 stage[(kTX + 2 * R) * (kTY + 2 * R)];
+  float4 hb1[(kTY + 2 * R) * kTX];
+  float4 hb2[(kTY + 2 * R) * kTX];
+  float tab[9 * (R + 1)];
+  int rows[kTY + 2 * R];
+  double red[kFilterBlock / kWave];
+};
+
+template <int R>
+__global__ __launch_bounds__(kFilterBlock) void forward_kernel(const ramlt_frame f, long long ntiles) {
+  __shared__ FwdLds<R> s;
+  const long long t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= ntiles) return;
+  const Rect r = tile_rect(f, t);
+  if (r.x0 >= r.x1 || r.y0 >= r.y1) return;
+  forward_tile<R>(f, r, s.stage, s.hb1);
 }
 
-using FrameKernel = void (*)(const ramlt_frame);
+template <int R>
+__global__ __launch_bounds__(kFilterBlock) void backward_kernel(const ramlt_frame f, long long ntiles) {
+  __shared__ BwdLds<R> s;
+  const long long t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= ntiles) return;
+  const Rect r = tile_rect(f, t);
+  if (r.x0 >= r.x1 || r.y0 >= r.y1) return;
+  backward_tile<R>(f, r, s.stage, s.hb1, s.hb2, s.tab, s.rows, s.red);
+}
+
+// Persistent forms for a batch: pop (frame, tile) pairs from the plan's queue.
+template <int R, bool BWD>
+__global__ __launch_bounds__(kFilterBlock) void filter_batched_kernel(const ramlt_frame *__restrict__ frames,
+                                                                      BatchPlan *plan) {
+  using Lds = typename std::conditional<BWD, BwdLds<R>, FwdLds<R>>::type;
+  __shared__ Lds s;
+  __shared__ unsigned long long slot;
+  const unsigned long long total = plan->total_tiles;
+  for (;;) {
+    if (threadIdx.x == 0) slot = atomicAdd(&plan->next_tile, 1ULL);
+    __syncthreads();
+    const unsigned long long t = slot;
+    __syncthreads();
+    if (t >= total) break;
+    int fi;
+    long long local;
+    plan_lookup(plan, t, &fi, &local);
+    const ramlt_frame f = frames[fi];
+    const Rect r = tile_rect(f, local);
+    if (r.x0 < r.x1 && r.y0 < r.y1) {  // block-uniform
+      if constexpr (BWD)
+        backward_tile<R>(f, r, s.stage, s.hb1, s.hb2, s.tab, s.rows, s.red);
+      else
+        forward_tile<R>(f, r, s.stage, s.hb1);
+    }
+    __syncthreads();  // LDS is reused by the next tile
+  }
+}
+
+__global__ __launch_bounds__(kLossBlock) void loss_seed_kernel(const ramlt_frame f) {
+  __shared__ double red[kLossBlock / kWave];
+  const long long P = (long long)f.W * f.H;
+  const long long per = (P + gridDim.x - 1) / gridDim.x;
+  const long long p0 = (long long)blockIdx.x * per;
+  if (p0 >= P) return;
+  loss_range(f, p0, min(per, P - p0), red);
+}
+
+__global__ __launch_bounds__(kLossBlock) void loss_seed_batched_kernel(const ramlt_frame *__restrict__ frames,
+                                                                       BatchPlan *plan) {
+  __shared__ double red[kLossBlock / kWave];
+  __shared__ unsigned long long slot;
+  const unsigned long long total = plan->total_tiles;
+  for (;;) {
+    if (threadIdx.x == 0) slot = atomicAdd(&plan->next_tile, 1ULL);
+    __syncthreads();
+    const unsigned long long t = slot;
+    __syncthreads();
+    if (t >= total) break;
+    int fi;
+    long long local;
+    plan_lookup(plan, t, &fi, &local);
+    const ramlt_frame f = frames[fi];
+    const long long P = (long long)f.W * f.H;
+    const long long p0 = local * kLossTilePixels;
+    loss_range(f, p0, min((long long)kLossTilePixels, P - p0), red);
+  }
+}
+
+using FrameKernel = void (*)(const ramlt_frame, long long);
+using BatchKernel = void (*)(const ramlt_frame *, BatchPlan *);
 
 template <int... Rs>
 struct KernelTables {
   static constexpr int kCount = sizeof...(Rs);
   static constexpr FrameKernel forward[kCount] = {forward_kernel<Rs>...};
   static constexpr FrameKernel backward[kCount] = {backward_kernel<Rs>...};
+  static constexpr BatchKernel forward_batched[kCount] = {filter_batched_kernel<Rs, false>...};
+  static constexpr BatchKernel backward_batched[kCount] = {filter_batched_kernel<Rs, true>...};
 };
 
 using Tables = KernelTables<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15>;
 
-unsigned filter_grid(const ramlt_frame &f) {
-  return (unsigned)(((f.W + kTX - 1) / kTX) * ((f.H + kTY - 1) / kTY));
+long long filter_tiles(const ramlt_frame &f) {
+  const bool al = aligned_tiling(f);
+  return (long long)tiles_along(f.W, f.n_regions, kTX, al) * tiles_along(f.H, f.n_regions, kTY, al);
+}
+
+hipError_t launch_filter(const FrameKernel *single, const BatchKernel *batched, int op, const ramlt_frame *fh,
+                         const ramlt_frame *fd, int n, void *ws, hipStream_t st) {
+  if (n == 1) {
+    const ramlt_frame &f = fh[0];
+    const long long nt = filter_tiles(f);
+    const unsigned grid = (unsigned)(((nt + 7) / 8) * 8);
+    hipLaunchKernelGGL(single[f.radius], dim3(grid), dim3(kFilterBlock), 0, st, f, nt);
+    return hipGetLastError();
+  }
+  int radii[RAMLT_MAX_RADIUS + 1];
+  const int nr = distinct_radii(fh, n, radii);
+  for (int g = 0; g < nr; ++g) {
+    BatchPlan *plan = (BatchPlan *)((char *)ws + (size_t)g * plan_bytes(n));
+    hipError_t e = launch_plan(fd, n, op, radii[g], plan, st);
+    if (e != hipSuccess) return e;
+    const int grid = persistent_grid((const void *)batched[radii[g]], kFilterBlock);
+    hipLaunchKernelGGL(batched[radii[g]], dim3(grid), dim3(kFilterBlock), 0, st, fd, plan);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
 
 hipError_t launch_filter_forward(const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws,
                                  hipStream_t st) {
-  (void)fd;
-  (void)ws;
-  for (int i = 0; i < n; ++i) {
-    const ramlt_frame &f = fh[i];
-    hipLaunchKernelGGL(Tables::forward[f.radius], dim3(filter_grid(f)), dim3(kFilterBlock), 0, st, f);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return launch_filter(Tables::forward, Tables::forward_batched, RAMLT_OP_FILTER_FORWARD, fh, fd, n, ws, st);
 }
 
 hipError_t launch_filter_backward(const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws,
                                   hipStream_t st) {
-  (void)fd;
-  (void)ws;
-  for (int i = 0; i < n; ++i) {
-    const ramlt_frame &f = fh[i];
-    hipLaunchKernelGGL(Tables::backward[f.radius], dim3(filter_grid(f)), dim3(kFilterBlock), 0, st, f);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return launch_filter(Tables::backward, Tables::backward_batched, RAMLT_OP_FILTER_BACKWARD, fh, fd, n, ws, st);
 }
 
 hipError_t launch_loss_seed(const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws, hipStream_t st) {
-  (void)fd;
-  (void)ws;
-  for (int i = 0; i < n; ++i) {
-    const ramlt_frame &f = fh[i];
-    const long long elems = 3LL * f.W * f.H;
-    long long blocks = (elems + kLossBlock - 1) / kLossBlock;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(loss_seed_kernel, dim3((unsigned)blocks), dim3(kLossBlock), 0, st, f);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  if (n == 1) {
+    const long long P = (long long)fh[0].W * fh[0].H;
+    long long blocks = (P + kLossTilePixels - 1) / kLossTilePixels;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(loss_seed_kernel, dim3((unsigned)blocks), dim3(kLossBlock), 0, st, fh[0]);
+    return hipGetLastError();
   }
-  return hipSuccess;
+  BatchPlan *plan = (BatchPlan *)ws;
+  hipError_t e = launch_plan(fd, n, RAMLT_OP_LOSS_SEED, -1, plan, st);
+  if (e != hipSuccess) return e;
+  const int grid = persistent_grid((const void *)loss_seed_batched_kernel, kLossBlock);
+  hipLaunchKernelGGL(loss_seed_batched_kernel, dim3(grid), dim3(kLossBlock), 0, st, fd, plan);
+  return hipGetLastError();
+}
+
+size_t workspace_bytes(const ramlt_frame *fh, int n, int op) {
+  if (n <= 1) return 0;
+  if (op == RAMLT_OP_FILTER_FORWARD || op == RAMLT_OP_FILTER_BACKWARD) {
+    int radii[RAMLT_MAX_RADIUS + 1];
+    return (size_t)distinct_radii(fh, n, radii) * plan_bytes(n);
+  }
+  return plan_bytes(n);
 }
 
 }  // namespace ramlt

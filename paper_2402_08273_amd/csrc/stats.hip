@@ -5,10 +5,11 @@
 // Design (HBM-bound: every sample is read exactly once, 40 B per sample with fp32
 // features):
 //  * one thread per pixel, 256 pixels per workgroup; consecutive lanes read consecutive
-//    x of one sample plane, so each wave load is a contiguous 256 B (fp32) run;
-//  * channels are processed one after another and samples are streamed in chunks of B
-//    registers, so the working set per thread stays small and many waves per CU keep
-//    enough loads in flight;
+//    x of one sample plane, so each wave load is a contiguous 256 B (fp32) run. Loads are
+//    non-temporal: the planes are streamed once;
+//  * channels are processed one after another and samples are streamed in register chunks
+//    of B, so the working set per thread stays small and several waves per SIMD keep loads
+//    in flight;
 //  * accumulation is fp64 about a shift K0 = the pixel's first sample, d_s = g_s - K0
 //    (exact for fp32 inputs). On CDNA4 fp64 FMA issues at the fp32 (non-packed) rate,
 //    so this costs registers, not time, and makes the one-pass formulas
@@ -18,7 +19,11 @@
 //    ~1e-13 relative to M2 even with a firefly as the first sample, where an fp32
 //    one-pass shifted sum loses most digits;
 //  * lag products are formed against a register ring of the last KT deviations; KT is a
-//    compile-time bucket >= K_L and lags beyond K_L are computed but not written.
+//    compile-time bucket >= K_L and lags beyond K_L are computed but not written;
+//  * the 23 per-pixel results are parked in LDS and written after the pixel's last load,
+//    with the "sc1" store policy. Stores share the in-order outstanding-operation counter
+//    with loads, and measured mixed read/write streams on MI355X run fastest this way.
+#include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -27,6 +32,16 @@ namespace ramlt {
 namespace {
 
 constexpr int kStatsBlock = 256;
+constexpr int kParked = 9 + 14;  // radiance mean/var/tau x 3, feature mean/var x 7
+constexpr int kStoreSC1 = 16;    // buffer cache-policy operand: sc1
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)0xFFFFFFFF, 0x00020000);
+}
+__device__ __forceinline__ void store_result(float *base, uint32_t idx, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), plane_rsrc(base), idx * 4u, 0,
+                                        kStoreSC1);
+}
 
 template <typename T>
 __device__ __forceinline__ float load_sample(const T *p);
@@ -37,13 +52,13 @@ __device__ __forceinline__ float load_sample<_Float16>(const _Float16 *p) {
   return (float)__builtin_nontemporal_load(p);
 }
 
-// Radiance channel: all Appendix A statistics of one pixel's sequence.
+// All Appendix A statistics of one radiance channel of one pixel. Results go to park[0],
+// park[kStatsBlock], park[2 * kStatsBlock] (mean, var, tau); lag correlations, if
+// requested, straight to lag_o[k * plane_elems].
 template <int KT, int B>
-__device__ __forceinline__ void radiance_channel(const float *__restrict__ plane0, int64_t stride_s,
-                                                 uint32_t off, int S, int K_L, float *__restrict__ mean_o,
-                                                 float *__restrict__ var_o, float *__restrict__ tau_o,
-                                                 float *__restrict__ lag_o, int64_t plane_elems,
-                                                 uint32_t out_off) {
+__device__ __forceinline__ void radiance_channel(const float *__restrict__ plane0, int64_t stride_s, uint32_t off,
+                                                 int S, int K_L, float *park, float *__restrict__ lag_o,
+                                                 int64_t plane_elems) {
   double K0 = 0.0;
   double T = 0.0, Q = 0.0;
   double P[KT > 0 ? KT : 1];
@@ -68,68 +83,72 @@ __device__ __forceinline__ void radiance_channel(const float *__restrict__ plane
   };
 
   int s0 = 0;
-  for (; s0 + B <= S; s0 += B) {
+  if (S >= B) {
+    // first chunk peeled: it fixes the shift K0 and the head samples
     float x[B];
 #pragma unroll
-    for (int i = 0; i < B; ++i) x[i] = load_sample(plane0 + (int64_t)(s0 + i) * stride_s + off);
-    if (s0 == 0) {
-      K0 = (double)x[0];
+    for (int i = 0; i < B; ++i) x[i] = load_sample(plane0 + (int64_t)i * stride_s + off);
+    K0 = (double)x[0];
 #pragma unroll
-      for (int i = 0; i < KT && i < B; ++i) head[i] = x[i];
-    }
+    for (int i = 0; i < KT && i < B; ++i) head[i] = x[i];
 #pragma unroll
     for (int i = 0; i < B; ++i) consume(x[i]);
-  }
-  if (s0 < S) {
-    const int n = S - s0;
-    float x[B];
+    for (s0 = B; s0 + B <= S; s0 += B) {
 #pragma unroll
-    for (int i = 0; i < B; ++i)
-      if (i < n) x[i] = load_sample(plane0 + (int64_t)(s0 + i) * stride_s + off);
-    if (s0 == 0) {
-      K0 = (double)x[0];
+      for (int i = 0; i < B; ++i) x[i] = load_sample(plane0 + (int64_t)(s0 + i) * stride_s + off);
 #pragma unroll
-      for (int i = 0; i < KT && i < B; ++i) head[i] = i < n ? x[i] : x[0];
+      for (int i = 0; i < B; ++i) consume(x[i]);
     }
+  }
+  // ragged tail (and S < B), one sample at a time
+#pragma unroll 1
+  for (; s0 < S; ++s0) {
+    const float g = load_sample(plane0 + (int64_t)s0 * stride_s + off);
+    if (s0 == 0) K0 = (double)g;
+    if (s0 < KT) {
 #pragma unroll
-    for (int i = 0; i < B; ++i)
-      if (i < n) consume(x[i]);
+      for (int k = 0; k < KT; ++k)
+        if (s0 == k) head[k] = g;
+    }
+    consume(g);
   }
 
   const double Sd = (double)S;
   const double m = T / Sd;
   double M2 = fma(-T, m, Q);
   M2 = M2 > 0.0 ? M2 : 0.0;
-  mean_o[out_off] = (float)(K0 + m);
-  var_o[out_off] = S >= 2 ? (float)(M2 / (Sd - 1.0)) : 0.0f;
+  park[0] = (float)(K0 + m);
+  park[kStatsBlock] = S >= 2 ? (float)(M2 / (Sd - 1.0)) : 0.0f;
 
   double tau = 1.0;
   if (KT > 0 && M2 > 0.0) {
     const double inv = 1.0 / M2;
+    const double m2 = m * m;
+    const double twoT = T + T;
+    const double Sm2 = Sd * m2;
     double head_k = 0.0, tail_k = 0.0;
 #pragma unroll
     for (int k = 1; k <= KT; ++k) {
-      // head_k = sum_{s<k} d_s, tail_k = sum of the last k deviations
-      head_k += (double)head[k - 1] - K0;
-      tail_k += ring[k - 1];
+      head_k += (double)head[k - 1] - K0;  // sum of the first k deviations
+      tail_k += ring[k - 1];               // sum of the last k deviations
       if (k <= K_L) {
-        const double C = P[k - 1] - m * (T - head_k) - m * (T - tail_k) + (Sd - k) * m * m;
+        // C_k = P_k - m (T - head_k) - m (T - tail_k) + (S - k) m^2
+        const double C = P[k - 1] - m * (twoT - head_k - tail_k) + (Sm2 - (double)k * m2);
         const double rho = C * inv;
         tau += 2.0 * rho;
-        if (lag_o) lag_o[(int64_t)(k - 1) * plane_elems + out_off] = (float)rho;
+        if (lag_o) lag_o[(int64_t)(k - 1) * plane_elems] = (float)rho;
       }
     }
   } else if (lag_o) {
-    for (int k = 0; k < K_L; ++k) lag_o[(int64_t)k * plane_elems + out_off] = 0.0f;
+    for (int k = 0; k < K_L; ++k) lag_o[(int64_t)k * plane_elems] = 0.0f;
   }
-  tau_o[out_off] = (float)tau;
+  park[2 * kStatsBlock] = (float)tau;
 }
 
-// Feature channel: mean and variance only.
+// Mean and variance of one feature channel of one pixel: park[0] and park[7 * kStatsBlock].
 template <typename T, int B>
 __device__ __forceinline__ void feature_channel(const T *__restrict__ plane0, int64_t stride_s, uint32_t off,
-                                                int S, float *__restrict__ mean_o,
-                                                float *__restrict__ var_o, uint32_t out_off) {
+                                                int S, float *park) {
   double K0 = 0.0, Ts = 0.0, Q = 0.0;
   int s0 = 0;
   for (; s0 + B <= S; s0 += B) {
@@ -155,59 +174,91 @@ __device__ __forceinline__ void feature_channel(const T *__restrict__ plane0, in
   const double m = Ts / Sd;
   double M2 = fma(-Ts, m, Q);
   M2 = M2 > 0.0 ? M2 : 0.0;
-  mean_o[out_off] = (float)(K0 + m);
-  var_o[out_off] = S >= 2 ? (float)(M2 / (Sd - 1.0)) : 0.0f;
+  park[0] = (float)(K0 + m);
+  park[RAMLT_N_FEATURES * kStatsBlock] = S >= 2 ? (float)(M2 / (Sd - 1.0)) : 0.0f;
 }
 
+// One 256-pixel tile (pixels pix0 .. pix0 + 255 of the frame, row-major).
 template <int KT, int B>
-__device__ __forceinline__ void stats_pixels(const ramlt_frame &f, long long pix) {
+__device__ __forceinline__ void stats_tile(const ramlt_frame &f, long long pix0, float *park_all) {
   const long long P = (long long)f.W * f.H;
+  const int t = threadIdx.x;
+  const long long pix = pix0 + t;
   if (pix >= P) return;
-  const int y = (int)(pix / f.W);
-  const int x = (int)(pix - (long long)y * f.W);
-  const uint32_t out_off = (uint32_t)pix;
+  float *park = park_all + t;
+  // W * H <= 2^30 (validated), so 32-bit division is exact
+  const int y = (int)((unsigned)pix / (unsigned)f.W);
+  const int x = (int)pix - y * f.W;
   const int K_L = min(f.max_lag, f.S - 1);
   const uint32_t roff = (uint32_t)((long long)y * f.rad_stride_y + x);
 #pragma unroll 1
   for (int c = 0; c < RAMLT_N_RADIANCE; ++c) {
     radiance_channel<KT, B>(f.radiance + c * f.rad_stride_c, f.rad_stride_s, roff, f.S, K_L,
-                            f.mean + c * P, f.var + c * P, f.tau + c * P,
-                            f.lag_corr ? f.lag_corr + (long long)c * K_L * P : nullptr, P, out_off);
+                            park + 3 * c * kStatsBlock,
+                            f.lag_corr ? f.lag_corr + (long long)c * K_L * P + pix : nullptr, P);
   }
-  if (f.features) {
+  const bool feat = f.features != nullptr;
+  if (feat) {
     const uint32_t foff = (uint32_t)((long long)y * f.feat_stride_y + x);
+    float *fpark = park + 9 * kStatsBlock;
     if (f.feat_dtype == RAMLT_F16) {
       const _Float16 *fb = (const _Float16 *)f.features;
 #pragma unroll 1
       for (int c = 0; c < RAMLT_N_FEATURES; ++c)
         feature_channel<_Float16, 16>(fb + c * f.feat_stride_c, f.feat_stride_s, foff, f.S,
-                                      f.feat_mean + c * P, f.feat_var + c * P, out_off);
+                                      fpark + c * kStatsBlock);
     } else {
       const float *fb = (const float *)f.features;
 #pragma unroll 1
       for (int c = 0; c < RAMLT_N_FEATURES; ++c)
-        feature_channel<float, 16>(fb + c * f.feat_stride_c, f.feat_stride_s, foff, f.S,
-                                   f.feat_mean + c * P, f.feat_var + c * P, out_off);
+        feature_channel<float, 16>(fb + c * f.feat_stride_c, f.feat_stride_s, foff, f.S, fpark + c * kStatsBlock);
+    }
+  }
+  // deferred result stores
+  const uint32_t o = (uint32_t)pix;
+#pragma unroll
+  for (int c = 0; c < RAMLT_N_RADIANCE; ++c) {
+    store_result(f.mean + c * P, o, park[(3 * c + 0) * kStatsBlock]);
+    store_result(f.var + c * P, o, park[(3 * c + 1) * kStatsBlock]);
+    store_result(f.tau + c * P, o, park[(3 * c + 2) * kStatsBlock]);
+  }
+  if (feat) {
+#pragma unroll
+    for (int c = 0; c < RAMLT_N_FEATURES; ++c) {
+      store_result(f.feat_mean + c * P, o, park[(9 + c) * kStatsBlock]);
+      store_result(f.feat_var + c * P, o, park[(16 + c) * kStatsBlock]);
     }
   }
 }
 
 template <int KT, int B>
 __global__ __launch_bounds__(kStatsBlock) void stats_kernel(const ramlt_frame f) {
-  stats_pixels<KT, B>(f, (long long)blockIdx.x * kStatsBlock + threadIdx.x);
+  __shared__ float park[kParked * kStatsBlock];
+  stats_tile<KT, B>(f, (long long)blockIdx.x * kStatsBlock, park);
 }
 
-}  // namespace
-
+// Persistent form for a batch of frames: workgroups pop 256-pixel tiles from the plan's
+// queue (frames ordered by samples per pixel, largest first) until it is empty.
 template <int KT, int B>
-static hipError_t launch_stats_single(const ramlt_frame &f, hipStream_t st) {
-  const long long P = (long long)f.W * f.H;
-  const unsigned grid = (unsigned)((P + kStatsBlock - 1) / kStatsBlock);
-  hipLaunchKernelGGL((stats_kernel<KT, B>), dim3(grid), dim3(kStatsBlock), 0, st, f);
-  return hipGetLastError();
+__global__ __launch_bounds__(kStatsBlock) void stats_batched_kernel(const ramlt_frame *__restrict__ frames,
+                                                                    BatchPlan *plan) {
+  __shared__ float park[kParked * kStatsBlock];
+  __shared__ unsigned long long slot;
+  const unsigned long long total = plan->total_tiles;
+  for (;;) {
+    if (threadIdx.x == 0) slot = atomicAdd(&plan->next_tile, 1ULL);
+    __syncthreads();
+    const unsigned long long t = slot;
+    __syncthreads();
+    if (t >= total) break;
+    int fi;
+    long long local;
+    plan_lookup(plan, t, &fi, &local);
+    stats_tile<KT, B>(frames[fi], local * kStatsBlock, park);
+  }
 }
 
-static int lag_bucket(int k) {
+int lag_bucket(int k) {
   if (k <= 0) return 0;
   if (k <= 1) return 1;
   if (k <= 2) return 2;
@@ -217,24 +268,36 @@ static int lag_bucket(int k) {
   return 32;
 }
 
-hipError_t launch_stats(const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws, hipStream_t st) {
-  (void)fd;
-  (void)ws;
-  hipError_t e = hipSuccess;
-  for (int i = 0; i < n && e == hipSuccess; ++i) {
-    const ramlt_frame &f = fh[i];
-    const int KT = lag_bucket(min(f.max_lag, f.S - 1));
-    switch (KT) {
-      case 0: e = launch_stats_single<0, 16>(f, st); break;
-      case 1: e = launch_stats_single<1, 16>(f, st); break;
-      case 2: e = launch_stats_single<2, 16>(f, st); break;
-      case 4: e = launch_stats_single<4, 16>(f, st); break;
-      case 8: e = launch_stats_single<8, 16>(f, st); break;
-      case 16: e = launch_stats_single<16, 16>(f, st); break;
-      default: e = launch_stats_single<32, 32>(f, st); break;
-    }
+template <int KT, int B>
+hipError_t launch_stats_kt(const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws, hipStream_t st) {
+  if (n == 1) {
+    const long long P = (long long)fh[0].W * fh[0].H;
+    const unsigned grid = (unsigned)((P + kStatsBlock - 1) / kStatsBlock);
+    hipLaunchKernelGGL((stats_kernel<KT, B>), dim3(grid), dim3(kStatsBlock), 0, st, fh[0]);
+    return hipGetLastError();
   }
-  return e;
+  BatchPlan *plan = (BatchPlan *)ws;
+  hipError_t e = launch_plan(fd, n, RAMLT_OP_STATS, -1, plan, st);
+  if (e != hipSuccess) return e;
+  const int grid = persistent_grid((const void *)stats_batched_kernel<KT, B>, kStatsBlock);
+  hipLaunchKernelGGL((stats_batched_kernel<KT, B>), dim3(grid), dim3(kStatsBlock), 0, st, fd, plan);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stats(const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws, hipStream_t st) {
+  int kl = 0;
+  for (int i = 0; i < n; ++i) kl = max(kl, min(fh[i].max_lag, fh[i].S - 1));
+  switch (lag_bucket(kl)) {
+    case 0: return launch_stats_kt<0, 16>(fh, fd, n, ws, st);
+    case 1: return launch_stats_kt<1, 16>(fh, fd, n, ws, st);
+    case 2: return launch_stats_kt<2, 16>(fh, fd, n, ws, st);
+    case 4: return launch_stats_kt<4, 16>(fh, fd, n, ws, st);
+    case 8: return launch_stats_kt<8, 16>(fh, fd, n, ws, st);
+    case 16: return launch_stats_kt<16, 16>(fh, fd, n, ws, st);
+    default: return launch_stats_kt<32, 32>(fh, fd, n, ws, st);
+  }
 }
 
 }  // namespace ramlt

@@ -130,17 +130,28 @@ def loss_seed(out, reference, grad_out=None, loss=None):
 
 
 def filter_backward(grad_out, mean, out, lam, radius, S, n_regions=None, lambda_min=LAMBDA_MIN_DEFAULT,
-                    want_grad_lambda=True, grad_radiance=None, grad_lambda=None):
-    """Adjoint of the filter: (G [3,H,W] = dL/dg for every sample, dL/dlambda [N*N])."""
+                    want_grad_lambda=True, grad_radiance=None, grad_lambda=None, reference=None, loss=None):
+    """Adjoint of the filter: (G [3,H,W] = dL/dg for every sample, dL/dlambda [N*N]).
+
+    With ``grad_out=None`` and a ``reference`` image, the MSE loss seed is fused into the
+    adjoint (U is never written); ``loss`` (fp64 [1]), if given, accumulates the MSE."""
     f = filter_frame(mean, lam, radius, n_regions, lambda_min)
-    _check_plane(grad_out, "grad_out")
     _check_plane(out, "out")
+    if grad_out is None:
+        if reference is None:
+            raise ValueError("filter_backward needs grad_out or a reference image")
+        _check_plane(reference, "reference")
+        f.reference = reference.data_ptr()
+        f.loss = _ptr(loss)
+    else:
+        _check_plane(grad_out, "grad_out")
+        f.grad_out = grad_out.data_ptr()
     f.S = int(S)
     if grad_radiance is None:
         grad_radiance = torch.empty_like(mean)
     if want_grad_lambda and grad_lambda is None:
         grad_lambda = torch.zeros_like(lam)
-    f.grad_out, f.out = grad_out.data_ptr(), out.data_ptr()
+    f.out = out.data_ptr()
     f.grad_radiance = grad_radiance.data_ptr()
     f.grad_lambda = _ptr(grad_lambda) if want_grad_lambda else None
     _abi.filter_backward([f], stream=_stream())

@@ -144,14 +144,48 @@ def test_filter_validation_errors(lib, name, mutate):
     assert _status(name, [f]) == _abi.RAMLT_EINVAL
 
 
-@pytest.mark.parametrize("field", ["grad_out", "grad_radiance"])
-def test_backward_requires_gradient_buffers(lib, field):
+def test_backward_requires_gradient_buffers(lib):
     f = _valid_filter_frame()
-    setattr(f, field, None)
+    f.grad_radiance = None
     assert _status("filter_backward", [f]) == _abi.RAMLT_EINVAL
     f = _valid_filter_frame()
     f.S = 0
     assert _status("filter_backward", [f]) == _abi.RAMLT_EINVAL
+    # no grad_out: the fused loss seed needs the reference image
+    f = _valid_filter_frame()
+    f.grad_out, f.reference = None, None
+    assert _status("filter_backward", [f]) == _abi.RAMLT_EINVAL
+    f = _valid_filter_frame()
+    f.grad_out = None
+    assert _status("filter_backward", [f]) in (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
+    f.loss = 0xB0004
+    assert _status("filter_backward", [f]) == _abi.RAMLT_EINVAL
+
+
+def test_batches_need_a_workspace(lib):
+    fs = [_valid_stats_frame(), _valid_stats_frame()]
+    need = _abi.workspace_size(fs, _abi.OP_STATS)
+    assert need >= 256 and need % 256 == 0
+    assert _abi.workspace_size(fs[:1], _abi.OP_STATS) == 0
+    dev_table = 0x1000000  # any 8-byte-aligned address: validation never dereferences it
+    assert _status("stats_accumulate", fs, frames_dev=dev_table) == _abi.RAMLT_EWORKSPACE
+    assert _status("stats_accumulate", fs, frames_dev=dev_table, workspace=0x2000000, ws_bytes=need - 8) == \
+        _abi.RAMLT_EWORKSPACE
+    assert _status("stats_accumulate", fs, frames_dev=dev_table, workspace=0x2000010, ws_bytes=need) == \
+        _abi.RAMLT_EWORKSPACE  # misaligned
+    assert _status("stats_accumulate", fs, frames_dev=dev_table, workspace=0x2000000, ws_bytes=need) in \
+        (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
+    # filter batches plan one queue per distinct radius
+    ff = [_valid_filter_frame(), _valid_filter_frame(), _valid_filter_frame()]
+    ff[1].radius = 5
+    one = _abi.workspace_size(ff[:1] + ff[:1], _abi.OP_FILTER_FORWARD)
+    assert _abi.workspace_size(ff, _abi.OP_FILTER_FORWARD) >= 2 * one - 256
+
+
+def test_side_limit(lib):
+    f = _valid_stats_frame()
+    f.W, f.H, f.rad_stride_y = 70000, 1, 70000
+    assert _status("stats_accumulate", [f]) == _abi.RAMLT_EUNSUPPORTED
 
 
 @pytest.mark.parametrize("field", ["out", "reference", "grad_out"])
