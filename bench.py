@@ -38,7 +38,9 @@ def parse():
     p.add_argument("--regions", type=int, default=N_DEFAULT)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-rows", type=int, default=0, help="rows of the frame the oracle times (0 = auto)")
-    p.add_argument("--traffic", type=str, default="", help="JSON file with rocprofv3 HBM byte counts")
+    p.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "stats_accumulate_traffic.txt"),
+                   help="rocprofv3 HBM byte count of the statistics kernel (JSON); ignored if the kernel "
+                        "source changed since it was taken")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of MIB MiB (counter calibration) and exit")
     return p.parse_args()
@@ -55,6 +57,22 @@ def calibrate_copy(mib):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}), flush=True)
+
+
+def measured_traffic(path, W, H, S):
+    """HBM bytes per statistics launch from a committed rocprofv3 count, or None if the
+    count is for another workload or the kernel source has changed since."""
+    import hashlib
+
+    if not path or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if (W, H, S) != (1920, 1080, 64):
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def stats_bytes(P, S, feat_bytes=4):
@@ -176,9 +194,7 @@ def main():
 
     sb = stats_bytes(P, S)
     achieved = sb / (stats_ms * 1e-3) / 1e9
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("stats_accumulate_bytes")
+    traffic = measured_traffic(args.traffic, W, H, S)
 
     result = {
         "metric": "Mpixel/s filtered (fwd, fwd+bwd) at 1080p 64spp; % of HBM roofline",

@@ -12,10 +12,12 @@ constexpr int kWave = 64;
 
 // Screen-grid region of a pixel centre: cell floor(N * (x + 1/2) / W) per axis, computed
 // in integers (Sec. 5.2 state-dependent parameters over the Sec. 6.1 uniform grid).
+// 32-bit unsigned arithmetic is exact: W, H <= 65536 and N <= 4096 are validated.
+__device__ __forceinline__ int cell_of(int c, int n, int N) {
+  return (int)(((unsigned)(2 * c + 1) * (unsigned)N) / (2u * (unsigned)n));
+}
 __device__ __forceinline__ int region_of(int x, int y, int W, int H, int N) {
-  const int kx = (int)(((int64_t)(2 * x + 1) * N) / (2 * (int64_t)W));
-  const int ky = (int)(((int64_t)(2 * y + 1) * N) / (2 * (int64_t)H));
-  return ky * N + kx;
+  return cell_of(y, H, N) * N + cell_of(x, W, N);
 }
 
 // 1/(2 sigma^2) for the region parameter lambda = log sigma^2 (Sec. 5.3), with lambda

@@ -142,25 +142,53 @@ __device__ __forceinline__ float4 load3(const float *p, long long P, long long o
 }
 
 // ------------------------------------------------------------------------ forward
+// 1-D normaliser along an axis: the full window sum Z = sum_{|d|<=R} w(|d|) away from the
+// border, the clipped sum within R of it.
+template <int R, int MOM>
+__device__ __forceinline__ float axis_sum(const float (&w)[R + 1], float full, int c, int n) {
+  return (c >= R && c + R < n) ? full : clipped_sum<R, MOM>(w, c, n);
+}
+
 template <int R>
-__device__ __forceinline__ void forward_tile(const ramlt_frame &f, const Rect &r, float4 *stage, float4 *hbuf) {
+__device__ __forceinline__ float window_sum(const float (&w)[R + 1]) {
+  float z = 0.f;
+#pragma unroll
+  for (int d = R; d >= 1; --d) z += w[d];
+  return 1.0f + 2.0f * z;
+}
+
+template <int R>
+__device__ __forceinline__ float window_moment2(const float (&w)[R + 1]) {
+  float z = 0.f;
+#pragma unroll
+  for (int d = R; d >= 1; --d) z += w[d] * (float)(d * d);
+  return 2.0f * z;
+}
+
+template <int R>
+__device__ __forceinline__ void forward_tile(const ramlt_frame &f, const Rect &r, float4 *stage, float4 *hbuf,
+                                             float *wtab) {
   constexpr int HX = kTX + 2 * R;
   constexpr int HY = kTY + 2 * R;
   const long long P = (long long)f.W * f.H;
-  stage_halo<R>(f, r.x0, r.y0, stage, [&](int gx, int gy) { return load3(f.mean, P, (long long)gy * f.W + gx); });
-  __syncthreads();
   const int tx = threadIdx.x % kTX;
   const int ty = threadIdx.x / kTX;
   const int x = r.x0 + tx;
   const int y = r.y0 + ty;
   const bool inside = x < r.x1 && y < r.y1;
-  const bool uniform = region_of(r.x0, r.y0, f.W, f.H, f.n_regions) ==
-                       region_of(r.x1 - 1, r.y1 - 1, f.W, f.H, f.n_regions);
+  const int k0 = region_of(r.x0, r.y0, f.W, f.H, f.n_regions);
+  const bool uniform = k0 == region_of(r.x1 - 1, r.y1 - 1, f.W, f.H, f.n_regions);
+  if (uniform && threadIdx.x <= R) {
+    const float beta = half_inv_var(f.lambda[k0], f.lambda_min);
+    wtab[threadIdx.x] = threadIdx.x == 0 ? 1.0f : expf(-(float)(threadIdx.x * threadIdx.x) * beta);
+  }
+  stage_halo<R>(f, r.x0, r.y0, stage, [&](int gx, int gy) { return load3(f.mean, P, (long long)gy * f.W + gx); });
+  __syncthreads();
   if (uniform) {
     // one sigma for the whole tile: rows, then columns
-    const float beta = half_inv_var(f.lambda[region_of(r.x0, r.y0, f.W, f.H, f.n_regions)], f.lambda_min);
     float w[R + 1];
-    gauss_weights<R>(beta, w);
+#pragma unroll
+    for (int d = 0; d <= R; ++d) w[d] = wtab[d];
     for (int i = threadIdx.x; i < HY * kTX; i += kFilterBlock) {
       const int hy = i / kTX;
       const int hx = i - hy * kTX;
@@ -187,7 +215,8 @@ __device__ __forceinline__ void forward_tile(const ramlt_frame &f, const Rect &r
         ay = fmaf(wy, h.y, ay);
         az = fmaf(wy, h.z, az);
       }
-      const float D = clipped_sum<R, 0>(w, x, f.W) * clipped_sum<R, 0>(w, y, f.H);
+      const float Z = window_sum<R>(w);
+      const float D = axis_sum<R, 0>(w, Z, x, f.W) * axis_sum<R, 0>(w, Z, y, f.H);
       const long long o = (long long)y * f.W + x;
       f.out[o] = ax / D;
       f.out[P + o] = ay / D;
@@ -276,11 +305,12 @@ __device__ __forceinline__ void reduce_lambda(float *grad_lambda, int key, float
   }
 }
 
-// Per-tile adjoint. LDS: stage (HX*HY float4), hb1/hb2 (HY*kTX float4 each), tab (weights
-// of up to 3x3 regions around the tile), rows (row slots of the halo), red (reductions).
+// Per-tile adjoint. LDS: stage (a_j, then the means; HX*HY float4), hb1/hb2
+// (HY*kTX float4), tab/ztab (1-D weights and window sums of the <= 3 x 3 regions around the
+// tile), rows (row slots of the halo), red (reductions).
 template <int R>
 __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &r, float4 *stage, float4 *hb1,
-                                              float4 *hb2, float *tab, int *rows, double *red) {
+                                              float4 *hb2, float *tab, float *ztab, int *rows, double *red) {
   constexpr int HX = kTX + 2 * R;
   constexpr int HY = kTY + 2 * R;
   const int W = f.W, H = f.H, N = f.n_regions;
@@ -301,6 +331,8 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
   const int kx_lo = cell_x(gx_lo, f), nsx = cell_x(gx_hi, f) - kx_lo + 1;
   const int ky_lo = cell_y(gy_lo, f), nsy = cell_y(gy_hi, f) - ky_lo + 1;
   const bool sep = nsx <= 3 && nsy <= 3;  // block-uniform
+  const int k0 = region_of(r.x0, r.y0, W, H, N);
+  const bool uniform = k0 == region_of(r.x1 - 1, r.y1 - 1, W, H, N);
 
   // U_j of an in-image pixel (given, or from the fused MSE seed)
   auto U_at = [&](long long q) -> float4 {
@@ -311,31 +343,62 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
     return load3(f.grad_out, P, q);
   };
 
-  // ---- stage a_j = U_j / (S D_j) and the source's region-column slot (or beta' for the
-  // direct path) over tile + halo
-  stage_halo<R>(f, r.x0, r.y0, stage, [&](int gx, int gy) {
-    const long long q = (long long)gy * W + gx;
-    const float beta = half_inv_var(f.lambda[region_of(gx, gy, W, H, N)], f.lambda_min);
-    float w[R + 1];
-    gauss_weights<R>(beta, w);
-    const float s = invS / (clipped_sum<R, 0>(w, gx, W) * clipped_sum<R, 0>(w, gy, H));
-    const float4 u = U_at(q);
-    const float tag = sep ? (float)(cell_x(gx, f) - kx_lo) : beta * kLog2e;
-    return make_float4(u.x * s, u.y * s, u.z * s, tag);
-  });
   if (sep) {
-    // weights of the (<= 3 x 3) regions around the tile, and row slots of the halo
-    for (int i = threadIdx.x; i < 9 * (R + 1); i += kFilterBlock) {
-      const int d = i % (R + 1), s = i / (R + 1);
-      const int sx = s % 3, sy = s / 3;
+    // weights and window sums of the (<= 3 x 3) regions around the tile; row slots
+    if (threadIdx.x < 9) {
+      const int sx = threadIdx.x % 3, sy = threadIdx.x / 3;
       const int kx = min(kx_lo + sx, N - 1), ky = min(ky_lo + sy, N - 1);
       const float beta = half_inv_var(f.lambda[ky * N + kx], f.lambda_min);
-      tab[i] = d == 0 ? 1.0f : expf(-(float)(d * d) * beta);
+      float w[R + 1];
+      gauss_weights<R>(beta, w);
+#pragma unroll
+      for (int d = 0; d <= R; ++d) tab[threadIdx.x * (R + 1) + d] = w[d];
+      ztab[threadIdx.x] = window_sum<R>(w);
     }
     for (int i = threadIdx.x; i < HY; i += kFilterBlock) {
       const int gy = min(max(r.y0 - R + i, 0), H - 1);
       rows[i] = cell_y(gy, f) - ky_lo;
     }
+    __syncthreads();
+  }
+
+  // ---- stage a_j = U_j / (S D_j) with the source's region-column slot (or beta' for the
+  // direct path), and the means, over tile + halo
+  for (int i = threadIdx.x; i < HX * HY; i += kFilterBlock) {
+    const int hy = i / HX;
+    const int hx = i - hy * HX;
+    const int gx = r.x0 - R + hx;
+    const int gy = r.y0 - R + hy;
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+      const long long q = (long long)gy * W + gx;
+      float D, tag;
+      if (sep) {
+        const int sx = cell_x(gx, f) - kx_lo;
+        const int slot = rows[hy] * 3 + sx;
+        const float z = ztab[slot];
+        float Dx = z, Dy = z;
+        if (gx < R || gx + R >= W || gy < R || gy + R >= H) {
+          float w[R + 1];
+#pragma unroll
+          for (int d = 0; d <= R; ++d) w[d] = tab[slot * (R + 1) + d];
+          Dx = axis_sum<R, 0>(w, z, gx, W);
+          Dy = axis_sum<R, 0>(w, z, gy, H);
+        }
+        D = Dx * Dy;
+        tag = (float)sx;
+      } else {
+        const float beta = half_inv_var(f.lambda[region_of(gx, gy, W, H, N)], f.lambda_min);
+        float w[R + 1];
+        gauss_weights<R>(beta, w);
+        D = clipped_sum<R, 0>(w, gx, W) * clipped_sum<R, 0>(w, gy, H);
+        tag = beta * kLog2e;
+      }
+      const float s = invS / D;
+      const float4 u = U_at(q);
+      a = make_float4(u.x * s, u.y * s, u.z * s, tag);
+    }
+    stage[i] = a;
   }
   __syncthreads();
 
@@ -353,16 +416,16 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
         for (int d = 0; d <= R; ++d) w[d] = wt[d];
         const float4 *src = stage + hy * HX + hx + R;
         const float fsx = (float)sx;
-        float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int dx = -R; dx <= R; ++dx) {
           const float4 v = src[dx];
-          const float ww = v.w == fsx ? w[dx < 0 ? -dx : dx] : 0.f;
-          a.x = fmaf(ww, v.x, a.x);
-          a.y = fmaf(ww, v.y, a.y);
-          a.z = fmaf(ww, v.z, a.z);
+          const float ww = (nsx == 1 || v.w == fsx) ? w[dx < 0 ? -dx : dx] : 0.f;
+          acc.x = fmaf(ww, v.x, acc.x);
+          acc.y = fmaf(ww, v.y, acc.y);
+          acc.z = fmaf(ww, v.z, acc.z);
         }
-        hb1[i] = a;
+        hb1[i] = acc;
       }
       __syncthreads();
       if (inside) {
@@ -414,16 +477,22 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
 
   // ---- dL/dlambda_k(j) += beta_j sum_c U_jc (N2_jc - out_jc H2_j) / D_j
   if (!f.grad_lambda) return;
-  __syncthreads();  // stage is rewritten below
-  stage_halo<R>(f, r.x0, r.y0, stage, [&](int gx, int gy) { return load3(f.mean, P, (long long)gy * W + gx); });
+  __syncthreads();  // stage is reused for the means
+  float4 *smu = stage;
+  stage_halo<R>(f, r.x0, r.y0, smu, [&](int gx, int gy) { return load3(f.mean, P, (long long)gy * W + gx); });
   __syncthreads();
-  const bool uniform = region_of(r.x0, r.y0, W, H, N) == region_of(r.x1 - 1, r.y1 - 1, W, H, N);
-  const int k_own = inside ? region_of(x, y, W, H, N) : region_of(r.x0, r.y0, W, H, N);
+  const int k_own = inside ? region_of(x, y, W, H, N) : k0;
   const float lam = f.lambda[k_own];
   const bool live = lam >= f.lambda_min;
   const float beta = half_inv_var(lam, f.lambda_min);
   float w[R + 1], wd2[R + 1];
-  gauss_weights<R>(beta, w);
+  if (sep && uniform) {
+    const int slot = (cell_y(r.y0, f) - ky_lo) * 3 + (cell_x(r.x0, f) - kx_lo);
+#pragma unroll
+    for (int d = 0; d <= R; ++d) w[d] = tab[slot * (R + 1) + d];
+  } else {
+    gauss_weights<R>(beta, w);
+  }
 #pragma unroll
   for (int d = 0; d <= R; ++d) wd2[d] = w[d] * (float)(d * d);
   float nx = 0.f, ny = 0.f, nz = 0.f;
@@ -432,7 +501,7 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
       for (int i = threadIdx.x; i < HY * kTX; i += kFilterBlock) {
         const int hy = i / kTX;
         const int hx = i - hy * kTX;
-        const float4 *row = stage + hy * HX + hx + R;
+        const float4 *row = smu + hy * HX + hx + R;
         float4 a1 = make_float4(0.f, 0.f, 0.f, 0.f), a2 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int dx = -R; dx <= R; ++dx) {
@@ -464,7 +533,7 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
   } else if (inside && live) {
 #pragma unroll
     for (int dy = -R; dy <= R; ++dy) {
-      const float4 *row = stage + (ty + R + dy) * HX + tx + R;
+      const float4 *row = smu + (ty + R + dy) * HX + tx + R;
       float r1x = 0.f, r1y = 0.f, r1z = 0.f, r2x = 0.f, r2y = 0.f, r2z = 0.f;
 #pragma unroll
       for (int dx = -R; dx <= R; ++dx) {
@@ -485,15 +554,22 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
   }
   float contrib = 0.f;
   if (inside && live) {
-    const float sx0 = clipped_sum<R, 0>(w, x, W), sy0 = clipped_sum<R, 0>(w, y, H);
-    const float sx2 = clipped_sum<R, 2>(w, x, W), sy2 = clipped_sum<R, 2>(w, y, H);
+    const float Z0 = window_sum<R>(w), Z2 = window_moment2<R>(w);
+    const float sx0 = axis_sum<R, 0>(w, Z0, x, W), sy0 = axis_sum<R, 0>(w, Z0, y, H);
+    const float sx2 = axis_sum<R, 2>(w, Z2, x, W), sy2 = axis_sum<R, 2>(w, Z2, y, H);
     const float H2 = sx2 * sy0 + sx0 * sy2;
     const float D = sx0 * sy0;
     const float4 u = U_at(o);
     const float t = u.x * (nx - f.out[o] * H2) + u.y * (ny - f.out[P + o] * H2) + u.z * (nz - f.out[2 * P + o] * H2);
     contrib = beta * t / D;
   }
-  reduce_lambda(f.grad_lambda, inside ? k_own : -1, contrib);
+  if (uniform) {
+    // one region for the whole tile: block reduction, one atomic
+    const double s = block_sum((double)contrib, red);
+    if (threadIdx.x == 0 && live) unsafeAtomicAdd(f.grad_lambda + k0, (float)s);
+  } else {
+    reduce_lambda(f.grad_lambda, inside ? k_own : -1, contrib);
+  }
 }
 
 // ------------------------------------------------------------------------ kernels
@@ -508,6 +584,7 @@ template <int R>
 struct FwdLds {
   float4 stage[(kTX + 2 * R) * (kTY + 2 * R)];
   float4 hb1[(kTY + 2 * R) * kTX];
+  float wtab[R + 1];
 };
 
 template <int R>
@@ -516,6 +593,7 @@ struct BwdLds {
   float4 hb1[(kTY + 2 * R) * kTX];
   float4 hb2[(kTY + 2 * R) * kTX];
   float tab[9 * (R + 1)];
+  float ztab[9];
   int rows[kTY + 2 * R];
   double red[kFilterBlock / kWave];
 };
@@ -527,7 +605,7 @@ __global__ __launch_bounds__(kFilterBlock) void forward_kernel(const ramlt_frame
   if (t >= ntiles) return;
   const Rect r = tile_rect(f, t);
   if (r.x0 >= r.x1 || r.y0 >= r.y1) return;
-  forward_tile<R>(f, r, s.stage, s.hb1);
+  forward_tile<R>(f, r, s.stage, s.hb1, s.wtab);
 }
 
 template <int R>
@@ -537,7 +615,7 @@ __global__ __launch_bounds__(kFilterBlock) void backward_kernel(const ramlt_fram
   if (t >= ntiles) return;
   const Rect r = tile_rect(f, t);
   if (r.x0 >= r.x1 || r.y0 >= r.y1) return;
-  backward_tile<R>(f, r, s.stage, s.hb1, s.hb2, s.tab, s.rows, s.red);
+  backward_tile<R>(f, r, s.stage, s.hb1, s.hb2, s.tab, s.ztab, s.rows, s.red);
 }
 
 // Persistent forms for a batch: pop (frame, tile) pairs from the plan's queue.
@@ -561,9 +639,9 @@ __global__ __launch_bounds__(kFilterBlock) void filter_batched_kernel(const raml
     const Rect r = tile_rect(f, local);
     if (r.x0 < r.x1 && r.y0 < r.y1) {  // block-uniform
       if constexpr (BWD)
-        backward_tile<R>(f, r, s.stage, s.hb1, s.hb2, s.tab, s.rows, s.red);
+        backward_tile<R>(f, r, s.stage, s.hb1, s.hb2, s.tab, s.ztab, s.rows, s.red);
       else
-        forward_tile<R>(f, r, s.stage, s.hb1);
+        forward_tile<R>(f, r, s.stage, s.hb1, s.wtab);
     }
     __syncthreads();  // LDS is reused by the next tile
   }
