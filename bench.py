@@ -130,9 +130,11 @@ def main():
     tabf = (_abi.RamltFrame * 1)(ff)
     tabu = (_abi.RamltFrame * 1)(fu)
     lib = _abi.load()
+    # the adjoint's workspace (per-tile partial sums), allocated once
+    ws_t, ws_ptr, ws_bytes = ops.workspace_for([ff], _abi.OP_FILTER_BACKWARD, dev)
 
     def call(fn, tab):
-        st = fn(tab, None, 1, None, 0, sh)
+        st = fn(tab, None, 1, ws_ptr, ws_bytes, sh)
         if st != 0:
             raise RuntimeError(_abi.last_error())
 

@@ -71,6 +71,7 @@ enum ramlt_op {
 #define RAMLT_MAX_RADIUS 15
 #define RAMLT_MAX_LAG 32
 #define RAMLT_MAX_FRAMES 4096
+#define RAMLT_MAX_REGIONS 4096             /* n_regions (grid side N) must not exceed this */
 #define RAMLT_MAX_PLANE_ELEMS (1LL << 30) /* (H-1)*stride_y + W and W*H must not exceed this */
 #define RAMLT_MAX_SIDE 65536               /* W and H must not exceed this               */
 
@@ -98,7 +99,7 @@ typedef struct ramlt_frame {
 
   /* filter parameters: lambda[n_regions * n_regions], row-major (ky, kx), in           */
   const float *lambda;
-  int32_t n_regions;      /* grid size N >= 1 (the paper's N_top = 20)                  */
+  int32_t n_regions;      /* grid size N, 1..RAMLT_MAX_REGIONS (the paper's N_top = 20)  */
   int32_t radius;         /* window radius r, 0..RAMLT_MAX_RADIUS; K = 2r + 1           */
   float lambda_min;       /* lower clamp of lambda (the paper uses -30); finite         */
   int32_t _reserved0;
@@ -144,8 +145,13 @@ int loss_seed(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
  * Requires: mean, out, lambda, grad_radiance, and either grad_out, or (grad_out NULL)
  * reference: then U = 2 (out - reference) / (3 W H) is formed inside the kernel (the
  * loss seed fused into the adjoint, nothing written to grad_out) and *loss, if not
- * NULL, accumulates the MSE as loss_seed would. grad_lambda may be NULL. The lambda and
- * loss sums use atomics, so their rounding order is not deterministic. */
+ * NULL, accumulates the MSE as loss_seed would. grad_lambda may be NULL.
+ * Workspace: always needed, ramlt_workspace_size(..., RAMLT_OP_FILTER_BACKWARD) bytes
+ * (per-tile partial sums of dL/dlambda and of the loss, then a plan per radius for a
+ * batch). The partials are added in a fixed order by a second kernel, one atomic add per
+ * (frame, region) and per frame: a single frame whose regions are >= 16 px wide and
+ * >= 4 px tall gets run-to-run identical grad_lambda and loss; smaller regions, and frames
+ * of a batch that share grad_lambda or loss, are summed in atomic (unordered) order. */
 int filter_backward(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
                     int32_t n_frames, void *workspace, size_t ws_bytes, void *stream);
 

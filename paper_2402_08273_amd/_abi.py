@@ -30,6 +30,7 @@ OP_FILTER_BACKWARD = 3
 MAX_RADIUS = 15
 MAX_LAG = 32
 MAX_FRAMES = 4096
+MAX_REGIONS = 4096
 
 EXPORTED = (
     "stats_accumulate",

@@ -71,8 +71,8 @@ int check_common(const ramlt_frame *fh, const ramlt_frame *fd, int32_t n) {
 }
 
 int check_filter_params(int i, const ramlt_frame &f) {
-  if (f.n_regions < 1 || f.n_regions > 4096)
-    return fail(RAMLT_EINVAL, "frame %d: n_regions %d outside 1..4096", i, f.n_regions);
+  if (f.n_regions < 1 || f.n_regions > RAMLT_MAX_REGIONS)
+    return fail(RAMLT_EINVAL, "frame %d: n_regions %d outside 1..%d", i, f.n_regions, RAMLT_MAX_REGIONS);
   if (f.radius < 0 || f.radius > RAMLT_MAX_RADIUS)
     return fail(RAMLT_EINVAL, "frame %d: radius %d outside 0..%d", i, f.radius, RAMLT_MAX_RADIUS);
   if (!std::isfinite(f.lambda_min)) return fail(RAMLT_EINVAL, "frame %d: lambda_min is not finite", i);
@@ -226,6 +226,6 @@ size_t ramlt_workspace_size(const ramlt_frame *frames_host, int32_t n_frames, in
 
 const char *ramlt_last_error(void) { return g_last_error.c_str(); }
 
-int32_t ramlt_abi_version(void) { return (int32_t)((sizeof(ramlt_frame) << 16) | 1); }
+int32_t ramlt_abi_version(void) { return (int32_t)((sizeof(ramlt_frame) << 16) | 2); }
 
 }  // extern "C"

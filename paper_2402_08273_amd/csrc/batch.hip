@@ -26,7 +26,7 @@ __device__ long long tiles_of(const ramlt_frame &f, int op, int radius_sel) {
       return (P + kLossTilePixels - 1) / kLossTilePixels;
     default:
       if (radius_sel >= 0 && f.radius != radius_sel) return 0;
-      return (long long)((f.W + kFilterTileW - 1) / kFilterTileW) * ((f.H + kFilterTileH - 1) / kFilterTileH);
+      return filter_tile_count(f);
   }
 }
 

@@ -45,28 +45,6 @@ struct Rect {
   int x0, y0, x1, y1;  // outputs [x0, x1) x [y0, y1)
 };
 
-// First coordinate (of n) whose cell floor((2c + 1) N / (2n)) is >= k. Every region is
-// at most ceil(n / N) wide. 32-bit arithmetic: n <= 65536 and N <= 4096 (validated).
-__host__ __device__ inline int region_start(int k, int n, int N) {
-  if (k <= 0) return 0;
-  if (k >= N) return n;
-  // (2c + 1) N >= 2 k n  <=>  c >= (2 k n - N) / (2 N)
-  const int num = 2 * k * n - N;
-  const int c = num <= 0 ? 0 : (int)(((unsigned)num + 2u * (unsigned)N - 1u) / (2u * (unsigned)N));
-  return c > n ? n : c;
-}
-
-__host__ __device__ inline bool aligned_tiling(const ramlt_frame &f) {
-  return f.W >= 16 * f.n_regions && f.H >= 4 * f.n_regions;
-}
-
-// Tiles per region along an axis when aligned (some may be empty), else 0.
-__host__ __device__ inline int tiles_per_region(int n, int N, int T) { return ((n + N - 1) / N + T - 1) / T; }
-
-__host__ __device__ inline int tiles_along(int n, int N, int T, bool aligned) {
-  return aligned ? N * tiles_per_region(n, N, T) : (n + T - 1) / T;
-}
-
 // Interval [lo, hi) of the idx-th tile along an axis (possibly empty when aligned).
 __device__ inline void tile_span(int idx, int n, int N, int T, bool aligned, int *lo, int *hi) {
   if (!aligned) {
@@ -305,14 +283,42 @@ __device__ __forceinline__ void reduce_lambda(float *grad_lambda, int key, float
   }
 }
 
-// Per-tile adjoint. LDS: stage (a_j, then the means; HX*HY float4), hb1/hb2
-// (HY*kTX float4), tab/ztab (1-D weights and window sums of the <= 3 x 3 regions around the
-// tile), rows (row slots of the halo), red (reductions).
 template <int R>
-__device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &r, float4 *stage, float4 *hb1,
-                                              float4 *hb2, float *tab, float *ztab, int *rows, double *red) {
-  constexpr int HX = kTX + 2 * R;
-  constexpr int HY = kTY + 2 * R;
+struct BwdLds {
+  static constexpr int HX = kTX + 2 * R;
+  static constexpr int HY = kTY + 2 * R;
+  static constexpr int RS = R > 0 ? R : 1;                              // strip width
+  static constexpr int HB2 = HY * (kTX > 4 * RS ? kTX : 4 * RS);        // hb2 also holds the strips
+  float4 stage[HX * HY];
+  float4 hb1[HY * kTX];
+  float4 hb2[HB2];
+  float tab[9 * (R + 1)];
+  float ztab[9];
+  int rows[HY];
+  double red[kFilterBlock / kWave];
+};
+
+// Per-tile adjoint.
+//
+// Transpose gather (separable path, region-aligned tiles): the tile's outputs lie in one
+// region column [rs, re). Sources of the window lie in that column ("own"), or within R
+// columns to its left or right (the neighbouring region columns). G is
+//   own pass:  rows-then-columns convolution of the own sources (neighbour sources zeroed),
+//              with each source row's weights (its region row may differ from the tile's);
+//   strips:    the <= R neighbour columns on each side, for the <= R output columns they
+//              reach, with the neighbour region's weights.
+// Lambda gather (all tiles of a region share sigma): rows-then-columns sums of mean and
+// mean * dx^2. Per-tile partial sums of dL/dlambda and of the loss go to lam_part /
+// loss_part[slot] when given (a fixed-order finalize kernel adds them up), else atomics.
+template <int R>
+__device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &r, long long slot, float *lam_part,
+                                              double *loss_part, BwdLds<R> &L) {
+  constexpr int HX = BwdLds<R>::HX;
+  constexpr int HY = BwdLds<R>::HY;
+  constexpr int RS = BwdLds<R>::RS;
+  float4 *stage = L.stage, *hb1 = L.hb1, *hb2 = L.hb2;
+  float *tab = L.tab, *ztab = L.ztab;
+  int *rows = L.rows;
   const int W = f.W, H = f.H, N = f.n_regions;
   const long long P = (long long)W * H;
   const bool fused = f.grad_out == nullptr;
@@ -326,13 +332,24 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
   const long long o = (long long)y * W + x;
 
   // Region columns / rows reachable from the tile's window.
-  const int gx_lo = max(r.x0 - R, 0), gx_hi = min(r.x0 + kTX + R, W) - 1;
-  const int gy_lo = max(r.y0 - R, 0), gy_hi = min(r.y0 + kTY + R, H) - 1;
-  const int kx_lo = cell_x(gx_lo, f), nsx = cell_x(gx_hi, f) - kx_lo + 1;
+  const int gx_lo = max(r.x0 - R, 0), gx_hi = min(r.x1 + R, W) - 1;
+  const int gy_lo = max(r.y0 - R, 0), gy_hi = min(r.y1 + R, H) - 1;
+  const int kx_lo = cell_x(gx_lo, f), kx_hi = cell_x(gx_hi, f);
   const int ky_lo = cell_y(gy_lo, f), nsy = cell_y(gy_hi, f) - ky_lo + 1;
-  const bool sep = nsx <= 3 && nsy <= 3;  // block-uniform
+  const int kx_own = cell_x(r.x0, f);
   const int k0 = region_of(r.x0, r.y0, W, H, N);
   const bool uniform = k0 == region_of(r.x1 - 1, r.y1 - 1, W, H, N);
+  // block-uniform: separable gather when the outputs share a region column and only one
+  // neighbour column lies within R on each side
+  const bool sep = uniform && kx_lo >= kx_own - 1 && kx_hi <= kx_own + 1 && nsy <= 3;
+  const int so = kx_own - kx_lo;  // own slot among the (<= 3) region columns
+  const int rs = region_start(kx_own, W, N), re = region_start(kx_own + 1, W, N);
+  const int nL = sep ? rs - gx_lo : 0;          // left strip width (<= R)
+  const int nR = sep ? gx_hi + 1 - re : 0;      // right strip width (<= R)
+  const int mL = nL > 0 ? min(r.x1, rs + R) - r.x0 : 0;  // outputs the left strip reaches
+  const int xR0 = max(r.x0, re - R);                      // first output the right strip reaches
+  const int mR = nR > 0 ? r.x1 - xR0 : 0;
+  float4 *lst = hb2, *rst = hb2 + HY * RS, *hbl = hb2 + 2 * HY * RS, *hbr = hb2 + 3 * HY * RS;
 
   // U_j of an in-image pixel (given, or from the fused MSE seed)
   auto U_at = [&](long long q) -> float4 {
@@ -362,8 +379,9 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
     __syncthreads();
   }
 
-  // ---- stage a_j = U_j / (S D_j) with the source's region-column slot (or beta' for the
-  // direct path), and the means, over tile + halo
+  // ---- stage a_j = U_j / (S D_j) over tile + halo: own-column sources in `stage`
+  // (others zero), neighbour columns in the strips; the direct path keeps every source with
+  // beta' = beta log2(e) in .w
   for (int i = threadIdx.x; i < HX * HY; i += kFilterBlock) {
     const int hy = i / HX;
     const int hx = i - hy * HX;
@@ -372,21 +390,20 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
     if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
       const long long q = (long long)gy * W + gx;
-      float D, tag;
+      float D, tag = 0.f;
       if (sep) {
         const int sx = cell_x(gx, f) - kx_lo;
-        const int slot = rows[hy] * 3 + sx;
-        const float z = ztab[slot];
+        const int sl = rows[hy] * 3 + sx;
+        const float z = ztab[sl];
         float Dx = z, Dy = z;
         if (gx < R || gx + R >= W || gy < R || gy + R >= H) {
           float w[R + 1];
 #pragma unroll
-          for (int d = 0; d <= R; ++d) w[d] = tab[slot * (R + 1) + d];
+          for (int d = 0; d <= R; ++d) w[d] = tab[sl * (R + 1) + d];
           Dx = axis_sum<R, 0>(w, z, gx, W);
           Dy = axis_sum<R, 0>(w, z, gy, H);
         }
         D = Dx * Dy;
-        tag = (float)sx;
       } else {
         const float beta = half_inv_var(f.lambda[region_of(gx, gy, W, H, N)], f.lambda_min);
         float w[R + 1];
@@ -398,6 +415,15 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
       const float4 u = U_at(q);
       a = make_float4(u.x * s, u.y * s, u.z * s, tag);
     }
+    if (sep) {  // every strip entry is written, zero for rows outside the image
+      if (gx < rs) {
+        if (gx >= rs - nL) lst[hy * RS + (gx - (rs - nL))] = a;
+        a = make_float4(0.f, 0.f, 0.f, 0.f);
+      } else if (gx >= re) {
+        if (gx < re + nR) rst[hy * RS + (gx - re)] = a;
+        a = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
     stage[i] = a;
   }
   __syncthreads();
@@ -405,41 +431,80 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
   // ---- G_p = sum_e a_{p+e} h(e; sigma of p+e)
   float gx_ = 0.f, gy_ = 0.f, gz_ = 0.f;
   if (sep) {
-    for (int sx = 0; sx < nsx; ++sx) {
-      // rows: H_sx(hy, x) = sum_dx w_(sx, row)(|dx|) a(hy, x + dx) [source column in slot sx]
-      for (int i = threadIdx.x; i < HY * kTX; i += kFilterBlock) {
-        const int hy = i / kTX;
-        const int hx = i - hy * kTX;
-        const float *wt = tab + (rows[hy] * 3 + sx) * (R + 1);
-        float w[R + 1];
+    // rows: own sources with the own column's weights for each source row
+    for (int i = threadIdx.x; i < HY * kTX; i += kFilterBlock) {
+      const int hy = i / kTX;
+      const int hx = i - hy * kTX;
+      const float *wt = tab + (rows[hy] * 3 + so) * (R + 1);
+      float w[R + 1];
 #pragma unroll
-        for (int d = 0; d <= R; ++d) w[d] = wt[d];
-        const float4 *src = stage + hy * HX + hx + R;
-        const float fsx = (float)sx;
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int d = 0; d <= R; ++d) w[d] = wt[d];
+      const float4 *src = stage + hy * HX + hx + R;
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int dx = -R; dx <= R; ++dx) {
-          const float4 v = src[dx];
-          const float ww = (nsx == 1 || v.w == fsx) ? w[dx < 0 ? -dx : dx] : 0.f;
+      for (int dx = -R; dx <= R; ++dx) {
+        const float4 v = src[dx];
+        const float ww = w[dx < 0 ? -dx : dx];
+        acc.x = fmaf(ww, v.x, acc.x);
+        acc.y = fmaf(ww, v.y, acc.y);
+        acc.z = fmaf(ww, v.z, acc.z);
+      }
+      hb1[i] = acc;
+    }
+    // rows: the strips, for the output columns they reach
+    const int nLitems = HY * mL, nRitems = HY * mR;
+    for (int i = threadIdx.x; i < nLitems + nRitems; i += kFilterBlock) {
+      const bool left = i < nLitems;
+      const int ii = left ? i : i - nLitems;
+      const int m = left ? mL : mR;
+      const int hy = ii / m;
+      const int c = ii - hy * m;
+      const float *wt = tab + (rows[hy] * 3 + (left ? so - 1 : so + 1)) * (R + 1);
+      const int xo = left ? r.x0 + c : xR0 + c;       // output column
+      const int s0 = left ? rs - nL : re;             // first strip column
+      const int ns = left ? nL : nR;
+      const float4 *strip = (left ? lst : rst) + hy * RS;
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int j = 0; j < RS; ++j) {
+        const int d = abs(s0 + j - xo);
+        if (j < ns && d <= R) {
+          const float4 v = strip[j];
+          const float ww = wt[d];
           acc.x = fmaf(ww, v.x, acc.x);
           acc.y = fmaf(ww, v.y, acc.y);
           acc.z = fmaf(ww, v.z, acc.z);
         }
-        hb1[i] = acc;
       }
-      __syncthreads();
-      if (inside) {
+      (left ? hbl : hbr)[hy * RS + c] = acc;
+    }
+    __syncthreads();
+    if (inside) {
 #pragma unroll
-        for (int dy = -R; dy <= R; ++dy) {
-          const int hy = ty + R + dy;
-          const float wy = tab[(rows[hy] * 3 + sx) * (R + 1) + (dy < 0 ? -dy : dy)];
-          const float4 h = hb1[hy * kTX + tx];
-          gx_ = fmaf(wy, h.x, gx_);
-          gy_ = fmaf(wy, h.y, gy_);
-          gz_ = fmaf(wy, h.z, gz_);
+      for (int dy = -R; dy <= R; ++dy) {
+        const int hy = ty + R + dy;
+        const int ay = dy < 0 ? -dy : dy;
+        const int rb = rows[hy] * 3;
+        const float wy = tab[(rb + so) * (R + 1) + ay];
+        const float4 h = hb1[hy * kTX + tx];
+        gx_ = fmaf(wy, h.x, gx_);
+        gy_ = fmaf(wy, h.y, gy_);
+        gz_ = fmaf(wy, h.z, gz_);
+        if (x - r.x0 < mL) {
+          const float wl = tab[(rb + so - 1) * (R + 1) + ay];
+          const float4 hl = hbl[hy * RS + (x - r.x0)];
+          gx_ = fmaf(wl, hl.x, gx_);
+          gy_ = fmaf(wl, hl.y, gy_);
+          gz_ = fmaf(wl, hl.z, gz_);
+        }
+        if (mR > 0 && x >= xR0) {
+          const float wr = tab[(rb + so + 1) * (R + 1) + ay];
+          const float4 hr = hbr[hy * RS + (x - xR0)];
+          gx_ = fmaf(wr, hr.x, gx_);
+          gy_ = fmaf(wr, hr.y, gy_);
+          gz_ = fmaf(wr, hr.z, gz_);
         }
       }
-      __syncthreads();
     }
   } else if (inside) {
 #pragma unroll
@@ -471,13 +536,18 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
         acc = fma((double)d, (double)d, acc);
       }
     }
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) unsafeAtomicAdd(f.loss, s / (3.0 * (double)P));
+    const double s = block_sum(acc, L.red);
+    if (threadIdx.x == 0) {
+      if (loss_part)
+        loss_part[slot] = s;
+      else
+        unsafeAtomicAdd(f.loss, s / (3.0 * (double)P));
+    }
   }
 
   // ---- dL/dlambda_k(j) += beta_j sum_c U_jc (N2_jc - out_jc H2_j) / D_j
   if (!f.grad_lambda) return;
-  __syncthreads();  // stage is reused for the means
+  __syncthreads();  // stage and hb2 are reused below
   float4 *smu = stage;
   stage_halo<R>(f, r.x0, r.y0, smu, [&](int gx, int gy) { return load3(f.mean, P, (long long)gy * W + gx); });
   __syncthreads();
@@ -486,10 +556,10 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
   const bool live = lam >= f.lambda_min;
   const float beta = half_inv_var(lam, f.lambda_min);
   float w[R + 1], wd2[R + 1];
-  if (sep && uniform) {
-    const int slot = (cell_y(r.y0, f) - ky_lo) * 3 + (cell_x(r.x0, f) - kx_lo);
+  if (sep) {
+    const int sl = (cell_y(r.y0, f) - ky_lo) * 3 + so;
 #pragma unroll
-    for (int d = 0; d <= R; ++d) w[d] = tab[slot * (R + 1) + d];
+    for (int d = 0; d <= R; ++d) w[d] = tab[sl * (R + 1) + d];
   } else {
     gauss_weights<R>(beta, w);
   }
@@ -564,12 +634,77 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
     contrib = beta * t / D;
   }
   if (uniform) {
-    // one region for the whole tile: block reduction, one atomic
-    const double s = block_sum((double)contrib, red);
-    if (threadIdx.x == 0 && live) unsafeAtomicAdd(f.grad_lambda + k0, (float)s);
+    // one region for the whole tile: block reduction, one partial (or atomic)
+    const double s = block_sum((double)contrib, L.red);
+    if (threadIdx.x == 0) {
+      if (lam_part && aligned_tiling(f))  // the finalize kernel reads region-aligned partials
+        lam_part[slot] = live ? (float)s : 0.f;
+      else if (live)
+        unsafeAtomicAdd(f.grad_lambda + k0, (float)s);
+    }
   } else {
     reduce_lambda(f.grad_lambda, inside ? k_own : -1, contrib);
   }
+}
+
+// Adds the per-tile partials in a fixed order. blockIdx.y = frame (its position q in a
+// batch plan, or the single frame); block x < kFinalizeLamBlocks(N) sums regions, one wave
+// per region (lane l takes the region's l-th, (l+64)-th, ... tile, then a butterfly sum);
+// the block after those sums the frame's loss partials. One atomic add per region and per
+// frame lands the result in grad_lambda / *loss.
+constexpr int kFinalizeWaves = kFilterBlock / kWave;
+
+__host__ __device__ inline int finalize_lam_blocks(int N) { return (N * N + kFinalizeWaves - 1) / kFinalizeWaves; }
+
+__global__ __launch_bounds__(kFilterBlock) void backward_finalize_kernel(const ramlt_frame single,
+                                                                        const ramlt_frame *__restrict__ frames,
+                                                                        BatchPlan *plan, const float *lam_part,
+                                                                        const double *loss_part) {
+  __shared__ double red[kFinalizeWaves];
+  ramlt_frame f;
+  long long base = 0;
+  if (plan) {
+    const int q = blockIdx.y;
+    f = frames[plan_order(plan)[q]];
+    const long long *pre = plan_prefix(plan, plan->n_frames);
+    if (pre[q + 1] == pre[q]) return;  // frame of another radius: not in this queue
+    base = pre[q];
+  } else {
+    f = single;
+  }
+  const int N = f.n_regions;
+  const bool al = aligned_tiling(f);
+  const int ntx = tiles_along(f.W, N, kTX, al), nty = tiles_along(f.H, N, kTY, al);
+  const int nlb = finalize_lam_blocks(N);
+  if ((int)blockIdx.x < nlb) {
+    if (!f.grad_lambda || !al) return;
+    const int k = blockIdx.x * kFinalizeWaves + threadIdx.x / kWave;
+    if (k >= N * N) return;  // wave-uniform
+    const int lane = threadIdx.x & (kWave - 1);
+    const int tpx = tiles_per_region(f.W, N, kTX), tpy = tiles_per_region(f.H, N, kTY);
+    const int ky = k / N, kx = k - ky * N;
+    float v = 0.f;
+    for (int l = lane; l < tpx * tpy; l += kWave) {
+      const int j = l / tpx, i = l - j * tpx;
+      v += lam_part[base + (long long)(ky * tpy + j) * ntx + (kx * tpx + i)];
+    }
+    v = wave_sum(v);
+    if (lane == 0 && v != 0.f) unsafeAtomicAdd(f.grad_lambda + k, v);
+    return;
+  }
+  if ((int)blockIdx.x != nlb || f.grad_out != nullptr || !f.loss) return;
+  const long long nt = (long long)ntx * nty;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  long long t = threadIdx.x;
+  for (; t + 3 * kFilterBlock < nt; t += 4 * kFilterBlock) {
+    acc0 += loss_part[base + t];
+    acc1 += loss_part[base + t + kFilterBlock];
+    acc2 += loss_part[base + t + 2 * kFilterBlock];
+    acc3 += loss_part[base + t + 3 * kFilterBlock];
+  }
+  for (; t < nt; t += kFilterBlock) acc0 += loss_part[base + t];
+  const double s = block_sum((acc0 + acc1) + (acc2 + acc3), red);
+  if (threadIdx.x == 0) unsafeAtomicAdd(f.loss, s / (3.0 * (double)f.W * (double)f.H));
 }
 
 // ------------------------------------------------------------------------ kernels
@@ -588,18 +723,8 @@ struct FwdLds {
 };
 
 template <int R>
-struct BwdLds {
-  float4 stage[(kTX + 2 * R) * (kTY + 2 * R)];
-  float4 hb1[(kTY + 2 * R) * kTX];
-  float4 hb2[(kTY + 2 * R) * kTX];
-  float tab[9 * (R + 1)];
-  float ztab[9];
-  int rows[kTY + 2 * R];
-  double red[kFilterBlock / kWave];
-};
-
-template <int R>
-__global__ __launch_bounds__(kFilterBlock) void forward_kernel(const ramlt_frame f, long long ntiles) {
+__global__ __launch_bounds__(kFilterBlock) void forward_kernel(const ramlt_frame f, long long ntiles,
+                                                               float *unused0, double *unused1) {
   __shared__ FwdLds<R> s;
   const long long t = xcd_tile(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
@@ -608,20 +733,33 @@ __global__ __launch_bounds__(kFilterBlock) void forward_kernel(const ramlt_frame
   forward_tile<R>(f, r, s.stage, s.hb1, s.wtab);
 }
 
+__device__ __forceinline__ void empty_tile_partials(const ramlt_frame &f, long long slot, float *lam_part,
+                                                    double *loss_part) {
+  if (threadIdx.x == 0) {
+    if (lam_part) lam_part[slot] = 0.f;
+    if (loss_part) loss_part[slot] = 0.0;
+  }
+}
+
 template <int R>
-__global__ __launch_bounds__(kFilterBlock) void backward_kernel(const ramlt_frame f, long long ntiles) {
+__global__ __launch_bounds__(kFilterBlock) void backward_kernel(const ramlt_frame f, long long ntiles,
+                                                                float *lam_part, double *loss_part) {
   __shared__ BwdLds<R> s;
   const long long t = xcd_tile(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
   const Rect r = tile_rect(f, t);
-  if (r.x0 >= r.x1 || r.y0 >= r.y1) return;
-  backward_tile<R>(f, r, s.stage, s.hb1, s.hb2, s.tab, s.ztab, s.rows, s.red);
+  if (r.x0 >= r.x1 || r.y0 >= r.y1) {
+    empty_tile_partials(f, t, lam_part, loss_part);
+    return;
+  }
+  backward_tile<R>(f, r, t, lam_part, loss_part, s);
 }
 
 // Persistent forms for a batch: pop (frame, tile) pairs from the plan's queue.
 template <int R, bool BWD>
 __global__ __launch_bounds__(kFilterBlock) void filter_batched_kernel(const ramlt_frame *__restrict__ frames,
-                                                                      BatchPlan *plan) {
+                                                                      BatchPlan *plan, float *lam_part,
+                                                                      double *loss_part) {
   using Lds = typename std::conditional<BWD, BwdLds<R>, FwdLds<R>>::type;
   __shared__ Lds s;
   __shared__ unsigned long long slot;
@@ -639,9 +777,11 @@ __global__ __launch_bounds__(kFilterBlock) void filter_batched_kernel(const raml
     const Rect r = tile_rect(f, local);
     if (r.x0 < r.x1 && r.y0 < r.y1) {  // block-uniform
       if constexpr (BWD)
-        backward_tile<R>(f, r, s.stage, s.hb1, s.hb2, s.tab, s.ztab, s.rows, s.red);
+        backward_tile<R>(f, r, (long long)t, lam_part, loss_part, s);
       else
         forward_tile<R>(f, r, s.stage, s.hb1, s.wtab);
+    } else if (BWD) {
+      empty_tile_partials(f, (long long)t, lam_part, loss_part);
     }
     __syncthreads();  // LDS is reused by the next tile
   }
@@ -677,8 +817,8 @@ __global__ __launch_bounds__(kLossBlock) void loss_seed_batched_kernel(const ram
   }
 }
 
-using FrameKernel = void (*)(const ramlt_frame, long long);
-using BatchKernel = void (*)(const ramlt_frame *, BatchPlan *);
+using FrameKernel = void (*)(const ramlt_frame, long long, float *, double *);
+using BatchKernel = void (*)(const ramlt_frame *, BatchPlan *, float *, double *);
 
 template <int... Rs>
 struct KernelTables {
@@ -691,30 +831,65 @@ struct KernelTables {
 
 using Tables = KernelTables<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15>;
 
-long long filter_tiles(const ramlt_frame &f) {
-  const bool al = aligned_tiling(f);
-  return (long long)tiles_along(f.W, f.n_regions, kTX, al) * tiles_along(f.H, f.n_regions, kTY, al);
+long long filter_tiles(const ramlt_frame &f) { return filter_tile_count(f); }
+
+// Workspace of filter operations on a batch: per distinct radius one plan, then (backward)
+// the per-tile partials: lam float[T], loss double[T], T = tiles of all frames.
+size_t partials_bytes(const ramlt_frame *fh, int n) {
+  long long T = 0;
+  for (int i = 0; i < n; ++i) T += filter_tiles(fh[i]);
+  const size_t b = (size_t)T * (sizeof(float) + sizeof(double));
+  return (b + 255) & ~(size_t)255;
 }
 
-hipError_t launch_filter(const FrameKernel *single, const BatchKernel *batched, int op, const ramlt_frame *fh,
-                         const ramlt_frame *fd, int n, void *ws, hipStream_t st) {
+hipError_t launch_filter(bool bwd, const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws,
+                         hipStream_t st) {
+  const FrameKernel *single = bwd ? Tables::backward : Tables::forward;
+  const BatchKernel *batched = bwd ? Tables::backward_batched : Tables::forward_batched;
+  const int op = bwd ? RAMLT_OP_FILTER_BACKWARD : RAMLT_OP_FILTER_FORWARD;
   if (n == 1) {
     const ramlt_frame &f = fh[0];
     const long long nt = filter_tiles(f);
+    float *lam_part = nullptr;
+    double *loss_part = nullptr;
+    if (bwd) {
+      lam_part = (float *)ws;
+      loss_part = (double *)((char *)ws + (((size_t)nt * sizeof(float) + 7) & ~(size_t)7));
+    }
     const unsigned grid = (unsigned)(((nt + 7) / 8) * 8);
-    hipLaunchKernelGGL(single[f.radius], dim3(grid), dim3(kFilterBlock), 0, st, f, nt);
+    hipLaunchKernelGGL(single[f.radius], dim3(grid), dim3(kFilterBlock), 0, st, f, nt, lam_part, loss_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !bwd) return e;
+    hipLaunchKernelGGL(backward_finalize_kernel, dim3(finalize_lam_blocks(f.n_regions) + 1), dim3(kFilterBlock), 0,
+                       st, f, (const ramlt_frame *)nullptr, (BatchPlan *)nullptr, lam_part, loss_part);
     return hipGetLastError();
   }
   int radii[RAMLT_MAX_RADIUS + 1];
   const int nr = distinct_radii(fh, n, radii);
+  const size_t pb = plan_bytes(n);
+  const size_t part = bwd ? partials_bytes(fh, n) : 0;
+  long long T = 0;
+  for (int i = 0; i < n; ++i) T += filter_tiles(fh[i]);
   for (int g = 0; g < nr; ++g) {
-    BatchPlan *plan = (BatchPlan *)((char *)ws + (size_t)g * plan_bytes(n));
+    char *base = (char *)ws + (size_t)g * (pb + part);
+    BatchPlan *plan = (BatchPlan *)base;
+    float *lam_part = bwd ? (float *)(base + pb) : nullptr;
+    double *loss_part = bwd ? (double *)(base + pb + (((size_t)T * sizeof(float) + 7) & ~(size_t)7)) : nullptr;
     hipError_t e = launch_plan(fd, n, op, radii[g], plan, st);
     if (e != hipSuccess) return e;
     const int grid = persistent_grid((const void *)batched[radii[g]], kFilterBlock);
-    hipLaunchKernelGGL(batched[radii[g]], dim3(grid), dim3(kFilterBlock), 0, st, fd, plan);
+    hipLaunchKernelGGL(batched[radii[g]], dim3(grid), dim3(kFilterBlock), 0, st, fd, plan, lam_part, loss_part);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (bwd) {
+      ramlt_frame none{};
+      int nmax = 1;
+      for (int i = 0; i < n; ++i) nmax = max(nmax, fh[i].n_regions);
+      hipLaunchKernelGGL(backward_finalize_kernel, dim3(finalize_lam_blocks(nmax) + 1, n), dim3(kFilterBlock), 0, st,
+                         none, fd, plan, lam_part, loss_part);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
@@ -723,12 +898,12 @@ hipError_t launch_filter(const FrameKernel *single, const BatchKernel *batched, 
 
 hipError_t launch_filter_forward(const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws,
                                  hipStream_t st) {
-  return launch_filter(Tables::forward, Tables::forward_batched, RAMLT_OP_FILTER_FORWARD, fh, fd, n, ws, st);
+  return launch_filter(false, fh, fd, n, ws, st);
 }
 
 hipError_t launch_filter_backward(const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws,
                                   hipStream_t st) {
-  return launch_filter(Tables::backward, Tables::backward_batched, RAMLT_OP_FILTER_BACKWARD, fh, fd, n, ws, st);
+  return launch_filter(true, fh, fd, n, ws, st);
 }
 
 hipError_t launch_loss_seed(const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws, hipStream_t st) {
@@ -748,8 +923,17 @@ hipError_t launch_loss_seed(const ramlt_frame *fh, const ramlt_frame *fd, int n,
 }
 
 size_t workspace_bytes(const ramlt_frame *fh, int n, int op) {
+  if (op == RAMLT_OP_FILTER_BACKWARD) {
+    if (n == 1) {
+      const long long nt = filter_tiles(fh[0]);
+      const size_t b = (((size_t)nt * sizeof(float) + 7) & ~(size_t)7) + (size_t)nt * sizeof(double);
+      return (b + 255) & ~(size_t)255;
+    }
+    int radii[RAMLT_MAX_RADIUS + 1];
+    return (size_t)distinct_radii(fh, n, radii) * (plan_bytes(n) + partials_bytes(fh, n));
+  }
   if (n <= 1) return 0;
-  if (op == RAMLT_OP_FILTER_FORWARD || op == RAMLT_OP_FILTER_BACKWARD) {
+  if (op == RAMLT_OP_FILTER_FORWARD) {
     int radii[RAMLT_MAX_RADIUS + 1];
     return (size_t)distinct_radii(fh, n, radii) * plan_bytes(n);
   }

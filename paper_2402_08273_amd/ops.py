@@ -41,6 +41,16 @@ def _check_plane(t, name, channels=3):
         raise ValueError(f"{name} must be a contiguous float32 device tensor [{channels}, H, W]")
 
 
+def workspace_for(frames, op, device):
+    """(tensor, 256-byte-aligned pointer, bytes) of the workspace ``op`` needs on
+    ``frames`` (``(None, None, 0)`` when it needs none)."""
+    need = _abi.workspace_size(frames, op)
+    if need == 0:
+        return None, None, 0
+    t = torch.empty(need + 256, device=device, dtype=torch.uint8)
+    return t, (t.data_ptr() + 255) // 256 * 256, need
+
+
 class Stats(NamedTuple):
     mean: torch.Tensor
     var: torch.Tensor
@@ -154,7 +164,9 @@ def filter_backward(grad_out, mean, out, lam, radius, S, n_regions=None, lambda_
     f.out = out.data_ptr()
     f.grad_radiance = grad_radiance.data_ptr()
     f.grad_lambda = _ptr(grad_lambda) if want_grad_lambda else None
-    _abi.filter_backward([f], stream=_stream())
+    ws, ws_ptr, ws_bytes = workspace_for([f], _abi.OP_FILTER_BACKWARD, mean.device)
+    _abi.filter_backward([f], workspace=ws_ptr, ws_bytes=ws_bytes, stream=_stream())
+    del ws  # freed blocks are reused in stream order, after this launch
     return grad_radiance, grad_lambda
 
 

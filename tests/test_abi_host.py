@@ -77,7 +77,13 @@ def _valid_filter_frame():
     return f
 
 
+FAKE_WORKSPACE = 0x4000000  # 256-byte aligned; validation never dereferences it
+
+
 def _status(name, frames, **kw):
+    # filter_backward always needs a workspace (per-tile partial sums); give it one
+    if name == "filter_backward" and "workspace" not in kw:
+        kw.update(workspace=FAKE_WORKSPACE, ws_bytes=_abi.workspace_size(frames, _abi.OP_FILTER_BACKWARD))
     return _abi.status_of(name, frames, **kw)
 
 
@@ -213,3 +219,17 @@ def test_workspace_size_is_safe_on_bad_input(lib):
     assert lib.ramlt_workspace_size(None, 1, 0) == 0
     arr = (_abi.RamltFrame * 1)(_valid_stats_frame())
     assert lib.ramlt_workspace_size(arr, 0, 0) == 0
+
+
+def test_backward_workspace_holds_tile_partials(lib):
+    f = _valid_filter_frame()
+    f.W, f.H, f.n_regions = 1920, 1080, 20
+    need = _abi.workspace_size([f], _abi.OP_FILTER_BACKWARD)
+    # region-aligned 32 x 8 tiles: 20 * 3 columns x 20 * 7 rows, a float and a double each
+    tiles = (20 * 3) * (20 * 7)
+    assert need % 256 == 0 and tiles * 12 <= need < tiles * 12 + 512
+    assert _abi.workspace_size([f], _abi.OP_FILTER_FORWARD) == 0
+    assert _status("filter_backward", [f], workspace=None, ws_bytes=0) == _abi.RAMLT_EWORKSPACE
+    assert _status("filter_backward", [f], workspace=FAKE_WORKSPACE, ws_bytes=need - 256) == _abi.RAMLT_EWORKSPACE
+    assert _status("filter_backward", [f], workspace=FAKE_WORKSPACE, ws_bytes=need) in (_abi.RAMLT_EHIP,
+                                                                                         _abi.RAMLT_OK)

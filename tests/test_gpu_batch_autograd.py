@@ -115,6 +115,53 @@ def test_batched_matches_single_frames_and_oracle():
     assert abs(_h(b.loss)[0] - loss_total) <= 1e-5 * loss_total
 
 
+# Frames large enough for region-aligned tiling (>= 16 N x 4 N pixels), each with its own
+# lambda table, grid size and gradient buffer; three radii, so the batch runs three queues.
+ALIGNED_SPECS = [(96, 40, 4, 3, 4), (130, 37, 8, 5, 4), (64, 16, 2, 0, 4), (200, 90, 5, 5, 6),
+                 (320, 80, 3, 3, 20)]
+
+
+def test_batched_region_aligned_frames():
+    frames, host = [], []
+    for i, (W, H, S, r, N) in enumerate(ALIGNED_SPECS):
+        rad, _ = make_frame(W, H, S, seed=30 + i, frame=i, with_features=False)
+        ref = make_reference(W, H, seed=3000 + i, frame=i, spp=16)
+        lam = make_lambda(N, seed=50 + i)
+        host.append((rad, ref, lam, N, r))
+        frames.append(FrameInput(_dev(rad), None, _dev(ref), _dev(lam), radius=r, n_regions=N))
+    b = FrameBatch(frames)
+    b.step()
+    torch.cuda.synchronize()
+    loss_total = 0.0
+    for i, (rad, ref, lam, N, r) in enumerate(host):
+        o = b.outputs[i]
+        S = rad.shape[1]
+        _check_chain(f"aligned frame {i}", rad, None, ref, lam, N, r, S,
+                     {k: _h(o[k]) for k in ("mean", "var", "tau")}, _h(o["out"]), None,
+                     _h(o["grad_radiance"]), _h(o["grad_lambda"]))
+        loss_total += _oracle_chain(rad, None, ref, lam, N, r, S)[2]
+    assert abs(_h(b.loss)[0] - loss_total) <= 1e-5 * loss_total
+
+
+def test_single_frame_adjoint_is_deterministic():
+    # region-aligned frame: dL/dlambda and the loss are per-tile partials added in a fixed order
+    W, H, S, N, r = 400, 120, 4, 20, 4
+    rad, _ = make_frame(W, H, S, seed=7, with_features=False)
+    ref = _dev(make_reference(W, H, seed=1007, spp=16))
+    lam = _dev(make_lambda(N, seed=99))
+    st = ops.stats(_dev(rad), None, 8)
+    out = ops.filter_forward(st.mean, lam, r, N)
+    runs = []
+    for _ in range(3):
+        loss = torch.zeros(1, device="cuda", dtype=torch.float64)
+        G, gl = ops.filter_backward(None, st.mean, out, lam, r, S, N, reference=ref, loss=loss)
+        runs.append((_h(G).copy(), _h(gl).copy(), _h(loss).copy()))
+    for G, gl, loss in runs[1:]:
+        assert np.array_equal(G, runs[0][0])
+        assert np.array_equal(gl, runs[0][1])
+        assert np.array_equal(loss, runs[0][2])
+
+
 def test_graph_replay_matches_eager():
     lam_d = _dev(make_lambda(20, seed=99))
     frames, _ = _batch_inputs(SPECS[:4], lam_d)
