@@ -3,13 +3,16 @@ MI355X, at 1920x1080 with 64 spp (fp32 RGB radiance + albedo/normal/depth featur
 window (radius 5), 20x20 region grid.
 
 One step = the whole hot path over one frame already resident in HBM:
-  stats_accumulate -> filter_forward -> loss_seed (MSE vs a 4096-spp reference) ->
-  filter_backward (gradients for every radiance sample and every region parameter).
-`value` is filtered Mpixel/s of that fwd+bwd step; the forward-only rate (stats + filter)
-is reported beside it. Inputs are synthetic and seeded (synth/), generated on the GPU
-before timing.
+  stats_accumulate -> filter_forward -> filter_backward with the MSE loss seed (vs a
+  4096-spp reference) fused in (gradients for every radiance sample and every region
+  parameter, and the loss).
+`value` is filtered Mpixel/s of that fwd+bwd step. Reported beside it: the forward-only
+rate (stats + filter), the step with a separate loss_seed kernel, the 32-frame batch of
+uneven frames replayed as one HIP graph per step, and the 3840x2160 / 256 spp / fp16
+feature frame with a 15x15 window. Inputs are synthetic and seeded (synth/), generated on
+the GPU before timing.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extra]
 """
 
 import argparse
@@ -23,20 +26,22 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-W_DEFAULT, H_DEFAULT, S_DEFAULT, R_DEFAULT, N_DEFAULT = 1920, 1080, 64, 5, 20
 
 
 def parse():
+    from synth.workloads import HD, N_REGIONS
+
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--width", type=int, default=W_DEFAULT)
-    p.add_argument("--height", type=int, default=H_DEFAULT)
-    p.add_argument("--spp", type=int, default=S_DEFAULT)
-    p.add_argument("--radius", type=int, default=R_DEFAULT)
-    p.add_argument("--regions", type=int, default=N_DEFAULT)
+    p.add_argument("--width", type=int, default=HD.W)
+    p.add_argument("--height", type=int, default=HD.H)
+    p.add_argument("--spp", type=int, default=HD.S)
+    p.add_argument("--radius", type=int, default=HD.radius)
+    p.add_argument("--regions", type=int, default=N_REGIONS)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-extra", action="store_true", help="skip the batched and 4K measurements")
     p.add_argument("--cpu-rows", type=int, default=0, help="rows of the frame the oracle times (0 = auto)")
     p.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "stats_accumulate_traffic.txt"),
                    help="rocprofv3 HBM byte count of the statistics kernel (JSON); ignored if the kernel "
@@ -80,11 +85,179 @@ def stats_bytes(P, S, feat_bytes=4):
     return P * S * (3 * 4 + 7 * feat_bytes) + P * 23 * 4
 
 
+# filter forward (mean read, out write) + fused adjoint (mean, out, reference read; G write)
+FILTER_STEP_BYTES_PER_PX = 24 + 48
+
+
+class SingleChain:
+    """Descriptors and buffers of one frame's step, built once; ``step()`` only launches:
+    stats -> filter -> zero the accumulators -> fused loss seed + adjoint (or, unfused,
+    loss_seed writing U and the adjoint reading it)."""
+
+    def __init__(self, W, H, S, r, N, seed, frame=0, fp16_features=False):
+        import torch
+
+        from paper_2402_08273_amd import _abi, ops
+        from synth import gpu as sgpu
+        from synth import make_lambda
+        from synth.workloads import LAMBDA_SEED, MAX_LAG, REFERENCE_SPP
+
+        dev = torch.device("cuda:0")
+        self.W, self.H, self.S, self.r, self.N = W, H, S, r, N
+        self.P = W * H
+        self.feat_bytes = 2 if fp16_features else 4
+        # inputs (untimed): seeded synthetic frame, reference, lambda table
+        self.rad, self.feat = sgpu.make_frame(W, H, S, seed=seed, frame=frame,
+                                              feature_dtype=torch.float16 if fp16_features else torch.float32)
+        self.ref = sgpu.make_reference(W, H, seed=seed + 1000, frame=frame, spp=REFERENCE_SPP)
+        self.lam = torch.from_numpy(make_lambda(N, seed=LAMBDA_SEED)).to(dev)
+        f32 = dict(device=dev, dtype=torch.float32)
+        mean, var, tau = (torch.empty((3, H, W), **f32) for _ in range(3))
+        fmean, fvar = torch.empty((7, H, W), **f32), torch.empty((7, H, W), **f32)
+        self.out, self.U, self.G = (torch.empty((3, H, W), **f32) for _ in range(3))
+        self.grad_lam = torch.zeros(N * N, **f32)
+        self.loss = torch.zeros(1, device=dev, dtype=torch.float64)
+        st_out = ops.Stats(mean, var, tau, None, fmean, fvar)
+        fs, _ = ops.stats_frame(self.rad, self.feat, MAX_LAG, st_out, with_lag_corr=False)
+        ff = ops.filter_frame(mean, self.lam, r, N)
+        ff.out, ff.S = self.out.data_ptr(), S
+        ff.reference, ff.loss = self.ref.data_ptr(), self.loss.data_ptr()
+        ff.grad_radiance, ff.grad_lambda = self.G.data_ptr(), self.grad_lam.data_ptr()
+        # fused: the MSE seed is formed inside the adjoint (grad_out NULL)
+        fu = _abi.RamltFrame.from_buffer_copy(ff)
+        fu.grad_out = self.U.data_ptr()  # unfused variant: loss_seed writes U, the adjoint reads it
+        self.stream = torch.cuda.current_stream()
+        self.sh = self.stream.cuda_stream
+        self.tabs = (_abi.RamltFrame * 1)(fs)
+        self.tabf = (_abi.RamltFrame * 1)(ff)
+        self.tabu = (_abi.RamltFrame * 1)(fu)
+        self.lib = _abi.load()
+        self._abi = _abi
+        # the adjoint's workspace (per-tile partial sums), allocated once
+        self.ws_t, self.ws_ptr, self.ws_bytes = ops.workspace_for([ff], _abi.OP_FILTER_BACKWARD, dev)
+        torch.cuda.synchronize()
+
+    def call(self, fn, tab):
+        st = fn(tab, None, 1, self.ws_ptr, self.ws_bytes, self.sh)
+        if st != 0:
+            raise RuntimeError(self._abi.last_error())
+
+    def stats(self):
+        self.call(self.lib.stats_accumulate, self.tabs)
+
+    def forward(self):
+        self.call(self.lib.filter_forward, self.tabf)
+
+    def step(self, marks=None, fused=True):
+        if marks is not None:
+            marks[0].record(self.stream)
+        self.stats()
+        if marks is not None:
+            marks[1].record(self.stream)
+        self.forward()
+        if marks is not None:
+            marks[2].record(self.stream)
+        self.grad_lam.zero_()
+        self.loss.zero_()
+        if fused:
+            self.call(self.lib.filter_backward, self.tabf)
+        else:
+            self.call(self.lib.loss_seed, self.tabu)
+            self.call(self.lib.filter_backward, self.tabu)
+
+    def algorithmic_bytes(self):
+        return stats_bytes(self.P, self.S, self.feat_bytes) + self.P * FILTER_STEP_BYTES_PER_PX
+
+
+def time_loop(stream, fn, steps):
+    """Milliseconds per call of fn() over `steps` calls, HIP events on the launch stream,
+    synchronised on both sides."""
+    import torch
+
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(steps):
+        fn()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def measure_uhd(steps, warmup):
+    """The 3840x2160, 256 spp, fp16-feature frame with a 15x15 window: fused fwd+bwd step."""
+    import torch
+
+    from synth.workloads import N_REGIONS, UHD
+
+    c = SingleChain(UHD.W, UHD.H, UHD.S, UHD.radius, N_REGIONS, UHD.seed, UHD.frame, UHD.fp16_features)
+    for _ in range(warmup):
+        c.step()
+    ms = time_loop(c.stream, c.step, steps)
+    ms_fwd = time_loop(c.stream, lambda: (c.stats(), c.forward()), steps)
+    b = c.algorithmic_bytes()
+    res = {
+        "workload": f"stats+filter fwd+bwd, {UHD.W}x{UHD.H}, {UHD.S} spp, fp32 radiance + fp16 features, "
+                    f"{2 * UHD.radius + 1}x{2 * UHD.radius + 1} window, {N_REGIONS}x{N_REGIONS} regions",
+        "mpx_s": round(c.P / (ms * 1e-3) / 1e6, 2),
+        "ms_per_step": round(ms, 4),
+        "fwd_mpx_s": round(c.P / (ms_fwd * 1e-3) / 1e6, 2),
+        "algorithmic_bytes": b,
+        "hbm_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    del c
+    torch.cuda.empty_cache()
+    return res
+
+
+def measure_batch32(steps, warmup):
+    """32 frames of uneven size and spp; each step is one HIP graph replay of persistent
+    launches over the whole batch (stats, filter, zeroing, fused loss seed + adjoint)."""
+    import torch
+
+    from paper_2402_08273_amd.batch import FrameBatch, FrameInput
+    from synth import gpu as sgpu
+    from synth import make_lambda
+    from synth.workloads import LAMBDA_SEED, MAX_LAG, N_REGIONS, REFERENCE_SPP, batch32, sample_bytes
+
+    specs = batch32()
+    lam = torch.from_numpy(make_lambda(N_REGIONS, seed=LAMBDA_SEED)).cuda()
+    frames = []
+    for sp in specs:
+        rad, feat = sgpu.make_frame(sp.W, sp.H, sp.S, seed=sp.seed, frame=sp.frame)
+        ref = sgpu.make_reference(sp.W, sp.H, seed=sp.seed + 1000, frame=sp.frame, spp=REFERENCE_SPP)
+        frames.append(FrameInput(rad, feat, ref, lam, radius=sp.radius, n_regions=N_REGIONS, max_lag=MAX_LAG))
+    b = FrameBatch(frames)
+    b.capture(warmup=1)
+    for _ in range(warmup):
+        b.replay()
+    stream = torch.cuda.current_stream()
+    ms = time_loop(stream, b.replay, steps)
+    P = sum(sp.W * sp.H for sp in specs)
+    nbytes = sum(sample_bytes(sp) + sp.W * sp.H * (23 * 4 + FILTER_STEP_BYTES_PER_PX) for sp in specs)
+    res = {
+        "workload": "32 frames 256x256..2048x1152, spp {4,16,64,256}, fp32 radiance+features, 11x11 window, "
+                    "20x20 regions; stats+filter fwd+bwd as one HIP graph replay per step",
+        "frames": len(specs),
+        "pixels": P,
+        "samples": sum(sp.W * sp.H * sp.S for sp in specs),
+        "mpx_s": round(P / (ms * 1e-3) / 1e6, 2),
+        "ms_per_step": round(ms, 4),
+        "algorithmic_bytes": nbytes,
+        "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    del b, frames
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this path has no multi-GPU form in this build "
-              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU. The multi-GPU form of this path (row bands with an r-row "
+              "halo, one all-reduce of dL/dlambda; frames of a batch spread over GPUs) is a design "
+              "only; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
@@ -93,110 +266,42 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2402_08273_amd import _abi, ops
-    from synth import gpu as sgpu
-    from synth import make_lambda
+    from synth.workloads import HD, MAX_LAG
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    torch.cuda.set_device(0)
     W, H, S, r, N = args.width, args.height, args.spp, args.radius, args.regions
-    P = W * H
-
-    # ---- inputs (untimed): seeded synthetic frame, reference, lambda table
-    rad, feat = sgpu.make_frame(W, H, S, seed=2, frame=0)
-    ref = sgpu.make_reference(W, H, seed=1002, frame=0, spp=4096)
-    lam = torch.from_numpy(make_lambda(N, seed=99)).to(dev)
-    torch.cuda.synchronize()
-
-    # ---- outputs and descriptors (built once; the timed loop only launches)
-    f32 = dict(device=dev, dtype=torch.float32)
-    mean, var, tau = (torch.empty((3, H, W), **f32) for _ in range(3))
-    fmean, fvar = torch.empty((7, H, W), **f32), torch.empty((7, H, W), **f32)
-    out, U, G = (torch.empty((3, H, W), **f32) for _ in range(3))
-    grad_lam = torch.zeros(N * N, **f32)
-    loss = torch.zeros(1, device=dev, dtype=torch.float64)
-    st_out = ops.Stats(mean, var, tau, None, fmean, fvar)
-    fs, _ = ops.stats_frame(rad, feat, 8, st_out, with_lag_corr=False)
-    ff = ops.filter_frame(mean, lam, r, N)
-    ff.out, ff.S = out.data_ptr(), S
-    ff.reference, ff.loss = ref.data_ptr(), loss.data_ptr()
-    ff.grad_radiance, ff.grad_lambda = G.data_ptr(), grad_lam.data_ptr()
-    # fused: the MSE seed is formed inside the adjoint (grad_out NULL)
-    fu = _abi.RamltFrame.from_buffer_copy(ff)
-    fu.grad_out = U.data_ptr()  # unfused variant: loss_seed writes U, the adjoint reads it
-    stream = torch.cuda.current_stream()
-    sh = stream.cuda_stream
-    tabs = (_abi.RamltFrame * 1)(fs)
-    tabf = (_abi.RamltFrame * 1)(ff)
-    tabu = (_abi.RamltFrame * 1)(fu)
-    lib = _abi.load()
-    # the adjoint's workspace (per-tile partial sums), allocated once
-    ws_t, ws_ptr, ws_bytes = ops.workspace_for([ff], _abi.OP_FILTER_BACKWARD, dev)
-
-    def call(fn, tab):
-        st = fn(tab, None, 1, ws_ptr, ws_bytes, sh)
-        if st != 0:
-            raise RuntimeError(_abi.last_error())
-
-    def step(timing=None, fused=True):
-        if timing is not None:
-            timing[0].record(stream)
-        call(lib.stats_accumulate, tabs)
-        if timing is not None:
-            timing[1].record(stream)
-        call(lib.filter_forward, tabf)
-        if timing is not None:
-            timing[2].record(stream)
-        grad_lam.zero_()
-        loss.zero_()
-        if fused:
-            call(lib.filter_backward, tabf)
-        else:
-            call(lib.loss_seed, tabu)
-            call(lib.filter_backward, tabu)
+    c = SingleChain(W, H, S, r, N, HD.seed, HD.frame)
+    P = c.P
 
     for _ in range(args.warmup):
-        step()
+        c.step()
     torch.cuda.synchronize()
 
     # ---- timed region: K whole steps; per-launch stats/forward durations from HIP events
     # recorded on the launch stream inside the same region
     marks = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    for k in range(args.steps):
-        step(marks[k])
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    ms_total = t_start.elapsed_time(t_end)
-    ms_step = ms_total / args.steps
+    it = iter(marks)
+    ms_step = time_loop(c.stream, lambda: c.step(next(it)), args.steps)
     stats_ms = float(np.mean([m[0].elapsed_time(m[1]) for m in marks]))
     fwd_ms = float(np.mean([m[0].elapsed_time(m[2]) for m in marks]))
+    # whole-step durations, one pair of events around each step: the median
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for e in ev:
+        e[0].record(c.stream)
+        c.step()
+        e[1].record(c.stream)
+    torch.cuda.synchronize()
+    step_ms_median = float(np.median([e[0].elapsed_time(e[1]) for e in ev]))
 
-    # unfused step (separate loss_seed kernel writing U), timed separately
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    for _ in range(args.steps):
-        step(fused=False)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    unfused_ms = t_start.elapsed_time(t_end) / args.steps
-
-    # forward-only rate (stats + filter), timed separately
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    for _ in range(args.steps):
-        call(lib.stats_accumulate, tabs)
-        call(lib.filter_forward, tabf)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    fwd_only_ms = t_start.elapsed_time(t_end) / args.steps
+    # unfused step (separate loss_seed kernel writing U), and forward only (stats + filter)
+    unfused_ms = time_loop(c.stream, lambda: c.step(fused=False), args.steps)
+    fwd_only_ms = time_loop(c.stream, lambda: (c.stats(), c.forward()), args.steps)
 
     sb = stats_bytes(P, S)
     achieved = sb / (stats_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.traffic, W, H, S)
+    step_bytes = c.algorithmic_bytes()
 
     result = {
         "metric": "Mpixel/s filtered (fwd, fwd+bwd) at 1080p 64spp; % of HBM roofline",
@@ -214,7 +319,8 @@ def main():
                 "fireflies; 4096-spp seeded reference)",
         "config": {"workload": f"stats+filter fwd+bwd, {W}x{H}, {S} spp, fp32 radiance+features, "
                                f"{2 * r + 1}x{2 * r + 1} window, {N}x{N} regions",
-                   "width": W, "height": H, "spp": S, "radius": r, "regions": N, "max_lag": 8},
+                   "width": W, "height": H, "spp": S, "radius": r, "regions": N, "max_lag": MAX_LAG},
+        "ms_per_step_median": round(step_ms_median, 4),
         "fwd_mpx_s": round(P / (fwd_only_ms * 1e-3) / 1e6, 2),
         "unfused_fwd_bwd_mpx_s": round(P / (unfused_ms * 1e-3) / 1e6, 2),
         "fwd_ms": round(fwd_only_ms, 4),
@@ -231,30 +337,39 @@ def main():
             "algorithmic_bytes": sb,
         },
         # whole step: stats + filter (mean re-read, out write) + fused adjoint (mean, out,
-        # reference read; G write) = 5.549 GB + 48 B/px at this size
-        "step_algorithmic_gbs": round((sb + P * (24 + 48)) / (ms_step * 1e-3) / 1e9, 1),
-        "step_hbm_frac": round((sb + P * (24 + 48)) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        # reference read; G write)
+        "step_algorithmic_gbs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "step_hbm_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
 
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(rad, feat, ref, lam, W, H, S, r, N, args.cpu_rows)
+        result["cpu_baseline"] = cpu_baseline(c.rad, c.feat, c.ref, c.lam, W, H, S, r, N, args.cpu_rows)
+    del c
+    torch.cuda.empty_cache()
+
+    if not args.no_extra:
+        print("measuring the 32-frame batch and the 4K frame", file=sys.stderr, flush=True)
+        result["batched"] = measure_batch32(args.steps, args.warmup)
+        result["uhd"] = measure_uhd(args.steps, args.warmup)
 
     print(json.dumps(result), flush=True)
 
 
-def _oracle_chain(rad_b, feat_b, ref_b, lam_h, S, r, N):
+def _oracle_chain(rad_b, feat_b, ref_b, lam_h, S, r, N, W, H):
     import oracle
 
+    crop = dict(origin=(0, 0), image_size=(W, H))
     st = oracle.stats_accumulate(rad_b, feat_b, 8)
-    out, _ = oracle.filter_forward(st["mean"], lam_h, N, r)
-    _, U = oracle.mse_loss_seed(out, ref_b)
-    oracle.filter_backward(U, st["mean"], out, lam_h, N, r, -30.0, S)
+    out, _ = oracle.filter_forward(st["mean"], lam_h, N, r, -30.0, **crop)
+    _, U = oracle.mse_loss_seed(out, ref_b, count=3 * W * H)
+    oracle.filter_backward(U, st["mean"], out, lam_h, N, r, -30.0, S, **crop)
 
 
 def cpu_baseline(rad, feat, ref, lam, W, H, S, r, N, rows, target_s=15.0):
     """The FP64 oracle, as it stands, on a band of rows of the same frame (same chain:
-    stats -> filter -> loss seed -> adjoint), timed on the host. Rate in Mpixel/s. The
-    band height is chosen from a 16-row probe so the timed run takes about target_s."""
+    stats -> filter -> loss seed -> adjoint, with the frame's regions), timed on the host.
+    Rate in Mpixel/s. The band height is chosen from a 16-row probe so the timed run takes
+    about target_s."""
     lam_h = lam.cpu().numpy()
 
     def band(n):
@@ -264,12 +379,12 @@ def cpu_baseline(rad, feat, ref, lam, W, H, S, r, N, rows, target_s=15.0):
     if not rows:
         probe = min(16, H)
         t0 = time.perf_counter()
-        _oracle_chain(*band(probe), lam_h, S, r, N)
+        _oracle_chain(*band(probe), lam_h, S, r, N, W, H)
         per_row = (time.perf_counter() - t0) / probe
         rows = int(max(probe, min(H, target_s / max(per_row, 1e-6))))
     data = band(rows)
     t0 = time.perf_counter()
-    _oracle_chain(*data, lam_h, S, r, N)
+    _oracle_chain(*data, lam_h, S, r, N, W, H)
     dt = time.perf_counter() - t0
     px = W * rows
     return {

@@ -41,10 +41,13 @@ LAMBDA_MIN_DEFAULT = -30.0
 N_REGIONS_DEFAULT = 20
 
 
-def region_index(W, H, n_regions):
-    """Region k(x, y) of every pixel centre, int64 [H, W]."""
-    x = np.arange(W, dtype=np.int64)
-    y = np.arange(H, dtype=np.int64)
+def region_index(W, H, n_regions, origin=(0, 0), shape=None):
+    """Region k(x, y) of every pixel centre of a W x H image, int64 [H, W]; or, with
+    ``origin = (x0, y0)`` and ``shape = (h, w)``, of the pixels x0 <= x < x0 + w,
+    y0 <= y < y0 + h only (a crop keeps the regions of the full image)."""
+    h, w = (H, W) if shape is None else shape
+    x = origin[0] + np.arange(w, dtype=np.int64)
+    y = origin[1] + np.arange(h, dtype=np.int64)
     kx = ((2 * x + 1) * n_regions) // (2 * W)
     ky = ((2 * y + 1) * n_regions) // (2 * H)
     return ky[:, None] * n_regions + kx[None, :]
@@ -69,22 +72,44 @@ def _shift(img, dx, dy):
     return out, mask
 
 
-def _pixel_sigma_sq(W, H, lam, n_regions, lambda_min):
-    k = region_index(W, H, n_regions)
+def _crop_geometry(arr, origin, image_size):
+    """(W, H, origin) of the image that the [.., h, w] array ``arr`` is a crop of.
+
+    Crops: the array holds pixels origin[0] <= x < origin[0] + w, origin[1] <= y < ...
+    of a W x H image. Regions and the border clipping are those of the full image, and
+    pixels outside the array count as outside; so a result is the full image's result
+    where every pixel it reads lies in the array (see each function)."""
+    h, w = arr.shape[-2:]
+    if image_size is None:
+        if tuple(origin) != (0, 0):
+            raise ValueError("a crop needs image_size")
+        return w, h, (0, 0)
+    W, H = image_size
+    x0, y0 = origin
+    if x0 < 0 or y0 < 0 or x0 + w > W or y0 + h > H:
+        raise ValueError("crop outside the image")
+    return W, H, (x0, y0)
+
+
+def _pixel_sigma_sq(W, H, lam, n_regions, lambda_min, origin=(0, 0), shape=None):
+    k = region_index(W, H, n_regions, origin, shape)
     return region_sigma_sq(lam, lambda_min)[k], k
 
 
 def filter_forward(mean, lam, n_regions=N_REGIONS_DEFAULT, radius=3,
-                   lambda_min=LAMBDA_MIN_DEFAULT):
+                   lambda_min=LAMBDA_MIN_DEFAULT, origin=(0, 0), image_size=None):
     """Filtered image from per-pixel means.
 
     mean: [C, H, W]; lam: [n_regions**2]. Returns (out [C,H,W], D [H,W]) in float64.
+    On a crop (``origin``, ``image_size = (W, H)``), out_j and D_j are exact for every j
+    whose window, clipped to the image, lies in the crop: j at least ``radius`` pixels
+    from each crop edge that is not an image edge.
     """
     mean = np.asarray(mean, dtype=np.float64)
-    H, W = mean.shape[-2:]
-    s2, _ = _pixel_sigma_sq(W, H, lam, n_regions, lambda_min)
+    W, H, origin = _crop_geometry(mean, origin, image_size)
+    s2, _ = _pixel_sigma_sq(W, H, lam, n_regions, lambda_min, origin, mean.shape[-2:])
     num = np.zeros_like(mean)
-    den = np.zeros((H, W))
+    den = np.zeros(mean.shape[-2:])
     for dy in range(-radius, radius + 1):
         for dx in range(-radius, radius + 1):
             h = np.exp(-(dx * dx + dy * dy) / (2.0 * s2))
@@ -95,38 +120,43 @@ def filter_forward(mean, lam, n_regions=N_REGIONS_DEFAULT, radius=3,
     return num / den[None], den
 
 
-def mse_loss_seed(out, reference):
-    """L = sum (out - R)^2 / (3P) and U = dL/dout = 2 (out - R) / (3P)."""
+def mse_loss_seed(out, reference, count=None):
+    """L = sum (out - R)^2 / (3P) and U = dL/dout = 2 (out - R) / (3P); 3P = out.size,
+    or ``count`` (the full image's 3P when out and R are crops: L is then the crop's share)."""
     out = np.asarray(out, dtype=np.float64)
     ref = np.asarray(reference, dtype=np.float64)
-    n = out.size
+    n = out.size if count is None else int(count)
     diff = out - ref
     return float((diff * diff).sum() / n), 2.0 * diff / n
 
 
 def filter_backward(grad_out, mean, out, lam, n_regions=N_REGIONS_DEFAULT, radius=3,
-                    lambda_min=LAMBDA_MIN_DEFAULT, S=1):
+                    lambda_min=LAMBDA_MIN_DEFAULT, S=1, origin=(0, 0), image_size=None):
     """Adjoint of :func:`filter_forward` composed with the per-pixel mean of S samples.
 
     grad_out U, mean, out: [C, H, W]. Returns (G [C,H,W], grad_lambda [n_regions**2]),
     where G_pc is dL/dg_{p,s,c} for every sample s of pixel p.
+    On a crop (``origin``, ``image_size``), with U and out valid on the whole crop: G_p is
+    exact for p at least 2 ``radius`` pixels from each crop edge that is not an image
+    edge, and grad_lambda[k] for a region k whose pixels all lie ``radius`` pixels inside
+    such edges (other entries hold partial sums).
     """
     U = np.asarray(grad_out, dtype=np.float64)
     mean = np.asarray(mean, dtype=np.float64)
     out = np.asarray(out, dtype=np.float64)
     lam = np.asarray(lam, dtype=np.float64)
-    H, W = mean.shape[-2:]
-    s2, k = _pixel_sigma_sq(W, H, lam, n_regions, lambda_min)
+    W, H, origin = _crop_geometry(mean, origin, image_size)
+    s2, k = _pixel_sigma_sq(W, H, lam, n_regions, lambda_min, origin, mean.shape[-2:])
     live = (lam >= lambda_min)[k]  # [H, W]: gradient passes through the clamp
     # D_j, recomputed from the same weights as the forward pass.
-    den = np.zeros((H, W))
+    den = np.zeros(mean.shape[-2:])
     for dy in range(-radius, radius + 1):
         for dx in range(-radius, radius + 1):
             _, inside = _shift(mean, dx, dy)
             den += np.where(inside, np.exp(-(dx * dx + dy * dy) / (2.0 * s2)), 0.0)
     a = U / den[None]  # U_j / D_j
     G = np.zeros_like(U)
-    per_pixel = np.zeros((H, W))
+    per_pixel = np.zeros(mean.shape[-2:])
     for dy in range(-radius, radius + 1):
         for dx in range(-radius, radius + 1):
             d2 = float(dx * dx + dy * dy)

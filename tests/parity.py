@@ -55,13 +55,14 @@ def stats_scales(radiance, st):
     }
 
 
-def filter_scale(mean, lam, n_regions, radius, lambda_min):
-    out, _ = oracle.filter_forward(np.abs(mean), lam, n_regions, radius, lambda_min)
+def filter_scale(mean, lam, n_regions, radius, lambda_min, **crop):
+    out, _ = oracle.filter_forward(np.abs(mean), lam, n_regions, radius, lambda_min, **crop)
     return out
 
 
-def backward_scales(u_scale, mean, out, lam, n_regions, radius, lambda_min, S):
-    """Scales for G and dL/dlambda given a non-negative per-pixel U scale."""
+def backward_scales(u_scale, mean, out, lam, n_regions, radius, lambda_min, S, **crop):
+    """Scales for G and dL/dlambda given a non-negative per-pixel U scale (``crop``:
+    origin / image_size as for the oracle)."""
     G_s, gl_s = oracle.filter_backward(u_scale, np.abs(mean), -np.abs(out), lam, n_regions, radius,
-                                       lambda_min, S)
+                                       lambda_min, S, **crop)
     return G_s, gl_s

@@ -295,3 +295,51 @@ def test_backward_mass_and_special_cases():
     G_m, gl_m = filter_backward(U, mean, out_m, lam_min, N, r, -30.0, S)
     np.testing.assert_allclose(G_m, U / S, rtol=1e-15)
     assert np.all(gl_m == 0.0)
+
+
+def test_crops_reproduce_the_full_image():
+    # a crop keeps the full image's regions and border: results agree where every pixel
+    # they read lies in the crop (r from non-image crop edges for out, 2r for G)
+    rng = np.random.default_rng(21)
+    H, W, N, r, S = 40, 52, 5, 3, 4
+    lam = rng.uniform(-1, 2, N * N)
+    mean = rng.random((3, H, W))
+    ref = rng.random((3, H, W))
+    out, D = filter_forward(mean, lam, N, r)
+    L, U = mse_loss_seed(out, ref)
+    G, gl = filter_backward(U, mean, out, lam, N, r, -30.0, S)
+    regions_checked = 0
+    for x0, y0, w, h in [(0, 0, 30, 25), (9, 7, 30, 26), (20, 14, 32, 26), (0, 20, 52, 20)]:
+        crop = dict(origin=(x0, y0), image_size=(W, H))
+        sl = (slice(None), slice(y0, y0 + h), slice(x0, x0 + w))
+        out_c, D_c = filter_forward(mean[sl], lam, N, r, **crop)
+
+        def interior(m):  # rows/columns at least m from crop edges that are not image edges
+            ys = slice(0 if y0 == 0 else m, h if y0 + h == H else h - m)
+            xs = slice(0 if x0 == 0 else m, w if x0 + w == W else w - m)
+            return ys, xs
+
+        ys, xs = interior(r)
+        np.testing.assert_allclose(out_c[:, ys, xs], out[sl][:, ys, xs], rtol=1e-14, atol=0)
+        np.testing.assert_allclose(D_c[ys, xs], D[sl[1:]][ys, xs], rtol=1e-14)
+        L_c, U_c = mse_loss_seed(out[sl], ref[sl], count=out.size)
+        np.testing.assert_array_equal(U_c, U[sl])
+        G_c, gl_c = filter_backward(U[sl], mean[sl], out[sl], lam, N, r, -30.0, S, **crop)
+        ys, xs = interior(2 * r)
+        np.testing.assert_allclose(G_c[:, ys, xs], G[sl][:, ys, xs], rtol=1e-12, atol=1e-15)
+        # regions lying r inside the non-image crop edges
+        k = region_index(W, H, N)
+        ys, xs = interior(r)
+        inner = np.zeros((H, W), bool)
+        inner[y0:y0 + h, x0:x0 + w][ys, xs] = True
+        full_regions = [kk for kk in range(N * N) if inner[k == kk].all()]
+        if x0 == 0 and y0 == 0 and w == W and h == H:
+            assert len(full_regions) == N * N
+        for kk in full_regions:
+            assert gl_c[kk] == pytest.approx(gl[kk], rel=1e-12, abs=1e-15)
+        regions_checked += len(full_regions)
+    assert regions_checked >= 4
+    # the pixel-count override: the crop's share of the loss
+    assert mse_loss_seed(out[:, :10], ref[:, :10], count=out.size)[0] < L
+    with pytest.raises(ValueError):
+        filter_forward(mean, lam, N, r, origin=(1, 0), image_size=(W, H))
