@@ -20,8 +20,10 @@ constexpr int kPlanBlock = 256;
 __device__ long long tiles_of(const ramlt_frame &f, int op, int radius_sel) {
   const long long P = (long long)f.W * f.H;
   switch (op) {
-    case RAMLT_OP_STATS:
-      return (P + kStatsTilePixels - 1) / kStatsTilePixels;
+    case RAMLT_OP_STATS: {
+      const long long unit = (long long)kStatsTilePixels * stats_unit_tiles(f.S);
+      return (P + unit - 1) / unit;
+    }
     case RAMLT_OP_LOSS_SEED:
       return (P + kLossTilePixels - 1) / kLossTilePixels;
     default:

@@ -16,6 +16,13 @@ constexpr int kFilterTileW = 32;
 constexpr int kFilterTileH = 8;
 constexpr int kLossTilePixels = 1024;
 
+// 256-pixel statistics tiles per batched work unit: enough that a unit reads >= 64
+// samples per pixel slot (1 for S >= 64, at most 16).
+__host__ __device__ inline int stats_unit_tiles(int S) {
+  const int m = S >= 64 ? 1 : (64 + S - 1) / (S > 0 ? S : 1);
+  return m > 16 ? 16 : m;
+}
+
 // Filter tiling, shared by the filter kernels and the batch planner. Output tiles are at
 // most kFilterTileW x kFilterTileH; when regions are >= 16 px wide and >= 4 px tall the
 // tiles are laid out inside each region column / row (some may be empty).

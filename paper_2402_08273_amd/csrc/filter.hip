@@ -39,6 +39,7 @@ constexpr int kTX = kFilterTileW;
 constexpr int kTY = kFilterTileH;
 constexpr int kFilterBlock = kTX * kTY;
 constexpr float kLog2e = 1.4426950408889634f;
+constexpr long long kMaxBatchGrid = 1LL << 22;  // workgroups of one batched launch
 
 // ------------------------------------------------------------------------ tiling
 struct Rect {
@@ -755,33 +756,30 @@ __global__ __launch_bounds__(kFilterBlock) void backward_kernel(const ramlt_fram
   backward_tile<R>(f, r, t, lam_part, loss_part, s);
 }
 
-// Persistent forms for a batch: pop (frame, tile) pairs from the plan's queue.
+// Batched forms: one workgroup per planned (frame, tile) pair, found by a binary search
+// of the plan's prefix sums. Filter tiles all cost about the same, so a plain grid (with
+// the XCD-aware order) balances as well as a work queue, without its atomics.
 template <int R, bool BWD>
 __global__ __launch_bounds__(kFilterBlock) void filter_batched_kernel(const ramlt_frame *__restrict__ frames,
                                                                       BatchPlan *plan, float *lam_part,
                                                                       double *loss_part) {
   using Lds = typename std::conditional<BWD, BwdLds<R>, FwdLds<R>>::type;
   __shared__ Lds s;
-  __shared__ unsigned long long slot;
-  const unsigned long long total = plan->total_tiles;
-  for (;;) {
-    if (threadIdx.x == 0) slot = atomicAdd(&plan->next_tile, 1ULL);
-    __syncthreads();
-    const unsigned long long t = slot;
-    __syncthreads();
-    if (t >= total) break;
+  const long long total = (long long)plan->total_tiles;
+  // one pass when the grid covers every tile; grid-stride passes beyond kMaxBatchGrid
+  for (long long t = xcd_tile(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
     int fi;
     long long local;
-    plan_lookup(plan, t, &fi, &local);
+    plan_lookup(plan, (unsigned long long)t, &fi, &local);
     const ramlt_frame f = frames[fi];
     const Rect r = tile_rect(f, local);
     if (r.x0 < r.x1 && r.y0 < r.y1) {  // block-uniform
       if constexpr (BWD)
-        backward_tile<R>(f, r, (long long)t, lam_part, loss_part, s);
+        backward_tile<R>(f, r, t, lam_part, loss_part, s);
       else
         forward_tile<R>(f, r, s.stage, s.hb1, s.wtab);
     } else if (BWD) {
-      empty_tile_partials(f, (long long)t, lam_part, loss_part);
+      empty_tile_partials(f, t, lam_part, loss_part);
     }
     __syncthreads();  // LDS is reused by the next tile
   }
@@ -799,21 +797,15 @@ __global__ __launch_bounds__(kLossBlock) void loss_seed_kernel(const ramlt_frame
 __global__ __launch_bounds__(kLossBlock) void loss_seed_batched_kernel(const ramlt_frame *__restrict__ frames,
                                                                        BatchPlan *plan) {
   __shared__ double red[kLossBlock / kWave];
-  __shared__ unsigned long long slot;
   const unsigned long long total = plan->total_tiles;
-  for (;;) {
-    if (threadIdx.x == 0) slot = atomicAdd(&plan->next_tile, 1ULL);
-    __syncthreads();
-    const unsigned long long t = slot;
-    __syncthreads();
-    if (t >= total) break;
+  for (unsigned long long t = blockIdx.x; t < total; t += gridDim.x) {
     int fi;
     long long local;
     plan_lookup(plan, t, &fi, &local);
     const ramlt_frame f = frames[fi];
     const long long P = (long long)f.W * f.H;
     const long long p0 = local * kLossTilePixels;
-    loss_range(f, p0, min((long long)kLossTilePixels, P - p0), red);
+    loss_range(f, p0, min((long long)kLossTilePixels, P - p0), red);  // ends with a barrier
   }
 }
 
@@ -877,7 +869,11 @@ hipError_t launch_filter(bool bwd, const ramlt_frame *fh, const ramlt_frame *fd,
     double *loss_part = bwd ? (double *)(base + pb + (((size_t)T * sizeof(float) + 7) & ~(size_t)7)) : nullptr;
     hipError_t e = launch_plan(fd, n, op, radii[g], plan, st);
     if (e != hipSuccess) return e;
-    const int grid = persistent_grid((const void *)batched[radii[g]], kFilterBlock);
+    long long tiles = 0;  // the planner counts the same tiles on the device
+    for (int i = 0; i < n; ++i)
+      if (fh[i].radius == radii[g]) tiles += filter_tiles(fh[i]);
+    if (tiles == 0) continue;
+    const unsigned grid = (unsigned)(((min(tiles, kMaxBatchGrid) + 7) / 8) * 8);
     hipLaunchKernelGGL(batched[radii[g]], dim3(grid), dim3(kFilterBlock), 0, st, fd, plan, lam_part, loss_part);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -917,8 +913,10 @@ hipError_t launch_loss_seed(const ramlt_frame *fh, const ramlt_frame *fd, int n,
   BatchPlan *plan = (BatchPlan *)ws;
   hipError_t e = launch_plan(fd, n, RAMLT_OP_LOSS_SEED, -1, plan, st);
   if (e != hipSuccess) return e;
-  const int grid = persistent_grid((const void *)loss_seed_batched_kernel, kLossBlock);
-  hipLaunchKernelGGL(loss_seed_batched_kernel, dim3(grid), dim3(kLossBlock), 0, st, fd, plan);
+  long long tiles = 0;  // as counted by the planner
+  for (int i = 0; i < n; ++i) tiles += ((long long)fh[i].W * fh[i].H + kLossTilePixels - 1) / kLossTilePixels;
+  hipLaunchKernelGGL(loss_seed_batched_kernel, dim3((unsigned)min(tiles, kMaxBatchGrid)), dim3(kLossBlock), 0, st,
+                     fd, plan);
   return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ namespace ramlt {
 namespace {
 
 constexpr int kStatsBlock = 256;
+static_assert(kStatsBlock == kStatsTilePixels, "one thread per pixel of a planned tile");
 constexpr int kParked = 9 + 14;  // radiance mean/var/tau x 3, feature mean/var x 7
 constexpr int kStoreSC1 = 16;    // buffer cache-policy operand: sc1
 
@@ -237,24 +238,35 @@ __global__ __launch_bounds__(kStatsBlock) void stats_kernel(const ramlt_frame f)
   stats_tile<KT, B>(f, (long long)blockIdx.x * kStatsBlock, park);
 }
 
-// Persistent form for a batch of frames: workgroups pop 256-pixel tiles from the plan's
-// queue (frames ordered by samples per pixel, largest first) until it is empty.
+// Persistent form for a batch of frames: workgroups pop work units from the plan's queue
+// (frames ordered by samples per pixel, largest first) until it is empty. A unit is
+// stats_unit_tiles(S) consecutive 256-pixel tiles, so units of frames with few samples per
+// pixel are not dominated by the queue pop. The next unit is claimed before the current
+// one is processed, which hides the atomic's latency.
 template <int KT, int B>
 __global__ __launch_bounds__(kStatsBlock) void stats_batched_kernel(const ramlt_frame *__restrict__ frames,
                                                                     BatchPlan *plan) {
   __shared__ float park[kParked * kStatsBlock];
-  __shared__ unsigned long long slot;
+  __shared__ unsigned long long slot[2];
   const unsigned long long total = plan->total_tiles;
-  for (;;) {
-    if (threadIdx.x == 0) slot = atomicAdd(&plan->next_tile, 1ULL);
-    __syncthreads();
-    const unsigned long long t = slot;
-    __syncthreads();
-    if (t >= total) break;
+  if (threadIdx.x == 0) slot[0] = atomicAdd(&plan->next_tile, 1ULL);
+  __syncthreads();
+  for (int i = 0;; i ^= 1) {
+    const unsigned long long t = slot[i];
+    if (t >= total) break;  // block-uniform
+    if (threadIdx.x == 0) slot[i ^ 1] = atomicAdd(&plan->next_tile, 1ULL);
     int fi;
     long long local;
     plan_lookup(plan, t, &fi, &local);
-    stats_tile<KT, B>(frames[fi], local * kStatsBlock, park);
+    const ramlt_frame f = frames[fi];
+    const long long P = (long long)f.W * f.H;
+    const int m = stats_unit_tiles(f.S);
+    for (int j = 0; j < m; ++j) {  // park entries are per thread: no barrier between tiles
+      const long long p0 = (local * m + j) * kStatsBlock;
+      if (p0 >= P) break;
+      stats_tile<KT, B>(f, p0, park);
+    }
+    __syncthreads();  // slot[i ^ 1] is written; slot[i] is free for the pop after next
   }
 }
 
