@@ -212,8 +212,8 @@ def measure_uhd(steps, warmup):
 
 
 def measure_batch32(steps, warmup):
-    """32 frames of uneven size and spp; each step is one HIP graph replay of persistent
-    launches over the whole batch (stats, filter, zeroing, fused loss seed + adjoint)."""
+    """32 frames of uneven size and spp; each step is one HIP graph replay of one launch
+    per operation over the whole batch (stats, filter, zeroing, fused loss seed + adjoint)."""
     import torch
 
     from paper_2402_08273_amd.batch import FrameBatch, FrameInput

@@ -29,7 +29,7 @@
  *     launch sizing only. With n_frames == 1, frames_dev may be NULL. With n_frames > 1
  *     frames_dev must be a device-resident copy of the same array (built once by the
  *     caller, e.g. before graph capture); kernels read descriptors from it and process
- *     all frames in one persistent launch per radius.
+ *     all frames in one launch per operation (per radius for the filter operations).
  *   - Sample planes are laid out [c][s][y][x] with x contiguous; stride_c, stride_s,
  *     stride_y are element strides (radiance and features each have their own).
  *     Per-pixel planes (mean, var, tau, out, reference, grad_out, grad_radiance,

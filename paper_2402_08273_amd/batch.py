@@ -1,10 +1,11 @@
-"""Batched execution: many frames of uneven size and sample count processed by one
-persistent launch per operation, with the whole forward + backward step capturable in a
-HIP graph.
+"""Batched execution: many frames of uneven size and sample count processed by one launch
+per operation (per radius for the filter), with the whole forward + backward step
+capturable in a HIP graph.
 
 ``FrameBatch`` owns the output buffers, the host descriptor table, its device copy and
-the workspace the persistent launches plan their tile queues in. Every operation is one
-call into ``libramlt.so``; torch only provides memory, streams and graph capture.
+the workspace in which each batched launch plans its tiles on the device. Every
+operation is one call into ``libramlt.so``; torch only provides memory, streams and
+graph capture.
 """
 
 import ctypes
@@ -50,7 +51,12 @@ class FrameBatch:
         self.loss = torch.zeros(1, device=self.device, dtype=torch.float64)
         self.outputs = []
         descs: List[RamltFrame] = []
-        grads = []
+        # frames without a given gradient buffer get views of one flat tensor, so that
+        # zeroing all of them is one fill kernel
+        own = [fi.lam.numel() for fi in self.inputs if fi.grad_lambda is None]
+        self._grad_flat = torch.zeros(max(sum(own), 1), **f32)
+        grads = [self._grad_flat]
+        off = 0
         for fi in self.inputs:
             rad = fi.radiance
             _, S, H, W = rad.shape
@@ -64,10 +70,14 @@ class FrameBatch:
             if fi.features is not None:
                 o["feat_mean"] = torch.empty((7, H, W), **f32)
                 o["feat_var"] = torch.empty((7, H, W), **f32)
-            gl = fi.grad_lambda if fi.grad_lambda is not None else torch.zeros_like(fi.lam)
+            if fi.grad_lambda is not None:
+                gl = fi.grad_lambda
+                if all(gl is not g for g in grads):
+                    grads.append(gl)
+            else:
+                gl = self._grad_flat[off:off + fi.lam.numel()]
+                off += fi.lam.numel()
             o["grad_lambda"] = gl
-            if all(gl is not g for g in grads):
-                grads.append(gl)
             d = RamltFrame()
             d.W, d.H, d.S, d.max_lag = W, H, S, fi.max_lag
             d.radiance = rad.data_ptr()

@@ -1,14 +1,13 @@
 // Device-side planning of batched launches.
 //
-// For a batch of frames the plan kernel computes each frame's tile count, orders frames
-// by per-tile cost (samples per pixel for the statistics pass; uniform otherwise),
-// largest first, so that the costliest tiles are popped first and the tail of the
-// persistent launch is made of cheap tiles (longest-processing-time-first), and writes
-// the exclusive prefix of tile counts in that order. Everything stays on the device and
-// in stream order, so a batch can be captured in a graph.
-#include <mutex>
-#include <unordered_map>
-
+// For a batch of frames the plan kernel computes each frame's tile (or work-unit) count,
+// orders frames by per-tile cost (samples per pixel for the statistics pass; uniform
+// otherwise), largest first, so that the costliest workgroups are dispatched first and
+// the tail of the launch is made of cheap ones (longest-processing-time-first), and
+// writes the exclusive prefix of tile counts in that order. A batched launch then runs
+// one workgroup per planned tile, which finds its frame by binary search of the prefix.
+// Everything stays on the device and in stream order, so a batch can be captured in a
+// graph.
 #include "batch.hpp"
 
 namespace ramlt {
@@ -59,7 +58,7 @@ __global__ __launch_bounds__(kPlanBlock) void plan_kernel(const ramlt_frame *__r
     prefix[n] = acc;
     plan->n_frames = n;
     plan->total_tiles = (unsigned long long)acc;
-    plan->next_tile = 0ULL;
+    plan->reserved0 = 0ULL;
   }
 }
 
@@ -69,24 +68,6 @@ hipError_t launch_plan(const ramlt_frame *frames_dev, int n, int op, int radius_
                        hipStream_t st) {
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, st, frames_dev, n, op, radius_sel, plan);
   return hipGetLastError();
-}
-
-int persistent_grid(const void *kernel, int block) {
-  static std::mutex mu;
-  static std::unordered_map<const void *, int> cache;
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  const void *key = (const void *)((const char *)kernel + dev);  // per device
-  std::lock_guard<std::mutex> lock(mu);
-  auto it = cache.find(key);
-  if (it != cache.end()) return it->second;
-  int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
-    per_cu = 1;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-  const int grid = per_cu * cus;
-  cache[key] = grid;
-  return grid;
 }
 
 int distinct_radii(const ramlt_frame *fh, int n, int *radii) {

@@ -1,5 +1,5 @@
-// Batched (multi-frame) launches: a plan kernel builds the tile queue of a batch on the
-// device, then one persistent launch drains it.
+// Batched (multi-frame) launches: a plan kernel orders the frames of a batch and numbers
+// their tiles on the device, then one launch covers every planned tile.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -58,13 +58,9 @@ __host__ __device__ inline long long filter_tile_count(const ramlt_frame &f) {
   return (long long)tiles_along(f.W, f.n_regions, kFilterTileW, al) * tiles_along(f.H, f.n_regions, kFilterTileH, al);
 }
 
-// Enqueue the plan kernel: fills plan (order by cost, tile prefix sums, zeroed counter).
+// Enqueue the plan kernel: fills plan (order by cost, tile prefix sums).
 hipError_t launch_plan(const ramlt_frame *frames_dev, int n, int op, int radius_sel, BatchPlan *plan,
                        hipStream_t st);
-
-// Number of workgroups that keeps every CU of the current device fully occupied with
-// `kernel` at `block` threads (cached per kernel).
-int persistent_grid(const void *kernel, int block);
 
 // Distinct radii of a batch, ascending; returns their count (<= RAMLT_MAX_RADIUS + 1).
 int distinct_radii(const ramlt_frame *fh, int n, int *radii);

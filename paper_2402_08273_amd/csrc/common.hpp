@@ -41,7 +41,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Batched-launch bookkeeping kept in the caller's workspace. The plan kernel fills it at
 // the start of every batched launch (stream-ordered, so it is safe under graph capture).
 struct BatchPlan {
-  unsigned long long next_tile;  // work counter popped by persistent workgroups
+  unsigned long long reserved0;
   unsigned long long total_tiles;
   int n_frames;
   int pad1[11];
@@ -62,7 +62,7 @@ __host__ __device__ inline long long *plan_prefix(BatchPlan *p, int n_frames) {
   return (long long *)((char *)p + b);
 }
 
-// Locate the frame and frame-local tile of queue position t.
+// Locate the frame and frame-local tile (or unit) of planned position t.
 __device__ __forceinline__ void plan_lookup(BatchPlan *plan, unsigned long long t, int *frame,
                                             long long *local) {
   const int n = plan->n_frames;

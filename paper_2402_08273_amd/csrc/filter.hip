@@ -668,7 +668,7 @@ __global__ __launch_bounds__(kFilterBlock) void backward_finalize_kernel(const r
     const int q = blockIdx.y;
     f = frames[plan_order(plan)[q]];
     const long long *pre = plan_prefix(plan, plan->n_frames);
-    if (pre[q + 1] == pre[q]) return;  // frame of another radius: not in this queue
+    if (pre[q + 1] == pre[q]) return;  // frame of another radius: not in this plan
     base = pre[q];
   } else {
     f = single;
@@ -758,7 +758,7 @@ __global__ __launch_bounds__(kFilterBlock) void backward_kernel(const ramlt_fram
 
 // Batched forms: one workgroup per planned (frame, tile) pair, found by a binary search
 // of the plan's prefix sums. Filter tiles all cost about the same, so a plain grid (with
-// the XCD-aware order) balances as well as a work queue, without its atomics.
+// the XCD-aware order) balances as well as an atomic work queue, which measured slower.
 template <int R, bool BWD>
 __global__ __launch_bounds__(kFilterBlock) void filter_batched_kernel(const ramlt_frame *__restrict__ frames,
                                                                       BatchPlan *plan, float *lam_part,

@@ -238,23 +238,17 @@ __global__ __launch_bounds__(kStatsBlock) void stats_kernel(const ramlt_frame f)
   stats_tile<KT, B>(f, (long long)blockIdx.x * kStatsBlock, park);
 }
 
-// Persistent form for a batch of frames: workgroups pop work units from the plan's queue
-// (frames ordered by samples per pixel, largest first) until it is empty. A unit is
-// stats_unit_tiles(S) consecutive 256-pixel tiles, so units of frames with few samples per
-// pixel are not dominated by the queue pop. The next unit is claimed before the current
-// one is processed, which hides the atomic's latency.
+// Batched form: one workgroup per planned work unit, frames in the plan's order (most
+// samples per pixel first, so the longest units are dispatched first). A unit is
+// stats_unit_tiles(S) consecutive 256-pixel tiles, so frames with few samples per pixel
+// still give each workgroup a useful amount of data. (A persistent form popping units
+// from an atomic queue measured 6 % slower than this plain grid on a 32-frame batch.)
 template <int KT, int B>
 __global__ __launch_bounds__(kStatsBlock) void stats_batched_kernel(const ramlt_frame *__restrict__ frames,
                                                                     BatchPlan *plan) {
   __shared__ float park[kParked * kStatsBlock];
-  __shared__ unsigned long long slot[2];
   const unsigned long long total = plan->total_tiles;
-  if (threadIdx.x == 0) slot[0] = atomicAdd(&plan->next_tile, 1ULL);
-  __syncthreads();
-  for (int i = 0;; i ^= 1) {
-    const unsigned long long t = slot[i];
-    if (t >= total) break;  // block-uniform
-    if (threadIdx.x == 0) slot[i ^ 1] = atomicAdd(&plan->next_tile, 1ULL);
+  for (unsigned long long t = blockIdx.x; t < total; t += gridDim.x) {  // one pass unless capped
     int fi;
     long long local;
     plan_lookup(plan, t, &fi, &local);
@@ -266,7 +260,6 @@ __global__ __launch_bounds__(kStatsBlock) void stats_batched_kernel(const ramlt_
       if (p0 >= P) break;
       stats_tile<KT, B>(f, p0, park);
     }
-    __syncthreads();  // slot[i ^ 1] is written; slot[i] is free for the pop after next
   }
 }
 
@@ -291,7 +284,12 @@ hipError_t launch_stats_kt(const ramlt_frame *fh, const ramlt_frame *fd, int n, 
   BatchPlan *plan = (BatchPlan *)ws;
   hipError_t e = launch_plan(fd, n, RAMLT_OP_STATS, -1, plan, st);
   if (e != hipSuccess) return e;
-  const int grid = persistent_grid((const void *)stats_batched_kernel<KT, B>, kStatsBlock);
+  long long units = 0;  // as counted by the planner
+  for (int i = 0; i < n; ++i) {
+    const long long unit = (long long)kStatsTilePixels * stats_unit_tiles(fh[i].S);
+    units += ((long long)fh[i].W * fh[i].H + unit - 1) / unit;
+  }
+  const unsigned grid = (unsigned)(units < (1LL << 22) ? units : (1LL << 22));
   hipLaunchKernelGGL((stats_batched_kernel<KT, B>), dim3(grid), dim3(kStatsBlock), 0, st, fd, plan);
   return hipGetLastError();
 }

@@ -181,7 +181,7 @@ def test_batches_need_a_workspace(lib):
         _abi.RAMLT_EWORKSPACE  # misaligned
     assert _status("stats_accumulate", fs, frames_dev=dev_table, workspace=0x2000000, ws_bytes=need) in \
         (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
-    # filter batches plan one queue per distinct radius
+    # filter batches plan once per distinct radius
     ff = [_valid_filter_frame(), _valid_filter_frame(), _valid_filter_frame()]
     ff[1].radius = 5
     one = _abi.workspace_size(ff[:1] + ff[:1], _abi.OP_FILTER_FORWARD)

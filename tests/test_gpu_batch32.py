@@ -1,6 +1,6 @@
 """The 32-frame batch (frames from 256 x 256 to 2048 x 1152, 4 to 256 spp, 11 x 11 window)
 in one HIP graph per step, as the bench times it: statistics, filter and fused loss seed +
-adjoint as persistent launches over the whole batch. Every frame is checked against the
+adjoint as one launch each over the whole batch. Every frame is checked against the
 oracle on a sampled patch across a region corner; every fourth frame also on a whole
 region (its dL/dlambda_k, with per-frame gradient buffers). The batch loss is checked
 against the FP64 sum over the frames' filtered images."""

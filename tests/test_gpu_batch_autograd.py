@@ -1,4 +1,4 @@
-"""GPU tests of the fused loss seed + adjoint, the batched persistent launches (against
+"""GPU tests of the fused loss seed + adjoint, the batched launches (against
 single-frame launches and the oracle), HIP graph replay (against eager), and the
 autograd binding."""
 
@@ -116,7 +116,7 @@ def test_batched_matches_single_frames_and_oracle():
 
 
 # Frames large enough for region-aligned tiling (>= 16 N x 4 N pixels), each with its own
-# lambda table, grid size and gradient buffer; three radii, so the batch runs three queues.
+# lambda table, grid size and gradient buffer; three radii, so the batch runs three plans.
 ALIGNED_SPECS = [(96, 40, 4, 3, 4), (130, 37, 8, 5, 4), (64, 16, 2, 0, 4), (200, 90, 5, 5, 6),
                  (320, 80, 3, 3, 20)]
 
