@@ -8,6 +8,10 @@
 // one workgroup per planned tile, which finds its frame by binary search of the prefix.
 // Everything stays on the device and in stream order, so a batch can be captured in a
 // graph.
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "batch.hpp"
 
 namespace ramlt {
@@ -39,6 +43,10 @@ __global__ __launch_bounds__(kPlanBlock) void plan_kernel(const ramlt_frame *__r
   long long *prefix = plan_prefix(plan, n);
   // rank = number of frames that go before frame i (higher cost, or equal cost and
   // lower index)
+  if (op == RAMLT_OP_FILTER_FORWARD || op == RAMLT_OP_FILTER_BACKWARD) {  // validated filter frames
+    TileGeom *geom = plan_geom(plan, n);
+    for (int i = threadIdx.x; i < n; i += kPlanBlock) geom[i] = make_geom(frames[i]);
+  }
   for (int i = threadIdx.x; i < n; i += kPlanBlock) {
     const long long ci = cost_of(frames[i], op);
     int rank = 0;
@@ -68,6 +76,23 @@ hipError_t launch_plan(const ramlt_frame *frames_dev, int n, int op, int radius_
                        hipStream_t st) {
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, st, frames_dev, n, op, radius_sel, plan);
   return hipGetLastError();
+}
+
+int resident_blocks(const void *kernel, int block) {
+  static std::mutex mu;
+  static std::map<std::pair<const void *, int>, int> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_pair(kernel, dev);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+  cache[key] = per_cu * cus;
+  return per_cu * cus;
 }
 
 int distinct_radii(const ramlt_frame *fh, int n, int *radii) {

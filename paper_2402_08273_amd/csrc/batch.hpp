@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 
 #include "common.hpp"
 #include "ramlt.h"
@@ -58,9 +59,92 @@ __host__ __device__ inline long long filter_tile_count(const ramlt_frame &f) {
   return (long long)tiles_along(f.W, f.n_regions, kFilterTileW, al) * tiles_along(f.H, f.n_regions, kFilterTileH, al);
 }
 
-// Enqueue the plan kernel: fills plan (order by cost, tile prefix sums).
+// Division by a per-frame constant with one multiply: for 1 <= d < 2^31 and
+// 0 <= n < 2^31, n / d == (n * m) >> s with s = 31 + ceil(log2 d), m = ceil(2^s / d)
+// (Granlund and Montgomery, "Division by invariant integers using multiplication", PLDI
+// 1994): with e = m d - 2^s in [0, d), n m / 2^s = n / d + n e / (d 2^s), and the excess
+// is below 1 / d because n e < 2^31 2^ceil(log2 d) = 2^s, so the floor is exact.
+struct FastDiv {
+  uint32_t m, s;
+};
+
+constexpr __host__ __device__ inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while (l < 31 && (1u << l) < d) ++l;
+  const uint32_t s = 31 + l;
+  return FastDiv{(uint32_t)((((uint64_t)1 << s) + d - 1) / d), s};
+}
+
+constexpr __host__ __device__ __forceinline__ uint32_t fast_div(uint32_t n, FastDiv D) {
+  return (uint32_t)(((uint64_t)n * D.m) >> D.s);
+}
+
+// Compile-time check against plain division: every divisor up to 1024 and the powers of
+// two and their neighbours up to 2^30, on numerators around multiples of the divisor and
+// at the top of the range.
+constexpr bool fastdiv_check_one(uint32_t d) {
+  const FastDiv D = make_fastdiv(d);
+  const uint32_t top = 0x7FFFFFFFu;
+  const uint32_t ns[] = {0u, 1u, d - 1u, d, d + 1u, 2u * d - 1u, 2u * d, 1000u * d - 1u, top, top - 1u, top - d,
+                         top / d * d, top / d * d - 1u};
+  for (uint32_t n : ns)
+    if (n <= top && fast_div(n, D) != n / d) return false;
+  return true;
+}
+
+constexpr bool fastdiv_check() {
+  for (uint32_t d = 1; d <= 1024; ++d)
+    if (!fastdiv_check_one(d)) return false;
+  for (uint32_t p = 1; p <= 30; ++p) {
+    const uint32_t b = 1u << p;
+    if (!fastdiv_check_one(b) || !fastdiv_check_one(b - 1) || !fastdiv_check_one(b + 1)) return false;
+  }
+  // divisors of the largest frames: 2W, 2H, 2N
+  return fastdiv_check_one(131072u) && fastdiv_check_one(2u * 3840u) && fastdiv_check_one(2u * 2160u) &&
+         fastdiv_check_one(2u * 1080u) && fastdiv_check_one(8192u) && fastdiv_check_one(40u);
+}
+static_assert(fastdiv_check(), "FastDiv disagrees with division");
+
+// Filter tiling of one frame in a form the kernels decode without divide instructions.
+// All numerators stay below 2^31: (2c + 1) N < 2^17 * 2^12, 2 k n < 2^30, tile indices
+// < 2^31 (W, H <= 65536, W H <= 2^30, N <= 4096 are validated).
+struct TileGeom {
+  int32_t W, H, N, aligned;
+  int32_t ntx, tpx, tpy, pad;
+  FastDiv d_ntx, d_tpx, d_tpy, d_2N, d_2W, d_2H;
+};
+
+__host__ __device__ inline TileGeom make_geom(const ramlt_frame &f) {
+  TileGeom g{};
+  g.W = f.W;
+  g.H = f.H;
+  g.N = f.n_regions;
+  g.aligned = aligned_tiling(f) ? 1 : 0;
+  g.ntx = tiles_along(f.W, f.n_regions, kFilterTileW, g.aligned);
+  g.tpx = g.aligned ? tiles_per_region(f.W, f.n_regions, kFilterTileW) : 1;
+  g.tpy = g.aligned ? tiles_per_region(f.H, f.n_regions, kFilterTileH) : 1;
+  g.d_ntx = make_fastdiv((uint32_t)g.ntx);
+  g.d_tpx = make_fastdiv((uint32_t)g.tpx);
+  g.d_tpy = make_fastdiv((uint32_t)g.tpy);
+  g.d_2N = make_fastdiv(2u * (uint32_t)f.n_regions);
+  g.d_2W = make_fastdiv(2u * (uint32_t)f.W);
+  g.d_2H = make_fastdiv(2u * (uint32_t)f.H);
+  return g;
+}
+
+static_assert(sizeof(TileGeom) == kPlanFrameBytes, "per-frame plan data is the tile geometry");
+
+__host__ __device__ inline TileGeom *plan_geom(BatchPlan *p, int n_frames) {
+  return (TileGeom *)plan_frame_data(p, n_frames);
+}
+
+// Enqueue the plan kernel: fills plan (order by cost, tile prefix sums, tile geometry).
 hipError_t launch_plan(const ramlt_frame *frames_dev, int n, int op, int radius_sel, BatchPlan *plan,
                        hipStream_t st);
+
+// Workgroups of `kernel` (with `block` threads) that fit on the current device at once:
+// occupancy per CU times the CU count (cached per kernel and device).
+int resident_blocks(const void *kernel, int block);
 
 // Distinct radii of a batch, ascending; returns their count (<= RAMLT_MAX_RADIUS + 1).
 int distinct_radii(const ramlt_frame *fh, int n, int *radii);

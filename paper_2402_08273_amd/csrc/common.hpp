@@ -45,14 +45,28 @@ struct BatchPlan {
   unsigned long long total_tiles;
   int n_frames;
   int pad1[11];
-  // followed by: int order[n_frames]; long long prefix[n_frames + 1]
+  // followed by: int order[n_frames]; long long prefix[n_frames + 1]; per-frame data
+  // (kPlanFrameBytes each, by frame index)
 };
 
-__host__ __device__ inline size_t plan_bytes(int n_frames) {
+// Bytes per frame of per-frame data the plan kernel stores after the prefix sums (the
+// filter's tile geometry), 16-byte aligned.
+constexpr size_t kPlanFrameBytes = 80;
+
+__host__ __device__ inline size_t plan_frames_offset(int n_frames) {
   size_t b = sizeof(BatchPlan) + sizeof(int) * (size_t)n_frames;
   b = (b + 7) & ~(size_t)7;
   b += sizeof(long long) * (size_t)(n_frames + 1);
+  return (b + 15) & ~(size_t)15;
+}
+
+__host__ __device__ inline size_t plan_bytes(int n_frames) {
+  const size_t b = plan_frames_offset(n_frames) + kPlanFrameBytes * (size_t)n_frames;
   return (b + 255) & ~(size_t)255;
+}
+
+__host__ __device__ inline void *plan_frame_data(BatchPlan *p, int n_frames) {
+  return (char *)p + plan_frames_offset(n_frames);
 }
 
 __host__ __device__ inline int *plan_order(BatchPlan *p) { return (int *)(p + 1); }

@@ -39,42 +39,68 @@ constexpr int kTX = kFilterTileW;
 constexpr int kTY = kFilterTileH;
 constexpr int kFilterBlock = kTX * kTY;
 constexpr float kLog2e = 1.4426950408889634f;
-constexpr long long kMaxBatchGrid = 1LL << 22;  // workgroups of one batched launch
+constexpr long long kMaxBatchGrid = 1LL << 22;  // workgroups of one loss-seed launch
 
 // ------------------------------------------------------------------------ tiling
+// All index arithmetic below divides by per-frame constants through FastDiv (TileGeom);
+// a divide instruction sequence per division was the largest share of these kernels'
+// scalar work.
 struct Rect {
   int x0, y0, x1, y1;  // outputs [x0, x1) x [y0, y1)
+  int kx, ky;          // the tile's region (aligned tiling), else -1
 };
 
-// Interval [lo, hi) of the idx-th tile along an axis (possibly empty when aligned).
-__device__ inline void tile_span(int idx, int n, int N, int T, bool aligned, int *lo, int *hi) {
-  if (!aligned) {
-    *lo = idx * T;
-    *hi = min(n, *lo + T);
-    return;
-  }
-  const int tpr = tiles_per_region(n, N, T);
-  const int k = idx / tpr;
-  const int i = idx - k * tpr;
-  const int a = region_start(k, n, N), b = region_start(k + 1, n, N);
-  *lo = min(a + i * T, b);
-  *hi = min(b, a + (i + 1) * T);
+__device__ __forceinline__ int cell_x(int x, const TileGeom &g) {
+  return (int)fast_div((uint32_t)(2 * x + 1) * (uint32_t)g.N, g.d_2W);
+}
+__device__ __forceinline__ int cell_y(int y, const TileGeom &g) {
+  return (int)fast_div((uint32_t)(2 * y + 1) * (uint32_t)g.N, g.d_2H);
+}
+__device__ __forceinline__ int region_at(const TileGeom &g, int x, int y) { return cell_y(y, g) * g.N + cell_x(x, g); }
+
+// First coordinate (of n) in region column / row k (the same as region_start).
+__device__ __forceinline__ int region_begin(const TileGeom &g, int k, int n) {
+  if (k <= 0) return 0;
+  if (k >= g.N) return n;
+  const int num = 2 * k * n - g.N;
+  return num <= 0 ? 0 : min((int)fast_div((uint32_t)num + 2u * (uint32_t)g.N - 1u, g.d_2N), n);
 }
 
-__device__ inline Rect tile_rect(const ramlt_frame &f, long long t) {
-  const bool al = aligned_tiling(f);
-  const int ntx = tiles_along(f.W, f.n_regions, kTX, al);
+// Output rectangle of tile t (possibly empty when aligned). Tile t < 2^31.
+__device__ __forceinline__ Rect tile_rect(const TileGeom &g, long long t) {
+  const uint32_t tt = (uint32_t)t;
+  const uint32_t tr = fast_div(tt, g.d_ntx);
+  const uint32_t tc = tt - tr * (uint32_t)g.ntx;
   Rect r;
-  tile_span((int)(t % ntx), f.W, f.n_regions, kTX, al, &r.x0, &r.x1);
-  tile_span((int)(t / ntx), f.H, f.n_regions, kTY, al, &r.y0, &r.y1);
+  if (g.aligned) {
+    const int kx = (int)fast_div(tc, g.d_tpx), i = (int)tc - kx * g.tpx;
+    const int ky = (int)fast_div(tr, g.d_tpy), j = (int)tr - ky * g.tpy;
+    const int bx = region_begin(g, kx + 1, g.W), by = region_begin(g, ky + 1, g.H);
+    r.x0 = min(region_begin(g, kx, g.W) + i * kTX, bx);
+    r.x1 = min(bx, r.x0 + kTX);
+    r.y0 = min(region_begin(g, ky, g.H) + j * kTY, by);
+    r.y1 = min(by, r.y0 + kTY);
+    r.kx = kx;
+    r.ky = ky;
+  } else {
+    r.x0 = (int)tc * kTX;
+    r.x1 = min(g.W, r.x0 + kTX);
+    r.y0 = (int)tr * kTY;
+    r.y1 = min(g.H, r.y0 + kTY);
+    r.kx = r.ky = -1;
+  }
   return r;
 }
 
-__device__ __forceinline__ int cell_x(int x, const ramlt_frame &f) {
-  return (int)(((unsigned)(2 * x + 1) * (unsigned)f.n_regions) / (2u * (unsigned)f.W));
+// Region of the tile's first pixel (clamped into the image: an empty tile of an aligned
+// tiling may start at x0 == W or y0 == H), and whether all its pixels share it.
+__device__ __forceinline__ int tile_region(const TileGeom &g, const Rect &r) {
+  if (r.kx >= 0) return r.ky * g.N + r.kx;
+  return region_at(g, min(r.x0, g.W - 1), min(r.y0, g.H - 1));
 }
-__device__ __forceinline__ int cell_y(int y, const ramlt_frame &f) {
-  return (int)(((unsigned)(2 * y + 1) * (unsigned)f.n_regions) / (2u * (unsigned)f.H));
+
+__device__ __forceinline__ bool tile_uniform(const TileGeom &g, const Rect &r) {
+  return r.kx >= 0 || region_at(g, r.x0, r.y0) == region_at(g, r.x1 - 1, r.y1 - 1);
 }
 
 // ------------------------------------------------------------------------ weights
@@ -99,20 +125,39 @@ __device__ __forceinline__ float clipped_sum(const float (&w)[R + 1], int c, int
   return s;
 }
 
-// Stage a float4 per halo pixel of the tile at (x0, y0): value(gx, gy) inside the image,
-// zero outside.
+// Halo items per thread: the (kTX + 2R) x (kTY + 2R) halo tile over the workgroup.
+template <int R>
+constexpr int halo_iters() {
+  return ((kTX + 2 * R) * (kTY + 2 * R) + kFilterBlock - 1) / kFilterBlock;
+}
+
+// Stage a float4 per halo pixel of the tile at (x0, y0): value(q) at the pixel's offset q
+// inside the image, zero outside. All of a thread's loads are issued before the first LDS
+// store (addresses are clamped into the image, so every load is in bounds), so the
+// workgroup waits for one memory round trip instead of one per item.
 template <int R, typename F>
 __device__ __forceinline__ void stage_halo(const ramlt_frame &f, int x0, int y0, float4 *lds, F value) {
   constexpr int HX = kTX + 2 * R;
   constexpr int HY = kTY + 2 * R;
-  for (int i = threadIdx.x; i < HX * HY; i += kFilterBlock) {
+  constexpr int NIT = halo_iters<R>();
+  float4 v[NIT];
+  bool ok[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int i = threadIdx.x + it * kFilterBlock;
     const int hy = i / HX;
     const int hx = i - hy * HX;
     const int gx = x0 - R + hx;
     const int gy = y0 - R + hy;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (gx >= 0 && gx < f.W && gy >= 0 && gy < f.H) v = value(gx, gy);
-    lds[i] = v;
+    ok[it] = i < HX * HY && gx >= 0 && gx < f.W && gy >= 0 && gy < f.H;
+    const int cx = min(max(gx, 0), f.W - 1);
+    const int cy = min(max(gy, 0), f.H - 1);
+    v[it] = value((long long)cy * f.W + cx);
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int i = threadIdx.x + it * kFilterBlock;
+    if (i < HX * HY) lds[i] = ok[it] ? v[it] : make_float4(0.f, 0.f, 0.f, 0.f);
   }
 }
 
@@ -144,30 +189,72 @@ __device__ __forceinline__ float window_moment2(const float (&w)[R + 1]) {
   return 2.0f * z;
 }
 
+// Halo values of one tile held in registers between their loads and their LDS stores, so
+// that a workgroup loads the next tile's halo while it computes the current one.
 template <int R>
-__device__ __forceinline__ void forward_tile(const ramlt_frame &f, const Rect &r, float4 *stage, float4 *hbuf,
-                                             float *wtab) {
+struct Halo {
+  float4 v[halo_iters<R>()];
+};
+
+// Issue the loads of value(q) for every halo pixel of the tile at (x0, y0) (addresses
+// clamped into the image, so every load is in bounds).
+template <int R, typename F>
+__device__ __forceinline__ void halo_load(const ramlt_frame &f, int x0, int y0, Halo<R> &h, F value) {
+  constexpr int HX = kTX + 2 * R;
+#pragma unroll
+  for (int it = 0; it < halo_iters<R>(); ++it) {
+    const int i = threadIdx.x + it * kFilterBlock;
+    const int hy = i / HX;
+    const int hx = i - hy * HX;
+    const int cx = min(max(x0 - R + hx, 0), f.W - 1);
+    const int cy = min(max(y0 - R + hy, 0), f.H - 1);
+    h.v[it] = value((long long)cy * f.W + cx);
+  }
+}
+
+// Store loaded halo values to LDS, zero for pixels outside the image.
+template <int R>
+__device__ __forceinline__ void halo_store(const ramlt_frame &f, int x0, int y0, const Halo<R> &h, float4 *lds) {
   constexpr int HX = kTX + 2 * R;
   constexpr int HY = kTY + 2 * R;
+#pragma unroll
+  for (int it = 0; it < halo_iters<R>(); ++it) {
+    const int i = threadIdx.x + it * kFilterBlock;
+    const int hy = i / HX;
+    const int hx = i - hy * HX;
+    const int gx = x0 - R + hx;
+    const int gy = y0 - R + hy;
+    const bool in = gx >= 0 && gx < f.W && gy >= 0 && gy < f.H;
+    if (i < HX * HY) lds[i] = in ? h.v[it] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+template <int R>
+struct FwdLds {
+  float4 stage[(kTX + 2 * R) * (kTY + 2 * R)];
+  float4 hb1[(kTY + 2 * R) * kTX];
+  float wtab[R + 1];
+};
+
+// The filter of one tile whose mean halo is in LDS (and, for a tile in one region, the
+// weights w(d) in wtab).
+template <int R>
+__device__ __forceinline__ void forward_compute(const ramlt_frame &f, const TileGeom &g, const Rect &r, bool uniform,
+                                                FwdLds<R> &L) {
+  constexpr int HX = kTX + 2 * R;
+  constexpr int HY = kTY + 2 * R;
+  float4 *stage = L.stage, *hbuf = L.hb1;
   const long long P = (long long)f.W * f.H;
   const int tx = threadIdx.x % kTX;
   const int ty = threadIdx.x / kTX;
   const int x = r.x0 + tx;
   const int y = r.y0 + ty;
   const bool inside = x < r.x1 && y < r.y1;
-  const int k0 = region_of(r.x0, r.y0, f.W, f.H, f.n_regions);
-  const bool uniform = k0 == region_of(r.x1 - 1, r.y1 - 1, f.W, f.H, f.n_regions);
-  if (uniform && threadIdx.x <= R) {
-    const float beta = half_inv_var(f.lambda[k0], f.lambda_min);
-    wtab[threadIdx.x] = threadIdx.x == 0 ? 1.0f : expf(-(float)(threadIdx.x * threadIdx.x) * beta);
-  }
-  stage_halo<R>(f, r.x0, r.y0, stage, [&](int gx, int gy) { return load3(f.mean, P, (long long)gy * f.W + gx); });
-  __syncthreads();
   if (uniform) {
     // one sigma for the whole tile: rows, then columns
     float w[R + 1];
 #pragma unroll
-    for (int d = 0; d <= R; ++d) w[d] = wtab[d];
+    for (int d = 0; d <= R; ++d) w[d] = L.wtab[d];
     for (int i = threadIdx.x; i < HY * kTX; i += kFilterBlock) {
       const int hy = i / kTX;
       const int hx = i - hy * kTX;
@@ -203,7 +290,7 @@ __device__ __forceinline__ void forward_tile(const ramlt_frame &f, const Rect &r
     }
   } else if (inside) {
     // per-pixel sigma: direct (2R+1)^2 gather
-    const int k = region_of(x, y, f.W, f.H, f.n_regions);
+    const int k = region_at(g, x, y);
     const float beta = half_inv_var(f.lambda[k], f.lambda_min);
     float w[R + 1];
     gauss_weights<R>(beta, w);
@@ -295,7 +382,8 @@ struct BwdLds {
   float4 hb2[HB2];
   float tab[9 * (R + 1)];
   float ztab[9];
-  int rows[HY];
+  int rows[HY];  // region row of each halo row, relative to the first (separable path)
+  int cols[HX];  // same for halo columns
   double red[kFilterBlock / kWave];
 };
 
@@ -312,14 +400,15 @@ struct BwdLds {
 // mean * dx^2. Per-tile partial sums of dL/dlambda and of the loss go to lam_part /
 // loss_part[slot] when given (a fixed-order finalize kernel adds them up), else atomics.
 template <int R>
-__device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &r, long long slot, float *lam_part,
+__device__ __forceinline__ void backward_tile(const ramlt_frame &f, const TileGeom &g, const Rect &r, long long slot,
+                                              float *lam_part,
                                               double *loss_part, BwdLds<R> &L) {
   constexpr int HX = BwdLds<R>::HX;
   constexpr int HY = BwdLds<R>::HY;
   constexpr int RS = BwdLds<R>::RS;
   float4 *stage = L.stage, *hb1 = L.hb1, *hb2 = L.hb2;
   float *tab = L.tab, *ztab = L.ztab;
-  int *rows = L.rows;
+  int *rows = L.rows, *cols = L.cols;
   const int W = f.W, H = f.H, N = f.n_regions;
   const long long P = (long long)W * H;
   const bool fused = f.grad_out == nullptr;
@@ -335,16 +424,16 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
   // Region columns / rows reachable from the tile's window.
   const int gx_lo = max(r.x0 - R, 0), gx_hi = min(r.x1 + R, W) - 1;
   const int gy_lo = max(r.y0 - R, 0), gy_hi = min(r.y1 + R, H) - 1;
-  const int kx_lo = cell_x(gx_lo, f), kx_hi = cell_x(gx_hi, f);
-  const int ky_lo = cell_y(gy_lo, f), nsy = cell_y(gy_hi, f) - ky_lo + 1;
-  const int kx_own = cell_x(r.x0, f);
-  const int k0 = region_of(r.x0, r.y0, W, H, N);
-  const bool uniform = k0 == region_of(r.x1 - 1, r.y1 - 1, W, H, N);
+  const int kx_lo = cell_x(gx_lo, g), kx_hi = cell_x(gx_hi, g);
+  const int ky_lo = cell_y(gy_lo, g), nsy = cell_y(gy_hi, g) - ky_lo + 1;
+  const int kx_own = r.kx >= 0 ? r.kx : cell_x(r.x0, g);
+  const int k0 = tile_region(g, r);
+  const bool uniform = tile_uniform(g, r);
   // block-uniform: separable gather when the outputs share a region column and only one
   // neighbour column lies within R on each side
   const bool sep = uniform && kx_lo >= kx_own - 1 && kx_hi <= kx_own + 1 && nsy <= 3;
   const int so = kx_own - kx_lo;  // own slot among the (<= 3) region columns
-  const int rs = region_start(kx_own, W, N), re = region_start(kx_own + 1, W, N);
+  const int rs = region_begin(g, kx_own, W), re = region_begin(g, kx_own + 1, W);
   const int nL = sep ? rs - gx_lo : 0;          // left strip width (<= R)
   const int nR = sep ? gx_hi + 1 - re : 0;      // right strip width (<= R)
   const int mL = nL > 0 ? min(r.x1, rs + R) - r.x0 : 0;  // outputs the left strip reaches
@@ -361,6 +450,19 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
     return load3(f.grad_out, P, q);
   };
 
+  // all loads of U first (clamped, in-bounds addresses; in flight while the tables are
+  // built), then the per-item arithmetic
+  constexpr int NIT = halo_iters<R>();
+  float4 uv[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int i = threadIdx.x + it * kFilterBlock;
+    const int hy = i / HX;
+    const int hx = i - hy * HX;
+    const int cx = min(max(r.x0 - R + hx, 0), W - 1);
+    const int cy = min(max(r.y0 - R + hy, 0), H - 1);
+    uv[it] = U_at((long long)cy * W + cx);
+  }
   if (sep) {
     // weights and window sums of the (<= 3 x 3) regions around the tile; row slots
     if (threadIdx.x < 9) {
@@ -375,7 +477,11 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
     }
     for (int i = threadIdx.x; i < HY; i += kFilterBlock) {
       const int gy = min(max(r.y0 - R + i, 0), H - 1);
-      rows[i] = cell_y(gy, f) - ky_lo;
+      rows[i] = cell_y(gy, g) - ky_lo;
+    }
+    for (int i = threadIdx.x; i < HX; i += kFilterBlock) {
+      const int gx = min(max(r.x0 - R + i, 0), W - 1);
+      cols[i] = cell_x(gx, g) - kx_lo;
     }
     __syncthreads();
   }
@@ -383,18 +489,19 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
   // ---- stage a_j = U_j / (S D_j) over tile + halo: own-column sources in `stage`
   // (others zero), neighbour columns in the strips; the direct path keeps every source with
   // beta' = beta log2(e) in .w
-  for (int i = threadIdx.x; i < HX * HY; i += kFilterBlock) {
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int i = threadIdx.x + it * kFilterBlock;
+    if (i >= HX * HY) break;
     const int hy = i / HX;
     const int hx = i - hy * HX;
     const int gx = r.x0 - R + hx;
     const int gy = r.y0 - R + hy;
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
     if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-      const long long q = (long long)gy * W + gx;
       float D, tag = 0.f;
       if (sep) {
-        const int sx = cell_x(gx, f) - kx_lo;
-        const int sl = rows[hy] * 3 + sx;
+        const int sl = rows[hy] * 3 + cols[hx];
         const float z = ztab[sl];
         float Dx = z, Dy = z;
         if (gx < R || gx + R >= W || gy < R || gy + R >= H) {
@@ -406,14 +513,14 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
         }
         D = Dx * Dy;
       } else {
-        const float beta = half_inv_var(f.lambda[region_of(gx, gy, W, H, N)], f.lambda_min);
+        const float beta = half_inv_var(f.lambda[region_at(g, gx, gy)], f.lambda_min);
         float w[R + 1];
         gauss_weights<R>(beta, w);
         D = clipped_sum<R, 0>(w, gx, W) * clipped_sum<R, 0>(w, gy, H);
         tag = beta * kLog2e;
       }
       const float s = invS / D;
-      const float4 u = U_at(q);
+      const float4 u = uv[it];
       a = make_float4(u.x * s, u.y * s, u.z * s, tag);
     }
     if (sep) {  // every strip entry is written, zero for rows outside the image
@@ -550,15 +657,15 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
   if (!f.grad_lambda) return;
   __syncthreads();  // stage and hb2 are reused below
   float4 *smu = stage;
-  stage_halo<R>(f, r.x0, r.y0, smu, [&](int gx, int gy) { return load3(f.mean, P, (long long)gy * W + gx); });
+  stage_halo<R>(f, r.x0, r.y0, smu, [&](long long q) { return load3(f.mean, P, q); });
   __syncthreads();
-  const int k_own = inside ? region_of(x, y, W, H, N) : k0;
+  const int k_own = inside ? region_at(g, x, y) : k0;
   const float lam = f.lambda[k_own];
   const bool live = lam >= f.lambda_min;
   const float beta = half_inv_var(lam, f.lambda_min);
   float w[R + 1], wd2[R + 1];
   if (sep) {
-    const int sl = (cell_y(r.y0, f) - ky_lo) * 3 + so;
+    const int sl = (cell_y(r.y0, g) - ky_lo) * 3 + so;
 #pragma unroll
     for (int d = 0; d <= R; ++d) w[d] = tab[sl * (R + 1) + d];
   } else {
@@ -638,7 +745,7 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const Rect &
     // one region for the whole tile: block reduction, one partial (or atomic)
     const double s = block_sum((double)contrib, L.red);
     if (threadIdx.x == 0) {
-      if (lam_part && aligned_tiling(f))  // the finalize kernel reads region-aligned partials
+      if (lam_part && g.aligned)  // the finalize kernel reads region-aligned partials
         lam_part[slot] = live ? (float)s : 0.f;
       else if (live)
         unsafeAtomicAdd(f.grad_lambda + k0, (float)s);
@@ -716,73 +823,79 @@ __device__ __forceinline__ long long xcd_tile(unsigned b, unsigned nblocks) {
   return (long long)(b & 7) * per + (b >> 3);
 }
 
-template <int R>
-struct FwdLds {
-  float4 stage[(kTX + 2 * R) * (kTY + 2 * R)];
-  float4 hb1[(kTY + 2 * R) * kTX];
-  float wtab[R + 1];
-};
-
-template <int R>
-__global__ __launch_bounds__(kFilterBlock) void forward_kernel(const ramlt_frame f, long long ntiles,
-                                                               float *unused0, double *unused1) {
-  __shared__ FwdLds<R> s;
-  const long long t = xcd_tile(blockIdx.x, gridDim.x);
-  if (t >= ntiles) return;
-  const Rect r = tile_rect(f, t);
-  if (r.x0 >= r.x1 || r.y0 >= r.y1) return;
-  forward_tile<R>(f, r, s.stage, s.hb1, s.wtab);
+// Frame, tiling and output rectangle of tile t: the single frame's tile t, or the planned
+// tile t of a batch.
+template <bool BATCH>
+__device__ __forceinline__ void fetch_tile(const ramlt_frame &single, const TileGeom &single_g,
+                                           const ramlt_frame *frames, BatchPlan *plan, long long t, ramlt_frame &f,
+                                           TileGeom &g, Rect &r) {
+  if constexpr (BATCH) {
+    int fi;
+    long long local;
+    plan_lookup(plan, (unsigned long long)t, &fi, &local);
+    f = frames[fi];
+    g = plan_geom(plan, plan->n_frames)[fi];
+    r = tile_rect(g, local);
+  } else {
+    f = single;
+    g = single_g;
+    r = tile_rect(g, t);
+  }
 }
 
-__device__ __forceinline__ void empty_tile_partials(const ramlt_frame &f, long long slot, float *lam_part,
-                                                    double *loss_part) {
+// Forward filter, one tile per workgroup: tile t0 + (the XCD-aware order of the workgroup)
+// of the single frame, or of a batch's plan. (A loop over several tiles per workgroup
+// kept more values live and cost occupancy; large launches are split by the host.)
+template <int R, bool BATCH>
+__global__ __launch_bounds__(kFilterBlock) void forward_kernel(const ramlt_frame single, const TileGeom single_g,
+                                                               const ramlt_frame *__restrict__ frames,
+                                                               BatchPlan *plan, long long ntiles, long long t0) {
+  __shared__ FwdLds<R> s;
+  const long long total = BATCH ? (long long)plan->total_tiles : ntiles;
+  const long long t = t0 + xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= total) return;
+  ramlt_frame f;
+  TileGeom g;
+  Rect r;
+  fetch_tile<BATCH>(single, single_g, frames, plan, t, f, g, r);
+  if (r.x0 >= r.x1 || r.y0 >= r.y1) return;  // block-uniform
+  const bool uniform = tile_uniform(g, r);
+  Halo<R> h;
+  halo_load<R>(f, r.x0, r.y0, h, [&](long long q) { return load3(f.mean, (long long)f.W * f.H, q); });
+  if (uniform && threadIdx.x <= R) {
+    const float beta = half_inv_var(f.lambda[tile_region(g, r)], f.lambda_min);
+    s.wtab[threadIdx.x] = threadIdx.x == 0 ? 1.0f : expf(-(float)(threadIdx.x * threadIdx.x) * beta);
+  }
+  halo_store<R>(f, r.x0, r.y0, h, s.stage);
+  __syncthreads();
+  forward_compute<R>(f, g, r, uniform, s);
+}
+
+__device__ __forceinline__ void empty_tile_partials(long long slot, float *lam_part, double *loss_part) {
   if (threadIdx.x == 0) {
     if (lam_part) lam_part[slot] = 0.f;
     if (loss_part) loss_part[slot] = 0.0;
   }
 }
 
-template <int R>
-__global__ __launch_bounds__(kFilterBlock) void backward_kernel(const ramlt_frame f, long long ntiles,
+// Adjoint, one tile per workgroup; per-tile partials go to slot t.
+template <int R, bool BATCH>
+__global__ __launch_bounds__(kFilterBlock) void backward_kernel(const ramlt_frame single, const TileGeom single_g,
+                                                                const ramlt_frame *__restrict__ frames,
+                                                                BatchPlan *plan, long long ntiles, long long t0,
                                                                 float *lam_part, double *loss_part) {
   __shared__ BwdLds<R> s;
-  const long long t = xcd_tile(blockIdx.x, gridDim.x);
-  if (t >= ntiles) return;
-  const Rect r = tile_rect(f, t);
-  if (r.x0 >= r.x1 || r.y0 >= r.y1) {
-    empty_tile_partials(f, t, lam_part, loss_part);
-    return;
-  }
-  backward_tile<R>(f, r, t, lam_part, loss_part, s);
-}
-
-// Batched forms: one workgroup per planned (frame, tile) pair, found by a binary search
-// of the plan's prefix sums. Filter tiles all cost about the same, so a plain grid (with
-// the XCD-aware order) balances as well as an atomic work queue, which measured slower.
-template <int R, bool BWD>
-__global__ __launch_bounds__(kFilterBlock) void filter_batched_kernel(const ramlt_frame *__restrict__ frames,
-                                                                      BatchPlan *plan, float *lam_part,
-                                                                      double *loss_part) {
-  using Lds = typename std::conditional<BWD, BwdLds<R>, FwdLds<R>>::type;
-  __shared__ Lds s;
-  const long long total = (long long)plan->total_tiles;
-  // one pass when the grid covers every tile; grid-stride passes beyond kMaxBatchGrid
-  for (long long t = xcd_tile(blockIdx.x, gridDim.x); t < total; t += gridDim.x) {
-    int fi;
-    long long local;
-    plan_lookup(plan, (unsigned long long)t, &fi, &local);
-    const ramlt_frame f = frames[fi];
-    const Rect r = tile_rect(f, local);
-    if (r.x0 < r.x1 && r.y0 < r.y1) {  // block-uniform
-      if constexpr (BWD)
-        backward_tile<R>(f, r, t, lam_part, loss_part, s);
-      else
-        forward_tile<R>(f, r, s.stage, s.hb1, s.wtab);
-    } else if (BWD) {
-      empty_tile_partials(f, t, lam_part, loss_part);
-    }
-    __syncthreads();  // LDS is reused by the next tile
-  }
+  const long long total = BATCH ? (long long)plan->total_tiles : ntiles;
+  const long long t = t0 + xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= total) return;
+  ramlt_frame f;
+  TileGeom g;
+  Rect r;
+  fetch_tile<BATCH>(single, single_g, frames, plan, t, f, g, r);
+  if (r.x0 < r.x1 && r.y0 < r.y1)  // block-uniform
+    backward_tile<R>(f, g, r, t, lam_part, loss_part, s);
+  else
+    empty_tile_partials(t, lam_part, loss_part);
 }
 
 __global__ __launch_bounds__(kLossBlock) void loss_seed_kernel(const ramlt_frame f) {
@@ -809,16 +922,18 @@ __global__ __launch_bounds__(kLossBlock) void loss_seed_batched_kernel(const ram
   }
 }
 
-using FrameKernel = void (*)(const ramlt_frame, long long, float *, double *);
-using BatchKernel = void (*)(const ramlt_frame *, BatchPlan *, float *, double *);
+using FwdKernel = void (*)(const ramlt_frame, const TileGeom, const ramlt_frame *, BatchPlan *, long long,
+                           long long);
+using BwdKernel = void (*)(const ramlt_frame, const TileGeom, const ramlt_frame *, BatchPlan *, long long, long long,
+                           float *, double *);
 
 template <int... Rs>
 struct KernelTables {
   static constexpr int kCount = sizeof...(Rs);
-  static constexpr FrameKernel forward[kCount] = {forward_kernel<Rs>...};
-  static constexpr FrameKernel backward[kCount] = {backward_kernel<Rs>...};
-  static constexpr BatchKernel forward_batched[kCount] = {filter_batched_kernel<Rs, false>...};
-  static constexpr BatchKernel backward_batched[kCount] = {filter_batched_kernel<Rs, true>...};
+  static constexpr FwdKernel forward[kCount] = {forward_kernel<Rs, false>...};
+  static constexpr FwdKernel forward_batched[kCount] = {forward_kernel<Rs, true>...};
+  static constexpr BwdKernel backward[kCount] = {backward_kernel<Rs, false>...};
+  static constexpr BwdKernel backward_batched[kCount] = {backward_kernel<Rs, true>...};
 };
 
 using Tables = KernelTables<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15>;
@@ -834,24 +949,36 @@ size_t partials_bytes(const ramlt_frame *fh, int n) {
   return (b + 255) & ~(size_t)255;
 }
 
+// One workgroup per tile, in launches of at most kMaxTileGrid workgroups (a multiple of 8
+// for the XCD-aware order).
+constexpr long long kMaxTileGrid = 1LL << 22;
+
+template <typename K, typename... Args>
+hipError_t launch_tiles(K kernel, long long tiles, hipStream_t st, const ramlt_frame &single, const TileGeom &g,
+                        const ramlt_frame *fd, BatchPlan *plan, long long ntiles, Args... rest) {
+  for (long long t0 = 0; t0 < tiles; t0 += kMaxTileGrid) {
+    const unsigned grid = (unsigned)(((min(tiles - t0, kMaxTileGrid) + 7) / 8) * 8);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kFilterBlock), 0, st, single, g, fd, plan, ntiles, t0, rest...);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_filter(bool bwd, const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws,
                          hipStream_t st) {
-  const FrameKernel *single = bwd ? Tables::backward : Tables::forward;
-  const BatchKernel *batched = bwd ? Tables::backward_batched : Tables::forward_batched;
-  const int op = bwd ? RAMLT_OP_FILTER_BACKWARD : RAMLT_OP_FILTER_FORWARD;
   if (n == 1) {
     const ramlt_frame &f = fh[0];
+    const TileGeom g = make_geom(f);
     const long long nt = filter_tiles(f);
-    float *lam_part = nullptr;
-    double *loss_part = nullptr;
-    if (bwd) {
-      lam_part = (float *)ws;
-      loss_part = (double *)((char *)ws + (((size_t)nt * sizeof(float) + 7) & ~(size_t)7));
-    }
-    const unsigned grid = (unsigned)(((nt + 7) / 8) * 8);
-    hipLaunchKernelGGL(single[f.radius], dim3(grid), dim3(kFilterBlock), 0, st, f, nt, lam_part, loss_part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !bwd) return e;
+    if (!bwd)
+      return launch_tiles(Tables::forward[f.radius], nt, st, f, g, (const ramlt_frame *)nullptr,
+                          (BatchPlan *)nullptr, nt);
+    float *lam_part = (float *)ws;
+    double *loss_part = (double *)((char *)ws + (((size_t)nt * sizeof(float) + 7) & ~(size_t)7));
+    hipError_t e = launch_tiles(Tables::backward[f.radius], nt, st, f, g, (const ramlt_frame *)nullptr,
+                                (BatchPlan *)nullptr, nt, lam_part, loss_part);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(backward_finalize_kernel, dim3(finalize_lam_blocks(f.n_regions) + 1), dim3(kFilterBlock), 0,
                        st, f, (const ramlt_frame *)nullptr, (BatchPlan *)nullptr, lam_part, loss_part);
     return hipGetLastError();
@@ -862,30 +989,33 @@ hipError_t launch_filter(bool bwd, const ramlt_frame *fh, const ramlt_frame *fd,
   const size_t part = bwd ? partials_bytes(fh, n) : 0;
   long long T = 0;
   for (int i = 0; i < n; ++i) T += filter_tiles(fh[i]);
+  const ramlt_frame none{};
+  const TileGeom none_g{};
   for (int g = 0; g < nr; ++g) {
     char *base = (char *)ws + (size_t)g * (pb + part);
     BatchPlan *plan = (BatchPlan *)base;
     float *lam_part = bwd ? (float *)(base + pb) : nullptr;
     double *loss_part = bwd ? (double *)(base + pb + (((size_t)T * sizeof(float) + 7) & ~(size_t)7)) : nullptr;
-    hipError_t e = launch_plan(fd, n, op, radii[g], plan, st);
+    hipError_t e = launch_plan(fd, n, bwd ? RAMLT_OP_FILTER_BACKWARD : RAMLT_OP_FILTER_FORWARD, radii[g], plan, st);
     if (e != hipSuccess) return e;
     long long tiles = 0;  // the planner counts the same tiles on the device
     for (int i = 0; i < n; ++i)
       if (fh[i].radius == radii[g]) tiles += filter_tiles(fh[i]);
     if (tiles == 0) continue;
-    const unsigned grid = (unsigned)(((min(tiles, kMaxBatchGrid) + 7) / 8) * 8);
-    hipLaunchKernelGGL(batched[radii[g]], dim3(grid), dim3(kFilterBlock), 0, st, fd, plan, lam_part, loss_part);
+    if (!bwd) {
+      e = launch_tiles(Tables::forward_batched[radii[g]], tiles, st, none, none_g, fd, plan, 0LL);
+      if (e != hipSuccess) return e;
+      continue;
+    }
+    e = launch_tiles(Tables::backward_batched[radii[g]], tiles, st, none, none_g, fd, plan, 0LL, lam_part,
+                     loss_part);
+    if (e != hipSuccess) return e;
+    int nmax = 1;
+    for (int i = 0; i < n; ++i) nmax = max(nmax, fh[i].n_regions);
+    hipLaunchKernelGGL(backward_finalize_kernel, dim3(finalize_lam_blocks(nmax) + 1, n), dim3(kFilterBlock), 0, st,
+                       none, fd, plan, lam_part, loss_part);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (bwd) {
-      ramlt_frame none{};
-      int nmax = 1;
-      for (int i = 0; i < n; ++i) nmax = max(nmax, fh[i].n_regions);
-      hipLaunchKernelGGL(backward_finalize_kernel, dim3(finalize_lam_blocks(nmax) + 1, n), dim3(kFilterBlock), 0, st,
-                         none, fd, plan, lam_part, loss_part);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
   }
   return hipSuccess;
 }
