@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--regions", type=int, default=N_REGIONS)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extra", action="store_true", help="skip the batched and 4K measurements")
+    p.add_argument("--only", choices=["batched", "uhd"], default=None,
+                   help="measure only the 32-frame batch or only the 4K frame and print that object "
+                        "(for profiling one workload)")
     p.add_argument("--cpu-rows", type=int, default=0, help="rows of the frame the oracle times (0 = auto)")
     p.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "stats_accumulate_traffic.txt"),
                    help="rocprofv3 HBM byte count of the statistics kernel (JSON); ignored if the kernel "
@@ -269,6 +272,10 @@ def main():
     from synth.workloads import HD, MAX_LAG
 
     torch.cuda.set_device(0)
+    if args.only:
+        fn = measure_batch32 if args.only == "batched" else measure_uhd
+        print(json.dumps(fn(args.steps, args.warmup)), flush=True)
+        return
     W, H, S, r, N = args.width, args.height, args.spp, args.radius, args.regions
     c = SingleChain(W, H, S, r, N, HD.seed, HD.frame)
     P = c.P
