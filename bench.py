@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--regions", type=int, default=N_REGIONS)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extra", action="store_true", help="skip the batched and 4K measurements")
+    p.add_argument("--no-tune", action="store_true",
+                   help="use the library's default filter schedule instead of the autotuned one")
     p.add_argument("--only", choices=["batched", "uhd"], default=None,
                    help="measure only the 32-frame batch or only the 4K frame and print that object "
                         "(for profiling one workload)")
@@ -97,7 +99,7 @@ class SingleChain:
     stats -> filter -> zero the accumulators -> fused loss seed + adjoint (or, unfused,
     loss_seed writing U and the adjoint reading it)."""
 
-    def __init__(self, W, H, S, r, N, seed, frame=0, fp16_features=False):
+    def __init__(self, W, H, S, r, N, seed, frame=0, fp16_features=False, tune=True):
         import torch
 
         from paper_2402_08273_amd import _abi, ops
@@ -136,9 +138,22 @@ class SingleChain:
         self.tabu = (_abi.RamltFrame * 1)(fu)
         self.lib = _abi.load()
         self._abi = _abi
+        self.schedule = 0
+        if tune:
+            # filter schedule (tile shape, window schedule) timed on this frame, untimed here
+            from paper_2402_08273_amd import tune as _tune
+
+            self.call0(self.lib.stats_accumulate, self.tabs)
+            self.schedule = _tune.tune_table(self.tabf, zero=[self.grad_lam, self.loss])
+            self.tabu[0].flags = self.tabf[0].flags
         # the adjoint's workspace (per-tile partial sums), allocated once
-        self.ws_t, self.ws_ptr, self.ws_bytes = ops.workspace_for([ff], _abi.OP_FILTER_BACKWARD, dev)
+        self.ws_t, self.ws_ptr, self.ws_bytes = ops.workspace_for([self.tabf[0]], _abi.OP_FILTER_BACKWARD, dev)
         torch.cuda.synchronize()
+
+    def call0(self, fn, tab):
+        st = fn(tab, None, 1, None, 0, self.sh)
+        if st != 0:
+            raise RuntimeError(self._abi.last_error())
 
     def call(self, fn, tab):
         st = fn(tab, None, 1, self.ws_ptr, self.ws_bytes, self.sh)
@@ -188,13 +203,14 @@ def time_loop(stream, fn, steps):
     return t0.elapsed_time(t1) / steps
 
 
-def measure_uhd(steps, warmup):
+def measure_uhd(steps, warmup, tune=True):
     """The 3840x2160, 256 spp, fp16-feature frame with a 15x15 window: fused fwd+bwd step."""
     import torch
 
+    from paper_2402_08273_amd.tune import schedule_name
     from synth.workloads import N_REGIONS, UHD
 
-    c = SingleChain(UHD.W, UHD.H, UHD.S, UHD.radius, N_REGIONS, UHD.seed, UHD.frame, UHD.fp16_features)
+    c = SingleChain(UHD.W, UHD.H, UHD.S, UHD.radius, N_REGIONS, UHD.seed, UHD.frame, UHD.fp16_features, tune)
     for _ in range(warmup):
         c.step()
     ms = time_loop(c.stream, c.step, steps)
@@ -208,18 +224,20 @@ def measure_uhd(steps, warmup):
         "fwd_mpx_s": round(c.P / (ms_fwd * 1e-3) / 1e6, 2),
         "algorithmic_bytes": b,
         "hbm_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "filter_schedule": schedule_name(c.tabf[0].flags),
     }
     del c
     torch.cuda.empty_cache()
     return res
 
 
-def measure_batch32(steps, warmup):
+def measure_batch32(steps, warmup, tune=True):
     """32 frames of uneven size and spp; each step is one HIP graph replay of one launch
     per operation over the whole batch (stats, filter, zeroing, fused loss seed + adjoint)."""
     import torch
 
     from paper_2402_08273_amd.batch import FrameBatch, FrameInput
+    from paper_2402_08273_amd.tune import schedule_name
     from synth import gpu as sgpu
     from synth import make_lambda
     from synth.workloads import LAMBDA_SEED, MAX_LAG, N_REGIONS, REFERENCE_SPP, batch32, sample_bytes
@@ -232,6 +250,9 @@ def measure_batch32(steps, warmup):
         ref = sgpu.make_reference(sp.W, sp.H, seed=sp.seed + 1000, frame=sp.frame, spp=REFERENCE_SPP)
         frames.append(FrameInput(rad, feat, ref, lam, radius=sp.radius, n_regions=N_REGIONS, max_lag=MAX_LAG))
     b = FrameBatch(frames)
+    if tune:
+        b.stats()
+        b.tune()
     b.capture(warmup=1)
     for _ in range(warmup):
         b.replay()
@@ -249,6 +270,7 @@ def measure_batch32(steps, warmup):
         "ms_per_step": round(ms, 4),
         "algorithmic_bytes": nbytes,
         "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "filter_schedule": schedule_name(b.table[0].flags),
     }
     del b, frames
     torch.cuda.empty_cache()
@@ -269,15 +291,16 @@ def main():
     import numpy as np
     import torch
 
+    from paper_2402_08273_amd.tune import schedule_name
     from synth.workloads import HD, MAX_LAG
 
     torch.cuda.set_device(0)
     if args.only:
         fn = measure_batch32 if args.only == "batched" else measure_uhd
-        print(json.dumps(fn(args.steps, args.warmup)), flush=True)
+        print(json.dumps(fn(args.steps, args.warmup, not args.no_tune)), flush=True)
         return
     W, H, S, r, N = args.width, args.height, args.spp, args.radius, args.regions
-    c = SingleChain(W, H, S, r, N, HD.seed, HD.frame)
+    c = SingleChain(W, H, S, r, N, HD.seed, HD.frame, tune=not args.no_tune)
     P = c.P
 
     for _ in range(args.warmup):
@@ -333,6 +356,7 @@ def main():
         "fwd_ms": round(fwd_only_ms, 4),
         "stats_ms": round(stats_ms, 4),
         "filter_forward_ms": round(fwd_ms - stats_ms, 4),
+        "filter_schedule": schedule_name(c.tabf[0].flags),
         "roofline": {
             "kernel": "stats_accumulate",
             "bound": "hbm",
@@ -356,8 +380,8 @@ def main():
 
     if not args.no_extra:
         print("measuring the 32-frame batch and the 4K frame", file=sys.stderr, flush=True)
-        result["batched"] = measure_batch32(args.steps, args.warmup)
-        result["uhd"] = measure_uhd(args.steps, args.warmup)
+        result["batched"] = measure_batch32(args.steps, args.warmup, not args.no_tune)
+        result["uhd"] = measure_uhd(args.steps, args.warmup, not args.no_tune)
 
     print(json.dumps(result), flush=True)
 

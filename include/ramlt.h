@@ -66,6 +66,17 @@ enum ramlt_op {
   RAMLT_OP_FILTER_BACKWARD = 3
 };
 
+/* Launch schedule in ramlt_frame.flags (results do not depend on it beyond fp32 rounding
+ * order; 0 selects the defaults). The autotuner (paper_2402_08273_amd/tune.py) picks them.
+ *   bits 0-1: output tile of the filter kernels (filter_forward, filter_backward);
+ *   bit 2:    RAMLT_SCHED_DIRECT: the filter gathers each (2r+1)^2 window directly instead of
+ *             a pass over rows then columns.
+ * Other bits must be 0. Frames of one batch with different tiles run in separate launches. */
+enum ramlt_tile { RAMLT_TILE_DEFAULT = 0, RAMLT_TILE_32X8 = 1, RAMLT_TILE_32X16 = 2, RAMLT_TILE_64X8 = 3 };
+#define RAMLT_TILE_MASK 3
+#define RAMLT_SCHED_DIRECT 4
+#define RAMLT_FLAGS_KNOWN (RAMLT_TILE_MASK | RAMLT_SCHED_DIRECT)
+
 #define RAMLT_N_RADIANCE 3
 #define RAMLT_N_FEATURES 7
 #define RAMLT_MAX_RADIUS 15
@@ -90,7 +101,7 @@ typedef struct ramlt_frame {
   const void *features;
   int64_t feat_stride_c, feat_stride_s, feat_stride_y;
   int32_t feat_dtype;     /* RAMLT_F32 or RAMLT_F16                                    */
-  int32_t flags;          /* reserved, must be 0                                        */
+  int32_t flags;          /* launch schedule, RAMLT_TILE_* | RAMLT_SCHED_*; 0 = defaults */
 
   /* stats, out: [3][H][W] each; lag_corr [3][K_L][H][W] or NULL                       */
   float *mean, *var, *tau, *lag_corr;

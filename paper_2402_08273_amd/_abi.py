@@ -22,6 +22,15 @@ RAMLT_EHIP = 4
 RAMLT_F32 = 0
 RAMLT_F16 = 1
 
+# ramlt_frame.flags: launch schedule (include/ramlt.h)
+RAMLT_TILE_DEFAULT = 0
+RAMLT_TILE_32X8 = 1
+RAMLT_TILE_32X16 = 2
+RAMLT_TILE_64X8 = 3
+RAMLT_TILE_MASK = 3
+RAMLT_SCHED_DIRECT = 4
+TILE_SHAPES = {RAMLT_TILE_32X8: (32, 8), RAMLT_TILE_32X16: (32, 16), RAMLT_TILE_64X8: (64, 8)}
+
 OP_STATS = 0
 OP_FILTER_FORWARD = 1
 OP_LOSS_SEED = 2

@@ -24,7 +24,7 @@ class FrameInput:
     (shared tensors are allowed) and the filter radius."""
 
     def __init__(self, radiance, features=None, reference=None, lam=None, radius=5, n_regions=20,
-                 lambda_min=LAMBDA_MIN_DEFAULT, max_lag=8, grad_lambda=None):
+                 lambda_min=LAMBDA_MIN_DEFAULT, max_lag=8, grad_lambda=None, schedule=0):
         self.radiance = radiance
         self.features = features
         self.reference = reference
@@ -34,6 +34,7 @@ class FrameInput:
         self.lambda_min = float(lambda_min)
         self.max_lag = int(max_lag)
         self.grad_lambda = grad_lambda
+        self.schedule = int(schedule)  # ramlt_frame.flags: filter tile shape / direct gather
 
 
 class FrameBatch:
@@ -91,6 +92,7 @@ class FrameBatch:
             d.mean, d.var, d.tau = o["mean"].data_ptr(), o["var"].data_ptr(), o["tau"].data_ptr()
             d.lambda_ = fi.lam.data_ptr()
             d.n_regions, d.radius, d.lambda_min = fi.n_regions, fi.radius, fi.lambda_min
+            d.flags = fi.schedule
             d.out = o["out"].data_ptr()
             if fi.reference is not None:
                 d.reference = fi.reference.data_ptr()
@@ -102,6 +104,11 @@ class FrameBatch:
         self._grads = grads
         self.n = len(descs)
         self.table = (RamltFrame * self.n)(*descs)
+        self._graph: Optional[torch.cuda.CUDAGraph] = None
+        self._upload()
+
+    def _upload(self):
+        """Device copy of the descriptor table and a workspace for every operation."""
         raw = bytes(ctypes.string_at(ctypes.addressof(self.table), ctypes.sizeof(self.table)))
         self.table_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
         ws = max(_abi.workspace_size(list(self.table), op) for op in
@@ -110,7 +117,20 @@ class FrameBatch:
         base = self.workspace.data_ptr()
         self.ws_ptr = (base + 255) // 256 * 256
         self.ws_bytes = max(ws, 256)
-        self._graph: Optional[torch.cuda.CUDAGraph] = None
+
+    def tune(self, **kw):
+        """Choose the filter's launch schedule (tile shape, window schedule) for this batch
+        by timing the candidates on its own frames (:mod:`.tune`, cached by shape), write it
+        into every descriptor and rebuild the device table and workspace. Needs the
+        statistics of the frames (run ``stats()`` first); clears the gradient and loss
+        accumulators. Call before ``capture()``."""
+        from . import tune as _tune
+
+        if self._graph is not None:
+            raise RuntimeError("tune() before capture()")
+        best = _tune.tune_table(self.table, device=self.device, zero=self._grads + [self.loss], **kw)
+        self._upload()
+        return best
 
     # ------------------------------------------------------------------ single ops
     def _call(self, name):

@@ -65,7 +65,7 @@ int check_common(const ramlt_frame *fh, const ramlt_frame *fd, int32_t n) {
       return fail(RAMLT_EUNSUPPORTED, "frame %d: W and H must be <= %d (got %d x %d)", i, RAMLT_MAX_SIDE, f.W, f.H);
     if ((long long)f.W * f.H > RAMLT_MAX_PLANE_ELEMS)
       return fail(RAMLT_EUNSUPPORTED, "frame %d: W*H exceeds %lld", i, (long long)RAMLT_MAX_PLANE_ELEMS);
-    if (f.flags != 0) return fail(RAMLT_EINVAL, "frame %d: flags must be 0", i);
+    if (f.flags & ~RAMLT_FLAGS_KNOWN) return fail(RAMLT_EINVAL, "frame %d: unknown flags 0x%x", i, (unsigned)f.flags);
   }
   return RAMLT_OK;
 }

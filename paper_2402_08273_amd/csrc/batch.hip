@@ -20,7 +20,7 @@ namespace {
 
 constexpr int kPlanBlock = 256;
 
-__device__ long long tiles_of(const ramlt_frame &f, int op, int radius_sel) {
+__device__ long long tiles_of(const ramlt_frame &f, int op, int group_sel) {
   const long long P = (long long)f.W * f.H;
   switch (op) {
     case RAMLT_OP_STATS: {
@@ -30,7 +30,7 @@ __device__ long long tiles_of(const ramlt_frame &f, int op, int radius_sel) {
     case RAMLT_OP_LOSS_SEED:
       return (P + kLossTilePixels - 1) / kLossTilePixels;
     default:
-      if (radius_sel >= 0 && f.radius != radius_sel) return 0;
+      if (group_sel >= 0 && filter_group(f) != group_sel) return 0;
       return filter_tile_count(f);
   }
 }
@@ -38,7 +38,7 @@ __device__ long long tiles_of(const ramlt_frame &f, int op, int radius_sel) {
 __device__ long long cost_of(const ramlt_frame &f, int op) { return op == RAMLT_OP_STATS ? f.S : 1; }
 
 __global__ __launch_bounds__(kPlanBlock) void plan_kernel(const ramlt_frame *__restrict__ frames, int n, int op,
-                                                          int radius_sel, BatchPlan *plan) {
+                                                          int group_sel, BatchPlan *plan) {
   int *order = plan_order(plan);
   long long *prefix = plan_prefix(plan, n);
   // rank = number of frames that go before frame i (higher cost, or equal cost and
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kPlanBlock) void plan_kernel(const ramlt_frame *__r
     long long acc = 0;
     for (int q = 0; q < n; ++q) {
       prefix[q] = acc;
-      acc += tiles_of(frames[order[q]], op, radius_sel);
+      acc += tiles_of(frames[order[q]], op, group_sel);
     }
     prefix[n] = acc;
     plan->n_frames = n;
@@ -72,9 +72,9 @@ __global__ __launch_bounds__(kPlanBlock) void plan_kernel(const ramlt_frame *__r
 
 }  // namespace
 
-hipError_t launch_plan(const ramlt_frame *frames_dev, int n, int op, int radius_sel, BatchPlan *plan,
+hipError_t launch_plan(const ramlt_frame *frames_dev, int n, int op, int group_sel, BatchPlan *plan,
                        hipStream_t st) {
-  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, st, frames_dev, n, op, radius_sel, plan);
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, st, frames_dev, n, op, group_sel, plan);
   return hipGetLastError();
 }
 
@@ -95,13 +95,15 @@ int resident_blocks(const void *kernel, int block) {
   return per_cu * cus;
 }
 
-int distinct_radii(const ramlt_frame *fh, int n, int *radii) {
-  bool seen[RAMLT_MAX_RADIUS + 1] = {};
-  for (int i = 0; i < n; ++i)
-    if (fh[i].radius >= 0 && fh[i].radius <= RAMLT_MAX_RADIUS) seen[fh[i].radius] = true;
+int distinct_groups(const ramlt_frame *fh, int n, int *groups) {
+  bool seen[kMaxFilterGroups] = {};
+  for (int i = 0; i < n; ++i) {
+    const int g = filter_group(fh[i]);
+    if (g >= 0 && g < kMaxFilterGroups) seen[g] = true;
+  }
   int k = 0;
-  for (int r = 0; r <= RAMLT_MAX_RADIUS; ++r)
-    if (seen[r]) radii[k++] = r;
+  for (int g = 0; g < kMaxFilterGroups; ++g)
+    if (seen[g]) groups[k++] = g;
   return k;
 }
 

@@ -10,11 +10,29 @@
 
 namespace ramlt {
 
-// Work units of the batched launches (the planner gives frames whose radius differs from
-// its radius_sel no filter tiles; radius_sel < 0 selects all).
+// Work units of the batched launches (the planner gives frames whose filter_group differs
+// from its group_sel no filter tiles; group_sel < 0 selects all).
 constexpr int kStatsTilePixels = 256;
-constexpr int kFilterTileW = 32;
-constexpr int kFilterTileH = 8;
+
+// Filter output tiles, by RAMLT_TILE_* kind (the default is 32 x 8).
+struct TileWH {
+  int w, h;
+};
+constexpr TileWH kTileShapes[4] = {{32, 8}, {32, 8}, {32, 16}, {64, 8}};
+
+__host__ __device__ constexpr int tile_kind(int32_t flags) {
+  return (flags & RAMLT_TILE_MASK) == RAMLT_TILE_DEFAULT ? RAMLT_TILE_32X8 : (flags & RAMLT_TILE_MASK);
+}
+__host__ __device__ constexpr int tile_w(int kind) { return kind == RAMLT_TILE_64X8 ? 64 : 32; }
+__host__ __device__ constexpr int tile_h(int kind) { return kind == RAMLT_TILE_32X16 ? 16 : 8; }
+static_assert(tile_w(RAMLT_TILE_64X8) == kTileShapes[RAMLT_TILE_64X8].w &&
+                  tile_h(RAMLT_TILE_32X16) == kTileShapes[RAMLT_TILE_32X16].h &&
+                  tile_w(RAMLT_TILE_32X8) == kTileShapes[RAMLT_TILE_32X8].w &&
+                  tile_h(RAMLT_TILE_32X8) == kTileShapes[RAMLT_TILE_32X8].h,
+              "tile table and accessors agree");
+
+// Batched filter launches group frames by (radius, tile kind).
+__host__ __device__ constexpr int filter_group(const ramlt_frame &f) { return f.radius + 16 * tile_kind(f.flags); }
 constexpr int kLossTilePixels = 1024;
 
 // 256-pixel statistics tiles per batched work unit: enough that a unit reads >= 64
@@ -25,8 +43,8 @@ __host__ __device__ inline int stats_unit_tiles(int S) {
 }
 
 // Filter tiling, shared by the filter kernels and the batch planner. Output tiles are at
-// most kFilterTileW x kFilterTileH; when regions are >= 16 px wide and >= 4 px tall the
-// tiles are laid out inside each region column / row (some may be empty).
+// most tile_w x tile_h of the frame's tile kind; when regions are >= 16 px wide and >= 4 px
+// tall the tiles are laid out inside each region column / row (some may be empty).
 
 // First coordinate (of n) whose cell floor((2c + 1) N / (2n)) is >= k. Every region is
 // at most ceil(n / N) wide. 32-bit arithmetic: n <= 65536 and N <= 4096 (validated).
@@ -56,7 +74,9 @@ __host__ __device__ inline long long filter_tile_count(const ramlt_frame &f) {
       f.n_regions > RAMLT_MAX_REGIONS)
     return 0;
   const bool al = aligned_tiling(f);
-  return (long long)tiles_along(f.W, f.n_regions, kFilterTileW, al) * tiles_along(f.H, f.n_regions, kFilterTileH, al);
+  const int kind = tile_kind(f.flags);
+  return (long long)tiles_along(f.W, f.n_regions, tile_w(kind), al) *
+         tiles_along(f.H, f.n_regions, tile_h(kind), al);
 }
 
 // Division by a per-frame constant with one multiply: for 1 <= d < 2^31 and
@@ -120,9 +140,10 @@ __host__ __device__ inline TileGeom make_geom(const ramlt_frame &f) {
   g.H = f.H;
   g.N = f.n_regions;
   g.aligned = aligned_tiling(f) ? 1 : 0;
-  g.ntx = tiles_along(f.W, f.n_regions, kFilterTileW, g.aligned);
-  g.tpx = g.aligned ? tiles_per_region(f.W, f.n_regions, kFilterTileW) : 1;
-  g.tpy = g.aligned ? tiles_per_region(f.H, f.n_regions, kFilterTileH) : 1;
+  const int kind = tile_kind(f.flags);
+  g.ntx = tiles_along(f.W, f.n_regions, tile_w(kind), g.aligned);
+  g.tpx = g.aligned ? tiles_per_region(f.W, f.n_regions, tile_w(kind)) : 1;
+  g.tpy = g.aligned ? tiles_per_region(f.H, f.n_regions, tile_h(kind)) : 1;
   g.d_ntx = make_fastdiv((uint32_t)g.ntx);
   g.d_tpx = make_fastdiv((uint32_t)g.tpx);
   g.d_tpy = make_fastdiv((uint32_t)g.tpy);
@@ -139,14 +160,16 @@ __host__ __device__ inline TileGeom *plan_geom(BatchPlan *p, int n_frames) {
 }
 
 // Enqueue the plan kernel: fills plan (order by cost, tile prefix sums, tile geometry).
-hipError_t launch_plan(const ramlt_frame *frames_dev, int n, int op, int radius_sel, BatchPlan *plan,
+hipError_t launch_plan(const ramlt_frame *frames_dev, int n, int op, int group_sel, BatchPlan *plan,
                        hipStream_t st);
 
 // Workgroups of `kernel` (with `block` threads) that fit on the current device at once:
 // occupancy per CU times the CU count (cached per kernel and device).
 int resident_blocks(const void *kernel, int block);
 
-// Distinct radii of a batch, ascending; returns their count (<= RAMLT_MAX_RADIUS + 1).
-int distinct_radii(const ramlt_frame *fh, int n, int *radii);
+// Distinct filter_group values of a batch, ascending; returns their count (at most
+// kMaxFilterGroups).
+constexpr int kMaxFilterGroups = 16 * 4;
+int distinct_groups(const ramlt_frame *fh, int n, int *groups);
 
 }  // namespace ramlt

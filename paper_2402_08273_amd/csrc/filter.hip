@@ -1,770 +1,25 @@
-// Regional reconstruction filter (forward), MSE loss seed, and the filter's adjoint.
-//
-// The filter is the pixel reconstruction filter h_j of the path integral (Sec. 3.1),
-// read as a normalised Gaussian over the (2R+1)^2 window clipped at the image border,
-// whose width sigma_k = sqrt(exp(lambda_k)) (Sec. 5.3) comes from the screen-grid region
-// of the output pixel (Sec. 5.2, Sec. 6.1).
-//
-// Tiling. Output tiles are at most 32 x 8 pixels and, when the regions are large enough
-// (>= 16 px wide and >= 4 px tall), never straddle a region boundary: tile columns and
-// rows are laid out inside each region column / row. Every output pixel of such a tile
-// shares one sigma, so the forward filter and the lambda gather are separable (a pass
-// over rows, then over columns) and the 1-D weights w(d) = exp(-d^2 / (2 sigma^2)) are
-// computed once per thread. Smaller regions use plain 32 x 8 tiles and a direct (2R+1)^2
-// gather with per-pixel weights.
-//
-// The tile plus an R-pixel halo of per-pixel values is staged in LDS as float4 (one
-// 16-byte LDS read per tap). Out-of-image halo entries are zero, so clipped taps
-// contribute nothing and the normaliser D_j = (sum of in-image 1-D weights along x) *
-// (same along y) is formed in closed form. Sums are formed row by row, then over rows,
-// which keeps the fp32 rounding error near 2(2R+1) ulp.
-//
-// Adjoint. G_p = (1/S) sum_j U_j h_jp / D_j weights each SOURCE j with its own sigma.
-// Sources of a tile's window lie in at most three region columns (the tile's and its two
-// neighbours); G is accumulated as a sum over those columns of separable convolutions of
-// the masked field a_j = U_j / (S D_j), with row weights taken from each source row's
-// region. With the fused loss seed (reference given, grad_out NULL), U_j = 2 (out_j - R_j)
-// / (3P) is formed on the fly and the loss is accumulated per tile in fp64.
-#include <type_traits>
-
-#include "batch.hpp"
-#include "common.hpp"
+// Launches of the regional reconstruction filter, its adjoint and the MSE loss seed, for
+// one frame or a batch (kernels: filter_kernels.hpp); the adjoint's fixed-order finalize
+// and the standalone loss-seed kernels.
+#include "filter_kernels.hpp"
 #include "launch.hpp"
 
 namespace ramlt {
 
 namespace {
 
-constexpr int kTX = kFilterTileW;
-constexpr int kTY = kFilterTileH;
-constexpr int kFilterBlock = kTX * kTY;
-constexpr float kLog2e = 1.4426950408889634f;
-constexpr long long kMaxBatchGrid = 1LL << 22;  // workgroups of one loss-seed launch
-
-// ------------------------------------------------------------------------ tiling
-// All index arithmetic below divides by per-frame constants through FastDiv (TileGeom);
-// a divide instruction sequence per division was the largest share of these kernels'
-// scalar work.
-struct Rect {
-  int x0, y0, x1, y1;  // outputs [x0, x1) x [y0, y1)
-  int kx, ky;          // the tile's region (aligned tiling), else -1
-};
-
-__device__ __forceinline__ int cell_x(int x, const TileGeom &g) {
-  return (int)fast_div((uint32_t)(2 * x + 1) * (uint32_t)g.N, g.d_2W);
-}
-__device__ __forceinline__ int cell_y(int y, const TileGeom &g) {
-  return (int)fast_div((uint32_t)(2 * y + 1) * (uint32_t)g.N, g.d_2H);
-}
-__device__ __forceinline__ int region_at(const TileGeom &g, int x, int y) { return cell_y(y, g) * g.N + cell_x(x, g); }
-
-// First coordinate (of n) in region column / row k (the same as region_start).
-__device__ __forceinline__ int region_begin(const TileGeom &g, int k, int n) {
-  if (k <= 0) return 0;
-  if (k >= g.N) return n;
-  const int num = 2 * k * n - g.N;
-  return num <= 0 ? 0 : min((int)fast_div((uint32_t)num + 2u * (uint32_t)g.N - 1u, g.d_2N), n);
-}
-
-// Output rectangle of tile t (possibly empty when aligned). Tile t < 2^31.
-__device__ __forceinline__ Rect tile_rect(const TileGeom &g, long long t) {
-  const uint32_t tt = (uint32_t)t;
-  const uint32_t tr = fast_div(tt, g.d_ntx);
-  const uint32_t tc = tt - tr * (uint32_t)g.ntx;
-  Rect r;
-  if (g.aligned) {
-    const int kx = (int)fast_div(tc, g.d_tpx), i = (int)tc - kx * g.tpx;
-    const int ky = (int)fast_div(tr, g.d_tpy), j = (int)tr - ky * g.tpy;
-    const int bx = region_begin(g, kx + 1, g.W), by = region_begin(g, ky + 1, g.H);
-    r.x0 = min(region_begin(g, kx, g.W) + i * kTX, bx);
-    r.x1 = min(bx, r.x0 + kTX);
-    r.y0 = min(region_begin(g, ky, g.H) + j * kTY, by);
-    r.y1 = min(by, r.y0 + kTY);
-    r.kx = kx;
-    r.ky = ky;
-  } else {
-    r.x0 = (int)tc * kTX;
-    r.x1 = min(g.W, r.x0 + kTX);
-    r.y0 = (int)tr * kTY;
-    r.y1 = min(g.H, r.y0 + kTY);
-    r.kx = r.ky = -1;
-  }
-  return r;
-}
-
-// Region of the tile's first pixel (clamped into the image: an empty tile of an aligned
-// tiling may start at x0 == W or y0 == H), and whether all its pixels share it.
-__device__ __forceinline__ int tile_region(const TileGeom &g, const Rect &r) {
-  if (r.kx >= 0) return r.ky * g.N + r.kx;
-  return region_at(g, min(r.x0, g.W - 1), min(r.y0, g.H - 1));
-}
-
-__device__ __forceinline__ bool tile_uniform(const TileGeom &g, const Rect &r) {
-  return r.kx >= 0 || region_at(g, r.x0, r.y0) == region_at(g, r.x1 - 1, r.y1 - 1);
-}
-
-// ------------------------------------------------------------------------ weights
-template <int R>
-__device__ __forceinline__ void gauss_weights(float beta, float (&w)[R + 1]) {
-  w[0] = 1.0f;
-#pragma unroll
-  for (int d = 1; d <= R; ++d) w[d] = expf(-(float)(d * d) * beta);
-}
-
-// Sum over the in-image offsets d in [-R, R] around coordinate c (0 <= c < n) of
-// w[|d|] (MOM = 0) or w[|d|] d^2 (MOM = 2).
-template <int R, int MOM>
-__device__ __forceinline__ float clipped_sum(const float (&w)[R + 1], int c, int n) {
-  float s = 0.0f;
-#pragma unroll
-  for (int d = -R; d <= R; ++d) {
-    const int a = d < 0 ? -d : d;
-    const float t = MOM == 0 ? w[a] : w[a] * (float)(a * a);
-    s += (c + d >= 0 && c + d < n) ? t : 0.0f;
-  }
-  return s;
-}
-
-// Halo items per thread: the (kTX + 2R) x (kTY + 2R) halo tile over the workgroup.
-template <int R>
-constexpr int halo_iters() {
-  return ((kTX + 2 * R) * (kTY + 2 * R) + kFilterBlock - 1) / kFilterBlock;
-}
-
-// Stage a float4 per halo pixel of the tile at (x0, y0): value(q) at the pixel's offset q
-// inside the image, zero outside. All of a thread's loads are issued before the first LDS
-// store (addresses are clamped into the image, so every load is in bounds), so the
-// workgroup waits for one memory round trip instead of one per item.
-template <int R, typename F>
-__device__ __forceinline__ void stage_halo(const ramlt_frame &f, int x0, int y0, float4 *lds, F value) {
-  constexpr int HX = kTX + 2 * R;
-  constexpr int HY = kTY + 2 * R;
-  constexpr int NIT = halo_iters<R>();
-  float4 v[NIT];
-  bool ok[NIT];
-#pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int i = threadIdx.x + it * kFilterBlock;
-    const int hy = i / HX;
-    const int hx = i - hy * HX;
-    const int gx = x0 - R + hx;
-    const int gy = y0 - R + hy;
-    ok[it] = i < HX * HY && gx >= 0 && gx < f.W && gy >= 0 && gy < f.H;
-    const int cx = min(max(gx, 0), f.W - 1);
-    const int cy = min(max(gy, 0), f.H - 1);
-    v[it] = value((long long)cy * f.W + cx);
-  }
-#pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int i = threadIdx.x + it * kFilterBlock;
-    if (i < HX * HY) lds[i] = ok[it] ? v[it] : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-}
-
-__device__ __forceinline__ float4 load3(const float *p, long long P, long long o) {
-  return make_float4(p[o], p[P + o], p[2 * P + o], 0.f);
-}
-
-// ------------------------------------------------------------------------ forward
-// 1-D normaliser along an axis: the full window sum Z = sum_{|d|<=R} w(|d|) away from the
-// border, the clipped sum within R of it.
-template <int R, int MOM>
-__device__ __forceinline__ float axis_sum(const float (&w)[R + 1], float full, int c, int n) {
-  return (c >= R && c + R < n) ? full : clipped_sum<R, MOM>(w, c, n);
-}
-
-template <int R>
-__device__ __forceinline__ float window_sum(const float (&w)[R + 1]) {
-  float z = 0.f;
-#pragma unroll
-  for (int d = R; d >= 1; --d) z += w[d];
-  return 1.0f + 2.0f * z;
-}
-
-template <int R>
-__device__ __forceinline__ float window_moment2(const float (&w)[R + 1]) {
-  float z = 0.f;
-#pragma unroll
-  for (int d = R; d >= 1; --d) z += w[d] * (float)(d * d);
-  return 2.0f * z;
-}
-
-// Halo values of one tile held in registers between their loads and their LDS stores, so
-// that a workgroup loads the next tile's halo while it computes the current one.
-template <int R>
-struct Halo {
-  float4 v[halo_iters<R>()];
-};
-
-// Issue the loads of value(q) for every halo pixel of the tile at (x0, y0) (addresses
-// clamped into the image, so every load is in bounds).
-template <int R, typename F>
-__device__ __forceinline__ void halo_load(const ramlt_frame &f, int x0, int y0, Halo<R> &h, F value) {
-  constexpr int HX = kTX + 2 * R;
-#pragma unroll
-  for (int it = 0; it < halo_iters<R>(); ++it) {
-    const int i = threadIdx.x + it * kFilterBlock;
-    const int hy = i / HX;
-    const int hx = i - hy * HX;
-    const int cx = min(max(x0 - R + hx, 0), f.W - 1);
-    const int cy = min(max(y0 - R + hy, 0), f.H - 1);
-    h.v[it] = value((long long)cy * f.W + cx);
-  }
-}
-
-// Store loaded halo values to LDS, zero for pixels outside the image.
-template <int R>
-__device__ __forceinline__ void halo_store(const ramlt_frame &f, int x0, int y0, const Halo<R> &h, float4 *lds) {
-  constexpr int HX = kTX + 2 * R;
-  constexpr int HY = kTY + 2 * R;
-#pragma unroll
-  for (int it = 0; it < halo_iters<R>(); ++it) {
-    const int i = threadIdx.x + it * kFilterBlock;
-    const int hy = i / HX;
-    const int hx = i - hy * HX;
-    const int gx = x0 - R + hx;
-    const int gy = y0 - R + hy;
-    const bool in = gx >= 0 && gx < f.W && gy >= 0 && gy < f.H;
-    if (i < HX * HY) lds[i] = in ? h.v[it] : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-}
-
-template <int R>
-struct FwdLds {
-  float4 stage[(kTX + 2 * R) * (kTY + 2 * R)];
-  float4 hb1[(kTY + 2 * R) * kTX];
-  float wtab[R + 1];
-};
-
-// The filter of one tile whose mean halo is in LDS (and, for a tile in one region, the
-// weights w(d) in wtab).
-template <int R>
-__device__ __forceinline__ void forward_compute(const ramlt_frame &f, const TileGeom &g, const Rect &r, bool uniform,
-                                                FwdLds<R> &L) {
-  constexpr int HX = kTX + 2 * R;
-  constexpr int HY = kTY + 2 * R;
-  float4 *stage = L.stage, *hbuf = L.hb1;
-  const long long P = (long long)f.W * f.H;
-  const int tx = threadIdx.x % kTX;
-  const int ty = threadIdx.x / kTX;
-  const int x = r.x0 + tx;
-  const int y = r.y0 + ty;
-  const bool inside = x < r.x1 && y < r.y1;
-  if (uniform) {
-    // one sigma for the whole tile: rows, then columns
-    float w[R + 1];
-#pragma unroll
-    for (int d = 0; d <= R; ++d) w[d] = L.wtab[d];
-    for (int i = threadIdx.x; i < HY * kTX; i += kFilterBlock) {
-      const int hy = i / kTX;
-      const int hx = i - hy * kTX;
-      const float4 *row = stage + hy * HX + hx + R;
-      float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-      for (int dx = -R; dx <= R; ++dx) {
-        const float4 m = row[dx];
-        const float ww = w[dx < 0 ? -dx : dx];
-        a.x = fmaf(ww, m.x, a.x);
-        a.y = fmaf(ww, m.y, a.y);
-        a.z = fmaf(ww, m.z, a.z);
-      }
-      hbuf[i] = a;
-    }
-    __syncthreads();
-    if (inside) {
-      float ax = 0.f, ay = 0.f, az = 0.f;
-#pragma unroll
-      for (int dy = -R; dy <= R; ++dy) {
-        const float4 h = hbuf[(ty + R + dy) * kTX + tx];
-        const float wy = w[dy < 0 ? -dy : dy];
-        ax = fmaf(wy, h.x, ax);
-        ay = fmaf(wy, h.y, ay);
-        az = fmaf(wy, h.z, az);
-      }
-      const float Z = window_sum<R>(w);
-      const float D = axis_sum<R, 0>(w, Z, x, f.W) * axis_sum<R, 0>(w, Z, y, f.H);
-      const long long o = (long long)y * f.W + x;
-      f.out[o] = ax / D;
-      f.out[P + o] = ay / D;
-      f.out[2 * P + o] = az / D;
-    }
-  } else if (inside) {
-    // per-pixel sigma: direct (2R+1)^2 gather
-    const int k = region_at(g, x, y);
-    const float beta = half_inv_var(f.lambda[k], f.lambda_min);
-    float w[R + 1];
-    gauss_weights<R>(beta, w);
-    float ax = 0.f, ay = 0.f, az = 0.f;
-#pragma unroll
-    for (int dy = -R; dy <= R; ++dy) {
-      const float4 *row = stage + (ty + R + dy) * HX + tx + R;
-      float rx = 0.f, ry = 0.f, rz = 0.f;
-#pragma unroll
-      for (int dx = -R; dx <= R; ++dx) {
-        const float4 m = row[dx];
-        const float ww = w[dx < 0 ? -dx : dx];
-        rx = fmaf(ww, m.x, rx);
-        ry = fmaf(ww, m.y, ry);
-        rz = fmaf(ww, m.z, rz);
-      }
-      const float wy = w[dy < 0 ? -dy : dy];
-      ax = fmaf(wy, rx, ax);
-      ay = fmaf(wy, ry, ay);
-      az = fmaf(wy, rz, az);
-    }
-    const float D = clipped_sum<R, 0>(w, x, f.W) * clipped_sum<R, 0>(w, y, f.H);
-    const long long o = (long long)y * f.W + x;
-    f.out[o] = ax / D;
-    f.out[P + o] = ay / D;
-    f.out[2 * P + o] = az / D;
-  }
-}
-
-// ------------------------------------------------------------------------ loss seed
-constexpr int kLossBlock = 256;
-
-__device__ __forceinline__ double block_sum(double v, double *red) {
-  v = wave_sum(v);
-  const int w = threadIdx.x / kWave;
-  if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) s += red[i];
-  __syncthreads();
-  return s;
-}
-
-// grad_out and the loss for pixels [p0, p0 + npix) of a frame (all three planes).
-__device__ __forceinline__ void loss_range(const ramlt_frame &f, long long p0, long long npix, double *red) {
-  const long long P = (long long)f.W * f.H;
-  const float scale = (float)(2.0 / (3.0 * (double)P));
-  double acc = 0.0;
-  for (long long i = threadIdx.x; i < npix; i += kLossBlock) {
-    const long long o = p0 + i;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float d = f.out[c * P + o] - f.reference[c * P + o];
-      f.grad_out[c * P + o] = d * scale;
-      acc = fma((double)d, (double)d, acc);
-    }
-  }
-  if (f.loss) {
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) unsafeAtomicAdd(f.loss, s / (3.0 * (double)P));
-  }
-}
-
-// ------------------------------------------------------------------------ backward
-// Segmented wave reduction keyed by region, then one float atomic per (wave, region).
-__device__ __forceinline__ void reduce_lambda(float *grad_lambda, int key, float contrib) {
-  const int lane = threadIdx.x & (kWave - 1);
-  for (;;) {
-    const unsigned long long pending = __ballot(key >= 0);
-    if (pending == 0ULL) break;
-    const int lead = __ffsll((long long)pending) - 1;
-    const int kk = __shfl(key, lead, kWave);
-    float v = (key == kk) ? contrib : 0.f;
-    v = wave_sum(v);
-    if (lane == lead) unsafeAtomicAdd(grad_lambda + kk, v);
-    if (key == kk) key = -1;
-  }
-}
-
-template <int R>
-struct BwdLds {
-  static constexpr int HX = kTX + 2 * R;
-  static constexpr int HY = kTY + 2 * R;
-  static constexpr int RS = R > 0 ? R : 1;                              // strip width
-  static constexpr int HB2 = HY * (kTX > 4 * RS ? kTX : 4 * RS);        // hb2 also holds the strips
-  float4 stage[HX * HY];
-  float4 hb1[HY * kTX];
-  float4 hb2[HB2];
-  float tab[9 * (R + 1)];
-  float ztab[9];
-  int rows[HY];  // region row of each halo row, relative to the first (separable path)
-  int cols[HX];  // same for halo columns
-  double red[kFilterBlock / kWave];
-};
-
-// Per-tile adjoint.
-//
-// Transpose gather (separable path, region-aligned tiles): the tile's outputs lie in one
-// region column [rs, re). Sources of the window lie in that column ("own"), or within R
-// columns to its left or right (the neighbouring region columns). G is
-//   own pass:  rows-then-columns convolution of the own sources (neighbour sources zeroed),
-//              with each source row's weights (its region row may differ from the tile's);
-//   strips:    the <= R neighbour columns on each side, for the <= R output columns they
-//              reach, with the neighbour region's weights.
-// Lambda gather (all tiles of a region share sigma): rows-then-columns sums of mean and
-// mean * dx^2. Per-tile partial sums of dL/dlambda and of the loss go to lam_part /
-// loss_part[slot] when given (a fixed-order finalize kernel adds them up), else atomics.
-template <int R>
-__device__ __forceinline__ void backward_tile(const ramlt_frame &f, const TileGeom &g, const Rect &r, long long slot,
-                                              float *lam_part,
-                                              double *loss_part, BwdLds<R> &L) {
-  constexpr int HX = BwdLds<R>::HX;
-  constexpr int HY = BwdLds<R>::HY;
-  constexpr int RS = BwdLds<R>::RS;
-  float4 *stage = L.stage, *hb1 = L.hb1, *hb2 = L.hb2;
-  float *tab = L.tab, *ztab = L.ztab;
-  int *rows = L.rows, *cols = L.cols;
-  const int W = f.W, H = f.H, N = f.n_regions;
-  const long long P = (long long)W * H;
-  const bool fused = f.grad_out == nullptr;
-  const float useed = (float)(2.0 / (3.0 * (double)P));
-  const float invS = 1.0f / (float)f.S;
-  const int tx = threadIdx.x % kTX;
-  const int ty = threadIdx.x / kTX;
-  const int x = r.x0 + tx;
-  const int y = r.y0 + ty;
-  const bool inside = x < r.x1 && y < r.y1;
-  const long long o = (long long)y * W + x;
-
-  // Region columns / rows reachable from the tile's window.
-  const int gx_lo = max(r.x0 - R, 0), gx_hi = min(r.x1 + R, W) - 1;
-  const int gy_lo = max(r.y0 - R, 0), gy_hi = min(r.y1 + R, H) - 1;
-  const int kx_lo = cell_x(gx_lo, g), kx_hi = cell_x(gx_hi, g);
-  const int ky_lo = cell_y(gy_lo, g), nsy = cell_y(gy_hi, g) - ky_lo + 1;
-  const int kx_own = r.kx >= 0 ? r.kx : cell_x(r.x0, g);
-  const int k0 = tile_region(g, r);
-  const bool uniform = tile_uniform(g, r);
-  // block-uniform: separable gather when the outputs share a region column and only one
-  // neighbour column lies within R on each side
-  const bool sep = uniform && kx_lo >= kx_own - 1 && kx_hi <= kx_own + 1 && nsy <= 3;
-  const int so = kx_own - kx_lo;  // own slot among the (<= 3) region columns
-  const int rs = region_begin(g, kx_own, W), re = region_begin(g, kx_own + 1, W);
-  const int nL = sep ? rs - gx_lo : 0;          // left strip width (<= R)
-  const int nR = sep ? gx_hi + 1 - re : 0;      // right strip width (<= R)
-  const int mL = nL > 0 ? min(r.x1, rs + R) - r.x0 : 0;  // outputs the left strip reaches
-  const int xR0 = max(r.x0, re - R);                      // first output the right strip reaches
-  const int mR = nR > 0 ? r.x1 - xR0 : 0;
-  float4 *lst = hb2, *rst = hb2 + HY * RS, *hbl = hb2 + 2 * HY * RS, *hbr = hb2 + 3 * HY * RS;
-
-  // U_j of an in-image pixel (given, or from the fused MSE seed)
-  auto U_at = [&](long long q) -> float4 {
-    if (fused) {
-      return make_float4(useed * (f.out[q] - f.reference[q]), useed * (f.out[P + q] - f.reference[P + q]),
-                         useed * (f.out[2 * P + q] - f.reference[2 * P + q]), 0.f);
-    }
-    return load3(f.grad_out, P, q);
-  };
-
-  // all loads of U first (clamped, in-bounds addresses; in flight while the tables are
-  // built), then the per-item arithmetic
-  constexpr int NIT = halo_iters<R>();
-  float4 uv[NIT];
-#pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int i = threadIdx.x + it * kFilterBlock;
-    const int hy = i / HX;
-    const int hx = i - hy * HX;
-    const int cx = min(max(r.x0 - R + hx, 0), W - 1);
-    const int cy = min(max(r.y0 - R + hy, 0), H - 1);
-    uv[it] = U_at((long long)cy * W + cx);
-  }
-  if (sep) {
-    // weights and window sums of the (<= 3 x 3) regions around the tile; row slots
-    if (threadIdx.x < 9) {
-      const int sx = threadIdx.x % 3, sy = threadIdx.x / 3;
-      const int kx = min(kx_lo + sx, N - 1), ky = min(ky_lo + sy, N - 1);
-      const float beta = half_inv_var(f.lambda[ky * N + kx], f.lambda_min);
-      float w[R + 1];
-      gauss_weights<R>(beta, w);
-#pragma unroll
-      for (int d = 0; d <= R; ++d) tab[threadIdx.x * (R + 1) + d] = w[d];
-      ztab[threadIdx.x] = window_sum<R>(w);
-    }
-    for (int i = threadIdx.x; i < HY; i += kFilterBlock) {
-      const int gy = min(max(r.y0 - R + i, 0), H - 1);
-      rows[i] = cell_y(gy, g) - ky_lo;
-    }
-    for (int i = threadIdx.x; i < HX; i += kFilterBlock) {
-      const int gx = min(max(r.x0 - R + i, 0), W - 1);
-      cols[i] = cell_x(gx, g) - kx_lo;
-    }
-    __syncthreads();
-  }
-
-  // ---- stage a_j = U_j / (S D_j) over tile + halo: own-column sources in `stage`
-  // (others zero), neighbour columns in the strips; the direct path keeps every source with
-  // beta' = beta log2(e) in .w
-#pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int i = threadIdx.x + it * kFilterBlock;
-    if (i >= HX * HY) break;
-    const int hy = i / HX;
-    const int hx = i - hy * HX;
-    const int gx = r.x0 - R + hx;
-    const int gy = r.y0 - R + hy;
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-      float D, tag = 0.f;
-      if (sep) {
-        const int sl = rows[hy] * 3 + cols[hx];
-        const float z = ztab[sl];
-        float Dx = z, Dy = z;
-        if (gx < R || gx + R >= W || gy < R || gy + R >= H) {
-          float w[R + 1];
-#pragma unroll
-          for (int d = 0; d <= R; ++d) w[d] = tab[sl * (R + 1) + d];
-          Dx = axis_sum<R, 0>(w, z, gx, W);
-          Dy = axis_sum<R, 0>(w, z, gy, H);
-        }
-        D = Dx * Dy;
-      } else {
-        const float beta = half_inv_var(f.lambda[region_at(g, gx, gy)], f.lambda_min);
-        float w[R + 1];
-        gauss_weights<R>(beta, w);
-        D = clipped_sum<R, 0>(w, gx, W) * clipped_sum<R, 0>(w, gy, H);
-        tag = beta * kLog2e;
-      }
-      const float s = invS / D;
-      const float4 u = uv[it];
-      a = make_float4(u.x * s, u.y * s, u.z * s, tag);
-    }
-    if (sep) {  // every strip entry is written, zero for rows outside the image
-      if (gx < rs) {
-        if (gx >= rs - nL) lst[hy * RS + (gx - (rs - nL))] = a;
-        a = make_float4(0.f, 0.f, 0.f, 0.f);
-      } else if (gx >= re) {
-        if (gx < re + nR) rst[hy * RS + (gx - re)] = a;
-        a = make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    }
-    stage[i] = a;
-  }
-  __syncthreads();
-
-  // ---- G_p = sum_e a_{p+e} h(e; sigma of p+e)
-  float gx_ = 0.f, gy_ = 0.f, gz_ = 0.f;
-  if (sep) {
-    // rows: own sources with the own column's weights for each source row
-    for (int i = threadIdx.x; i < HY * kTX; i += kFilterBlock) {
-      const int hy = i / kTX;
-      const int hx = i - hy * kTX;
-      const float *wt = tab + (rows[hy] * 3 + so) * (R + 1);
-      float w[R + 1];
-#pragma unroll
-      for (int d = 0; d <= R; ++d) w[d] = wt[d];
-      const float4 *src = stage + hy * HX + hx + R;
-      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-      for (int dx = -R; dx <= R; ++dx) {
-        const float4 v = src[dx];
-        const float ww = w[dx < 0 ? -dx : dx];
-        acc.x = fmaf(ww, v.x, acc.x);
-        acc.y = fmaf(ww, v.y, acc.y);
-        acc.z = fmaf(ww, v.z, acc.z);
-      }
-      hb1[i] = acc;
-    }
-    // rows: the strips, for the output columns they reach
-    const int nLitems = HY * mL, nRitems = HY * mR;
-    for (int i = threadIdx.x; i < nLitems + nRitems; i += kFilterBlock) {
-      const bool left = i < nLitems;
-      const int ii = left ? i : i - nLitems;
-      const int m = left ? mL : mR;
-      const int hy = ii / m;
-      const int c = ii - hy * m;
-      const float *wt = tab + (rows[hy] * 3 + (left ? so - 1 : so + 1)) * (R + 1);
-      const int xo = left ? r.x0 + c : xR0 + c;       // output column
-      const int s0 = left ? rs - nL : re;             // first strip column
-      const int ns = left ? nL : nR;
-      const float4 *strip = (left ? lst : rst) + hy * RS;
-      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-      for (int j = 0; j < RS; ++j) {
-        const int d = abs(s0 + j - xo);
-        if (j < ns && d <= R) {
-          const float4 v = strip[j];
-          const float ww = wt[d];
-          acc.x = fmaf(ww, v.x, acc.x);
-          acc.y = fmaf(ww, v.y, acc.y);
-          acc.z = fmaf(ww, v.z, acc.z);
-        }
-      }
-      (left ? hbl : hbr)[hy * RS + c] = acc;
-    }
-    __syncthreads();
-    if (inside) {
-#pragma unroll
-      for (int dy = -R; dy <= R; ++dy) {
-        const int hy = ty + R + dy;
-        const int ay = dy < 0 ? -dy : dy;
-        const int rb = rows[hy] * 3;
-        const float wy = tab[(rb + so) * (R + 1) + ay];
-        const float4 h = hb1[hy * kTX + tx];
-        gx_ = fmaf(wy, h.x, gx_);
-        gy_ = fmaf(wy, h.y, gy_);
-        gz_ = fmaf(wy, h.z, gz_);
-        if (x - r.x0 < mL) {
-          const float wl = tab[(rb + so - 1) * (R + 1) + ay];
-          const float4 hl = hbl[hy * RS + (x - r.x0)];
-          gx_ = fmaf(wl, hl.x, gx_);
-          gy_ = fmaf(wl, hl.y, gy_);
-          gz_ = fmaf(wl, hl.z, gz_);
-        }
-        if (mR > 0 && x >= xR0) {
-          const float wr = tab[(rb + so + 1) * (R + 1) + ay];
-          const float4 hr = hbr[hy * RS + (x - xR0)];
-          gx_ = fmaf(wr, hr.x, gx_);
-          gy_ = fmaf(wr, hr.y, gy_);
-          gz_ = fmaf(wr, hr.z, gz_);
-        }
-      }
-    }
-  } else if (inside) {
-#pragma unroll
-    for (int dy = -R; dy <= R; ++dy) {
-      const float4 *row = stage + (ty + R + dy) * HX + tx + R;
-#pragma unroll
-      for (int dx = -R; dx <= R; ++dx) {
-        const float4 a = row[dx];
-        const float h = __builtin_amdgcn_exp2f(-(float)(dx * dx + dy * dy) * a.w);
-        gx_ = fmaf(h, a.x, gx_);
-        gy_ = fmaf(h, a.y, gy_);
-        gz_ = fmaf(h, a.z, gz_);
-      }
-    }
-  }
-  if (inside) {
-    f.grad_radiance[o] = gx_;
-    f.grad_radiance[P + o] = gy_;
-    f.grad_radiance[2 * P + o] = gz_;
-  }
-
-  // ---- loss value of the tile's pixels (fused seed)
-  if (fused && f.loss) {
-    double acc = 0.0;
-    if (inside) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float d = f.out[c * P + o] - f.reference[c * P + o];
-        acc = fma((double)d, (double)d, acc);
-      }
-    }
-    const double s = block_sum(acc, L.red);
-    if (threadIdx.x == 0) {
-      if (loss_part)
-        loss_part[slot] = s;
-      else
-        unsafeAtomicAdd(f.loss, s / (3.0 * (double)P));
-    }
-  }
-
-  // ---- dL/dlambda_k(j) += beta_j sum_c U_jc (N2_jc - out_jc H2_j) / D_j
-  if (!f.grad_lambda) return;
-  __syncthreads();  // stage and hb2 are reused below
-  float4 *smu = stage;
-  stage_halo<R>(f, r.x0, r.y0, smu, [&](long long q) { return load3(f.mean, P, q); });
-  __syncthreads();
-  const int k_own = inside ? region_at(g, x, y) : k0;
-  const float lam = f.lambda[k_own];
-  const bool live = lam >= f.lambda_min;
-  const float beta = half_inv_var(lam, f.lambda_min);
-  float w[R + 1], wd2[R + 1];
-  if (sep) {
-    const int sl = (cell_y(r.y0, g) - ky_lo) * 3 + so;
-#pragma unroll
-    for (int d = 0; d <= R; ++d) w[d] = tab[sl * (R + 1) + d];
-  } else {
-    gauss_weights<R>(beta, w);
-  }
-#pragma unroll
-  for (int d = 0; d <= R; ++d) wd2[d] = w[d] * (float)(d * d);
-  float nx = 0.f, ny = 0.f, nz = 0.f;
-  if (uniform) {
-    if (live) {
-      for (int i = threadIdx.x; i < HY * kTX; i += kFilterBlock) {
-        const int hy = i / kTX;
-        const int hx = i - hy * kTX;
-        const float4 *row = smu + hy * HX + hx + R;
-        float4 a1 = make_float4(0.f, 0.f, 0.f, 0.f), a2 = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int dx = -R; dx <= R; ++dx) {
-          const float4 m = row[dx];
-          const int ax = dx < 0 ? -dx : dx;
-          a1.x = fmaf(w[ax], m.x, a1.x);
-          a1.y = fmaf(w[ax], m.y, a1.y);
-          a1.z = fmaf(w[ax], m.z, a1.z);
-          a2.x = fmaf(wd2[ax], m.x, a2.x);
-          a2.y = fmaf(wd2[ax], m.y, a2.y);
-          a2.z = fmaf(wd2[ax], m.z, a2.z);
-        }
-        hb1[i] = a1;
-        hb2[i] = a2;
-      }
-    }
-    __syncthreads();
-    if (inside && live) {
-#pragma unroll
-      for (int dy = -R; dy <= R; ++dy) {
-        const int ay = dy < 0 ? -dy : dy;
-        const float4 h1 = hb1[(ty + R + dy) * kTX + tx];
-        const float4 h2 = hb2[(ty + R + dy) * kTX + tx];
-        nx = fmaf(w[ay], h2.x, fmaf(wd2[ay], h1.x, nx));
-        ny = fmaf(w[ay], h2.y, fmaf(wd2[ay], h1.y, ny));
-        nz = fmaf(w[ay], h2.z, fmaf(wd2[ay], h1.z, nz));
-      }
-    }
-  } else if (inside && live) {
-#pragma unroll
-    for (int dy = -R; dy <= R; ++dy) {
-      const float4 *row = smu + (ty + R + dy) * HX + tx + R;
-      float r1x = 0.f, r1y = 0.f, r1z = 0.f, r2x = 0.f, r2y = 0.f, r2z = 0.f;
-#pragma unroll
-      for (int dx = -R; dx <= R; ++dx) {
-        const float4 m = row[dx];
-        const int ax = dx < 0 ? -dx : dx;
-        r1x = fmaf(w[ax], m.x, r1x);
-        r1y = fmaf(w[ax], m.y, r1y);
-        r1z = fmaf(w[ax], m.z, r1z);
-        r2x = fmaf(wd2[ax], m.x, r2x);
-        r2y = fmaf(wd2[ax], m.y, r2y);
-        r2z = fmaf(wd2[ax], m.z, r2z);
-      }
-      const int ay = dy < 0 ? -dy : dy;
-      nx = fmaf(w[ay], r2x, fmaf(wd2[ay], r1x, nx));
-      ny = fmaf(w[ay], r2y, fmaf(wd2[ay], r1y, ny));
-      nz = fmaf(w[ay], r2z, fmaf(wd2[ay], r1z, nz));
-    }
-  }
-  float contrib = 0.f;
-  if (inside && live) {
-    const float Z0 = window_sum<R>(w), Z2 = window_moment2<R>(w);
-    const float sx0 = axis_sum<R, 0>(w, Z0, x, W), sy0 = axis_sum<R, 0>(w, Z0, y, H);
-    const float sx2 = axis_sum<R, 2>(w, Z2, x, W), sy2 = axis_sum<R, 2>(w, Z2, y, H);
-    const float H2 = sx2 * sy0 + sx0 * sy2;
-    const float D = sx0 * sy0;
-    const float4 u = U_at(o);
-    const float t = u.x * (nx - f.out[o] * H2) + u.y * (ny - f.out[P + o] * H2) + u.z * (nz - f.out[2 * P + o] * H2);
-    contrib = beta * t / D;
-  }
-  if (uniform) {
-    // one region for the whole tile: block reduction, one partial (or atomic)
-    const double s = block_sum((double)contrib, L.red);
-    if (threadIdx.x == 0) {
-      if (lam_part && g.aligned)  // the finalize kernel reads region-aligned partials
-        lam_part[slot] = live ? (float)s : 0.f;
-      else if (live)
-        unsafeAtomicAdd(f.grad_lambda + k0, (float)s);
-    }
-  } else {
-    reduce_lambda(f.grad_lambda, inside ? k_own : -1, contrib);
-  }
-}
+using namespace filt;
 
 // Adds the per-tile partials in a fixed order. blockIdx.y = frame (its position q in a
 // batch plan, or the single frame); block x < kFinalizeLamBlocks(N) sums regions, one wave
 // per region (lane l takes the region's l-th, (l+64)-th, ... tile, then a butterfly sum);
 // the block after those sums the frame's loss partials. One atomic add per region and per
 // frame lands the result in grad_lambda / *loss.
-constexpr int kFinalizeWaves = kFilterBlock / kWave;
+constexpr int kFinalizeWaves = kFinalizeBlock / kWave;
 
 __host__ __device__ inline int finalize_lam_blocks(int N) { return (N * N + kFinalizeWaves - 1) / kFinalizeWaves; }
 
-__global__ __launch_bounds__(kFilterBlock) void backward_finalize_kernel(const ramlt_frame single,
+__global__ __launch_bounds__(kFinalizeBlock) void backward_finalize_kernel(const ramlt_frame single,
                                                                         const ramlt_frame *__restrict__ frames,
                                                                         BatchPlan *plan, const float *lam_part,
                                                                         const double *loss_part) {
@@ -775,21 +30,22 @@ __global__ __launch_bounds__(kFilterBlock) void backward_finalize_kernel(const r
     const int q = blockIdx.y;
     f = frames[plan_order(plan)[q]];
     const long long *pre = plan_prefix(plan, plan->n_frames);
-    if (pre[q + 1] == pre[q]) return;  // frame of another radius: not in this plan
+    if (pre[q + 1] == pre[q]) return;  // frame of another launch group: not in this plan
     base = pre[q];
   } else {
     f = single;
   }
   const int N = f.n_regions;
   const bool al = aligned_tiling(f);
-  const int ntx = tiles_along(f.W, N, kTX, al), nty = tiles_along(f.H, N, kTY, al);
+  const int tw = tile_w(tile_kind(f.flags)), th = tile_h(tile_kind(f.flags));
+  const int ntx = tiles_along(f.W, N, tw, al), nty = tiles_along(f.H, N, th, al);
   const int nlb = finalize_lam_blocks(N);
   if ((int)blockIdx.x < nlb) {
     if (!f.grad_lambda || !al) return;
     const int k = blockIdx.x * kFinalizeWaves + threadIdx.x / kWave;
     if (k >= N * N) return;  // wave-uniform
     const int lane = threadIdx.x & (kWave - 1);
-    const int tpx = tiles_per_region(f.W, N, kTX), tpy = tiles_per_region(f.H, N, kTY);
+    const int tpx = tiles_per_region(f.W, N, tw), tpy = tiles_per_region(f.H, N, th);
     const int ky = k / N, kx = k - ky * N;
     float v = 0.f;
     for (int l = lane; l < tpx * tpy; l += kWave) {
@@ -804,98 +60,15 @@ __global__ __launch_bounds__(kFilterBlock) void backward_finalize_kernel(const r
   const long long nt = (long long)ntx * nty;
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   long long t = threadIdx.x;
-  for (; t + 3 * kFilterBlock < nt; t += 4 * kFilterBlock) {
+  for (; t + 3 * kFinalizeBlock < nt; t += 4 * kFinalizeBlock) {
     acc0 += loss_part[base + t];
-    acc1 += loss_part[base + t + kFilterBlock];
-    acc2 += loss_part[base + t + 2 * kFilterBlock];
-    acc3 += loss_part[base + t + 3 * kFilterBlock];
+    acc1 += loss_part[base + t + kFinalizeBlock];
+    acc2 += loss_part[base + t + 2 * kFinalizeBlock];
+    acc3 += loss_part[base + t + 3 * kFinalizeBlock];
   }
-  for (; t < nt; t += kFilterBlock) acc0 += loss_part[base + t];
+  for (; t < nt; t += kFinalizeBlock) acc0 += loss_part[base + t];
   const double s = block_sum((acc0 + acc1) + (acc2 + acc3), red);
   if (threadIdx.x == 0) unsafeAtomicAdd(f.loss, s / (3.0 * (double)f.W * (double)f.H));
-}
-
-// ------------------------------------------------------------------------ kernels
-// XCD-aware order for single-frame grids: consecutive workgroup ids land on different
-// XCDs, so give each XCD a contiguous band of tiles (its halos overlap in that XCD's L2).
-__device__ __forceinline__ long long xcd_tile(unsigned b, unsigned nblocks) {
-  const unsigned per = (nblocks + 7) / 8;
-  return (long long)(b & 7) * per + (b >> 3);
-}
-
-// Frame, tiling and output rectangle of tile t: the single frame's tile t, or the planned
-// tile t of a batch.
-template <bool BATCH>
-__device__ __forceinline__ void fetch_tile(const ramlt_frame &single, const TileGeom &single_g,
-                                           const ramlt_frame *frames, BatchPlan *plan, long long t, ramlt_frame &f,
-                                           TileGeom &g, Rect &r) {
-  if constexpr (BATCH) {
-    int fi;
-    long long local;
-    plan_lookup(plan, (unsigned long long)t, &fi, &local);
-    f = frames[fi];
-    g = plan_geom(plan, plan->n_frames)[fi];
-    r = tile_rect(g, local);
-  } else {
-    f = single;
-    g = single_g;
-    r = tile_rect(g, t);
-  }
-}
-
-// Forward filter, one tile per workgroup: tile t0 + (the XCD-aware order of the workgroup)
-// of the single frame, or of a batch's plan. (A loop over several tiles per workgroup
-// kept more values live and cost occupancy; large launches are split by the host.)
-template <int R, bool BATCH>
-__global__ __launch_bounds__(kFilterBlock) void forward_kernel(const ramlt_frame single, const TileGeom single_g,
-                                                               const ramlt_frame *__restrict__ frames,
-                                                               BatchPlan *plan, long long ntiles, long long t0) {
-  __shared__ FwdLds<R> s;
-  const long long total = BATCH ? (long long)plan->total_tiles : ntiles;
-  const long long t = t0 + xcd_tile(blockIdx.x, gridDim.x);
-  if (t >= total) return;
-  ramlt_frame f;
-  TileGeom g;
-  Rect r;
-  fetch_tile<BATCH>(single, single_g, frames, plan, t, f, g, r);
-  if (r.x0 >= r.x1 || r.y0 >= r.y1) return;  // block-uniform
-  const bool uniform = tile_uniform(g, r);
-  Halo<R> h;
-  halo_load<R>(f, r.x0, r.y0, h, [&](long long q) { return load3(f.mean, (long long)f.W * f.H, q); });
-  if (uniform && threadIdx.x <= R) {
-    const float beta = half_inv_var(f.lambda[tile_region(g, r)], f.lambda_min);
-    s.wtab[threadIdx.x] = threadIdx.x == 0 ? 1.0f : expf(-(float)(threadIdx.x * threadIdx.x) * beta);
-  }
-  halo_store<R>(f, r.x0, r.y0, h, s.stage);
-  __syncthreads();
-  forward_compute<R>(f, g, r, uniform, s);
-}
-
-__device__ __forceinline__ void empty_tile_partials(long long slot, float *lam_part, double *loss_part) {
-  if (threadIdx.x == 0) {
-    if (lam_part) lam_part[slot] = 0.f;
-    if (loss_part) loss_part[slot] = 0.0;
-  }
-}
-
-// Adjoint, one tile per workgroup; per-tile partials go to slot t.
-template <int R, bool BATCH>
-__global__ __launch_bounds__(kFilterBlock) void backward_kernel(const ramlt_frame single, const TileGeom single_g,
-                                                                const ramlt_frame *__restrict__ frames,
-                                                                BatchPlan *plan, long long ntiles, long long t0,
-                                                                float *lam_part, double *loss_part) {
-  __shared__ BwdLds<R> s;
-  const long long total = BATCH ? (long long)plan->total_tiles : ntiles;
-  const long long t = t0 + xcd_tile(blockIdx.x, gridDim.x);
-  if (t >= total) return;
-  ramlt_frame f;
-  TileGeom g;
-  Rect r;
-  fetch_tile<BATCH>(single, single_g, frames, plan, t, f, g, r);
-  if (r.x0 < r.x1 && r.y0 < r.y1)  // block-uniform
-    backward_tile<R>(f, g, r, t, lam_part, loss_part, s);
-  else
-    empty_tile_partials(t, lam_part, loss_part);
 }
 
 __global__ __launch_bounds__(kLossBlock) void loss_seed_kernel(const ramlt_frame f) {
@@ -922,26 +95,19 @@ __global__ __launch_bounds__(kLossBlock) void loss_seed_batched_kernel(const ram
   }
 }
 
-using FwdKernel = void (*)(const ramlt_frame, const TileGeom, const ramlt_frame *, BatchPlan *, long long,
-                           long long);
-using BwdKernel = void (*)(const ramlt_frame, const TileGeom, const ramlt_frame *, BatchPlan *, long long, long long,
-                           float *, double *);
-
-template <int... Rs>
-struct KernelTables {
-  static constexpr int kCount = sizeof...(Rs);
-  static constexpr FwdKernel forward[kCount] = {forward_kernel<Rs, false>...};
-  static constexpr FwdKernel forward_batched[kCount] = {forward_kernel<Rs, true>...};
-  static constexpr BwdKernel backward[kCount] = {backward_kernel<Rs, false>...};
-  static constexpr BwdKernel backward_batched[kCount] = {backward_kernel<Rs, true>...};
-};
-
-using Tables = KernelTables<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15>;
+KindKernels kernels_of(int kind) {
+  switch (kind) {
+    case RAMLT_TILE_32X16: return kernels_32x16();
+    case RAMLT_TILE_64X8: return kernels_64x8();
+    default: return kernels_32x8();
+  }
+}
 
 long long filter_tiles(const ramlt_frame &f) { return filter_tile_count(f); }
 
-// Workspace of filter operations on a batch: per distinct radius one plan, then (backward)
-// the per-tile partials: lam float[T], loss double[T], T = tiles of all frames.
+// Workspace of filter operations on a batch: per launch group (radius, tile kind) one
+// plan, then (backward) the per-tile partials: lam float[T], loss double[T], T = tiles of
+// all frames.
 size_t partials_bytes(const ramlt_frame *fh, int n) {
   long long T = 0;
   for (int i = 0; i < n; ++i) T += filter_tiles(fh[i]);
@@ -954,11 +120,11 @@ size_t partials_bytes(const ramlt_frame *fh, int n) {
 constexpr long long kMaxTileGrid = 1LL << 22;
 
 template <typename K, typename... Args>
-hipError_t launch_tiles(K kernel, long long tiles, hipStream_t st, const ramlt_frame &single, const TileGeom &g,
-                        const ramlt_frame *fd, BatchPlan *plan, long long ntiles, Args... rest) {
+hipError_t launch_tiles(K kernel, int block, long long tiles, hipStream_t st, const ramlt_frame &single,
+                        const TileGeom &g, const ramlt_frame *fd, BatchPlan *plan, long long ntiles, Args... rest) {
   for (long long t0 = 0; t0 < tiles; t0 += kMaxTileGrid) {
     const unsigned grid = (unsigned)(((min(tiles - t0, kMaxTileGrid) + 7) / 8) * 8);
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kFilterBlock), 0, st, single, g, fd, plan, ntiles, t0, rest...);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, st, single, g, fd, plan, ntiles, t0, rest...);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -969,50 +135,53 @@ hipError_t launch_filter(bool bwd, const ramlt_frame *fh, const ramlt_frame *fd,
                          hipStream_t st) {
   if (n == 1) {
     const ramlt_frame &f = fh[0];
+    const KindKernels K = kernels_of(tile_kind(f.flags));
     const TileGeom g = make_geom(f);
     const long long nt = filter_tiles(f);
     if (!bwd)
-      return launch_tiles(Tables::forward[f.radius], nt, st, f, g, (const ramlt_frame *)nullptr,
+      return launch_tiles(K.forward[f.radius], K.block, nt, st, f, g, (const ramlt_frame *)nullptr,
                           (BatchPlan *)nullptr, nt);
     float *lam_part = (float *)ws;
     double *loss_part = (double *)((char *)ws + (((size_t)nt * sizeof(float) + 7) & ~(size_t)7));
-    hipError_t e = launch_tiles(Tables::backward[f.radius], nt, st, f, g, (const ramlt_frame *)nullptr,
+    hipError_t e = launch_tiles(K.backward[f.radius], K.block, nt, st, f, g, (const ramlt_frame *)nullptr,
                                 (BatchPlan *)nullptr, nt, lam_part, loss_part);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(backward_finalize_kernel, dim3(finalize_lam_blocks(f.n_regions) + 1), dim3(kFilterBlock), 0,
-                       st, f, (const ramlt_frame *)nullptr, (BatchPlan *)nullptr, lam_part, loss_part);
+    hipLaunchKernelGGL(backward_finalize_kernel, dim3(finalize_lam_blocks(f.n_regions) + 1), dim3(kFinalizeBlock),
+                       0, st, f, (const ramlt_frame *)nullptr, (BatchPlan *)nullptr, lam_part, loss_part);
     return hipGetLastError();
   }
-  int radii[RAMLT_MAX_RADIUS + 1];
-  const int nr = distinct_radii(fh, n, radii);
+  int groups[kMaxFilterGroups];
+  const int ng = distinct_groups(fh, n, groups);
   const size_t pb = plan_bytes(n);
   const size_t part = bwd ? partials_bytes(fh, n) : 0;
   long long T = 0;
   for (int i = 0; i < n; ++i) T += filter_tiles(fh[i]);
   const ramlt_frame none{};
   const TileGeom none_g{};
-  for (int g = 0; g < nr; ++g) {
-    char *base = (char *)ws + (size_t)g * (pb + part);
+  for (int q = 0; q < ng; ++q) {
+    const int radius = groups[q] % 16;
+    const KindKernels K = kernels_of(groups[q] / 16);
+    char *base = (char *)ws + (size_t)q * (pb + part);
     BatchPlan *plan = (BatchPlan *)base;
     float *lam_part = bwd ? (float *)(base + pb) : nullptr;
     double *loss_part = bwd ? (double *)(base + pb + (((size_t)T * sizeof(float) + 7) & ~(size_t)7)) : nullptr;
-    hipError_t e = launch_plan(fd, n, bwd ? RAMLT_OP_FILTER_BACKWARD : RAMLT_OP_FILTER_FORWARD, radii[g], plan, st);
+    hipError_t e = launch_plan(fd, n, bwd ? RAMLT_OP_FILTER_BACKWARD : RAMLT_OP_FILTER_FORWARD, groups[q], plan, st);
     if (e != hipSuccess) return e;
     long long tiles = 0;  // the planner counts the same tiles on the device
     for (int i = 0; i < n; ++i)
-      if (fh[i].radius == radii[g]) tiles += filter_tiles(fh[i]);
+      if (filter_group(fh[i]) == groups[q]) tiles += filter_tiles(fh[i]);
     if (tiles == 0) continue;
     if (!bwd) {
-      e = launch_tiles(Tables::forward_batched[radii[g]], tiles, st, none, none_g, fd, plan, 0LL);
+      e = launch_tiles(K.forward_batched[radius], K.block, tiles, st, none, none_g, fd, plan, 0LL);
       if (e != hipSuccess) return e;
       continue;
     }
-    e = launch_tiles(Tables::backward_batched[radii[g]], tiles, st, none, none_g, fd, plan, 0LL, lam_part,
+    e = launch_tiles(K.backward_batched[radius], K.block, tiles, st, none, none_g, fd, plan, 0LL, lam_part,
                      loss_part);
     if (e != hipSuccess) return e;
     int nmax = 1;
     for (int i = 0; i < n; ++i) nmax = max(nmax, fh[i].n_regions);
-    hipLaunchKernelGGL(backward_finalize_kernel, dim3(finalize_lam_blocks(nmax) + 1, n), dim3(kFilterBlock), 0, st,
+    hipLaunchKernelGGL(backward_finalize_kernel, dim3(finalize_lam_blocks(nmax) + 1, n), dim3(kFinalizeBlock), 0, st,
                        none, fd, plan, lam_part, loss_part);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1057,13 +226,13 @@ size_t workspace_bytes(const ramlt_frame *fh, int n, int op) {
       const size_t b = (((size_t)nt * sizeof(float) + 7) & ~(size_t)7) + (size_t)nt * sizeof(double);
       return (b + 255) & ~(size_t)255;
     }
-    int radii[RAMLT_MAX_RADIUS + 1];
-    return (size_t)distinct_radii(fh, n, radii) * (plan_bytes(n) + partials_bytes(fh, n));
+    int groups[kMaxFilterGroups];
+    return (size_t)distinct_groups(fh, n, groups) * (plan_bytes(n) + partials_bytes(fh, n));
   }
   if (n <= 1) return 0;
   if (op == RAMLT_OP_FILTER_FORWARD) {
-    int radii[RAMLT_MAX_RADIUS + 1];
-    return (size_t)distinct_radii(fh, n, radii) * plan_bytes(n);
+    int groups[kMaxFilterGroups];
+    return (size_t)distinct_groups(fh, n, groups) * plan_bytes(n);
   }
   return plan_bytes(n);
 }

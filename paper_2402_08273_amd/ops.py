@@ -98,7 +98,7 @@ def stats(radiance, features=None, max_lag=8, with_lag_corr=True, out: Optional[
     return out
 
 
-def filter_frame(mean, lam, radius, n_regions=None, lambda_min=LAMBDA_MIN_DEFAULT):
+def filter_frame(mean, lam, radius, n_regions=None, lambda_min=LAMBDA_MIN_DEFAULT, schedule=0):
     _check_plane(mean, "mean")
     if n_regions is None:
         n_regions = int(round(lam.numel() ** 0.5))
@@ -111,12 +111,14 @@ def filter_frame(mean, lam, radius, n_regions=None, lambda_min=LAMBDA_MIN_DEFAUL
     f.n_regions = int(n_regions)
     f.radius = int(radius)
     f.lambda_min = float(lambda_min)
+    f.flags = int(schedule)  # RAMLT_TILE_* | RAMLT_SCHED_*: launch schedule only
     return f
 
 
-def filter_forward(mean, lam, radius, n_regions=None, lambda_min=LAMBDA_MIN_DEFAULT, out=None):
-    """Regional reconstruction filter of per-pixel means -> [3, H, W]."""
-    f = filter_frame(mean, lam, radius, n_regions, lambda_min)
+def filter_forward(mean, lam, radius, n_regions=None, lambda_min=LAMBDA_MIN_DEFAULT, out=None, schedule=0):
+    """Regional reconstruction filter of per-pixel means -> [3, H, W]. ``schedule``:
+    ramlt_frame.flags (tile shape, direct gather), e.g. from :mod:`.tune`."""
+    f = filter_frame(mean, lam, radius, n_regions, lambda_min, schedule)
     if out is None:
         out = torch.empty_like(mean)
     f.out = out.data_ptr()
@@ -140,12 +142,14 @@ def loss_seed(out, reference, grad_out=None, loss=None):
 
 
 def filter_backward(grad_out, mean, out, lam, radius, S, n_regions=None, lambda_min=LAMBDA_MIN_DEFAULT,
-                    want_grad_lambda=True, grad_radiance=None, grad_lambda=None, reference=None, loss=None):
+                    want_grad_lambda=True, grad_radiance=None, grad_lambda=None, reference=None, loss=None,
+                    schedule=0):
     """Adjoint of the filter: (G [3,H,W] = dL/dg for every sample, dL/dlambda [N*N]).
 
     With ``grad_out=None`` and a ``reference`` image, the MSE loss seed is fused into the
-    adjoint (U is never written); ``loss`` (fp64 [1]), if given, accumulates the MSE."""
-    f = filter_frame(mean, lam, radius, n_regions, lambda_min)
+    adjoint (U is never written); ``loss`` (fp64 [1]), if given, accumulates the MSE.
+    ``schedule``: as for :func:`filter_forward`."""
+    f = filter_frame(mean, lam, radius, n_regions, lambda_min, schedule)
     _check_plane(out, "out")
     if grad_out is None:
         if reference is None:

@@ -111,7 +111,8 @@ def test_valid_arguments_reach_the_device_check(lib):
         (lambda f: setattr(f, "lag_corr", 0x40003), _abi.RAMLT_EINVAL),
         (lambda f: setattr(f, "rad_stride_y", 7), _abi.RAMLT_EINVAL),
         (lambda f: setattr(f, "rad_stride_s", 0), _abi.RAMLT_EINVAL),
-        (lambda f: setattr(f, "flags", 1), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "flags", 8), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "flags", -1), _abi.RAMLT_EINVAL),
         (lambda f: (setattr(f, "H", 1 << 16), setattr(f, "rad_stride_y", 1 << 15)), _abi.RAMLT_EUNSUPPORTED),
         (lambda f: (setattr(f, "features", 0x100000), setattr(f, "feat_dtype", 7),
                     setattr(f, "feat_stride_c", 512), setattr(f, "feat_stride_s", 32),
@@ -233,3 +234,26 @@ def test_backward_workspace_holds_tile_partials(lib):
     assert _status("filter_backward", [f], workspace=FAKE_WORKSPACE, ws_bytes=need - 256) == _abi.RAMLT_EWORKSPACE
     assert _status("filter_backward", [f], workspace=FAKE_WORKSPACE, ws_bytes=need) in (_abi.RAMLT_EHIP,
                                                                                          _abi.RAMLT_OK)
+
+
+def test_schedule_flags(lib):
+    # every tile kind and the direct schedule are valid; other bits are not
+    for flags in range(8):
+        f = _valid_filter_frame()
+        f.flags = flags
+        assert _status("filter_forward", [f]) in (_abi.RAMLT_EHIP, _abi.RAMLT_OK), flags
+    f = _valid_filter_frame()
+    f.W, f.H, f.n_regions = 1920, 1080, 20
+    base = _abi.workspace_size([f], _abi.OP_FILTER_BACKWARD)
+    f.flags = _abi.RAMLT_TILE_32X16  # half the tile rows: 20 * 3 x 20 * 4 tiles
+    assert _abi.workspace_size([f], _abi.OP_FILTER_BACKWARD) < base
+    assert (20 * 3) * (20 * 4) * 12 <= _abi.workspace_size([f], _abi.OP_FILTER_BACKWARD)
+    f.flags = _abi.RAMLT_TILE_64X8 | _abi.RAMLT_SCHED_DIRECT  # 20 * 2 x 20 * 7 tiles
+    assert (20 * 2) * (20 * 7) * 12 <= _abi.workspace_size([f], _abi.OP_FILTER_BACKWARD) < base
+    # a batch plans once per (radius, tile kind)
+    a, b = _valid_filter_frame(), _valid_filter_frame()
+    one = _abi.workspace_size([a, b], _abi.OP_FILTER_FORWARD)
+    b.flags = _abi.RAMLT_TILE_32X16
+    assert _abi.workspace_size([a, b], _abi.OP_FILTER_FORWARD) == 2 * one
+    b.flags = _abi.RAMLT_SCHED_DIRECT  # the schedule bit needs no launch of its own
+    assert _abi.workspace_size([a, b], _abi.OP_FILTER_FORWARD) == one

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2402_08273_amd import ops
+from paper_2402_08273_amd import _abi, ops
 from paper_2402_08273_amd.batch import FrameBatch, FrameInput
 from parity import backward_scales, check, filter_scale, stats_scales
 from synth import make_frame, make_lambda, make_reference
@@ -128,7 +128,10 @@ def test_batched_region_aligned_frames():
         ref = make_reference(W, H, seed=3000 + i, frame=i, spp=16)
         lam = make_lambda(N, seed=50 + i)
         host.append((rad, ref, lam, N, r))
-        frames.append(FrameInput(_dev(rad), None, _dev(ref), _dev(lam), radius=r, n_regions=N))
+        # mixed launch schedules: tile kinds and the direct gather inside one batch
+        sched = [0, _abi.RAMLT_TILE_32X16, _abi.RAMLT_TILE_64X8, _abi.RAMLT_SCHED_DIRECT,
+                 _abi.RAMLT_TILE_32X16 | _abi.RAMLT_SCHED_DIRECT][i]
+        frames.append(FrameInput(_dev(rad), None, _dev(ref), _dev(lam), radius=r, n_regions=N, schedule=sched))
     b = FrameBatch(frames)
     b.step()
     torch.cuda.synchronize()
@@ -207,3 +210,39 @@ def test_autograd_regional_filter():
     G_s, gl_s = backward_scales(u_scale, o["mean"], out_o, lam, N, r, -30.0, S)
     check("autograd G", g[:, 0], G_o, G_s)
     check("autograd grad_lambda", _h(lam_t.grad), gl_o, gl_s)
+
+
+def test_tuned_batch_matches_oracle(tmp_path):
+    # the autotuner picks a schedule by timing, writes it into the batch, and the tuned
+    # step still matches the oracle; a second batch of the same shapes reads the cache
+    from paper_2402_08273_amd import tune
+
+    cache = tune.TuneCache(str(tmp_path / "tune.json"))
+    lam = make_lambda(20, seed=99)
+    lam_d = _dev(lam)
+    frames, host = _batch_inputs(SPECS[:3], lam_d)
+    b = FrameBatch(frames)
+    b.stats()
+    best = b.tune(cache=cache, reps=3, warmup=1)
+    assert best in tune.CANDIDATES
+    assert all(d.flags == best for d in b.table)
+    key = tune.workload_key(b.table, tune.device_arch())
+    assert cache.record(key)["schedule"] == best and len(cache.record(key)["ms"]) == len(tune.CANDIDATES)
+    b.step()
+    torch.cuda.synchronize()
+    gl_sum, gl_scale, loss_total = np.zeros(400), np.zeros(400), 0.0
+    for i, (rad, feats, ref, r) in enumerate(host):
+        o = b.outputs[i]
+        gl_s = _check_chain(f"tuned frame {i}", rad, feats, ref, lam, 20, r, rad.shape[1],
+                            {k: _h(o[k]) for k in ("mean", "var", "tau")}, _h(o["out"]), None,
+                            _h(o["grad_radiance"]), None)
+        ch = _oracle_chain(rad, feats, ref, lam, 20, r, rad.shape[1])
+        loss_total += ch[2]
+        gl_sum += ch[5]
+        gl_scale += gl_s
+    check("tuned batch grad_lambda", _h(b.outputs[0]["grad_lambda"]), gl_sum, gl_scale)
+    assert abs(_h(b.loss)[0] - loss_total) <= 1e-5 * loss_total
+    frames2, _ = _batch_inputs(SPECS[:3], lam_d)
+    b2 = FrameBatch(frames2)
+    b2.stats()
+    assert b2.tune(cache=cache) == best  # from the cache, no timing

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2402_08273_amd import ops
+from paper_2402_08273_amd import _abi, ops
 from parity import TOL, backward_scales, check, filter_scale, stats_scales
 from synth import ar1_samples, make_frame, make_lambda, make_reference
 from synth.numpy_gen import NOISE_CONST, NOISE_UNIFORM
@@ -110,6 +110,30 @@ def test_filter_forward_parity(W, H, N, r):
     out = ops.filter_forward(_dev(mean32), _dev(lam), r, N, -30.0)
     ref, _ = oracle.filter_forward(mean32, lam, N, r, -30.0)
     check("out", _host(out), ref, filter_scale(mean32, lam, N, r, -30.0))
+
+
+SCHEDULES = [_abi.RAMLT_TILE_32X16, _abi.RAMLT_TILE_64X8, _abi.RAMLT_TILE_32X8 | _abi.RAMLT_SCHED_DIRECT,
+             _abi.RAMLT_TILE_64X8 | _abi.RAMLT_SCHED_DIRECT]
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("W,H,N,r", [(130, 70, 4, 3), (96, 54, 40, 5), (333, 190, 3, 7), (41, 9, 5, 15)])
+def test_filter_schedules_parity(W, H, N, r, schedule):
+    # every tile shape and the direct gather: forward and adjoint against the oracle
+    print(f"schedule {schedule} W={W} H={H} N={N} r={r}", flush=True)
+    _, mean32, lam = _filter_inputs(W, H, 4, N, seed=W * 3 + H)
+    lam[:: max(1, N)] = -35.0
+    out = ops.filter_forward(_dev(mean32), _dev(lam), r, N, -30.0, schedule=schedule)
+    ref, _ = oracle.filter_forward(mean32, lam, N, r, -30.0)
+    check("out", _host(out), ref, filter_scale(mean32, lam, N, r, -30.0))
+    out32 = ref.astype(np.float32)
+    S = 8
+    U32 = (np.random.default_rng(W).standard_normal((3, H, W)) * 1e-3).astype(np.float32)
+    G, gl = ops.filter_backward(_dev(U32), _dev(mean32), _dev(out32), _dev(lam), r, S, N, schedule=schedule)
+    G_ref, gl_ref = oracle.filter_backward(U32, mean32, out32, lam, N, r, -30.0, S)
+    G_s, gl_s = backward_scales(np.abs(U32), mean32, out32, lam, N, r, -30.0, S)
+    check("G", _host(G), G_ref, G_s)
+    check("grad_lambda", _host(gl), gl_ref, gl_s)
 
 
 def test_filter_forward_invariants_on_gpu():
