@@ -14,7 +14,10 @@ for a reader to check against the paper by eye:
   (Sec. 3.1, eq. path_integral) with its width taken from the per-region parameter
   lambda_k = log sigma_k^2 (Sec. 5.3, "Updating the Scaling Parameter") through the
   state-dependent lookup of Sec. 5.2 on the N x N screen grid of Sec. 6.1; its adjoint;
-  and the MSE loss used to drive the adjoint.
+  and the MSE loss used to drive the adjoint;
+* :mod:`oracle.region_adapt` -- the regional adaptation of lambda_k from a stream of
+  (region, acceptance probability) proposals: Algorithm 1 with eqs. est_exp_acc,
+  update_lambda and step_size_n, one proposal at a time.
 
 Parity status: every function is pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_*.py`` (brute force on tiny inputs, exact rational examples, closed forms
@@ -36,3 +39,4 @@ from .regional_filter import (  # noqa: F401
     mse_loss_seed,
     filter_backward,
 )
+from . import region_adapt  # noqa: F401
