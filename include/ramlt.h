@@ -166,6 +166,60 @@ int loss_seed(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
 int filter_backward(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
                     int32_t n_frames, void *workspace, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------------
+ * Regional adaptation of the scaling parameters (Algorithm 1 with eqs. est_exp_acc,
+ * update_lambda and step_size_n; parameters of Sec. 7.1).
+ *
+ * A batch of proposals i = 0..n-1 carries the region k_i of the chain's current state
+ * (Alg. 1 line 8) and its acceptance probability alpha_i (line 11). Regions are
+ * independent (Sec. 5.3, "Criterion for Adaptation"); within a region the proposals are
+ * taken in index order, exactly as the sequential algorithm would visit them:
+ *   A_k += alpha_i; i_k += 1; once i_k reaches L:
+ *     alpha_hat = A_k / L; gamma = min(gamma_max, gamma_scale / sqrt(n_k));
+ *     lambda_k = max(lambda_k + gamma * sgn(alpha_hat - alpha_target), lambda_min);
+ *     i_k = 0; A_k = 0; n_k += 1.
+ * (The listing tests i_k > L but divides by L; the update here fires at i_k == L. The
+ * Sec. 5.3 prose states the direction of the update the other way round from eq.
+ * update_lambda; the equation is followed. sgn(0) = 0; a NaN alpha gives sgn 0.)
+ * alpha is accumulated in fp64 in the proposals' order, so every decision and every state
+ * value equals the sequential algorithm's in fp64 (the same IEEE operations in the same
+ * order). Proposals whose region is outside [0, n_regions) are skipped. The state carries
+ * over between calls: consecutive batches equal one batch of their concatenation. */
+typedef struct ramlt_adapt_params {
+  int32_t n_regions;      /* m, 1..RAMLT_MAX_ADAPT_REGIONS                               */
+  int32_t L;              /* visits per update (the paper's L = 10), 1..RAMLT_MAX_ADAPT_L */
+  double gamma_max;       /* eq. step_size_n cap (paper: 1); finite                       */
+  double gamma_scale;     /* eq. step_size_n scale (paper: 5); finite                     */
+  double alpha_target;    /* alpha* (paper: 0.5); finite                                  */
+  double lambda_min;      /* lower limit of lambda (paper: -30); finite                   */
+} ramlt_adapt_params;
+
+/* Per-region state, DEVICE arrays of n_regions entries, read and updated in place.
+ * Initial values (Alg. 1 lines 2-7): lambda = lambda_init (paper: 1), acc = 0,
+ * visits = 0, updates = 1. Invariant kept by every call: 0 <= visits < L. */
+typedef struct ramlt_region_state {
+  double *lambda;         /* lambda_k = log sigma_k^2                                    */
+  double *acc;            /* A_k, accumulated acceptance of the pending visits           */
+  int32_t *visits;        /* i_k, visits since the last update                           */
+  int32_t *updates;       /* n_k, 1 + number of updates so far                          */
+  float *lambda_f32;      /* optional (NULL = none): lambda_k rounded to float, the table
+                             filter_forward reads                                        */
+} ramlt_region_state;
+
+#define RAMLT_MAX_ADAPT_REGIONS (1 << 24)
+#define RAMLT_MAX_ADAPT_L (1 << 20)
+#define RAMLT_MAX_PROPOSALS (1LL << 30)
+
+/* region: DEVICE int32[n]; alpha: DEVICE float[n]; n in 0..RAMLT_MAX_PROPOSALS (0 = no
+ * work). params, state: HOST structs. workspace: DEVICE, 256-byte aligned, at least
+ * ramlt_adapt_workspace_size(n, n_regions) bytes (proposals sorted by region, stably,
+ * and region boundaries). Errors as for the other entry points. */
+int region_adapt(const ramlt_adapt_params *params, const ramlt_region_state *state, const int32_t *region,
+                 const float *alpha, int64_t n_proposals, void *workspace, size_t ws_bytes, void *stream);
+
+/* Workspace bytes of region_adapt (0 for n_proposals <= 0 or invalid sizes). */
+size_t ramlt_adapt_workspace_size(int64_t n_proposals, int32_t n_regions);
+
 /* Bytes of device workspace `op` needs for these frames (0 if none). Workspace is
  * caller-owned, 256-byte aligned, and may be reused across calls on one stream. */
 size_t ramlt_workspace_size(const ramlt_frame *frames_host, int32_t n_frames, int32_t op);

@@ -49,7 +49,13 @@ EXPORTED = (
     "ramlt_workspace_size",
     "ramlt_last_error",
     "ramlt_abi_version",
+    "region_adapt",
+    "ramlt_adapt_workspace_size",
 )
+
+MAX_ADAPT_REGIONS = 1 << 24
+MAX_ADAPT_L = 1 << 20
+MAX_PROPOSALS = 1 << 30
 
 
 class RamltFrame(ctypes.Structure):
@@ -90,6 +96,31 @@ class RamltFrame(ctypes.Structure):
     ]
 
 
+class RamltAdaptParams(ctypes.Structure):
+    """Mirror of ``ramlt_adapt_params`` (host struct)."""
+
+    _fields_ = [
+        ("n_regions", ctypes.c_int32),
+        ("L", ctypes.c_int32),
+        ("gamma_max", ctypes.c_double),
+        ("gamma_scale", ctypes.c_double),
+        ("alpha_target", ctypes.c_double),
+        ("lambda_min", ctypes.c_double),
+    ]
+
+
+class RamltRegionState(ctypes.Structure):
+    """Mirror of ``ramlt_region_state`` (host struct of device pointers)."""
+
+    _fields_ = [
+        ("lambda_", ctypes.c_void_p),
+        ("acc", ctypes.c_void_p),
+        ("visits", ctypes.c_void_p),
+        ("updates", ctypes.c_void_p),
+        ("lambda_f32", ctypes.c_void_p),
+    ]
+
+
 class RamltError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"ramlt status {status}: {message}")
@@ -122,6 +153,12 @@ def load():
     lib.ramlt_last_error.restype = ctypes.c_char_p
     lib.ramlt_abi_version.argtypes = []
     lib.ramlt_abi_version.restype = ctypes.c_int32
+    lib.region_adapt.argtypes = [ctypes.POINTER(RamltAdaptParams), ctypes.POINTER(RamltRegionState),
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t,
+                                 ctypes.c_void_p]
+    lib.region_adapt.restype = ctypes.c_int
+    lib.ramlt_adapt_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int32]
+    lib.ramlt_adapt_workspace_size.restype = ctypes.c_size_t
     if (lib.ramlt_abi_version() >> 16) != ctypes.sizeof(RamltFrame):
         raise RuntimeError("ramlt_frame layout mismatch between libramlt.so and the binding")
     _lib = lib
@@ -176,3 +213,26 @@ def status_of(name, frames, frames_dev=None, workspace=None, ws_bytes=0, stream=
     lib = load()
     arr, n = _table(frames)
     return getattr(lib, name)(arr, frames_dev, n, workspace, ws_bytes, stream)
+
+
+def region_adapt(params, state, region, alpha, n, workspace=None, ws_bytes=0, stream=None):
+    """Call ``region_adapt``; raises RamltError on a non-zero status."""
+    lib = load()
+    st = lib.region_adapt(ctypes.byref(params) if params is not None else None,
+                          ctypes.byref(state) if state is not None else None, region, alpha, n, workspace,
+                          ws_bytes, stream)
+    if st != RAMLT_OK:
+        raise RamltError(st, last_error())
+    return st
+
+
+def adapt_status(params, state, region, alpha, n, workspace=None, ws_bytes=0, stream=None):
+    """Status of a ``region_adapt`` call (no exception), for validation tests."""
+    lib = load()
+    return lib.region_adapt(ctypes.byref(params) if params is not None else None,
+                            ctypes.byref(state) if state is not None else None, region, alpha, n, workspace,
+                            ws_bytes, stream)
+
+
+def adapt_workspace_size(n, m):
+    return int(load().ramlt_adapt_workspace_size(n, m))

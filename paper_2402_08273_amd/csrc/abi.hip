@@ -191,9 +191,61 @@ int run_op(int op, const char *name, Validator v, Launcher l, const ramlt_frame 
   return RAMLT_OK;
 }
 
+int validate_adapt(const ramlt_adapt_params *p, const ramlt_region_state *s, const int32_t *region,
+                   const float *alpha, int64_t n) {
+  if (!p) return fail(RAMLT_EINVAL, "region_adapt: params is NULL");
+  if (!s) return fail(RAMLT_EINVAL, "region_adapt: state is NULL");
+  if (p->n_regions < 1 || p->n_regions > RAMLT_MAX_ADAPT_REGIONS)
+    return fail(RAMLT_EINVAL, "region_adapt: n_regions %d outside 1..%d", p->n_regions, RAMLT_MAX_ADAPT_REGIONS);
+  if (p->L < 1 || p->L > RAMLT_MAX_ADAPT_L)
+    return fail(RAMLT_EINVAL, "region_adapt: L %d outside 1..%d", p->L, RAMLT_MAX_ADAPT_L);
+  if (!std::isfinite(p->gamma_max) || !std::isfinite(p->gamma_scale) || !std::isfinite(p->alpha_target) ||
+      !std::isfinite(p->lambda_min))
+    return fail(RAMLT_EINVAL, "region_adapt: gamma_max, gamma_scale, alpha_target, lambda_min must be finite");
+  if (n < 0 || n > RAMLT_MAX_PROPOSALS)
+    return fail(RAMLT_EINVAL, "region_adapt: n_proposals %lld outside 0..%lld", (long long)n,
+                (long long)RAMLT_MAX_PROPOSALS);
+  if (!s->lambda || !aligned(s->lambda, 8) || !s->acc || !aligned(s->acc, 8))
+    return fail(RAMLT_EINVAL, "region_adapt: state.lambda and state.acc must be 8-byte aligned device pointers");
+  if (!s->visits || !aligned(s->visits, 4) || !s->updates || !aligned(s->updates, 4))
+    return fail(RAMLT_EINVAL, "region_adapt: state.visits and state.updates must be 4-byte aligned device pointers");
+  if (s->lambda_f32 && !aligned(s->lambda_f32, 4))
+    return fail(RAMLT_EINVAL, "region_adapt: state.lambda_f32 must be 4-byte aligned");
+  if (n > 0 && (!region || !aligned(region, 4) || !alpha || !aligned(alpha, 4)))
+    return fail(RAMLT_EINVAL, "region_adapt: region and alpha must be 4-byte aligned device pointers");
+  return RAMLT_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int region_adapt(const ramlt_adapt_params *params, const ramlt_region_state *state, const int32_t *region,
+                 const float *alpha, int64_t n_proposals, void *workspace, size_t ws_bytes, void *stream) {
+  int r = validate_adapt(params, state, region, alpha, n_proposals);
+  if (r) return r;
+  const size_t need = ramlt::adapt_workspace_bytes(n_proposals, params->n_regions);
+  if (need > 0) {
+    if (workspace == nullptr || ws_bytes < need)
+      return fail(RAMLT_EWORKSPACE, "region_adapt needs %zu bytes of workspace, got %zu", need,
+                  workspace == nullptr ? (size_t)0 : ws_bytes);
+    if (!aligned(workspace, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
+  }
+  r = check_device();
+  if (r) return r;
+  const hipError_t e = ramlt::launch_region_adapt(*params, *state, region, alpha, n_proposals, workspace,
+                                                  (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RAMLT_EHIP, "region_adapt: %s", hipGetErrorString(e));
+  g_last_error.clear();
+  return RAMLT_OK;
+}
+
+size_t ramlt_adapt_workspace_size(int64_t n_proposals, int32_t n_regions) {
+  if (n_proposals <= 0 || n_proposals > RAMLT_MAX_PROPOSALS || n_regions < 1 ||
+      n_regions > RAMLT_MAX_ADAPT_REGIONS)
+    return 0;
+  return ramlt::adapt_workspace_bytes(n_proposals, n_regions);
+}
 
 int stats_accumulate(const ramlt_frame *frames_host, const ramlt_frame *frames_dev, int32_t n_frames,
                      void *workspace, size_t ws_bytes, void *stream) {

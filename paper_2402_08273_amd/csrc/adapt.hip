@@ -1,0 +1,302 @@
+// Regional adaptation of the scaling parameters lambda_k (Algorithm 1 with eqs.
+// est_exp_acc, update_lambda and step_size_n) for a batch of proposals.
+//
+// The sequential algorithm visits the proposals in order and updates the state of the
+// region each one falls in. Regions are independent, so the batch is regrouped by region,
+// stably (a proposal keeps its place among the proposals of its region), and every region
+// then replays its own sub-sequence:
+//
+//   1. stable LSD radix sort of (region, proposal index) by region, 8 bits per pass:
+//      per-tile digit histograms -> one exclusive scan (digit-major) -> a stable scatter
+//      that ranks equal digits inside each wave by ballot and across waves through LDS;
+//   2. region boundaries: the first sorted position of every region;
+//   3. one wave per region: lanes sum the acceptance of whole windows of L visits (fp64,
+//      in proposal order, the first window continuing the carried A_k), then every lane
+//      replays the window decisions in order (step size, sign, clamp) and the remainder
+//      becomes the new pending sum.
+//
+// Proposals with a region outside [0, m) get the key m and are sorted past every region;
+// step 3 never reads them.
+#include "launch.hpp"
+
+#include <stdint.h>
+
+namespace ramlt {
+
+namespace {
+
+constexpr int kSortBlock = 256;
+constexpr int kSortItems = 16;                        // per thread
+constexpr int kSortTile = kSortBlock * kSortItems;    // proposals per workgroup and pass
+constexpr int kDigitBits = 8;
+constexpr int kDigits = 1 << kDigitBits;
+constexpr int kScanBlock = 1024;
+constexpr int kWavesPerBlock = kSortBlock / 64;
+
+__device__ __forceinline__ uint32_t input_key(const int32_t *region, long long pos, int m) {
+  const int32_t k = region[pos];
+  return (k < 0 || k >= m) ? (uint32_t)m : (uint32_t)k;
+}
+
+// Pass p of the sort, histogram: hist[d * nblocks + b] = proposals of tile b whose digit p
+// is d. Pass 0 reads the regions (and maps invalid ones to m), later passes the keys.
+__global__ __launch_bounds__(kSortBlock) void sort_hist_kernel(const int32_t *__restrict__ region,
+                                                               const uint32_t *__restrict__ keys, long long n, int m,
+                                                               int shift, uint32_t *__restrict__ hist,
+                                                               int nblocks) {
+  __shared__ uint32_t h[kDigits];
+  for (int d = threadIdx.x; d < kDigits; d += kSortBlock) h[d] = 0;
+  __syncthreads();
+  const long long base = (long long)blockIdx.x * kSortTile;
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const long long pos = base + (long long)j * kSortBlock + threadIdx.x;
+    if (pos < n) {
+      const uint32_t key = keys ? keys[pos] : input_key(region, pos, m);
+      atomicAdd(&h[(key >> shift) & (kDigits - 1)], 1u);
+    }
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < kDigits; d += kSortBlock) hist[(long long)d * nblocks + blockIdx.x] = h[d];
+}
+
+// In-place exclusive scan of v[0..len) with one workgroup: each thread scans a contiguous
+// chunk; chunk totals are scanned in LDS.
+__global__ __launch_bounds__(kScanBlock) void exclusive_scan_kernel(uint32_t *__restrict__ v, long long len) {
+  __shared__ uint32_t part[kScanBlock];
+  const long long chunk = (len + kScanBlock - 1) / kScanBlock;
+  const long long b = (long long)threadIdx.x * chunk;
+  const long long e = min(len, b + chunk);
+  uint32_t s = 0;
+  for (long long i = b; i < e; ++i) s += v[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {  // Hillis-Steele, inclusive
+    const uint32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (long long i = b; i < e; ++i) {
+    const uint32_t x = v[i];
+    v[i] = run;
+    run += x;
+  }
+}
+
+// Pass p of the sort, stable scatter. The tile is taken in rounds of 256 proposals in
+// index order; inside a round the rank of a proposal among equal digits is (proposals of
+// earlier rounds, from `base`) + (earlier waves of the round) + (earlier lanes of its wave,
+// by ballot). Order therefore follows the proposal index.
+__global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(
+    const int32_t *__restrict__ region, const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ idx_in,
+    long long n, int m, int shift, const uint32_t *__restrict__ hist, int nblocks, uint32_t *__restrict__ keys_out,
+    uint32_t *__restrict__ idx_out) {
+  __shared__ uint32_t base[kDigits];
+  __shared__ uint32_t wcount[kWavesPerBlock][kDigits];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int d = threadIdx.x; d < kDigits; d += kSortBlock) base[d] = hist[(long long)d * nblocks + blockIdx.x];
+  const long long tile = (long long)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortItems; ++r) {
+    for (int d = lane; d < kDigits; d += 64) wcount[wave][d] = 0;
+    __syncthreads();
+    const long long pos = tile + (long long)r * kSortBlock + threadIdx.x;
+    const bool valid = pos < n;
+    uint32_t key = 0, idx = 0;
+    if (valid) {
+      key = keys_in ? keys_in[pos] : input_key(region, pos, m);
+      idx = idx_in ? idx_in[pos] : (uint32_t)pos;
+    }
+    const int d = valid ? (int)((key >> shift) & (kDigits - 1)) : -1;
+    // rank among the earlier lanes of this wave with the same digit
+    unsigned long long todo = __ballot(valid);
+    uint32_t rank = 0;
+    while (todo) {  // wave-uniform: one iteration per distinct digit in the wave
+      const int leader = __ffsll((long long)todo) - 1;
+      const int dl = __shfl(d, leader, 64);
+      const unsigned long long peers = __ballot(valid && d == dl);
+      if (d == dl) rank = (uint32_t)__popcll(peers & __lanemask_lt());
+      if (lane == leader) wcount[wave][dl] = (uint32_t)__popcll(peers);
+      todo &= ~peers;
+    }
+    __syncthreads();
+    // per digit: offsets of the waves of this round, and the base for the next round
+    for (int dd = threadIdx.x; dd < kDigits; dd += kSortBlock) {
+      uint32_t run = base[dd];
+#pragma unroll
+      for (int w = 0; w < kWavesPerBlock; ++w) {
+        const uint32_t c = wcount[w][dd];
+        wcount[w][dd] = run;
+        run += c;
+      }
+      base[dd] = run;
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t out = wcount[wave][d] + rank;
+      if ((long long)out < n) {  // always true for consistent histograms
+        keys_out[out] = key;
+        idx_out[out] = idx;
+      }
+    }
+    __syncthreads();  // wcount is cleared by the next round
+  }
+}
+
+// start[k] = first sorted position with key >= k, for k = 0..m+1 (start[m+1] = n).
+__global__ void region_starts_kernel(const uint32_t *__restrict__ keys, long long n, int m,
+                                     uint32_t *__restrict__ start) {
+  const long long pos = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= n) return;
+  // keys are <= m by construction; the clamps keep every write inside start[0 .. m+1]
+  const long long cur = min((long long)keys[pos], (long long)m);
+  const long long prev = pos ? min((long long)keys[pos - 1], (long long)m) : -1;
+  for (long long k = prev + 1; k <= cur; ++k) start[k] = (uint32_t)pos;
+  if (pos == n - 1)
+    for (long long k = cur + 1; k <= (long long)m + 1; ++k) start[k] = (uint32_t)n;
+}
+
+// One wave per region: replay its proposals (sorted positions start[k] .. start[k+1]).
+__global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_t *__restrict__ start,
+                                                                   const uint32_t *__restrict__ idx,
+                                                                   const float *__restrict__ alpha, long long n,
+                                                                   const ramlt_adapt_params p,
+                                                                   const ramlt_region_state s) {
+  // alpha of sorted position t (the index is < n by construction; checked all the same)
+  auto alpha_at = [&](long long t) -> double {
+    const uint32_t j = idx[t];
+    return (long long)j < n ? (double)alpha[j] : 0.0;
+  };
+  const int k = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= p.n_regions) return;  // wave-uniform
+  const long long hi = min((long long)start[k + 1], n);
+  const long long lo = min((long long)start[k], hi);
+  const long long c = hi - lo;
+  if (c == 0) {
+    if (s.lambda_f32 && lane == 0) s.lambda_f32[k] = (float)s.lambda[k];
+    return;
+  }
+  const int L = p.L;
+  const int i0 = s.visits[k];
+  const double A0 = s.acc[k];
+  double lam = s.lambda[k];
+  long long nk = s.updates[k];
+  // visits that complete the pending window (0 <= i0 < L by the state invariant)
+  const long long need0 = i0 < L && i0 >= 0 ? (long long)(L - i0) : 1;
+  if (c < need0) {
+    if (lane == 0) {
+      double a = A0;
+      for (long long t = lo; t < hi; ++t) a += alpha_at(t);
+      s.acc[k] = a;
+      s.visits[k] = i0 + (int)c;
+      if (s.lambda_f32) s.lambda_f32[k] = (float)lam;
+    }
+    return;
+  }
+  const long long nw = 1 + (c - need0) / L;      // completed windows
+  const long long rem = (c - need0) % L;         // visits pending after the last window
+  for (long long w0 = 0; w0 < nw; w0 += 64) {
+    // lanes: the window sums of this chunk, each in proposal order
+    const long long w = w0 + lane;
+    int sgn = 0;
+    if (w < nw) {
+      const long long b = w == 0 ? lo : lo + need0 + (w - 1) * L;
+      const long long len = w == 0 ? need0 : L;
+      double a = w == 0 ? A0 : 0.0;
+      for (long long t = 0; t < len; ++t) a += alpha_at(b + t);
+      const double ahat = a / (double)L;
+      sgn = (ahat > p.alpha_target) - (ahat < p.alpha_target);
+    }
+    // every lane replays the chunk's updates in order (same values in every lane)
+    const int cnt = (int)min((long long)64, nw - w0);
+    for (int j = 0; j < cnt; ++j) {
+      const int sj = __shfl(sgn, j, 64);
+      const double gamma = fmin(p.gamma_max, p.gamma_scale / sqrt((double)nk));
+      lam = fmax(lam + gamma * (double)sj, p.lambda_min);
+      ++nk;
+    }
+  }
+  if (lane == 0) {
+    double a = 0.0;
+    for (long long t = hi - rem; t < hi; ++t) a += alpha_at(t);
+    s.acc[k] = a;
+    s.visits[k] = (int)rem;
+    s.lambda[k] = lam;
+    s.updates[k] = (int)nk;
+    if (s.lambda_f32) s.lambda_f32[k] = (float)lam;
+  }
+}
+
+int sort_passes(int m) {  // digits of the largest key, m (invalid proposals)
+  int bits = 1;
+  while (bits < 31 && ((long long)1 << bits) <= (long long)m) ++bits;
+  return (bits + kDigitBits - 1) / kDigitBits;
+}
+
+struct AdaptWorkspace {
+  uint32_t *keys[2], *idx[2], *hist, *start;
+  size_t bytes;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+AdaptWorkspace carve(void *ws, long long n, int m) {
+  const long long nblocks = (n + kSortTile - 1) / kSortTile;
+  AdaptWorkspace w{};
+  char *p = (char *)ws;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char *q = p ? p + off : nullptr;
+    off += align256(b);
+    return (uint32_t *)q;
+  };
+  w.keys[0] = take((size_t)n * 4);
+  w.keys[1] = take((size_t)n * 4);
+  w.idx[0] = take((size_t)n * 4);
+  w.idx[1] = take((size_t)n * 4);
+  w.hist = take((size_t)kDigits * (size_t)nblocks * 4);
+  w.start = take(((size_t)m + 2) * 4);
+  w.bytes = off;
+  return w;
+}
+
+}  // namespace
+
+size_t adapt_workspace_bytes(long long n, int m) {
+  if (n <= 0 || m < 1) return 0;
+  return carve(nullptr, n, m).bytes;
+}
+
+hipError_t launch_region_adapt(const ramlt_adapt_params &p, const ramlt_region_state &s, const int32_t *region,
+                               const float *alpha, long long n, void *ws, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int m = p.n_regions;
+  const AdaptWorkspace w = carve(ws, n, m);
+  const int nblocks = (int)((n + kSortTile - 1) / kSortTile);
+  const int passes = sort_passes(m);
+  const long long hist_len = (long long)kDigits * nblocks;
+  int cur = 0;  // buffers holding the keys of the previous pass (none before pass 0)
+  for (int q = 0; q < passes; ++q) {
+    const uint32_t *kin = q ? w.keys[cur] : nullptr;
+    const uint32_t *iin = q ? w.idx[cur] : nullptr;
+    const int out = q ? cur ^ 1 : 0;
+    hipLaunchKernelGGL(sort_hist_kernel, dim3(nblocks), dim3(kSortBlock), 0, st, region, kin, n, m, q * kDigitBits,
+                       w.hist, nblocks);
+    hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(kScanBlock), 0, st, w.hist, hist_len);
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(nblocks), dim3(kSortBlock), 0, st, region, kin, iin, n, m,
+                       q * kDigitBits, w.hist, nblocks, w.keys[out], w.idx[out]);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    cur = out;
+  }
+  hipLaunchKernelGGL(region_starts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.keys[cur], n, m,
+                     w.start);
+  hipLaunchKernelGGL(region_update_kernel, dim3((unsigned)((m + kWavesPerBlock - 1) / kWavesPerBlock)),
+                     dim3(kSortBlock), 0, st, w.start, w.idx[cur], alpha, n, p, s);
+  return hipGetLastError();
+}
+
+}  // namespace ramlt

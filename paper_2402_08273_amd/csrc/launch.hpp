@@ -17,4 +17,9 @@ hipError_t launch_filter_backward(const ramlt_frame *fh, const ramlt_frame *fd, 
                                   hipStream_t st);
 size_t workspace_bytes(const ramlt_frame *fh, int n, int op);
 
+// Regional adaptation (adapt.hip): n proposals, validated parameters and state.
+hipError_t launch_region_adapt(const ramlt_adapt_params &p, const ramlt_region_state &s, const int32_t *region,
+                               const float *alpha, long long n, void *ws, hipStream_t st);
+size_t adapt_workspace_bytes(long long n, int m);
+
 }  // namespace ramlt

@@ -214,3 +214,53 @@ class MSELoss(torch.autograd.Function):
     def backward(ctx, g):
         (grad,) = ctx.saved_tensors
         return grad * g.to(grad.dtype), None
+
+
+# ---------------------------------------------------------------------------- adaptation
+class RegionAdapter:
+    """Per-region adaptive scaling parameters (Algorithm 1) on the device.
+
+    Holds the state (lambda_k and its float copy for the filter, A_k, i_k, n_k) for
+    ``n_regions`` regions and feeds batches of proposals (region int32 [n], acceptance
+    probability float32 [n], device tensors) through ``region_adapt``. Defaults are the
+    paper's parameters (Sec. 7.1): L = 10, gamma_max = 1, gamma_scale = 5, alpha* = 0.5,
+    lambda_init = 1, lambda_min = -30.
+    """
+
+    def __init__(self, n_regions, L=10, gamma_max=1.0, gamma_scale=5.0, alpha_target=0.5,
+                 lambda_init=1.0, lambda_min=LAMBDA_MIN_DEFAULT, device="cuda"):
+        dev = torch.device(device)
+        m = int(n_regions)
+        self.lam = torch.full((m,), float(lambda_init), device=dev, dtype=torch.float64)
+        self.acc = torch.zeros(m, device=dev, dtype=torch.float64)
+        self.visits = torch.zeros(m, device=dev, dtype=torch.int32)
+        self.updates = torch.ones(m, device=dev, dtype=torch.int32)
+        self.lam_f32 = self.lam.float()  # the filter's lambda table
+        self.params = _abi.RamltAdaptParams(m, int(L), float(gamma_max), float(gamma_scale), float(alpha_target),
+                                            float(lambda_min))
+        self.state = _abi.RamltRegionState(self.lam.data_ptr(), self.acc.data_ptr(), self.visits.data_ptr(),
+                                           self.updates.data_ptr(), self.lam_f32.data_ptr())
+        self.device = dev
+        self._ws = None
+        self._ws_bytes = 0
+
+    def workspace(self, n):
+        need = _abi.adapt_workspace_size(n, self.params.n_regions)
+        if need > self._ws_bytes:
+            self._ws = torch.empty(need + 256, device=self.device, dtype=torch.uint8)
+            self._ws_bytes = need
+        if need == 0:
+            return None, 0
+        return (self._ws.data_ptr() + 255) // 256 * 256, need
+
+    def step(self, region, alpha):
+        """Adapt on one batch of proposals, in index order within each region."""
+        if region.dtype != torch.int32 or alpha.dtype != torch.float32 or not region.is_cuda or not alpha.is_cuda:
+            raise ValueError("region must be an int32 and alpha a float32 device tensor")
+        if region.dim() != 1 or region.shape != alpha.shape or not region.is_contiguous() or not alpha.is_contiguous():
+            raise ValueError("region and alpha must be contiguous 1-D tensors of equal length")
+        n = region.numel()
+        ws, ws_bytes = self.workspace(n)
+        _abi.region_adapt(self.params, self.state, region.data_ptr() if n else None,
+                          alpha.data_ptr() if n else None, n, ws, ws_bytes, _stream())
+        return self

@@ -257,3 +257,44 @@ def test_schedule_flags(lib):
     assert _abi.workspace_size([a, b], _abi.OP_FILTER_FORWARD) == 2 * one
     b.flags = _abi.RAMLT_SCHED_DIRECT  # the schedule bit needs no launch of its own
     assert _abi.workspace_size([a, b], _abi.OP_FILTER_FORWARD) == one
+
+
+def _adapt_args():
+    p = _abi.RamltAdaptParams(400, 10, 1.0, 5.0, 0.5, -30.0)
+    s = _abi.RamltRegionState(0x100000, 0x200000, 0x300000, 0x400000, None)
+    return p, s
+
+
+def test_region_adapt_validation(lib):
+    ws = 0x4000000
+    need = _abi.adapt_workspace_size(1000, 400)
+    assert need > 1000 * 16 and need % 256 == 0
+    assert _abi.adapt_workspace_size(0, 400) == 0 and _abi.adapt_workspace_size(10, 0) == 0
+    p, s = _adapt_args()
+    ok = _abi.adapt_status(p, s, 0x500000, 0x600000, 1000, ws, need)
+    assert ok in (_abi.RAMLT_EHIP, _abi.RAMLT_OK), _abi.last_error()
+    # empty batch: no workspace needed, pointers may be NULL
+    assert _abi.adapt_status(p, s, None, None, 0) in (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
+    bad = [
+        lambda p, s: setattr(p, "n_regions", 0),
+        lambda p, s: setattr(p, "n_regions", (1 << 24) + 1),
+        lambda p, s: setattr(p, "L", 0),
+        lambda p, s: setattr(p, "gamma_scale", float("nan")),
+        lambda p, s: setattr(p, "lambda_min", float("-inf")),
+        lambda p, s: setattr(s, "lambda_", None),
+        lambda p, s: setattr(s, "acc", 0x200004),  # fp64 needs 8-byte alignment
+        lambda p, s: setattr(s, "visits", None),
+        lambda p, s: setattr(s, "lambda_f32", 0x700002),
+    ]
+    for mutate in bad:
+        p, s = _adapt_args()
+        mutate(p, s)
+        assert _abi.adapt_status(p, s, 0x500000, 0x600000, 1000, ws, need) == _abi.RAMLT_EINVAL
+    p, s = _adapt_args()
+    assert _abi.adapt_status(p, s, None, 0x600000, 1000, ws, need) == _abi.RAMLT_EINVAL
+    assert _abi.adapt_status(p, s, 0x500000, 0x600000, -1, ws, need) == _abi.RAMLT_EINVAL
+    assert _abi.adapt_status(p, s, 0x500000, 0x600000, 1000, None, 0) == _abi.RAMLT_EWORKSPACE
+    assert _abi.adapt_status(p, s, 0x500000, 0x600000, 1000, ws, need - 1) == _abi.RAMLT_EWORKSPACE
+    assert _abi.adapt_status(p, s, 0x500000, 0x600000, 1000, ws + 16, need) == _abi.RAMLT_EWORKSPACE
+    assert _abi.adapt_status(None, s, 0x500000, 0x600000, 1000, ws, need) == _abi.RAMLT_EINVAL
+    assert _abi.adapt_status(p, None, 0x500000, 0x600000, 1000, ws, need) == _abi.RAMLT_EINVAL

@@ -1,0 +1,105 @@
+"""GPU parity of region_adapt (regional adaptation, Algorithm 1) against the sequential
+FP64 oracle: integer state exactly, A_k exactly (the same fp64 additions in the same
+order), lambda_k to 1e-12 (the same IEEE operations; the square root of the step size is
+the only library call), on streams spanning one to three radix passes, several batches in
+a row, and the edge cases (L = 1, one region, out-of-range keys, acceptance exactly at the
+target, NaN acceptance, empty batches)."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import region_adapt as ora
+from paper_2402_08273_amd.ops import RegionAdapter
+from synth.proposals import make_proposals
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _compare(name, ad, st, regions=None):
+    torch.cuda.synchronize()
+    sel = slice(None) if regions is None else regions
+    vis = ad.visits.cpu().numpy()[sel]
+    upd = ad.updates.cpu().numpy()[sel]
+    acc = ad.acc.cpu().numpy()[sel]
+    lam = ad.lam.cpu().numpy()[sel]
+    lam32 = ad.lam_f32.cpu().numpy()[sel]
+    assert np.array_equal(vis, st["visits"][sel]), name
+    assert np.array_equal(upd, st["updates"][sel]), name
+    assert np.array_equal(acc, st["acc"][sel]), (name, np.abs(acc - st["acc"][sel]).max())
+    err = np.abs(lam - st["lambda"][sel]).max()
+    assert err <= 1e-12, (name, err)
+    assert np.array_equal(lam32, lam.astype(np.float32)), name
+
+
+@pytest.mark.parametrize("m,n,L,batches", [(1, 50, 1, 2), (5, 997, 2, 3), (400, 200_000, 10, 3),
+                                           (3000, 150_000, 37, 2), (70_000, 300_000, 10, 2)])
+def test_region_adapt_parity(m, n, L, batches):
+    print(f"region_adapt parity m={m} n={n} L={L} batches={batches}", flush=True)
+    ad = RegionAdapter(m, L=L)
+    st = ora.initial_state(m)
+    for b in range(batches):
+        region, alpha = make_proposals(n, m, seed=m + L, batch=b)
+        ad.step(_dev(region), _dev(alpha))
+        ora.adapt(st, region, alpha, L=L)
+        _compare(f"m={m} batch {b}", ad, st)
+
+
+def test_region_adapt_edge_cases():
+    m, L = 4, 3
+    ad = RegionAdapter(m, L=L)
+    st = ora.initial_state(m)
+    cases = [
+        (np.array([], np.int32), np.array([], np.float32)),                     # empty batch
+        (np.array([-5, 4, 99, -1], np.int32), np.array([0.9] * 4, np.float32)),  # all out of range
+        (np.array([0, 0, 0, 1, 1, 1], np.int32), np.array([0.5] * 6, np.float32)),  # mean == target: sgn 0
+        (np.array([2, 2, 2], np.int32), np.array([np.nan, 0.9, 0.9], np.float32)),  # NaN: sgn 0
+        (np.array([3] * 31, np.int32), np.full(31, 0.0625, np.float32)),         # many updates, one region
+    ]
+    for i, (region, alpha) in enumerate(cases):
+        ad.step(_dev(region), _dev(alpha))
+        ora.adapt(st, region, alpha, L=L)
+        torch.cuda.synchronize()
+        vis, upd = ad.visits.cpu().numpy(), ad.updates.cpu().numpy()
+        acc, lam = ad.acc.cpu().numpy(), ad.lam.cpu().numpy()
+        assert np.array_equal(vis, st["visits"]) and np.array_equal(upd, st["updates"]), i
+        # NaN propagates into a pending A_k on both sides; compare with NaN == NaN
+        assert np.array_equal(acc, st["acc"], equal_nan=True), i
+        assert np.array_equal(lam, st["lambda"]), i
+
+
+def test_region_adapt_batches_compose_on_gpu():
+    m, n = 400, 120_000
+    region, alpha = make_proposals(n, m, seed=11)
+    one = RegionAdapter(m)
+    one.step(_dev(region), _dev(alpha))
+    two = RegionAdapter(m)
+    two.step(_dev(region[:50_001]), _dev(alpha[:50_001]))
+    two.step(_dev(region[50_001:]), _dev(alpha[50_001:]))
+    torch.cuda.synchronize()
+    for a, b in [(one.lam, two.lam), (one.acc, two.acc), (one.visits, two.visits), (one.updates, two.updates)]:
+        assert torch.equal(a, b)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("m", [400, 20 * 20 * 50 * 50])
+def test_region_adapt_full_size_sampled_regions(m):
+    # 16 M proposals, the bench's launch configuration; regions are independent, so the
+    # oracle replays the sub-streams of sampled regions (each in its own order)
+    n = 1 << 24
+    print(f"region_adapt full size m={m} n={n}", flush=True)
+    region, alpha = make_proposals(n, m, seed=3)
+    ad = RegionAdapter(m)
+    ad.step(_dev(region), _dev(alpha))
+    counts = np.bincount(region[(region >= 0) & (region < m)], minlength=m)
+    picks = np.unique(np.concatenate([[0, 1, m - 1], np.argsort(counts)[-3:],
+                                      np.random.default_rng(0).integers(0, m, 8)]))
+    st = ora.initial_state(m)
+    for k in picks:
+        sel = region == k
+        ora.adapt(st, region[sel], alpha[sel])
+    _compare(f"full size m={m}", ad, st, regions=picks)
