@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="skip the batched and 4K measurements")
     p.add_argument("--no-tune", action="store_true",
                    help="use the library's default filter schedule instead of the autotuned one")
-    p.add_argument("--only", choices=["batched", "uhd"], default=None,
+    p.add_argument("--only", choices=["batched", "uhd", "adapt"], default=None,
                    help="measure only the 32-frame batch or only the 4K frame and print that object "
                         "(for profiling one workload)")
     p.add_argument("--cpu-rows", type=int, default=0, help="rows of the frame the oracle times (0 = auto)")
@@ -277,6 +277,60 @@ def measure_batch32(steps, warmup, tune=True):
     return res
 
 
+ADAPT_PROPOSALS = 1 << 24
+ADAPT_REGION_COUNTS = (20 * 20, 20 * 20 * 50 * 50)  # the 2-D grid N_top^2; the 4-D grid N_top^2 N_bottom^2
+
+
+def measure_adapt(steps, warmup, cpu=True):
+    """region_adapt on 16 M proposals per batch (seeded stream of synth.proposals), for the
+    paper's 2-D grid (400 regions) and 4-D grid (10^6 regions); one step = one batch.
+    Algorithmic bytes: the proposals (region int32 + alpha float32 = 8 B each) and the
+    per-region state read and written (lambda, A_k: 2 x 8 B, i_k, n_k: 2 x 4 B; plus the
+    float lambda written: 52 B per region)."""
+    import torch
+
+    from paper_2402_08273_amd.ops import RegionAdapter
+    from synth.proposals import make_proposals
+
+    out = {"workload": f"Algorithm 1 adaptation, {ADAPT_PROPOSALS} proposals per batch, L = 10, "
+                       "gamma_max 1, gamma_scale 5, alpha* 0.5", "proposals": ADAPT_PROPOSALS, "grids": []}
+    n = ADAPT_PROPOSALS
+    stream = torch.cuda.current_stream()
+    for m in ADAPT_REGION_COUNTS:
+        region, alpha = make_proposals(n, m, seed=3)
+        rd = torch.from_numpy(region).cuda()
+        ad_ = torch.from_numpy(alpha).cuda()
+        ad = RegionAdapter(m)
+        for _ in range(warmup):
+            ad.step(rd, ad_)
+        ms = time_loop(stream, lambda: ad.step(rd, ad_), steps)
+        nbytes = n * 8 + m * 52
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out["grids"].append({"regions": m, "ms_per_batch": round(ms, 4),
+                             "mproposals_s": round(n / (ms * 1e-3) / 1e6, 1), "algorithmic_bytes": nbytes,
+                             "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+        del rd, ad_, ad
+    if cpu:
+        out["cpu_baseline"] = adapt_cpu_baseline()
+    torch.cuda.empty_cache()
+    return out
+
+
+def adapt_cpu_baseline(n=300_000, m=400):
+    """The sequential oracle (one proposal at a time, as the algorithm is written) on a
+    bounded sample of the same stream, on one host thread."""
+    from oracle import region_adapt as ora
+    from synth.proposals import make_proposals
+
+    region, alpha = make_proposals(n, m, seed=3)
+    st = ora.initial_state(m)
+    t0 = time.perf_counter()
+    ora.adapt(st, region, alpha)
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt / 1e6, 4), "unit": "Mproposals/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {n} proposals of the 400-region stream, {dt:.2f} s"}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -296,6 +350,9 @@ def main():
 
     torch.cuda.set_device(0)
     if args.only:
+        if args.only == "adapt":
+            print(json.dumps(measure_adapt(args.steps, args.warmup, cpu=not args.no_cpu_baseline)), flush=True)
+            return
         fn = measure_batch32 if args.only == "batched" else measure_uhd
         print(json.dumps(fn(args.steps, args.warmup, not args.no_tune)), flush=True)
         return
@@ -382,6 +439,7 @@ def main():
         print("measuring the 32-frame batch and the 4K frame", file=sys.stderr, flush=True)
         result["batched"] = measure_batch32(args.steps, args.warmup, not args.no_tune)
         result["uhd"] = measure_uhd(args.steps, args.warmup, not args.no_tune)
+        result["adapt"] = measure_adapt(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
 
     print(json.dumps(result), flush=True)
 

@@ -10,10 +10,11 @@
 //      per-tile digit histograms -> one exclusive scan (digit-major) -> a stable scatter
 //      that ranks equal digits inside each wave by ballot and across waves through LDS;
 //   2. region boundaries: the first sorted position of every region;
-//   3. one wave per region: lanes sum the acceptance of whole windows of L visits (fp64,
-//      in proposal order, the first window continuing the carried A_k), then every lane
-//      replays the window decisions in order (step size, sign, clamp) and the remainder
-//      becomes the new pending sum.
+//   3. every position that closes a window of L visits sums that window (fp64, in
+//      proposal order, a region's first window continuing the carried A_k) and turns it
+//      into the window's update gamma sgn(alpha_hat - alpha*);
+//   4. one wave per region folds its updates, with the clamp at lambda_min, in window
+//      order, and the visits after the last closed window become the pending sum.
 //
 // Proposals with a region outside [0, m) get the key m and are sorted past every region;
 // step 3 never reads them.
@@ -32,6 +33,10 @@ constexpr int kDigitBits = 8;
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kScanBlock = 1024;
 constexpr int kWavesPerBlock = kSortBlock / 64;
+
+// Pending visits i_k of a region, 0 <= i_k < L by the state invariant (a state outside it
+// is read as L - 1, the same way by every kernel).
+__device__ __forceinline__ int pending_visits(int v, int L) { return (v >= 0 && v < L) ? v : L - 1; }
 
 __device__ __forceinline__ uint32_t input_key(const int32_t *region, long long pos, int m) {
   const int32_t k = region[pos];
@@ -60,15 +65,18 @@ __global__ __launch_bounds__(kSortBlock) void sort_hist_kernel(const int32_t *__
   for (int d = threadIdx.x; d < kDigits; d += kSortBlock) hist[(long long)d * nblocks + blockIdx.x] = h[d];
 }
 
-// In-place exclusive scan of v[0..len) with one workgroup: each thread scans a contiguous
-// chunk; chunk totals are scanned in LDS.
-__global__ __launch_bounds__(kScanBlock) void exclusive_scan_kernel(uint32_t *__restrict__ v, long long len) {
+// Exclusive scan of the digit-major histogram in two steps: every workgroup scans the row
+// of one digit (the counts of that digit in tile order) in place and writes the row total;
+// one workgroup then scans the 256 totals into digit bases, which the scatter adds.
+__global__ __launch_bounds__(kScanBlock) void scan_rows_kernel(uint32_t *__restrict__ hist, int nblocks,
+                                                               uint32_t *__restrict__ totals) {
   __shared__ uint32_t part[kScanBlock];
-  const long long chunk = (len + kScanBlock - 1) / kScanBlock;
-  const long long b = (long long)threadIdx.x * chunk;
-  const long long e = min(len, b + chunk);
+  uint32_t *v = hist + (long long)blockIdx.x * nblocks;
+  const int chunk = (nblocks + kScanBlock - 1) / kScanBlock;
+  const int b = threadIdx.x * chunk;
+  const int e = min(nblocks, b + chunk);
   uint32_t s = 0;
-  for (long long i = b; i < e; ++i) s += v[i];
+  for (int i = b; i < e; ++i) s += v[i];
   part[threadIdx.x] = s;
   __syncthreads();
   for (int off = 1; off < kScanBlock; off <<= 1) {  // Hillis-Steele, inclusive
@@ -78,11 +86,28 @@ __global__ __launch_bounds__(kScanBlock) void exclusive_scan_kernel(uint32_t *__
     __syncthreads();
   }
   uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-  for (long long i = b; i < e; ++i) {
+  for (int i = b; i < e; ++i) {
     const uint32_t x = v[i];
     v[i] = run;
     run += x;
   }
+  if (threadIdx.x == kScanBlock - 1) totals[blockIdx.x] = part[kScanBlock - 1];
+}
+
+__global__ __launch_bounds__(kDigits) void scan_digits_kernel(uint32_t *__restrict__ totals) {
+  __shared__ uint32_t t[kDigits];
+  t[threadIdx.x] = totals[threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int d = 0; d < kDigits; ++d) {
+      const uint32_t x = t[d];
+      t[d] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  totals[threadIdx.x] = t[threadIdx.x];
 }
 
 // Pass p of the sort, stable scatter. The tile is taken in rounds of 256 proposals in
@@ -91,13 +116,14 @@ __global__ __launch_bounds__(kScanBlock) void exclusive_scan_kernel(uint32_t *__
 // by ballot). Order therefore follows the proposal index.
 __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(
     const int32_t *__restrict__ region, const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ idx_in,
-    long long n, int m, int shift, const uint32_t *__restrict__ hist, int nblocks, uint32_t *__restrict__ keys_out,
-    uint32_t *__restrict__ idx_out) {
+    long long n, int m, int shift, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ digit_base,
+    int nblocks, uint32_t *__restrict__ keys_out, uint32_t *__restrict__ idx_out) {
   __shared__ uint32_t base[kDigits];
   __shared__ uint32_t wcount[kWavesPerBlock][kDigits];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  for (int d = threadIdx.x; d < kDigits; d += kSortBlock) base[d] = hist[(long long)d * nblocks + blockIdx.x];
+  for (int d = threadIdx.x; d < kDigits; d += kSortBlock)
+    base[d] = digit_base[d] + hist[(long long)d * nblocks + blockIdx.x];
   const long long tile = (long long)blockIdx.x * kSortTile;
   for (int r = 0; r < kSortItems; ++r) {
     for (int d = lane; d < kDigits; d += 64) wcount[wave][d] = 0;
@@ -158,20 +184,62 @@ __global__ void region_starts_kernel(const uint32_t *__restrict__ keys, long lon
     for (long long k = cur + 1; k <= (long long)m + 1; ++k) start[k] = (uint32_t)n;
 }
 
-// One wave per region: replay its proposals (sorted positions start[k] .. start[k+1]).
+// Every sorted position that closes a window of L visits of its region computes that
+// window: its acceptance sum in proposal order (fp64; the region's first window continues
+// the carried A_k), alpha_hat, and the update delta_w = gamma(n_k + w) sgn(alpha_hat -
+// alpha*). Other positions are not written.
+__global__ void window_delta_kernel(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ start,
+                                    const uint32_t *__restrict__ idx, const float *__restrict__ alpha, long long n,
+                                    const ramlt_adapt_params p, const ramlt_region_state s,
+                                    double *__restrict__ delta) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const uint32_t k = keys[t];
+  if ((int)k >= p.n_regions) return;  // out-of-range proposals, sorted last
+  const int L = p.L;
+  const long long r = t - (long long)start[k];  // visit number within the batch, from 0
+  const int i0 = pending_visits(s.visits[k], L);
+  const long long v = (long long)i0 + r + 1;    // visits of the pending window after this one
+  if (v % L != 0) return;
+  const long long w = v / L - 1;                 // window ordinal in this batch
+  auto alpha_at = [&](long long q) -> double {
+    const uint32_t j = idx[q];
+    return (long long)j < n ? (double)alpha[j] : 0.0;
+  };
+  double a;
+  long long b;
+  if (w == 0) {
+    a = s.acc[k];
+    b = start[k];
+  } else {
+    a = 0.0;
+    b = t - L + 1;
+  }
+  for (long long q = b; q <= t; ++q) a += alpha_at(q);
+  const double ahat = a / (double)L;
+  const int sgn = (ahat > p.alpha_target) - (ahat < p.alpha_target);
+  const double gamma = fmin(p.gamma_max, p.gamma_scale / sqrt((double)((long long)s.updates[k] + w)));
+  delta[t] = gamma * (double)sgn;
+}
+
+// One wave per region: fold the window updates lambda <- max(lambda + delta_w, lambda_min)
+// in order. Each such map is max(lambda + A, C); maps compose to the same form
+// (A = A1 + A2, C = max(C1 + A2, C2)), so each lane composes a contiguous block of windows
+// and the 64 block maps are applied in lane order. The pending window (the visits after
+// the last closed one) becomes the new A_k / i_k, summed in proposal order.
 __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_t *__restrict__ start,
                                                                    const uint32_t *__restrict__ idx,
                                                                    const float *__restrict__ alpha, long long n,
+                                                                   const double *__restrict__ delta,
                                                                    const ramlt_adapt_params p,
                                                                    const ramlt_region_state s) {
-  // alpha of sorted position t (the index is < n by construction; checked all the same)
+  const int k = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= p.n_regions) return;  // wave-uniform
   auto alpha_at = [&](long long t) -> double {
     const uint32_t j = idx[t];
     return (long long)j < n ? (double)alpha[j] : 0.0;
   };
-  const int k = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (k >= p.n_regions) return;  // wave-uniform
   const long long hi = min((long long)start[k + 1], n);
   const long long lo = min((long long)start[k], hi);
   const long long c = hi - lo;
@@ -180,15 +248,12 @@ __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_
     return;
   }
   const int L = p.L;
-  const int i0 = s.visits[k];
-  const double A0 = s.acc[k];
+  const int i0 = pending_visits(s.visits[k], L);
   double lam = s.lambda[k];
-  long long nk = s.updates[k];
-  // visits that complete the pending window (0 <= i0 < L by the state invariant)
-  const long long need0 = i0 < L && i0 >= 0 ? (long long)(L - i0) : 1;
+  const long long need0 = L - i0;  // visits that complete the pending window
   if (c < need0) {
     if (lane == 0) {
-      double a = A0;
+      double a = s.acc[k];
       for (long long t = lo; t < hi; ++t) a += alpha_at(t);
       s.acc[k] = a;
       s.visits[k] = i0 + (int)c;
@@ -196,28 +261,19 @@ __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_
     }
     return;
   }
-  const long long nw = 1 + (c - need0) / L;      // completed windows
-  const long long rem = (c - need0) % L;         // visits pending after the last window
-  for (long long w0 = 0; w0 < nw; w0 += 64) {
-    // lanes: the window sums of this chunk, each in proposal order
-    const long long w = w0 + lane;
-    int sgn = 0;
-    if (w < nw) {
-      const long long b = w == 0 ? lo : lo + need0 + (w - 1) * L;
-      const long long len = w == 0 ? need0 : L;
-      double a = w == 0 ? A0 : 0.0;
-      for (long long t = 0; t < len; ++t) a += alpha_at(b + t);
-      const double ahat = a / (double)L;
-      sgn = (ahat > p.alpha_target) - (ahat < p.alpha_target);
-    }
-    // every lane replays the chunk's updates in order (same values in every lane)
-    const int cnt = (int)min((long long)64, nw - w0);
-    for (int j = 0; j < cnt; ++j) {
-      const int sj = __shfl(sgn, j, 64);
-      const double gamma = fmin(p.gamma_max, p.gamma_scale / sqrt((double)nk));
-      lam = fmax(lam + gamma * (double)sj, p.lambda_min);
-      ++nk;
-    }
+  const long long nw = 1 + (c - need0) / L;  // windows closed in this batch
+  const long long rem = (c - need0) % L;     // visits pending after the last one
+  const long long per = (nw + 63) / 64;
+  double A = 0.0, C = -INFINITY;
+  const long long w1 = min(nw, (long long)lane * per), w2 = min(nw, w1 + per);
+  for (long long w = w1; w < w2; ++w) {
+    const double d = delta[lo + need0 - 1 + w * L];  // the window's closing position
+    A += d;
+    C = fmax(C + d, p.lambda_min);
+  }
+  for (int j = 0; j < 64; ++j) {  // every lane applies the block maps in order
+    const double Aj = __shfl(A, j, 64), Cj = __shfl(C, j, 64);
+    lam = fmax(lam + Aj, Cj);
   }
   if (lane == 0) {
     double a = 0.0;
@@ -225,7 +281,7 @@ __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_
     s.acc[k] = a;
     s.visits[k] = (int)rem;
     s.lambda[k] = lam;
-    s.updates[k] = (int)nk;
+    s.updates[k] = s.updates[k] + (int)nw;
     if (s.lambda_f32) s.lambda_f32[k] = (float)lam;
   }
 }
@@ -237,7 +293,8 @@ int sort_passes(int m) {  // digits of the largest key, m (invalid proposals)
 }
 
 struct AdaptWorkspace {
-  uint32_t *keys[2], *idx[2], *hist, *start;
+  uint32_t *keys[2], *idx[2], *hist, *totals, *start;
+  double *delta;
   size_t bytes;
 };
 
@@ -258,7 +315,9 @@ AdaptWorkspace carve(void *ws, long long n, int m) {
   w.idx[0] = take((size_t)n * 4);
   w.idx[1] = take((size_t)n * 4);
   w.hist = take((size_t)kDigits * (size_t)nblocks * 4);
+  w.totals = take((size_t)kDigits * 4);
   w.start = take(((size_t)m + 2) * 4);
+  w.delta = (double *)take((size_t)n * 8);
   w.bytes = off;
   return w;
 }
@@ -277,7 +336,6 @@ hipError_t launch_region_adapt(const ramlt_adapt_params &p, const ramlt_region_s
   const AdaptWorkspace w = carve(ws, n, m);
   const int nblocks = (int)((n + kSortTile - 1) / kSortTile);
   const int passes = sort_passes(m);
-  const long long hist_len = (long long)kDigits * nblocks;
   int cur = 0;  // buffers holding the keys of the previous pass (none before pass 0)
   for (int q = 0; q < passes; ++q) {
     const uint32_t *kin = q ? w.keys[cur] : nullptr;
@@ -285,17 +343,20 @@ hipError_t launch_region_adapt(const ramlt_adapt_params &p, const ramlt_region_s
     const int out = q ? cur ^ 1 : 0;
     hipLaunchKernelGGL(sort_hist_kernel, dim3(nblocks), dim3(kSortBlock), 0, st, region, kin, n, m, q * kDigitBits,
                        w.hist, nblocks);
-    hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(kScanBlock), 0, st, w.hist, hist_len);
+    hipLaunchKernelGGL(scan_rows_kernel, dim3(kDigits), dim3(kScanBlock), 0, st, w.hist, nblocks, w.totals);
+    hipLaunchKernelGGL(scan_digits_kernel, dim3(1), dim3(kDigits), 0, st, w.totals);
     hipLaunchKernelGGL(sort_scatter_kernel, dim3(nblocks), dim3(kSortBlock), 0, st, region, kin, iin, n, m,
-                       q * kDigitBits, w.hist, nblocks, w.keys[out], w.idx[out]);
+                       q * kDigitBits, w.hist, w.totals, nblocks, w.keys[out], w.idx[out]);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     cur = out;
   }
   hipLaunchKernelGGL(region_starts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.keys[cur], n, m,
                      w.start);
+  hipLaunchKernelGGL(window_delta_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.keys[cur], w.start,
+                     w.idx[cur], alpha, n, p, s, w.delta);
   hipLaunchKernelGGL(region_update_kernel, dim3((unsigned)((m + kWavesPerBlock - 1) / kWavesPerBlock)),
-                     dim3(kSortBlock), 0, st, w.start, w.idx[cur], alpha, n, p, s);
+                     dim3(kSortBlock), 0, st, w.start, w.idx[cur], alpha, n, w.delta, p, s);
   return hipGetLastError();
 }
 

@@ -1,9 +1,9 @@
 """GPU parity of region_adapt (regional adaptation, Algorithm 1) against the sequential
-FP64 oracle: integer state exactly, A_k exactly (the same fp64 additions in the same
-order), lambda_k to 1e-12 (the same IEEE operations; the square root of the step size is
-the only library call), on streams spanning one to three radix passes, several batches in
-a row, and the edge cases (L = 1, one region, out-of-range keys, acceptance exactly at the
-target, NaN acceptance, empty batches)."""
+FP64 oracle: integer state and every update decision exactly, A_k exactly (the same fp64
+additions in the same order), lambda_k within the rounding bound of summing its updates
+in a different association (lambda_tol), on streams spanning one to three radix passes,
+several batches in a row, and the edge cases (L = 1, one region, out-of-range keys,
+acceptance exactly at the target, NaN acceptance, empty batches)."""
 
 import numpy as np
 import pytest
@@ -20,7 +20,17 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def _compare(name, ad, st, regions=None):
+def lambda_tol(updates):
+    """|lambda_gpu - lambda_oracle| bound for a region that applied `updates` window updates
+    in the batch: both sum the same deltas (|delta| <= gamma_max = 1) in fp64, the oracle
+    one after another, the GPU in up to 64 blocks then block by block, so each side's
+    rounding error is at most (updates + 1) ulp of a partial sum of magnitude
+    <= |lambda_0| + updates <= 31 + updates."""
+    u = np.asarray(updates, dtype=np.float64)
+    return 2.0 * (u + 1.0) * (31.0 + u) * 2.0 ** -52 + 1e-15
+
+
+def _compare(name, ad, st, regions=None, updates_before=None):
     torch.cuda.synchronize()
     sel = slice(None) if regions is None else regions
     vis = ad.visits.cpu().numpy()[sel]
@@ -31,8 +41,10 @@ def _compare(name, ad, st, regions=None):
     assert np.array_equal(vis, st["visits"][sel]), name
     assert np.array_equal(upd, st["updates"][sel]), name
     assert np.array_equal(acc, st["acc"][sel]), (name, np.abs(acc - st["acc"][sel]).max())
-    err = np.abs(lam - st["lambda"][sel]).max()
-    assert err <= 1e-12, (name, err)
+    before = 1 if updates_before is None else updates_before[sel]
+    err = np.abs(lam - st["lambda"][sel])
+    tol = lambda_tol(st["updates"][sel] - before)
+    assert np.all(err <= tol), (name, float(err.max()), float(tol.min()))
     assert np.array_equal(lam32, lam.astype(np.float32)), name
 
 
@@ -44,9 +56,12 @@ def test_region_adapt_parity(m, n, L, batches):
     st = ora.initial_state(m)
     for b in range(batches):
         region, alpha = make_proposals(n, m, seed=m + L, batch=b)
+        before = st["updates"].copy()
         ad.step(_dev(region), _dev(alpha))
         ora.adapt(st, region, alpha, L=L)
-        _compare(f"m={m} batch {b}", ad, st)
+        # the oracle restarts from the GPU's lambda so rounding differences do not compound
+        _compare(f"m={m} batch {b}", ad, st, updates_before=before)
+        st["lambda"] = ad.lam.cpu().numpy().copy()
 
 
 def test_region_adapt_edge_cases():
@@ -69,7 +84,7 @@ def test_region_adapt_edge_cases():
         assert np.array_equal(vis, st["visits"]) and np.array_equal(upd, st["updates"]), i
         # NaN propagates into a pending A_k on both sides; compare with NaN == NaN
         assert np.array_equal(acc, st["acc"], equal_nan=True), i
-        assert np.array_equal(lam, st["lambda"]), i
+        assert np.all(np.abs(lam - st["lambda"]) <= lambda_tol(st["updates"])), i
 
 
 def test_region_adapt_batches_compose_on_gpu():
@@ -81,8 +96,10 @@ def test_region_adapt_batches_compose_on_gpu():
     two.step(_dev(region[:50_001]), _dev(alpha[:50_001]))
     two.step(_dev(region[50_001:]), _dev(alpha[50_001:]))
     torch.cuda.synchronize()
-    for a, b in [(one.lam, two.lam), (one.acc, two.acc), (one.visits, two.visits), (one.updates, two.updates)]:
+    for a, b in [(one.acc, two.acc), (one.visits, two.visits), (one.updates, two.updates)]:
         assert torch.equal(a, b)
+    tol = torch.from_numpy(lambda_tol(one.updates.cpu().numpy())).cuda()
+    assert torch.all((one.lam - two.lam).abs() <= tol)
 
 
 @pytest.mark.slow
