@@ -6,9 +6,9 @@
 // stably (a proposal keeps its place among the proposals of its region), and every region
 // then replays its own sub-sequence:
 //
-//   1. stable LSD radix sort of (region, proposal index) by region, 8 bits per pass:
-//      per-tile digit histograms -> one exclusive scan (digit-major) -> a stable scatter
-//      that ranks equal digits inside each wave by ballot and across waves through LDS;
+//   1. stable LSD radix sort of (region, alpha) by region, 8 bits per pass: per-tile digit
+//      histograms -> an exclusive scan (digit-major) -> a stable scatter that ranks equal
+//      digits inside each wave by ballots (one per digit bit) and across waves in LDS;
 //   2. region boundaries: the first sorted position of every region;
 //   3. every position that closes a window of L visits sums that window (fp64, in
 //      proposal order, a region's first window continuing the carried A_k) and turns it
@@ -110,14 +110,15 @@ __global__ __launch_bounds__(kDigits) void scan_digits_kernel(uint32_t *__restri
   totals[threadIdx.x] = t[threadIdx.x];
 }
 
-// Pass p of the sort, stable scatter. The tile is taken in rounds of 256 proposals in
-// index order; inside a round the rank of a proposal among equal digits is (proposals of
-// earlier rounds, from `base`) + (earlier waves of the round) + (earlier lanes of its wave,
-// by ballot). Order therefore follows the proposal index.
+// Pass p of the sort, stable scatter of (key, alpha). The tile is taken in rounds of 256
+// proposals in index order; inside a round the rank of a proposal among equal digits is
+// (proposals of earlier rounds, from `base`) + (earlier waves of the round) + (earlier
+// lanes of its wave, by ballot). Order therefore follows the proposal index.
 __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(
-    const int32_t *__restrict__ region, const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ idx_in,
-    long long n, int m, int shift, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ digit_base,
-    int nblocks, uint32_t *__restrict__ keys_out, uint32_t *__restrict__ idx_out) {
+    const int32_t *__restrict__ region, const float *__restrict__ alpha, const uint32_t *__restrict__ keys_in,
+    const float *__restrict__ val_in, long long n, int m, int shift, const uint32_t *__restrict__ hist,
+    const uint32_t *__restrict__ digit_base, int nblocks, uint32_t *__restrict__ keys_out,
+    float *__restrict__ val_out) {
   __shared__ uint32_t base[kDigits];
   __shared__ uint32_t wcount[kWavesPerBlock][kDigits];
   const int lane = threadIdx.x & 63;
@@ -130,23 +131,23 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(
     __syncthreads();
     const long long pos = tile + (long long)r * kSortBlock + threadIdx.x;
     const bool valid = pos < n;
-    uint32_t key = 0, idx = 0;
+    uint32_t key = 0;
+    float val = 0.f;
     if (valid) {
       key = keys_in ? keys_in[pos] : input_key(region, pos, m);
-      idx = idx_in ? idx_in[pos] : (uint32_t)pos;
+      val = val_in ? val_in[pos] : alpha[pos];
     }
-    const int d = valid ? (int)((key >> shift) & (kDigits - 1)) : -1;
-    // rank among the earlier lanes of this wave with the same digit
-    unsigned long long todo = __ballot(valid);
-    uint32_t rank = 0;
-    while (todo) {  // wave-uniform: one iteration per distinct digit in the wave
-      const int leader = __ffsll((long long)todo) - 1;
-      const int dl = __shfl(d, leader, 64);
-      const unsigned long long peers = __ballot(valid && d == dl);
-      if (d == dl) rank = (uint32_t)__popcll(peers & __lanemask_lt());
-      if (lane == leader) wcount[wave][dl] = (uint32_t)__popcll(peers);
-      todo &= ~peers;
+    const int d = valid ? (int)((key >> shift) & (kDigits - 1)) : 0;
+    // lanes of this wave with the same digit: the AND over the digit's bits of the lanes
+    // that agree on that bit (one ballot per bit)
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < kDigitBits; ++bit) {
+      const unsigned long long ones = __ballot((d >> bit) & 1);
+      peers &= ((d >> bit) & 1) ? ones : ~ones;
     }
+    const uint32_t rank = (uint32_t)__popcll(peers & __lanemask_lt());
+    if (valid && rank == 0) wcount[wave][d] = (uint32_t)__popcll(peers);  // the digit's first lane
     __syncthreads();
     // per digit: offsets of the waves of this round, and the base for the next round
     for (int dd = threadIdx.x; dd < kDigits; dd += kSortBlock) {
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(
       const uint32_t out = wcount[wave][d] + rank;
       if ((long long)out < n) {  // always true for consistent histograms
         keys_out[out] = key;
-        idx_out[out] = idx;
+        val_out[out] = val;
       }
     }
     __syncthreads();  // wcount is cleared by the next round
@@ -189,7 +190,7 @@ __global__ void region_starts_kernel(const uint32_t *__restrict__ keys, long lon
 // the carried A_k), alpha_hat, and the update delta_w = gamma(n_k + w) sgn(alpha_hat -
 // alpha*). Other positions are not written.
 __global__ void window_delta_kernel(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ start,
-                                    const uint32_t *__restrict__ idx, const float *__restrict__ alpha, long long n,
+                                    const float *__restrict__ alpha_sorted, long long n,
                                     const ramlt_adapt_params p, const ramlt_region_state s,
                                     double *__restrict__ delta) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -202,10 +203,6 @@ __global__ void window_delta_kernel(const uint32_t *__restrict__ keys, const uin
   const long long v = (long long)i0 + r + 1;    // visits of the pending window after this one
   if (v % L != 0) return;
   const long long w = v / L - 1;                 // window ordinal in this batch
-  auto alpha_at = [&](long long q) -> double {
-    const uint32_t j = idx[q];
-    return (long long)j < n ? (double)alpha[j] : 0.0;
-  };
   double a;
   long long b;
   if (w == 0) {
@@ -215,7 +212,7 @@ __global__ void window_delta_kernel(const uint32_t *__restrict__ keys, const uin
     a = 0.0;
     b = t - L + 1;
   }
-  for (long long q = b; q <= t; ++q) a += alpha_at(q);
+  for (long long q = b; q <= t; ++q) a += (double)alpha_sorted[q];
   const double ahat = a / (double)L;
   const int sgn = (ahat > p.alpha_target) - (ahat < p.alpha_target);
   const double gamma = fmin(p.gamma_max, p.gamma_scale / sqrt((double)((long long)s.updates[k] + w)));
@@ -228,18 +225,14 @@ __global__ void window_delta_kernel(const uint32_t *__restrict__ keys, const uin
 // and the 64 block maps are applied in lane order. The pending window (the visits after
 // the last closed one) becomes the new A_k / i_k, summed in proposal order.
 __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_t *__restrict__ start,
-                                                                   const uint32_t *__restrict__ idx,
-                                                                   const float *__restrict__ alpha, long long n,
-                                                                   const double *__restrict__ delta,
+                                                                   const float *__restrict__ alpha_sorted,
+                                                                   long long n, const double *__restrict__ delta,
                                                                    const ramlt_adapt_params p,
                                                                    const ramlt_region_state s) {
   const int k = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (k >= p.n_regions) return;  // wave-uniform
-  auto alpha_at = [&](long long t) -> double {
-    const uint32_t j = idx[t];
-    return (long long)j < n ? (double)alpha[j] : 0.0;
-  };
+  auto alpha_at = [&](long long t) -> double { return (double)alpha_sorted[t]; };
   const long long hi = min((long long)start[k + 1], n);
   const long long lo = min((long long)start[k], hi);
   const long long c = hi - lo;
@@ -271,7 +264,8 @@ __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_
     A += d;
     C = fmax(C + d, p.lambda_min);
   }
-  for (int j = 0; j < 64; ++j) {  // every lane applies the block maps in order
+  const int used = (int)((nw + per - 1) / per);  // lanes holding a block of windows
+  for (int j = 0; j < used; ++j) {  // every lane applies the block maps in order
     const double Aj = __shfl(A, j, 64), Cj = __shfl(C, j, 64);
     lam = fmax(lam + Aj, Cj);
   }
@@ -293,7 +287,8 @@ int sort_passes(int m) {  // digits of the largest key, m (invalid proposals)
 }
 
 struct AdaptWorkspace {
-  uint32_t *keys[2], *idx[2], *hist, *totals, *start;
+  uint32_t *keys[2], *hist, *totals, *start;
+  float *vals[2];
   double *delta;
   size_t bytes;
 };
@@ -312,8 +307,8 @@ AdaptWorkspace carve(void *ws, long long n, int m) {
   };
   w.keys[0] = take((size_t)n * 4);
   w.keys[1] = take((size_t)n * 4);
-  w.idx[0] = take((size_t)n * 4);
-  w.idx[1] = take((size_t)n * 4);
+  w.vals[0] = (float *)take((size_t)n * 4);
+  w.vals[1] = (float *)take((size_t)n * 4);
   w.hist = take((size_t)kDigits * (size_t)nblocks * 4);
   w.totals = take((size_t)kDigits * 4);
   w.start = take(((size_t)m + 2) * 4);
@@ -339,14 +334,14 @@ hipError_t launch_region_adapt(const ramlt_adapt_params &p, const ramlt_region_s
   int cur = 0;  // buffers holding the keys of the previous pass (none before pass 0)
   for (int q = 0; q < passes; ++q) {
     const uint32_t *kin = q ? w.keys[cur] : nullptr;
-    const uint32_t *iin = q ? w.idx[cur] : nullptr;
+    const float *vin = q ? w.vals[cur] : nullptr;
     const int out = q ? cur ^ 1 : 0;
     hipLaunchKernelGGL(sort_hist_kernel, dim3(nblocks), dim3(kSortBlock), 0, st, region, kin, n, m, q * kDigitBits,
                        w.hist, nblocks);
     hipLaunchKernelGGL(scan_rows_kernel, dim3(kDigits), dim3(kScanBlock), 0, st, w.hist, nblocks, w.totals);
     hipLaunchKernelGGL(scan_digits_kernel, dim3(1), dim3(kDigits), 0, st, w.totals);
-    hipLaunchKernelGGL(sort_scatter_kernel, dim3(nblocks), dim3(kSortBlock), 0, st, region, kin, iin, n, m,
-                       q * kDigitBits, w.hist, w.totals, nblocks, w.keys[out], w.idx[out]);
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(nblocks), dim3(kSortBlock), 0, st, region, alpha, kin, vin, n, m,
+                       q * kDigitBits, w.hist, w.totals, nblocks, w.keys[out], w.vals[out]);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     cur = out;
@@ -354,9 +349,9 @@ hipError_t launch_region_adapt(const ramlt_adapt_params &p, const ramlt_region_s
   hipLaunchKernelGGL(region_starts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.keys[cur], n, m,
                      w.start);
   hipLaunchKernelGGL(window_delta_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.keys[cur], w.start,
-                     w.idx[cur], alpha, n, p, s, w.delta);
+                     w.vals[cur], n, p, s, w.delta);
   hipLaunchKernelGGL(region_update_kernel, dim3((unsigned)((m + kWavesPerBlock - 1) / kWavesPerBlock)),
-                     dim3(kSortBlock), 0, st, w.start, w.idx[cur], alpha, n, w.delta, p, s);
+                     dim3(kSortBlock), 0, st, w.start, w.vals[cur], n, w.delta, p, s);
   return hipGetLastError();
 }
 
