@@ -13,8 +13,9 @@
 //   3. every position that closes a window of L visits sums that window (fp64, in
 //      proposal order, a region's first window continuing the carried A_k) and turns it
 //      into the window's update gamma sgn(alpha_hat - alpha*);
-//   4. one wave per region folds its updates, with the clamp at lambda_min, in window
-//      order, and the visits after the last closed window become the pending sum.
+//   4. one thread per region (one wave for regions closing more than 64 windows) folds
+//      its updates, with the clamp at lambda_min, in window order, and the visits after
+//      the last closed window become the pending sum.
 //
 // Proposals with a region outside [0, m) get the key m and are sorted past every region;
 // step 3 never reads them.
@@ -110,36 +111,60 @@ __global__ __launch_bounds__(kDigits) void scan_digits_kernel(uint32_t *__restri
   totals[threadIdx.x] = t[threadIdx.x];
 }
 
-// Pass p of the sort, stable scatter of (key, alpha). The tile is taken in rounds of 256
-// proposals in index order; inside a round the rank of a proposal among equal digits is
-// (proposals of earlier rounds, from `base`) + (earlier waves of the round) + (earlier
-// lanes of its wave, by ballot). Order therefore follows the proposal index.
+// Pass p of the sort, stable scatter of (key, alpha). The tile is ranked in rounds of 256
+// proposals in index order: the rank of a proposal among equal digits is (earlier rounds)
+// + (earlier waves of the round) + (earlier lanes of its wave, from one ballot per digit
+// bit), so order follows the proposal index. Ranked proposals are first placed in LDS in
+// digit order, then written out run by run, so consecutive threads write consecutive
+// addresses of one digit's destination range.
 __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(
     const int32_t *__restrict__ region, const float *__restrict__ alpha, const uint32_t *__restrict__ keys_in,
     const float *__restrict__ val_in, long long n, int m, int shift, const uint32_t *__restrict__ hist,
     const uint32_t *__restrict__ digit_base, int nblocks, uint32_t *__restrict__ keys_out,
     float *__restrict__ val_out) {
-  __shared__ uint32_t base[kDigits];
+  __shared__ uint32_t lkey[kSortTile];
+  __shared__ float lval[kSortTile];
+  __shared__ uint32_t lstart[kDigits];  // first LDS slot of each digit in this tile
+  __shared__ uint32_t gbase[kDigits];   // first destination of each digit from this tile
+  __shared__ uint32_t run[kDigits];     // proposals of each digit ranked so far
   __shared__ uint32_t wcount[kWavesPerBlock][kDigits];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  for (int d = threadIdx.x; d < kDigits; d += kSortBlock)
-    base[d] = digit_base[d] + hist[(long long)d * nblocks + blockIdx.x];
   const long long tile = (long long)blockIdx.x * kSortTile;
+  const int count = (int)min((long long)kSortTile, n - tile);
+  // this tile's digit counts (the same as its histogram column), their exclusive prefix
+  for (int d = threadIdx.x; d < kDigits; d += kSortBlock) run[d] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < count; i += kSortBlock) {
+    const uint32_t key = keys_in ? keys_in[tile + i] : input_key(region, tile + i, m);
+    atomicAdd(&run[(key >> shift) & (kDigits - 1)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int d = 0; d < kDigits; ++d) {
+      lstart[d] = acc;
+      acc += run[d];
+    }
+  }
+  for (int d = threadIdx.x; d < kDigits; d += kSortBlock)
+    gbase[d] = digit_base[d] + hist[(long long)d * nblocks + blockIdx.x];
+  __syncthreads();
+  for (int d = threadIdx.x; d < kDigits; d += kSortBlock) run[d] = 0;
   for (int r = 0; r < kSortItems; ++r) {
     for (int d = lane; d < kDigits; d += 64) wcount[wave][d] = 0;
     __syncthreads();
-    const long long pos = tile + (long long)r * kSortBlock + threadIdx.x;
-    const bool valid = pos < n;
+    const int i = r * kSortBlock + threadIdx.x;  // slot in the tile, in index order
+    const bool valid = i < count;
     uint32_t key = 0;
     float val = 0.f;
     if (valid) {
-      key = keys_in ? keys_in[pos] : input_key(region, pos, m);
-      val = val_in ? val_in[pos] : alpha[pos];
+      key = keys_in ? keys_in[tile + i] : input_key(region, tile + i, m);
+      val = val_in ? val_in[tile + i] : alpha[tile + i];
     }
     const int d = valid ? (int)((key >> shift) & (kDigits - 1)) : 0;
     // lanes of this wave with the same digit: the AND over the digit's bits of the lanes
-    // that agree on that bit (one ballot per bit)
+    // that agree on that bit
     unsigned long long peers = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < kDigitBits; ++bit) {
@@ -149,33 +174,44 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(
     const uint32_t rank = (uint32_t)__popcll(peers & __lanemask_lt());
     if (valid && rank == 0) wcount[wave][d] = (uint32_t)__popcll(peers);  // the digit's first lane
     __syncthreads();
-    // per digit: offsets of the waves of this round, and the base for the next round
+    // per digit: offsets of the waves of this round, and the running count
     for (int dd = threadIdx.x; dd < kDigits; dd += kSortBlock) {
-      uint32_t run = base[dd];
+      uint32_t acc = run[dd];
 #pragma unroll
       for (int w = 0; w < kWavesPerBlock; ++w) {
         const uint32_t c = wcount[w][dd];
-        wcount[w][dd] = run;
-        run += c;
+        wcount[w][dd] = acc;
+        acc += c;
       }
-      base[dd] = run;
+      run[dd] = acc;
     }
     __syncthreads();
     if (valid) {
-      const uint32_t out = wcount[wave][d] + rank;
-      if ((long long)out < n) {  // always true for consistent histograms
-        keys_out[out] = key;
-        val_out[out] = val;
+      const uint32_t slot = lstart[d] + wcount[wave][d] + rank;
+      if ((int)slot < count) {  // always true: the counts above are this tile's
+        lkey[slot] = key;
+        lval[slot] = val;
       }
     }
     __syncthreads();  // wcount is cleared by the next round
+  }
+  // write out in slot order: runs of equal digits go to consecutive destinations
+  for (int i = threadIdx.x; i < count; i += kSortBlock) {
+    const uint32_t key = lkey[i];
+    const int d = (int)((key >> shift) & (kDigits - 1));
+    const long long out = (long long)gbase[d] + (i - (int)lstart[d]);
+    if (out < n) {  // always true for consistent histograms
+      keys_out[out] = key;
+      val_out[out] = lval[i];
+    }
   }
 }
 
 // start[k] = first sorted position with key >= k, for k = 0..m+1 (start[m+1] = n).
 __global__ void region_starts_kernel(const uint32_t *__restrict__ keys, long long n, int m,
-                                     uint32_t *__restrict__ start) {
+                                     uint32_t *__restrict__ start, uint32_t *__restrict__ n_big) {
   const long long pos = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos == 0) *n_big = 0;  // the list of large regions is rebuilt by region_update_kernel
   if (pos >= n) return;
   // keys are <= m by construction; the clamps keep every write inside start[0 .. m+1]
   const long long cur = min((long long)keys[pos], (long long)m);
@@ -219,64 +255,111 @@ __global__ void window_delta_kernel(const uint32_t *__restrict__ keys, const uin
   delta[t] = gamma * (double)sgn;
 }
 
-// One wave per region: fold the window updates lambda <- max(lambda + delta_w, lambda_min)
-// in order. Each such map is max(lambda + A, C); maps compose to the same form
-// (A = A1 + A2, C = max(C1 + A2, C2)), so each lane composes a contiguous block of windows
-// and the 64 block maps are applied in lane order. The pending window (the visits after
-// the last closed one) becomes the new A_k / i_k, summed in proposal order.
+// Region k's share of the sorted batch and the pending-window bookkeeping.
+struct RegionSpan {
+  long long lo, hi, need0;  // sorted positions [lo, hi); visits that close the pending window
+  int i0;
+};
+
+__device__ __forceinline__ RegionSpan region_span(const uint32_t *start, long long n, int k, const ramlt_adapt_params &p,
+                                                  const ramlt_region_state &s) {
+  RegionSpan r;
+  r.hi = min((long long)start[k + 1], n);
+  r.lo = min((long long)start[k], r.hi);
+  r.i0 = pending_visits(s.visits[k], p.L);
+  r.need0 = p.L - r.i0;
+  return r;
+}
+
+constexpr int kSmallWindows = 64;  // regions closing more windows go to the wave kernel
+
+// One thread per region. A region whose batch closes at most kSmallWindows windows is
+// finished here: its window updates lambda <- max(lambda + delta_w, lambda_min) applied in
+// order, the visits after the last closed window summed (in proposal order) into the new
+// A_k / i_k. Larger regions are listed for region_update_wave_kernel.
 __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_t *__restrict__ start,
                                                                    const float *__restrict__ alpha_sorted,
                                                                    long long n, const double *__restrict__ delta,
                                                                    const ramlt_adapt_params p,
-                                                                   const ramlt_region_state s) {
-  const int k = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (k >= p.n_regions) return;  // wave-uniform
-  auto alpha_at = [&](long long t) -> double { return (double)alpha_sorted[t]; };
-  const long long hi = min((long long)start[k + 1], n);
-  const long long lo = min((long long)start[k], hi);
-  const long long c = hi - lo;
-  if (c == 0) {
-    if (s.lambda_f32 && lane == 0) s.lambda_f32[k] = (float)s.lambda[k];
+                                                                   const ramlt_region_state s,
+                                                                   uint32_t *__restrict__ big,
+                                                                   uint32_t *__restrict__ n_big) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= p.n_regions) return;
+  const RegionSpan r = region_span(start, n, k, p, s);
+  const long long c = r.hi - r.lo;
+  double lam = s.lambda[k];
+  if (c < r.need0) {  // no window closes: only the pending sum grows
+    if (c > 0) {
+      double a = s.acc[k];
+      for (long long t = r.lo; t < r.hi; ++t) a += (double)alpha_sorted[t];
+      s.acc[k] = a;
+      s.visits[k] = r.i0 + (int)c;
+    }
+    if (s.lambda_f32) s.lambda_f32[k] = (float)lam;
     return;
   }
   const int L = p.L;
-  const int i0 = pending_visits(s.visits[k], L);
-  double lam = s.lambda[k];
-  const long long need0 = L - i0;  // visits that complete the pending window
-  if (c < need0) {
-    if (lane == 0) {
-      double a = s.acc[k];
-      for (long long t = lo; t < hi; ++t) a += alpha_at(t);
-      s.acc[k] = a;
-      s.visits[k] = i0 + (int)c;
-      if (s.lambda_f32) s.lambda_f32[k] = (float)lam;
-    }
+  const long long nw = 1 + (c - r.need0) / L;
+  if (nw > kSmallWindows) {
+    big[atomicAdd(n_big, 1u)] = (uint32_t)k;  // order of the list is irrelevant
     return;
   }
-  const long long nw = 1 + (c - need0) / L;  // windows closed in this batch
-  const long long rem = (c - need0) % L;     // visits pending after the last one
-  const long long per = (nw + 63) / 64;
-  double A = 0.0, C = -INFINITY;
-  const long long w1 = min(nw, (long long)lane * per), w2 = min(nw, w1 + per);
-  for (long long w = w1; w < w2; ++w) {
-    const double d = delta[lo + need0 - 1 + w * L];  // the window's closing position
-    A += d;
-    C = fmax(C + d, p.lambda_min);
-  }
-  const int used = (int)((nw + per - 1) / per);  // lanes holding a block of windows
-  for (int j = 0; j < used; ++j) {  // every lane applies the block maps in order
-    const double Aj = __shfl(A, j, 64), Cj = __shfl(C, j, 64);
-    lam = fmax(lam + Aj, Cj);
-  }
-  if (lane == 0) {
-    double a = 0.0;
-    for (long long t = hi - rem; t < hi; ++t) a += alpha_at(t);
-    s.acc[k] = a;
-    s.visits[k] = (int)rem;
-    s.lambda[k] = lam;
-    s.updates[k] = s.updates[k] + (int)nw;
-    if (s.lambda_f32) s.lambda_f32[k] = (float)lam;
+  const long long rem = (c - r.need0) % L;
+  for (long long w = 0; w < nw; ++w) lam = fmax(lam + delta[r.lo + r.need0 - 1 + w * L], p.lambda_min);
+  double a = 0.0;
+  for (long long t = r.hi - rem; t < r.hi; ++t) a += (double)alpha_sorted[t];
+  s.acc[k] = a;
+  s.visits[k] = (int)rem;
+  s.lambda[k] = lam;
+  s.updates[k] = s.updates[k] + (int)nw;
+  if (s.lambda_f32) s.lambda_f32[k] = (float)lam;
+}
+
+// One wave per listed region (grid-stride over the list): the window updates are maps
+// lambda -> max(lambda + A, C); maps compose to the same form (A = A1 + A2,
+// C = max(C1 + A2, C2)), so each lane composes a contiguous block of windows and the
+// block maps are applied in lane order.
+__global__ __launch_bounds__(kSortBlock) void region_update_wave_kernel(const uint32_t *__restrict__ start,
+                                                                        const float *__restrict__ alpha_sorted,
+                                                                        long long n, const double *__restrict__ delta,
+                                                                        const ramlt_adapt_params p,
+                                                                        const ramlt_region_state s,
+                                                                        const uint32_t *__restrict__ big,
+                                                                        const uint32_t *__restrict__ n_big) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t count = *n_big;
+  const uint32_t waves = gridDim.x * kWavesPerBlock;
+  for (uint32_t i = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); i < count; i += waves) {
+    const int k = (int)big[i];
+    const RegionSpan r = region_span(start, n, k, p, s);
+    const int L = p.L;
+    const long long c = r.hi - r.lo;
+    const long long nw = 1 + (c - r.need0) / L;  // > kSmallWindows
+    const long long rem = (c - r.need0) % L;
+    const long long per = (nw + 63) / 64;
+    double A = 0.0, C = -INFINITY;
+    const long long w1 = min(nw, (long long)lane * per), w2 = min(nw, w1 + per);
+    for (long long w = w1; w < w2; ++w) {
+      const double d = delta[r.lo + r.need0 - 1 + w * L];  // the window's closing position
+      A += d;
+      C = fmax(C + d, p.lambda_min);
+    }
+    double lam = s.lambda[k];
+    const int used = (int)((nw + per - 1) / per);  // lanes holding a block of windows
+    for (int j = 0; j < used; ++j) {              // every lane applies the block maps in order
+      const double Aj = __shfl(A, j, 64), Cj = __shfl(C, j, 64);
+      lam = fmax(lam + Aj, Cj);
+    }
+    if (lane == 0) {
+      double a = 0.0;
+      for (long long t = r.hi - rem; t < r.hi; ++t) a += (double)alpha_sorted[t];
+      s.acc[k] = a;
+      s.visits[k] = (int)rem;
+      s.lambda[k] = lam;
+      s.updates[k] = s.updates[k] + (int)nw;
+      if (s.lambda_f32) s.lambda_f32[k] = (float)lam;
+    }
   }
 }
 
@@ -287,7 +370,7 @@ int sort_passes(int m) {  // digits of the largest key, m (invalid proposals)
 }
 
 struct AdaptWorkspace {
-  uint32_t *keys[2], *hist, *totals, *start;
+  uint32_t *keys[2], *hist, *totals, *start, *big, *n_big;
   float *vals[2];
   double *delta;
   size_t bytes;
@@ -312,6 +395,8 @@ AdaptWorkspace carve(void *ws, long long n, int m) {
   w.hist = take((size_t)kDigits * (size_t)nblocks * 4);
   w.totals = take((size_t)kDigits * 4);
   w.start = take(((size_t)m + 2) * 4);
+  w.big = take((size_t)m * 4);
+  w.n_big = take(4);
   w.delta = (double *)take((size_t)n * 8);
   w.bytes = off;
   return w;
@@ -347,11 +432,14 @@ hipError_t launch_region_adapt(const ramlt_adapt_params &p, const ramlt_region_s
     cur = out;
   }
   hipLaunchKernelGGL(region_starts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.keys[cur], n, m,
-                     w.start);
+                     w.start, w.n_big);
   hipLaunchKernelGGL(window_delta_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.keys[cur], w.start,
                      w.vals[cur], n, p, s, w.delta);
-  hipLaunchKernelGGL(region_update_kernel, dim3((unsigned)((m + kWavesPerBlock - 1) / kWavesPerBlock)),
-                     dim3(kSortBlock), 0, st, w.start, w.vals[cur], n, w.delta, p, s);
+  hipLaunchKernelGGL(region_update_kernel, dim3((unsigned)((m + kSortBlock - 1) / kSortBlock)), dim3(kSortBlock), 0,
+                     st, w.start, w.vals[cur], n, w.delta, p, s, w.big, w.n_big);
+  // large regions: at most n / (L kSmallWindows) of them; a fixed grid strides the list
+  hipLaunchKernelGGL(region_update_wave_kernel, dim3(256), dim3(kSortBlock), 0, st, w.start, w.vals[cur], n, w.delta,
+                     p, s, w.big, w.n_big);
   return hipGetLastError();
 }
 
