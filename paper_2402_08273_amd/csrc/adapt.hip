@@ -248,7 +248,8 @@ __global__ void window_delta_kernel(const uint32_t *__restrict__ keys, const uin
     a = 0.0;
     b = t - L + 1;
   }
-  for (long long q = b; q <= t; ++q) a += (double)alpha_sorted[q];
+#pragma unroll 8
+  for (long long q = b; q <= t; ++q) a += (double)alpha_sorted[q];  // loads issue ahead of the adds
   const double ahat = a / (double)L;
   const int sgn = (ahat > p.alpha_target) - (ahat < p.alpha_target);
   const double gamma = fmin(p.gamma_max, p.gamma_scale / sqrt((double)((long long)s.updates[k] + w)));
