@@ -341,7 +341,8 @@ __global__ __launch_bounds__(kSortBlock) void region_update_wave_kernel(const ui
     const long long per = (nw + 63) / 64;
     double A = 0.0, C = -INFINITY;
     const long long w1 = min(nw, (long long)lane * per), w2 = min(nw, w1 + per);
-    for (long long w = w1; w < w2; ++w) {
+#pragma unroll 16
+    for (long long w = w1; w < w2; ++w) {  // loads issue ahead of the dependent fold
       const double d = delta[r.lo + r.need0 - 1 + w * L];  // the window's closing position
       A += d;
       C = fmax(C + d, p.lambda_min);
