@@ -13,7 +13,7 @@
 //   3. every position that closes a window of L visits sums that window (fp64, in
 //      proposal order, a region's first window continuing the carried A_k) and turns it
 //      into the window's update gamma sgn(alpha_hat - alpha*);
-//   4. one thread per region (one wave for regions closing more than 64 windows) folds
+//   4. one thread per region (a workgroup for regions closing more than 64 windows) folds
 //      its updates, with the clamp at lambda_min, in window order, and the visits after
 //      the last closed window become the pending sum.
 //
@@ -277,7 +277,7 @@ constexpr int kSmallWindows = 64;  // regions closing more windows go to the wav
 // One thread per region. A region whose batch closes at most kSmallWindows windows is
 // finished here: its window updates lambda <- max(lambda + delta_w, lambda_min) applied in
 // order, the visits after the last closed window summed (in proposal order) into the new
-// A_k / i_k. Larger regions are listed for region_update_wave_kernel.
+// A_k / i_k. Larger regions are listed for region_update_wave_kernel (a workgroup each).
 __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_t *__restrict__ start,
                                                                    const float *__restrict__ alpha_sorted,
                                                                    long long n, const double *__restrict__ delta,
@@ -317,10 +317,10 @@ __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_
   if (s.lambda_f32) s.lambda_f32[k] = (float)lam;
 }
 
-// One wave per listed region (grid-stride over the list): the window updates are maps
-// lambda -> max(lambda + A, C); maps compose to the same form (A = A1 + A2,
-// C = max(C1 + A2, C2)), so each lane composes a contiguous block of windows and the
-// block maps are applied in lane order.
+// One workgroup per listed region (grid-stride over the list): the window updates are
+// maps lambda -> max(lambda + A, C); maps compose to the same form (A = A1 + A2,
+// C = max(C1 + A2, C2)), so each thread composes a contiguous block of windows and thread
+// 0 applies the 256 block maps in thread order.
 __global__ __launch_bounds__(kSortBlock) void region_update_wave_kernel(const uint32_t *__restrict__ start,
                                                                         const float *__restrict__ alpha_sorted,
                                                                         long long n, const double *__restrict__ delta,
@@ -328,32 +328,31 @@ __global__ __launch_bounds__(kSortBlock) void region_update_wave_kernel(const ui
                                                                         const ramlt_region_state s,
                                                                         const uint32_t *__restrict__ big,
                                                                         const uint32_t *__restrict__ n_big) {
-  const int lane = threadIdx.x & 63;
+  __shared__ double mA[kSortBlock], mC[kSortBlock];
   const uint32_t count = *n_big;
-  const uint32_t waves = gridDim.x * kWavesPerBlock;
-  for (uint32_t i = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); i < count; i += waves) {
+  for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {  // block-uniform
     const int k = (int)big[i];
     const RegionSpan r = region_span(start, n, k, p, s);
     const int L = p.L;
     const long long c = r.hi - r.lo;
     const long long nw = 1 + (c - r.need0) / L;  // > kSmallWindows
     const long long rem = (c - r.need0) % L;
-    const long long per = (nw + 63) / 64;
+    const long long per = (nw + kSortBlock - 1) / kSortBlock;
     double A = 0.0, C = -INFINITY;
-    const long long w1 = min(nw, (long long)lane * per), w2 = min(nw, w1 + per);
+    const long long w1 = min(nw, (long long)threadIdx.x * per), w2 = min(nw, w1 + per);
 #pragma unroll 16
     for (long long w = w1; w < w2; ++w) {  // loads issue ahead of the dependent fold
       const double d = delta[r.lo + r.need0 - 1 + w * L];  // the window's closing position
       A += d;
       C = fmax(C + d, p.lambda_min);
     }
-    double lam = s.lambda[k];
-    const int used = (int)((nw + per - 1) / per);  // lanes holding a block of windows
-    for (int j = 0; j < used; ++j) {              // every lane applies the block maps in order
-      const double Aj = __shfl(A, j, 64), Cj = __shfl(C, j, 64);
-      lam = fmax(lam + Aj, Cj);
-    }
-    if (lane == 0) {
+    mA[threadIdx.x] = A;
+    mC[threadIdx.x] = C;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double lam = s.lambda[k];
+      const int used = (int)((nw + per - 1) / per);  // threads holding a block of windows
+      for (int j = 0; j < used; ++j) lam = fmax(lam + mA[j], mC[j]);
       double a = 0.0;
       for (long long t = r.hi - rem; t < r.hi; ++t) a += (double)alpha_sorted[t];
       s.acc[k] = a;
@@ -362,6 +361,7 @@ __global__ __launch_bounds__(kSortBlock) void region_update_wave_kernel(const ui
       s.updates[k] = s.updates[k] + (int)nw;
       if (s.lambda_f32) s.lambda_f32[k] = (float)lam;
     }
+    __syncthreads();  // mA / mC are reused for the next listed region
   }
 }
 
