@@ -17,7 +17,10 @@ for a reader to check against the paper by eye:
   and the MSE loss used to drive the adjoint;
 * :mod:`oracle.region_adapt` -- the regional adaptation of lambda_k from a stream of
   (region, acceptance probability) proposals: Algorithm 1 with eqs. est_exp_acc,
-  update_lambda and step_size_n, one proposal at a time.
+  update_lambda and step_size_n, one proposal at a time;
+* :mod:`oracle.quadtree` -- quadtree partitions (a forest: one tree for the screen, one per
+  top-level grid cell for the 4-D partition), leaf lookup and the counting-based refinement
+  of Sec. 5.4, pointer-based.
 
 Parity status: every function is pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_*.py`` (brute force on tiny inputs, exact rational examples, closed forms
@@ -39,4 +42,4 @@ from .regional_filter import (  # noqa: F401
     mse_loss_seed,
     filter_backward,
 )
-from . import region_adapt  # noqa: F401
+from . import quadtree, region_adapt  # noqa: F401
