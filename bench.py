@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="skip the batched and 4K measurements")
     p.add_argument("--no-tune", action="store_true",
                    help="use the library's default filter schedule instead of the autotuned one")
-    p.add_argument("--only", choices=["batched", "uhd", "adapt"], default=None,
+    p.add_argument("--only", choices=["batched", "uhd", "adapt", "quadtree"], default=None,
                    help="measure only the 32-frame batch or only the 4K frame and print that object "
                         "(for profiling one workload)")
     p.add_argument("--cpu-rows", type=int, default=0, help="rows of the frame the oracle times (0 = auto)")
@@ -331,6 +331,108 @@ def adapt_cpu_baseline(n=300_000, m=400):
             "sample": f"the first {n} proposals of the 400-region stream, {dt:.2f} s"}
 
 
+def _grow_quadtree(wl, device="cuda"):
+    """The forest of a quadtree workload grown over its refinement rounds on the device
+    (lookups with visit counting, then a refinement that hands lambda and n_k / 4 to the
+    children), and the timed lookup batch."""
+    import torch
+
+    from paper_2402_08273_amd.ops import Quadtree, RegionAdapter
+    from synth.points import make_points
+
+    R = wl["n_roots"]
+    t = Quadtree(R, wl["capacity"], device)
+    ad = RegionAdapter(wl["capacity"], device=device)
+    root, x, y = make_points(wl["grow_points"], R, seed=wl["seed"], batch=0)
+    dev = lambda a: torch.from_numpy(a).to(device)
+    g = (dev(x), dev(y), None if R == 1 else dev(root))
+    for _ in range(wl["rounds"]):
+        t.lookup(*g)
+        t.refine(wl["m_split"], ad)
+    del g
+    root, x, y = make_points(wl["lookup_points"], R, seed=wl["seed"], batch=1)
+    batch = (dev(x), dev(y), None if R == 1 else dev(root))
+    return t, ad, batch
+
+
+def measure_quadtree(steps, warmup, cpu=True):
+    """Quadtree partitions (2-D: one tree; 4-D: a tree per cell of the 20 x 20 screen grid),
+    grown with M_split = 5000 after batches of 10^7 lookups: the lookup of 16 M points with
+    visit counting (one step = one batch; algorithmic bytes = x, y (and the root for 4-D)
+    read + the leaf written: 12 or 16 B per point; the node table is LDS/L2 resident) and one
+    refinement pass on the counts of that batch, state inheritance included."""
+    import torch
+
+    from synth.workloads import QUADTREE_2D, QUADTREE_4D
+
+    stream = torch.cuda.current_stream()
+    out = {"workload": "quadtree lookup of 16 M points with visit counting, and one refinement pass "
+                       "(M_split 5000) on their counts", "trees": []}
+    for name, wl in (("2d", QUADTREE_2D), ("4d", QUADTREE_4D)):
+        t, ad, (x, y, root) = _grow_quadtree(wl)
+        n = x.numel()
+        leaf = torch.empty(n, device=x.device, dtype=torch.int32)
+        fn = lambda: t.lookup(x, y, root, out=leaf)
+        for _ in range(warmup):
+            fn()
+        nodes = t.n_nodes
+        ms = time_loop(stream, fn, steps)
+        ms_nc = time_loop(stream, lambda: t.lookup(x, y, root, count=False, out=leaf), steps)
+        bpp = 12 if root is None else 16
+        gbs = n * bpp / (ms * 1e-3) / 1e9
+        # one refinement on the counts of one batch: restore the same tree before each pass
+        t.visits.zero_()
+        fn()
+        snap = [a.clone() for a in (t.child, t.depth, t.visits, t.n_nodes_dev, ad.lam, ad.acc, ad.visits,
+                                    ad.updates, ad.lam_f32)]
+        live = (t.child, t.depth, t.visits, t.n_nodes_dev, ad.lam, ad.acc, ad.visits, ad.updates, ad.lam_f32)
+        times = []
+        for rep in range(max(3, steps)):
+            for a, b in zip(live, snap):
+                a.copy_(b)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            t.refine(wl["m_split"], ad)
+            e1.record(stream)
+            times.append((e0, e1))
+        torch.cuda.synchronize()
+        rms = sorted(a.elapsed_time(b) for a, b in times)[len(times) // 2]
+        depth = int(t.depth[:t.n_nodes].max())
+        out["trees"].append({"partition": name, "roots": wl["n_roots"], "nodes": nodes, "max_depth": depth,
+                             "splits_in_timed_refine": (t.n_nodes - nodes) // 4,
+                             "lookup_ms": round(ms, 4), "glookups_s": round(n / (ms * 1e-3) / 1e9, 2),
+                             "lookup_nocount_ms": round(ms_nc, 4),
+                             "bytes_per_point": bpp, "achieved_gbs": round(gbs, 1),
+                             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "refine_ms": round(rms, 4)})
+        del t, ad, x, y, root, leaf, snap, live
+    if cpu:
+        out["cpu_baseline"] = quadtree_cpu_baseline()
+    torch.cuda.empty_cache()
+    return out
+
+
+def quadtree_cpu_baseline(n=2_000_000):
+    """The oracle's vectorised lookup (every point descends one level per step) on the 2-D
+    forest grown by the oracle itself from the first 10^6 growth points, timed on a bounded
+    sample of the timed batch, on one host thread."""
+    from oracle import quadtree as oqt
+    from synth.points import make_points
+    from synth.workloads import QUADTREE_2D as wl
+
+    f = oqt.Forest(1, wl["capacity"])
+    _, gx, gy = make_points(1_000_000, 1, seed=wl["seed"], batch=0)
+    for _ in range(wl["rounds"]):
+        f.lookup_many(None, gx, gy)
+        f.refine(wl["m_split"] // 10)
+    _, x, y = make_points(n, 1, seed=wl["seed"], batch=1)
+    t0 = time.perf_counter()
+    f.lookup_many(None, x, y)
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt / 1e6, 3), "unit": "Mlookups/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} points on a {len(f.nodes)}-node tree (10^6 growth points per round, "
+                      f"M_split 500), {dt:.2f} s"}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -352,6 +454,9 @@ def main():
     if args.only:
         if args.only == "adapt":
             print(json.dumps(measure_adapt(args.steps, args.warmup, cpu=not args.no_cpu_baseline)), flush=True)
+            return
+        if args.only == "quadtree":
+            print(json.dumps(measure_quadtree(args.steps, args.warmup, cpu=not args.no_cpu_baseline)), flush=True)
             return
         fn = measure_batch32 if args.only == "batched" else measure_uhd
         print(json.dumps(fn(args.steps, args.warmup, not args.no_tune)), flush=True)
@@ -440,6 +545,7 @@ def main():
         result["batched"] = measure_batch32(args.steps, args.warmup, not args.no_tune)
         result["uhd"] = measure_uhd(args.steps, args.warmup, not args.no_tune)
         result["adapt"] = measure_adapt(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
+        result["quadtree"] = measure_quadtree(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
 
     print(json.dumps(result), flush=True)
 

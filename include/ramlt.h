@@ -220,6 +220,69 @@ int region_adapt(const ramlt_adapt_params *params, const ramlt_region_state *sta
 /* Workspace bytes of region_adapt (0 for n_proposals <= 0 or invalid sizes). */
 size_t ramlt_adapt_workspace_size(int64_t n_proposals, int32_t n_regions);
 
+/* ------------------------------------------------------------------------------------
+ * Quadtree partitions (Sec. 5.4 "Quadtree Partition", "Refining Quadtree Partition",
+ * "4d Partition"; Sec. 6 "Explicit Synchronization for Refinement of Partitions").
+ *
+ * A forest of n_roots quadtrees, each over the unit square [0,1]^2: one tree for the 2-D
+ * screen partition; one tree per screen grid cell for the 4-D partition (the tree then
+ * covers the two coordinates of the outgoing direction). The regions are the leaves; a
+ * node's index is its region key (for region_adapt and its state arrays).
+ *
+ * Nodes are numbered in creation order: the roots 0..n_roots-1, then the four children of
+ * each split, consecutively (child q covers the quadrant q = right + 2 * top). Node i is
+ * stored as child[i] (index of its first child, or -1 for a leaf) and depth[i] (0 for a
+ * root; a node at depth d has side 2^-d). Its square follows from the path of quadrants
+ * from its root. Leaves deeper than RAMLT_QT_MAX_DEPTH are never made, so every square
+ * corner is exact in float32. */
+typedef struct ramlt_quadtree {
+  int32_t n_roots;        /* trees, 1..capacity                                           */
+  int32_t capacity;       /* entries of child / depth / visits, 1..RAMLT_MAX_QT_NODES      */
+  int32_t *child;         /* DEVICE [capacity]; entries >= *n_nodes are unused            */
+  int32_t *depth;         /* DEVICE [capacity]                                            */
+  int32_t *visits;        /* DEVICE [capacity]: lookups counted per leaf since the last
+                             refinement (the split criterion; separate from the region
+                             state's i_k, which restarts every L visits)                 */
+  int32_t *n_nodes;       /* DEVICE [1]: nodes in use                                     */
+} ramlt_quadtree;
+
+#define RAMLT_QT_MAX_DEPTH 20
+#define RAMLT_MAX_QT_NODES (1 << 26)
+#define RAMLT_MAX_QT_POINTS (1LL << 30)
+
+/* Reset the forest to its n_roots roots (each a leaf at depth 0 with no visits); sets
+ * *n_nodes = n_roots. The tree struct is HOST memory holding device pointers. */
+int quadtree_init(const ramlt_quadtree *tree, void *stream);
+
+/* Region of each point: descend from tree root[i] (root == NULL: tree 0), choosing at a
+ * node with lower corner (x0, y0) and side s the child (x >= x0 + s/2) + 2 (y >= y0 + s/2),
+ * down to a leaf. leaf[i] = that leaf's index, or -1 when root[i] is outside
+ * [0, n_roots), x or y is outside [0, 1] or NaN, or the stored links are inconsistent (a
+ * first child outside [n_roots, capacity - 4], or more than RAMLT_QT_MAX_DEPTH levels).
+ * count != 0 also adds 1 to visits[leaf] for every point with a region (integer atomics,
+ * so the counts do not depend on the order).
+ * root: DEVICE int32[n] or NULL; x, y: DEVICE float[n]; leaf: DEVICE int32[n]; n in
+ * 0..RAMLT_MAX_QT_POINTS. Errors: RAMLT_EINVAL for bad sizes or pointers. */
+int quadtree_lookup(const ramlt_quadtree *tree, const int32_t *root, const float *x, const float *y,
+                    int32_t *leaf, int64_t n_points, int32_t count, void *stream);
+
+/* One refinement pass: every leaf with more than m_split visits and depth below
+ * RAMLT_QT_MAX_DEPTH splits into four children, in increasing node order; children made
+ * in this pass are not considered again. When fewer than 4 * (number of such leaves)
+ * entries are free, only the first floor((capacity - n_nodes) / 4) of them split. Every
+ * visit counter then restarts from 0, and *n_nodes grows by 4 per split.
+ * state (optional, NULL = none): the region state (ramlt_region_state, n_regions >=
+ * capacity entries) of region_adapt; each child gets the parent's lambda (and lambda_f32)
+ * as it is, updates = max(1, floor(parent updates / 4)) (the paper gives n_k / 4; it is
+ * rounded down and kept >= 1 so the step size stays finite), and an empty pending window
+ * (acc = 0, visits = 0). m_split >= 0. workspace: DEVICE, 256-byte aligned, at least
+ * ramlt_quadtree_workspace_size(capacity) bytes. The result is deterministic. */
+int quadtree_refine(const ramlt_quadtree *tree, int32_t m_split, const ramlt_region_state *state,
+                    void *workspace, size_t ws_bytes, void *stream);
+
+/* Workspace bytes of quadtree_refine (0 for an invalid capacity). */
+size_t ramlt_quadtree_workspace_size(int32_t capacity);
+
 /* Bytes of device workspace `op` needs for these frames (0 if none). Workspace is
  * caller-owned, 256-byte aligned, and may be reused across calls on one stream. */
 size_t ramlt_workspace_size(const ramlt_frame *frames_host, int32_t n_frames, int32_t op);

@@ -24,6 +24,8 @@ coordinates). The regions are the leaves. Nodes are numbered in creation order: 
 
 import math
 
+import numpy as np
+
 MAX_DEPTH = 20
 
 
@@ -68,6 +70,44 @@ class Forest:
         if count:
             node.visits += 1
         return node.index
+
+    def lookup_many(self, root, x, y, count=True):
+        """lookup() of many points at once: every point descends one level per step, so
+        the half side h is the same for all points at a step. root: int array (or None for
+        tree 0), x, y: float arrays. Returns int64 leaf indices (-1 where none)."""
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        root = np.zeros(x.shape, dtype=np.int64) if root is None else np.asarray(root, dtype=np.int64)
+        child = np.asarray(self.child_array(), dtype=np.int64)
+        valid = (root >= 0) & (root < self.n_roots) & (x >= 0) & (x <= 1) & (y >= 0) & (y <= 1)
+        node = np.where(valid, root, 0)
+        x0 = np.zeros(x.shape)
+        y0 = np.zeros(x.shape)
+        h = 0.5
+        for _ in range(MAX_DEPTH + 1):
+            first = child[node]
+            inner = valid & (first >= 0)
+            if not inner.any():
+                break
+            right = x >= x0 + h
+            top = y >= y0 + h
+            node = np.where(inner, first + right + 2 * top, node)
+            x0 = np.where(inner & right, x0 + h, x0)
+            y0 = np.where(inner & top, y0 + h, y0)
+            h /= 2
+        leaf = np.where(valid, node, -1)
+        if count:
+            hits = np.bincount(leaf[valid], minlength=len(self.nodes))
+            for n, c in zip(self.nodes, hits.tolist()):
+                n.visits += c
+        return leaf
+
+    def visits_array(self):
+        return [n.visits for n in self.nodes]
+
+    def corners(self):
+        """(x0, y0, side) of every node, in node order."""
+        return [(n.x0, n.y0, n.side) for n in self.nodes]
 
     def refine(self, m_split, state=None):
         """One refinement pass; `state` (oracle.region_adapt state arrays indexed by node,

@@ -51,11 +51,18 @@ EXPORTED = (
     "ramlt_abi_version",
     "region_adapt",
     "ramlt_adapt_workspace_size",
+    "quadtree_init",
+    "quadtree_lookup",
+    "quadtree_refine",
+    "ramlt_quadtree_workspace_size",
 )
 
 MAX_ADAPT_REGIONS = 1 << 24
 MAX_ADAPT_L = 1 << 20
 MAX_PROPOSALS = 1 << 30
+QT_MAX_DEPTH = 20
+MAX_QT_NODES = 1 << 26
+MAX_QT_POINTS = 1 << 30
 
 
 class RamltFrame(ctypes.Structure):
@@ -121,6 +128,19 @@ class RamltRegionState(ctypes.Structure):
     ]
 
 
+class RamltQuadtree(ctypes.Structure):
+    """Mirror of ``ramlt_quadtree`` (host struct of device pointers)."""
+
+    _fields_ = [
+        ("n_roots", ctypes.c_int32),
+        ("capacity", ctypes.c_int32),
+        ("child", ctypes.c_void_p),
+        ("depth", ctypes.c_void_p),
+        ("visits", ctypes.c_void_p),
+        ("n_nodes", ctypes.c_void_p),
+    ]
+
+
 class RamltError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"ramlt status {status}: {message}")
@@ -159,6 +179,17 @@ def load():
     lib.region_adapt.restype = ctypes.c_int
     lib.ramlt_adapt_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int32]
     lib.ramlt_adapt_workspace_size.restype = ctypes.c_size_t
+    qt = ctypes.POINTER(RamltQuadtree)
+    lib.quadtree_init.argtypes = [qt, ctypes.c_void_p]
+    lib.quadtree_init.restype = ctypes.c_int
+    lib.quadtree_lookup.argtypes = [qt, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]
+    lib.quadtree_lookup.restype = ctypes.c_int
+    lib.quadtree_refine.argtypes = [qt, ctypes.c_int32, ctypes.POINTER(RamltRegionState), ctypes.c_void_p,
+                                    ctypes.c_size_t, ctypes.c_void_p]
+    lib.quadtree_refine.restype = ctypes.c_int
+    lib.ramlt_quadtree_workspace_size.argtypes = [ctypes.c_int32]
+    lib.ramlt_quadtree_workspace_size.restype = ctypes.c_size_t
     if (lib.ramlt_abi_version() >> 16) != ctypes.sizeof(RamltFrame):
         raise RuntimeError("ramlt_frame layout mismatch between libramlt.so and the binding")
     _lib = lib
@@ -236,3 +267,41 @@ def adapt_status(params, state, region, alpha, n, workspace=None, ws_bytes=0, st
 
 def adapt_workspace_size(n, m):
     return int(load().ramlt_adapt_workspace_size(n, m))
+
+
+def _ref(x):
+    return ctypes.byref(x) if x is not None else None
+
+
+def _check(st):
+    if st != RAMLT_OK:
+        raise RamltError(st, last_error())
+    return st
+
+
+def quadtree_init_status(tree, stream=None):
+    return load().quadtree_init(_ref(tree), stream)
+
+
+def quadtree_lookup_status(tree, root, x, y, leaf, n, count, stream=None):
+    return load().quadtree_lookup(_ref(tree), root, x, y, leaf, n, int(count), stream)
+
+
+def quadtree_refine_status(tree, m_split, state, workspace=None, ws_bytes=0, stream=None):
+    return load().quadtree_refine(_ref(tree), m_split, _ref(state), workspace, ws_bytes, stream)
+
+
+def quadtree_init(tree, stream=None):
+    return _check(quadtree_init_status(tree, stream))
+
+
+def quadtree_lookup(tree, root, x, y, leaf, n, count, stream=None):
+    return _check(quadtree_lookup_status(tree, root, x, y, leaf, n, count, stream))
+
+
+def quadtree_refine(tree, m_split, state, workspace=None, ws_bytes=0, stream=None):
+    return _check(quadtree_refine_status(tree, m_split, state, workspace, ws_bytes, stream))
+
+
+def quadtree_workspace_size(capacity):
+    return int(load().ramlt_quadtree_workspace_size(capacity))

@@ -216,9 +216,83 @@ int validate_adapt(const ramlt_adapt_params *p, const ramlt_region_state *s, con
   return RAMLT_OK;
 }
 
+int validate_tree(const char *fn, const ramlt_quadtree *t) {
+  if (!t) return fail(RAMLT_EINVAL, "%s: tree is NULL", fn);
+  if (t->capacity < 1 || t->capacity > RAMLT_MAX_QT_NODES)
+    return fail(RAMLT_EINVAL, "%s: capacity %d outside 1..%d", fn, t->capacity, RAMLT_MAX_QT_NODES);
+  if (t->n_roots < 1 || t->n_roots > t->capacity)
+    return fail(RAMLT_EINVAL, "%s: n_roots %d outside 1..capacity (%d)", fn, t->n_roots, t->capacity);
+  if (!t->child || !aligned(t->child, 4) || !t->depth || !aligned(t->depth, 4) || !t->visits ||
+      !aligned(t->visits, 4) || !t->n_nodes || !aligned(t->n_nodes, 4))
+    return fail(RAMLT_EINVAL, "%s: child, depth, visits and n_nodes must be 4-byte aligned device pointers", fn);
+  return RAMLT_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int quadtree_init(const ramlt_quadtree *tree, void *stream) {
+  int r = validate_tree("quadtree_init", tree);
+  if (r) return r;
+  r = check_device();
+  if (r) return r;
+  const hipError_t e = ramlt::launch_quadtree_init(*tree, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RAMLT_EHIP, "quadtree_init: %s", hipGetErrorString(e));
+  g_last_error.clear();
+  return RAMLT_OK;
+}
+
+int quadtree_lookup(const ramlt_quadtree *tree, const int32_t *root, const float *x, const float *y,
+                    int32_t *leaf, int64_t n_points, int32_t count, void *stream) {
+  int r = validate_tree("quadtree_lookup", tree);
+  if (r) return r;
+  if (n_points < 0 || n_points > RAMLT_MAX_QT_POINTS)
+    return fail(RAMLT_EINVAL, "quadtree_lookup: n_points %lld outside 0..%lld", (long long)n_points,
+                (long long)RAMLT_MAX_QT_POINTS);
+  if (n_points > 0 && (!x || !aligned(x, 4) || !y || !aligned(y, 4) || !leaf || !aligned(leaf, 4)))
+    return fail(RAMLT_EINVAL, "quadtree_lookup: x, y and leaf must be 4-byte aligned device pointers");
+  if (root && !aligned(root, 4)) return fail(RAMLT_EINVAL, "quadtree_lookup: root is not 4-byte aligned");
+  r = check_device();
+  if (r) return r;
+  const hipError_t e =
+      ramlt::launch_quadtree_lookup(*tree, root, x, y, leaf, n_points, count != 0, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RAMLT_EHIP, "quadtree_lookup: %s", hipGetErrorString(e));
+  g_last_error.clear();
+  return RAMLT_OK;
+}
+
+int quadtree_refine(const ramlt_quadtree *tree, int32_t m_split, const ramlt_region_state *state, void *workspace,
+                    size_t ws_bytes, void *stream) {
+  int r = validate_tree("quadtree_refine", tree);
+  if (r) return r;
+  if (m_split < 0) return fail(RAMLT_EINVAL, "quadtree_refine: m_split %d is negative", m_split);
+  if (state) {
+    if (!state->lambda || !aligned(state->lambda, 8) || !state->acc || !aligned(state->acc, 8))
+      return fail(RAMLT_EINVAL, "quadtree_refine: state.lambda and state.acc must be 8-byte aligned device pointers");
+    if (!state->visits || !aligned(state->visits, 4) || !state->updates || !aligned(state->updates, 4))
+      return fail(RAMLT_EINVAL,
+                  "quadtree_refine: state.visits and state.updates must be 4-byte aligned device pointers");
+    if (state->lambda_f32 && !aligned(state->lambda_f32, 4))
+      return fail(RAMLT_EINVAL, "quadtree_refine: state.lambda_f32 must be 4-byte aligned");
+  }
+  const size_t need = ramlt::quadtree_workspace_bytes(tree->capacity);
+  if (workspace == nullptr || ws_bytes < need)
+    return fail(RAMLT_EWORKSPACE, "quadtree_refine needs %zu bytes of workspace, got %zu", need,
+                workspace == nullptr ? (size_t)0 : ws_bytes);
+  if (!aligned(workspace, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
+  r = check_device();
+  if (r) return r;
+  const hipError_t e = ramlt::launch_quadtree_refine(*tree, m_split, state, workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RAMLT_EHIP, "quadtree_refine: %s", hipGetErrorString(e));
+  g_last_error.clear();
+  return RAMLT_OK;
+}
+
+size_t ramlt_quadtree_workspace_size(int32_t capacity) {
+  if (capacity < 1 || capacity > RAMLT_MAX_QT_NODES) return 0;
+  return ramlt::quadtree_workspace_bytes(capacity);
+}
 
 int region_adapt(const ramlt_adapt_params *params, const ramlt_region_state *state, const int32_t *region,
                  const float *alpha, int64_t n_proposals, void *workspace, size_t ws_bytes, void *stream) {
@@ -278,6 +352,6 @@ size_t ramlt_workspace_size(const ramlt_frame *frames_host, int32_t n_frames, in
 
 const char *ramlt_last_error(void) { return g_last_error.c_str(); }
 
-int32_t ramlt_abi_version(void) { return (int32_t)((sizeof(ramlt_frame) << 16) | 2); }
+int32_t ramlt_abi_version(void) { return (int32_t)((sizeof(ramlt_frame) << 16) | 3); }
 
 }  // extern "C"

@@ -22,4 +22,12 @@ hipError_t launch_region_adapt(const ramlt_adapt_params &p, const ramlt_region_s
                                const float *alpha, long long n, void *ws, hipStream_t st);
 size_t adapt_workspace_bytes(long long n, int m);
 
+// Quadtree partitions (quadtree.hip): validated tree descriptor and arguments.
+hipError_t launch_quadtree_init(const ramlt_quadtree &t, hipStream_t st);
+hipError_t launch_quadtree_lookup(const ramlt_quadtree &t, const int32_t *root, const float *x, const float *y,
+                                  int32_t *leaf, long long n, int count, hipStream_t st);
+hipError_t launch_quadtree_refine(const ramlt_quadtree &t, int m_split, const ramlt_region_state *s, void *ws,
+                                  hipStream_t st);
+size_t quadtree_workspace_bytes(int capacity);
+
 }  // namespace ramlt

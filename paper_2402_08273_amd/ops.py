@@ -264,3 +264,63 @@ class RegionAdapter:
         _abi.region_adapt(self.params, self.state, region.data_ptr() if n else None,
                           alpha.data_ptr() if n else None, n, ws, ws_bytes, _stream())
         return self
+
+
+class Quadtree:
+    """A forest of quadtrees on the device (Sec. 5.4): ``n_roots`` trees over [0,1]^2,
+    storage for ``capacity`` nodes. Leaves are regions; a node index is a region key for
+    :class:`RegionAdapter` (give it ``n_regions >= capacity``).
+
+    ``lookup(x, y, root=None, count=True)`` returns the leaf of every point (int32, -1 for
+    none) and counts visits per leaf; ``refine(m_split, adapter=None)`` splits the leaves
+    visited more than ``m_split`` times since the last refinement, passing lambda and
+    n_k / 4 on to the children in ``adapter``'s state."""
+
+    def __init__(self, n_roots, capacity, device="cuda"):
+        dev = torch.device(device)
+        cap = int(capacity)
+        self.child = torch.empty(cap, device=dev, dtype=torch.int32)
+        self.depth = torch.empty(cap, device=dev, dtype=torch.int32)
+        self.visits = torch.empty(cap, device=dev, dtype=torch.int32)
+        self.n_nodes_dev = torch.empty(1, device=dev, dtype=torch.int32)
+        self.tree = _abi.RamltQuadtree(int(n_roots), cap, self.child.data_ptr(), self.depth.data_ptr(),
+                                       self.visits.data_ptr(), self.n_nodes_dev.data_ptr())
+        self.device = dev
+        need = _abi.quadtree_workspace_size(cap)
+        self._ws = torch.empty(need + 256, device=dev, dtype=torch.uint8)
+        self._ws_ptr = (self._ws.data_ptr() + 255) // 256 * 256
+        self._ws_bytes = need
+        _abi.quadtree_init(self.tree, _stream())
+
+    @property
+    def n_nodes(self):
+        return int(self.n_nodes_dev.item())
+
+    def reset(self):
+        _abi.quadtree_init(self.tree, _stream())
+        return self
+
+    def lookup(self, x, y, root=None, count=True, out=None):
+        for t in (x, y):
+            if t.dtype != torch.float32 or not t.is_cuda or t.dim() != 1 or not t.is_contiguous():
+                raise ValueError("x and y must be contiguous 1-D float32 device tensors")
+        if x.shape != y.shape:
+            raise ValueError("x and y differ in length")
+        if root is not None and (root.dtype != torch.int32 or not root.is_cuda or root.shape != x.shape
+                                 or not root.is_contiguous()):
+            raise ValueError("root must be a contiguous int32 device tensor like x")
+        n = x.numel()
+        leaf = out if out is not None else torch.empty(n, device=self.device, dtype=torch.int32)
+        if leaf.dtype != torch.int32 or leaf.shape != x.shape or not leaf.is_contiguous():
+            raise ValueError("out must be a contiguous int32 tensor like x")
+        _abi.quadtree_lookup(self.tree, root.data_ptr() if (root is not None and n) else None,
+                             x.data_ptr() if n else None, y.data_ptr() if n else None,
+                             leaf.data_ptr() if n else None, n, 1 if count else 0, _stream())
+        return leaf
+
+    def refine(self, m_split, adapter=None):
+        if adapter is not None and adapter.params.n_regions < self.tree.capacity:
+            raise ValueError("the adapter needs n_regions >= the tree capacity")
+        _abi.quadtree_refine(self.tree, int(m_split), adapter.state if adapter is not None else None,
+                             self._ws_ptr, self._ws_bytes, _stream())
+        return self

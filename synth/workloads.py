@@ -49,3 +49,14 @@ def batch32(seed: int = 4) -> List[FrameSpec]:
 def sample_bytes(spec: FrameSpec) -> int:
     """Bytes of the sample planes of one frame: 3 fp32 radiance + 7 feature planes."""
     return spec.W * spec.H * spec.S * (3 * 4 + 7 * (2 if spec.fp16_features else 4))
+
+
+# Quadtree partitions (Sec. 5.4 with the parameters of Sec. 7.1: M_split = 5000,
+# M_refine = 1e7): the forest grows over `rounds` refinements, each after a batch of
+# `grow_points` lookups (batch 0 of the point recipe, the chains' stationary distribution
+# sampled once and revisited), then `lookup_points` lookups (batch 1) are timed.
+# 2-D: one tree over the screen; 4-D: one tree per cell of the 20 x 20 screen grid.
+QUADTREE_2D = dict(n_roots=1, capacity=1 << 16, m_split=5000, grow_points=10_000_000, rounds=8,
+                   lookup_points=1 << 24, seed=31)
+QUADTREE_4D = dict(n_roots=N_REGIONS * N_REGIONS, capacity=1 << 16, m_split=5000, grow_points=10_000_000,
+                   rounds=8, lookup_points=1 << 24, seed=32)

@@ -298,3 +298,55 @@ def test_region_adapt_validation(lib):
     assert _abi.adapt_status(p, s, 0x500000, 0x600000, 1000, ws + 16, need) == _abi.RAMLT_EWORKSPACE
     assert _abi.adapt_status(None, s, 0x500000, 0x600000, 1000, ws, need) == _abi.RAMLT_EINVAL
     assert _abi.adapt_status(p, None, 0x500000, 0x600000, 1000, ws, need) == _abi.RAMLT_EINVAL
+
+
+def _tree():
+    return _abi.RamltQuadtree(4, 1000, 0x100000, 0x200000, 0x300000, 0x400000)
+
+
+def test_quadtree_validation(lib):
+    ws = FAKE_WORKSPACE
+    need = _abi.quadtree_workspace_size(1000)
+    assert need >= 256 + 2 * 4 and need % 256 == 0
+    assert _abi.quadtree_workspace_size(0) == 0 and _abi.quadtree_workspace_size((1 << 26) + 1) == 0
+    ok = (_abi.RAMLT_EHIP, _abi.RAMLT_OK)  # valid: fails at the device check without a GPU
+    t = _tree()
+    assert _abi.quadtree_init_status(t) in ok, _abi.last_error()
+    assert _abi.quadtree_lookup_status(t, 0x500000, 0x600000, 0x700000, 0x800000, 100, 1) in ok
+    assert _abi.quadtree_lookup_status(t, None, 0x600000, 0x700000, 0x800000, 100, 0) in ok  # root optional
+    assert _abi.quadtree_lookup_status(t, None, None, None, None, 0, 1) in ok  # empty batch
+    assert _abi.quadtree_refine_status(t, 5000, None, ws, need) in ok
+    s = _abi.RamltRegionState(0x900000, 0xA00000, 0xB00000, 0xC00000, None)
+    assert _abi.quadtree_refine_status(t, 5000, s, ws, need) in ok
+    bad_tree = [
+        lambda t: setattr(t, "capacity", 0),
+        lambda t: setattr(t, "capacity", (1 << 26) + 1),
+        lambda t: setattr(t, "n_roots", 0),
+        lambda t: setattr(t, "n_roots", 1001),
+        lambda t: setattr(t, "child", None),
+        lambda t: setattr(t, "depth", 0x200002),
+        lambda t: setattr(t, "visits", None),
+        lambda t: setattr(t, "n_nodes", 0x400001),
+    ]
+    for mutate in bad_tree:
+        t = _tree()
+        mutate(t)
+        assert _abi.quadtree_init_status(t) == _abi.RAMLT_EINVAL
+        assert _abi.quadtree_lookup_status(t, None, 0x600000, 0x700000, 0x800000, 100, 1) == _abi.RAMLT_EINVAL
+        assert _abi.quadtree_refine_status(t, 5000, None, ws, need) == _abi.RAMLT_EINVAL
+    t = _tree()
+    assert _abi.quadtree_init_status(None) == _abi.RAMLT_EINVAL
+    assert _abi.quadtree_lookup_status(t, None, None, 0x700000, 0x800000, 100, 1) == _abi.RAMLT_EINVAL
+    assert _abi.quadtree_lookup_status(t, None, 0x600000, 0x700000, 0x800002, 100, 1) == _abi.RAMLT_EINVAL
+    assert _abi.quadtree_lookup_status(t, 0x500002, 0x600000, 0x700000, 0x800000, 100, 1) == _abi.RAMLT_EINVAL
+    assert _abi.quadtree_lookup_status(t, None, 0x600000, 0x700000, 0x800000, -1, 1) == _abi.RAMLT_EINVAL
+    assert _abi.quadtree_lookup_status(t, None, 0x600000, 0x700000, 0x800000, (1 << 30) + 1, 1) == \
+        _abi.RAMLT_EINVAL
+    assert _abi.quadtree_refine_status(t, -1, None, ws, need) == _abi.RAMLT_EINVAL
+    assert _abi.quadtree_refine_status(t, 5000, None, None, 0) == _abi.RAMLT_EWORKSPACE
+    assert _abi.quadtree_refine_status(t, 5000, None, ws, need - 1) == _abi.RAMLT_EWORKSPACE
+    assert _abi.quadtree_refine_status(t, 5000, None, ws + 16, need) == _abi.RAMLT_EWORKSPACE
+    for field, val in (("lambda_", 0x900004), ("acc", None), ("updates", 0xC00002), ("lambda_f32", 0xD00001)):
+        s = _abi.RamltRegionState(0x900000, 0xA00000, 0xB00000, 0xC00000, None)
+        setattr(s, field, val)
+        assert _abi.quadtree_refine_status(t, 5000, s, ws, need) == _abi.RAMLT_EINVAL

@@ -107,3 +107,27 @@ def test_depth_limit():
             f.lookup(0, 1e-9, 1e-9)
         f.refine(1)
     assert max(f.depth_array()) == qt.MAX_DEPTH
+
+
+def test_vectorised_lookup_equals_pointer_descent():
+    # the level-synchronous lookup_many is the per-point pointer descent, also at cell
+    # corners, on the boundary x = 1 and for invalid points, and counts the same visits
+    a = qt.Forest(n_roots=4, capacity=20_000)
+    b = qt.Forest(n_roots=4, capacity=20_000)
+    for r in range(5):
+        rng = np.random.default_rng(50 + r)
+        n = 3000
+        x = (rng.random(n) ** 3).astype(np.float32)
+        y = rng.random(n).astype(np.float32)
+        x[:40] = np.round(x[:40] * 64) / 64            # exactly on cell corners
+        y[40:60] = 1.0
+        x[60] = np.nan
+        y[61] = -0.25
+        root = rng.integers(-1, 5, n)                  # includes -1 and 4 (invalid)
+        got = a.lookup_many(root, x, y)
+        want = [b.lookup(int(t), float(u), float(v)) for t, u, v in zip(root, x, y)]
+        assert got.tolist() == want
+        assert a.visits_array() == b.visits_array()
+        assert a.refine(60) == b.refine(60)
+    assert a.child_array() == b.child_array()
+    assert len(a.nodes) > 100
