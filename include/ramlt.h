@@ -168,7 +168,7 @@ int filter_backward(const ramlt_frame *frames_host, const ramlt_frame *frames_de
 
 /* ---------------------------------------------------------------------------------
  * Regional adaptation of the scaling parameters (Algorithm 1 with eqs. est_exp_acc,
- * update_lambda and step_size_n; parameters of Sec. 7.1).
+ * update_lambda and step_size_n; parameters of Sec. 8.1).
  *
  * A batch of proposals i = 0..n-1 carries the region k_i of the chain's current state
  * (Alg. 1 line 8) and its acceptance probability alpha_i (line 11). Regions are
@@ -221,8 +221,8 @@ int region_adapt(const ramlt_adapt_params *params, const ramlt_region_state *sta
 size_t ramlt_adapt_workspace_size(int64_t n_proposals, int32_t n_regions);
 
 /* ------------------------------------------------------------------------------------
- * Quadtree partitions (Sec. 5.4 "Quadtree Partition", "Refining Quadtree Partition",
- * "4d Partition"; Sec. 6 "Explicit Synchronization for Refinement of Partitions").
+ * Quadtree partitions (Sec. 6.1 "Quadtree Partition", Sec. 6.2 "Refining Quadtree Partition",
+ * Sec. 6.3 "4d Partition"; Sec. 7 "Explicit Synchronization for Refinement of Partitions").
  *
  * A forest of n_roots quadtrees, each over the unit square [0,1]^2: one tree for the 2-D
  * screen partition; one tree per screen grid cell for the 4-D partition (the tree then

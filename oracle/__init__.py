@@ -20,7 +20,7 @@ for a reader to check against the paper by eye:
   update_lambda and step_size_n, one proposal at a time;
 * :mod:`oracle.quadtree` -- quadtree partitions (a forest: one tree for the screen, one per
   top-level grid cell for the 4-D partition), leaf lookup and the counting-based refinement
-  of Sec. 5.4, pointer-based.
+  of Sec. 6.1-6.3, pointer-based.
 
 Parity status: every function is pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_*.py`` (brute force on tiny inputs, exact rational examples, closed forms

@@ -1,5 +1,5 @@
-"""Quadtree partitions and their refinement (Sec. 5.4 "Quadtree Partition", "Refining
-Quadtree Partition", "4d Partition"), pointer-based, in plain Python.
+"""Quadtree partitions and their refinement (Sec. 6.1 "Quadtree Partition", Sec. 6.2 "Refining
+Quadtree Partition", Sec. 6.3 "4d Partition"), pointer-based, in plain Python.
 
 TEST INFRASTRUCTURE (see the package docstring): only tests/, smoke() and bench.py's
 cpu_baseline leg may use it.

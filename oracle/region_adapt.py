@@ -7,7 +7,7 @@ cpu_baseline leg may use it.
 
 Each proposal i carries the region k_i of the current state (Alg. 1, line 8) and its
 acceptance probability alpha_i = alpha(x_i, y_i) (line 11). Per region the algorithm keeps
-lambda_k (initial scaling parameter, Sec. 7.1: 1), the visit count i_k, the accumulated
+lambda_k (initial scaling parameter, Sec. 8.1: 1), the visit count i_k, the accumulated
 acceptance A_k and the update count n_k (initially 1), and for every visit:
 
     A_k += alpha_i;  i_k += 1
@@ -23,7 +23,7 @@ Readings where the paper is inconsistent or silent:
 * the prose of Sec. 5.3 states the direction of the update the other way round from eq.
   update_lambda; the equation is followed (lambda grows when the estimated acceptance is
   above the target);
-* lambda is limited below by the minimum scaling parameter (Sec. 7.1, -30) after every
+* lambda is limited below by the minimum scaling parameter (Sec. 8.1, -30) after every
   update: lambda_k = max(lambda_k + gamma sgn(...), lambda_min);
 * sgn(0) = 0;
 * regions are independent (Sec. 5.3, "Criterion for Adaptation"), and within a region the

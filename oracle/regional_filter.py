@@ -18,7 +18,7 @@ Sources in the paper and the readings taken where it is silent:
   raster position in [0,1]^2 (Sec. 5.4 "2d Partition for the Lens Perturbation",
   Sec. 6.1 "Grid Partition"). The region is that of the OUTPUT pixel j, at its centre:
   k_x = floor((2x + 1) N / (2W)), k_y = floor((2y + 1) N / (2H)), k = k_y N + k_x.
-* lambda is clamped below at the paper's minimum scaling parameter, -30 (Sec. 7.1
+* lambda is clamped below at the paper's minimum scaling parameter, -30 (Sec. 8.1
   "Parameters"); N defaults to the paper's top-level grid size 20 (same paragraph).
 
     h_jp   = exp(-(dx^2 + dy^2) / (2 sigma_{k(j)}^2)),  sigma^2 = exp(max(lambda, lambda_min))

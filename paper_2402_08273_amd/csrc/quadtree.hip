@@ -1,4 +1,4 @@
-// Quadtree partitions (Sec. 5.4): a forest of quadtrees stored as flat arrays, leaf lookup
+// Quadtree partitions (Sec. 6.1-6.3): a forest of quadtrees stored as flat arrays, leaf lookup
 // by descent, and a deterministic refinement pass.
 //
 // Layout: node i has child[i] (first of its four consecutive children, -1 for a leaf) and

@@ -223,7 +223,7 @@ class RegionAdapter:
     Holds the state (lambda_k and its float copy for the filter, A_k, i_k, n_k) for
     ``n_regions`` regions and feeds batches of proposals (region int32 [n], acceptance
     probability float32 [n], device tensors) through ``region_adapt``. Defaults are the
-    paper's parameters (Sec. 7.1): L = 10, gamma_max = 1, gamma_scale = 5, alpha* = 0.5,
+    paper's parameters (Sec. 8.1): L = 10, gamma_max = 1, gamma_scale = 5, alpha* = 0.5,
     lambda_init = 1, lambda_min = -30.
     """
 
@@ -267,7 +267,7 @@ class RegionAdapter:
 
 
 class Quadtree:
-    """A forest of quadtrees on the device (Sec. 5.4): ``n_roots`` trees over [0,1]^2,
+    """A forest of quadtrees on the device (Sec. 6.1-6.3): ``n_roots`` trees over [0,1]^2,
     storage for ``capacity`` nodes. Leaves are regions; a node index is a region key for
     :class:`RegionAdapter` (give it ``n_regions >= capacity``).
 

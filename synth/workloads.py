@@ -51,7 +51,7 @@ def sample_bytes(spec: FrameSpec) -> int:
     return spec.W * spec.H * spec.S * (3 * 4 + 7 * (2 if spec.fp16_features else 4))
 
 
-# Quadtree partitions (Sec. 5.4 with the parameters of Sec. 7.1: M_split = 5000,
+# Quadtree partitions (Sec. 6.1-6.3 with the parameters of Sec. 8.1: M_split = 5000,
 # M_refine = 1e7): the forest grows over `rounds` refinements, each after a batch of
 # `grow_points` lookups (batch 0 of the point recipe, the chains' stationary distribution
 # sampled once and revisited), then `lookup_points` lookups (batch 1) are timed.

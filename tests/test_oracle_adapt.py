@@ -1,5 +1,5 @@
 """Pins of the regional adaptation oracle (Algorithm 1; eqs. est_exp_acc, update_lambda,
-step_size_n; parameters of Sec. 7.1)."""
+step_size_n; parameters of Sec. 8.1)."""
 
 import math
 
@@ -32,7 +32,7 @@ def test_hand_worked_example():
 
 
 def test_step_size_schedule():
-    # Sec. 7.1: gamma_max = 1, gamma_scale = 5, so gamma_n = 1 up to n = 25, then 5 / sqrt n
+    # Sec. 8.1: gamma_max = 1, gamma_scale = 5, so gamma_n = 1 up to n = 25, then 5 / sqrt n
     assert [ra.step_size(n) for n in (1, 4, 25)] == [1.0, 1.0, 1.0]
     assert ra.step_size(26) < 1.0 and ra.step_size(100) == 0.5
     assert ra.step_size(10 ** 6) == pytest.approx(5e-3)

@@ -1,4 +1,4 @@
-"""Pins of the quadtree oracle (Sec. 5.4: quadtree partition, refinement, 4d partition)."""
+"""Pins of the quadtree oracle (Sec. 6.1-6.3: quadtree partition, refinement, 4d partition)."""
 
 import numpy as np
 import pytest
