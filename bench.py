@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="skip the batched and 4K measurements")
     p.add_argument("--no-tune", action="store_true",
                    help="use the library's default filter schedule instead of the autotuned one")
-    p.add_argument("--only", choices=["batched", "uhd", "adapt", "quadtree"], default=None,
+    p.add_argument("--only", choices=["batched", "uhd", "adapt", "quadtree", "perturb"], default=None,
                    help="measure only the 32-frame batch or only the 4K frame and print that object "
                         "(for profiling one workload)")
     p.add_argument("--cpu-rows", type=int, default=0, help="rows of the frame the oracle times (0 = auto)")
@@ -331,6 +331,54 @@ def adapt_cpu_baseline(n=300_000, m=400):
             "sample": f"the first {n} proposals of the 400-region stream, {dt:.2f} s"}
 
 
+def measure_perturb(steps, warmup, cpu=True):
+    """Direction perturbation (truncated-normal polar angle, sigma from each proposal's
+    region) on 16 M proposals per batch, for 400 and 10^6 regions. Algorithmic bytes per
+    proposal: region 4 + omega 12 + (u, v) 8 read, omega' 12 + theta' 4 written = 40 B
+    (plus the lambda table, 8 B per region)."""
+    import torch
+
+    from paper_2402_08273_amd import ops
+    from synth.directions import make_lambda_table, make_perturb_inputs
+
+    n = ADAPT_PROPOSALS
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"direction perturbation, {n} proposals per batch, sigma_k = sqrt(exp(lambda_k))",
+           "proposals": n, "grids": []}
+    for m in ADAPT_REGION_COUNTS:
+        lam = torch.from_numpy(make_lambda_table(m, seed=5)).cuda()
+        region, omega, uv = (torch.from_numpy(a).cuda() for a in make_perturb_inputs(n, m, seed=6))
+        fn = lambda: ops.perturb_directions(lam, region, omega, uv, theta=True)
+        for _ in range(warmup):
+            fn()
+        ms = time_loop(stream, fn, steps)
+        nbytes = n * 40 + m * 8
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out["grids"].append({"regions": m, "ms_per_batch": round(ms, 4),
+                             "gproposals_s": round(n / (ms * 1e-3) / 1e9, 2), "algorithmic_bytes": nbytes,
+                             "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+        del lam, region, omega, uv
+    if cpu:
+        out["cpu_baseline"] = perturb_cpu_baseline()
+    torch.cuda.empty_cache()
+    return out
+
+
+def perturb_cpu_baseline(n=2_000_000, m=400):
+    """The oracle (vectorised NumPy/SciPy, float64) on a bounded sample of the 400-region
+    stream, on one host thread."""
+    from oracle import direction_sampler as ods
+    from synth.directions import make_lambda_table, make_perturb_inputs
+
+    lam = make_lambda_table(m, seed=5)
+    region, omega, uv = make_perturb_inputs(n, m, seed=6)
+    t0 = time.perf_counter()
+    ods.perturb_directions(lam, region, omega, uv)
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt / 1e6, 3), "unit": "Mproposals/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {n} proposals of the 400-region stream, {dt:.2f} s"}
+
+
 def _grow_quadtree(wl, device="cuda"):
     """The forest of a quadtree workload grown over its refinement rounds on the device
     (lookups with visit counting, then a refinement that hands lambda and n_k / 4 to the
@@ -455,6 +503,9 @@ def main():
         if args.only == "adapt":
             print(json.dumps(measure_adapt(args.steps, args.warmup, cpu=not args.no_cpu_baseline)), flush=True)
             return
+        if args.only == "perturb":
+            print(json.dumps(measure_perturb(args.steps, args.warmup, cpu=not args.no_cpu_baseline)), flush=True)
+            return
         if args.only == "quadtree":
             print(json.dumps(measure_quadtree(args.steps, args.warmup, cpu=not args.no_cpu_baseline)), flush=True)
             return
@@ -546,6 +597,7 @@ def main():
         result["uhd"] = measure_uhd(args.steps, args.warmup, not args.no_tune)
         result["adapt"] = measure_adapt(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
         result["quadtree"] = measure_quadtree(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
+        result["perturb"] = measure_perturb(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
 
     print(json.dumps(result), flush=True)
 

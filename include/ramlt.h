@@ -283,6 +283,29 @@ int quadtree_refine(const ramlt_quadtree *tree, int32_t m_split, const ramlt_reg
 /* Workspace bytes of quadtree_refine (0 for an invalid capacity). */
 size_t ramlt_quadtree_workspace_size(int32_t capacity);
 
+/* ------------------------------------------------------------------------------------
+ * Direction perturbation (Sec. 3.3 "Perturbing Ray Directions"; the scale of region k is
+ * sigma_k = sqrt(exp(lambda_k)), Sec. 5.3).
+ *
+ * For proposal i with region k = region[i], current direction omega_i (unit) and uniforms
+ * (u, v) = uv[i] in [0, 1):
+ *   theta' = sigma_k Phi^-1(Phi(-a) + u (Phi(a) - Phi(-a))), a = pi / sigma_k: the normal
+ *            N(0, sigma_k^2) truncated to [-pi, pi], by its inverse CDF (fp64);
+ *   phi'   = 2 pi v;
+ *   omega' = sin theta' (cos phi' t + sin phi' b) + cos theta' omega_i (fp32),
+ * with (t, b) the orthonormal basis of omega_i of Duff et al., "Building an Orthonormal
+ * Basis, Revisited" (JCGT 2017): s = sign(z), a = -1/(s + z), c = x y a,
+ * t = (1 + s x^2 a, s c, -s x), b = (c, s + y^2 a, -y). (The paper leaves the azimuth origin
+ * open; every choice gives the same distribution.) u = 1/2 leaves omega unchanged; theta'
+ * is clamped to [-pi, pi] (reached only at u = 0). A region outside [0, n_regions) gives NaN
+ * outputs; NaN inputs propagate. omega is used as given (not renormalised).
+ * lambda: DEVICE double[n_regions] (e.g. ramlt_region_state.lambda), 8-byte aligned;
+ * region: DEVICE int32[n]; omega, omega_out: DEVICE float[n][3]; uv: DEVICE float[n][2],
+ * 8-byte aligned; theta_out: DEVICE float[n] or NULL. n in 0..RAMLT_MAX_PROPOSALS;
+ * n_regions in 1..RAMLT_MAX_ADAPT_REGIONS. Errors: RAMLT_EINVAL for bad sizes/pointers. */
+int perturb_directions(const double *lambda, int32_t n_regions, const int32_t *region, const float *omega,
+                       const float *uv, float *omega_out, float *theta_out, int64_t n, void *stream);
+
 /* Bytes of device workspace `op` needs for these frames (0 if none). Workspace is
  * caller-owned, 256-byte aligned, and may be reused across calls on one stream. */
 size_t ramlt_workspace_size(const ramlt_frame *frames_host, int32_t n_frames, int32_t op);

@@ -55,6 +55,7 @@ EXPORTED = (
     "quadtree_lookup",
     "quadtree_refine",
     "ramlt_quadtree_workspace_size",
+    "perturb_directions",
 )
 
 MAX_ADAPT_REGIONS = 1 << 24
@@ -188,6 +189,10 @@ def load():
     lib.quadtree_refine.argtypes = [qt, ctypes.c_int32, ctypes.POINTER(RamltRegionState), ctypes.c_void_p,
                                     ctypes.c_size_t, ctypes.c_void_p]
     lib.quadtree_refine.restype = ctypes.c_int
+    lib.perturb_directions.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p]
+    lib.perturb_directions.restype = ctypes.c_int
     lib.ramlt_quadtree_workspace_size.argtypes = [ctypes.c_int32]
     lib.ramlt_quadtree_workspace_size.restype = ctypes.c_size_t
     if (lib.ramlt_abi_version() >> 16) != ctypes.sizeof(RamltFrame):
@@ -305,3 +310,11 @@ def quadtree_refine(tree, m_split, state, workspace=None, ws_bytes=0, stream=Non
 
 def quadtree_workspace_size(capacity):
     return int(load().ramlt_quadtree_workspace_size(capacity))
+
+
+def perturb_directions_status(lam, n_regions, region, omega, uv, omega_out, theta_out, n, stream=None):
+    return load().perturb_directions(lam, n_regions, region, omega, uv, omega_out, theta_out, n, stream)
+
+
+def perturb_directions(lam, n_regions, region, omega, uv, omega_out, theta_out, n, stream=None):
+    return _check(perturb_directions_status(lam, n_regions, region, omega, uv, omega_out, theta_out, n, stream))

@@ -289,6 +289,34 @@ int quadtree_refine(const ramlt_quadtree *tree, int32_t m_split, const ramlt_reg
   return RAMLT_OK;
 }
 
+int perturb_directions(const double *lambda, int32_t n_regions, const int32_t *region, const float *omega,
+                       const float *uv, float *omega_out, float *theta_out, int64_t n, void *stream) {
+  if (n_regions < 1 || n_regions > RAMLT_MAX_ADAPT_REGIONS)
+    return fail(RAMLT_EINVAL, "perturb_directions: n_regions %d outside 1..%d", n_regions,
+                RAMLT_MAX_ADAPT_REGIONS);
+  if (!lambda || !aligned(lambda, 8))
+    return fail(RAMLT_EINVAL, "perturb_directions: lambda must be an 8-byte aligned device pointer");
+  if (n < 0 || n > RAMLT_MAX_PROPOSALS)
+    return fail(RAMLT_EINVAL, "perturb_directions: n %lld outside 0..%lld", (long long)n,
+                (long long)RAMLT_MAX_PROPOSALS);
+  if (n > 0) {
+    if (!region || !aligned(region, 4) || !omega || !aligned(omega, 4) || !omega_out || !aligned(omega_out, 4))
+      return fail(RAMLT_EINVAL, "perturb_directions: region, omega and omega_out must be 4-byte aligned device "
+                                "pointers");
+    if (!uv || !aligned(uv, 8))
+      return fail(RAMLT_EINVAL, "perturb_directions: uv must be an 8-byte aligned device pointer");
+    if (theta_out && !aligned(theta_out, 4))
+      return fail(RAMLT_EINVAL, "perturb_directions: theta_out is not 4-byte aligned");
+  }
+  int r = check_device();
+  if (r) return r;
+  const hipError_t e =
+      ramlt::launch_perturb(lambda, n_regions, region, omega, uv, omega_out, theta_out, n, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RAMLT_EHIP, "perturb_directions: %s", hipGetErrorString(e));
+  g_last_error.clear();
+  return RAMLT_OK;
+}
+
 size_t ramlt_quadtree_workspace_size(int32_t capacity) {
   if (capacity < 1 || capacity > RAMLT_MAX_QT_NODES) return 0;
   return ramlt::quadtree_workspace_bytes(capacity);

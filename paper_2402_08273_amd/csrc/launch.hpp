@@ -30,4 +30,8 @@ hipError_t launch_quadtree_refine(const ramlt_quadtree &t, int m_split, const ra
                                   hipStream_t st);
 size_t quadtree_workspace_bytes(int capacity);
 
+// Direction perturbation (perturb.hip): validated arguments.
+hipError_t launch_perturb(const double *lambda, int m, const int32_t *region, const float *omega, const float *uv,
+                          float *omega_out, float *theta_out, long long n, hipStream_t st);
+
 }  // namespace ramlt

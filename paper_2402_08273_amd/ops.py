@@ -324,3 +324,24 @@ class Quadtree:
         _abi.quadtree_refine(self.tree, int(m_split), adapter.state if adapter is not None else None,
                              self._ws_ptr, self._ws_bytes, _stream())
         return self
+
+
+def perturb_directions(lam, region, omega, uv, theta=False):
+    """Proposed directions (Sec. 3.3, truncated-normal polar angle with sigma_k =
+    sqrt(exp(lambda_k)) of each proposal's region): lam float64 [m] (e.g.
+    ``RegionAdapter.lam``), region int32 [n], omega float32 [n, 3] (unit), uv float32
+    [n, 2] uniforms. Returns omega' [n, 3] (and theta' [n] with ``theta=True``)."""
+    n = region.numel()
+    if lam.dtype != torch.float64 or lam.dim() != 1 or not lam.is_contiguous() or not lam.is_cuda:
+        raise ValueError("lam must be a contiguous 1-D float64 device tensor")
+    if region.dtype != torch.int32 or region.dim() != 1 or not region.is_contiguous():
+        raise ValueError("region must be a contiguous 1-D int32 tensor")
+    if omega.dtype != torch.float32 or tuple(omega.shape) != (n, 3) or not omega.is_contiguous():
+        raise ValueError("omega must be a contiguous float32 [n, 3] tensor")
+    if uv.dtype != torch.float32 or tuple(uv.shape) != (n, 2) or not uv.is_contiguous():
+        raise ValueError("uv must be a contiguous float32 [n, 2] tensor")
+    out = torch.empty_like(omega)
+    th = torch.empty(n, device=omega.device, dtype=torch.float32) if theta else None
+    p = (lambda t: t.data_ptr() if (t is not None and n) else None)
+    _abi.perturb_directions(lam.data_ptr(), lam.numel(), p(region), p(omega), p(uv), p(out), p(th), n, _stream())
+    return (out, th) if theta else out

@@ -350,3 +350,19 @@ def test_quadtree_validation(lib):
         s = _abi.RamltRegionState(0x900000, 0xA00000, 0xB00000, 0xC00000, None)
         setattr(s, field, val)
         assert _abi.quadtree_refine_status(t, 5000, s, ws, need) == _abi.RAMLT_EINVAL
+
+
+def test_perturb_directions_validation(lib):
+    ok = (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
+    args = dict(lam=0x100000, n_regions=400, region=0x200000, omega=0x300000, uv=0x400000,
+                omega_out=0x500000, theta_out=0x600000, n=1000)
+    st = lambda **kw: _abi.perturb_directions_status(**{**args, **kw})
+    assert st() in ok, _abi.last_error()
+    assert st(theta_out=None) in ok
+    assert st(region=None, omega=None, uv=None, omega_out=None, theta_out=None, n=0) in ok
+    bad = [dict(n_regions=0), dict(n_regions=(1 << 24) + 1), dict(lam=None), dict(lam=0x100004),
+           dict(n=-1), dict(n=(1 << 30) + 1), dict(region=None), dict(region=0x200002), dict(omega=None),
+           dict(omega=0x300001), dict(uv=None), dict(uv=0x400004), dict(omega_out=None),
+           dict(theta_out=0x600002)]
+    for kw in bad:
+        assert st(**kw) == _abi.RAMLT_EINVAL, kw
