@@ -302,9 +302,15 @@ size_t ramlt_quadtree_workspace_size(int32_t capacity);
  * lambda: DEVICE double[n_regions] (e.g. ramlt_region_state.lambda), 8-byte aligned;
  * region: DEVICE int32[n]; omega, omega_out: DEVICE float[n][3]; uv: DEVICE float[n][2],
  * 8-byte aligned; theta_out: DEVICE float[n] or NULL. n in 0..RAMLT_MAX_PROPOSALS;
- * n_regions in 1..RAMLT_MAX_ADAPT_REGIONS. Errors: RAMLT_EINVAL for bad sizes/pointers. */
+ * n_regions in 1..RAMLT_MAX_ADAPT_REGIONS. workspace: DEVICE, 256-byte aligned, at least
+ * ramlt_perturb_workspace_size(n_regions) bytes (per-region terms that depend on sigma only,
+ * for up to 65536 regions; 0 bytes, and NULL allowed, above that or for n = 0). Errors: RAMLT_EINVAL for bad sizes/pointers, RAMLT_EWORKSPACE. */
 int perturb_directions(const double *lambda, int32_t n_regions, const int32_t *region, const float *omega,
-                       const float *uv, float *omega_out, float *theta_out, int64_t n, void *stream);
+                       const float *uv, float *omega_out, float *theta_out, int64_t n, void *workspace,
+                       size_t ws_bytes, void *stream);
+
+/* Workspace bytes of perturb_directions (0 for an invalid n_regions). */
+size_t ramlt_perturb_workspace_size(int32_t n_regions);
 
 /* Bytes of device workspace `op` needs for these frames (0 if none). Workspace is
  * caller-owned, 256-byte aligned, and may be reused across calls on one stream. */

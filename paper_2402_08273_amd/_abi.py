@@ -56,6 +56,7 @@ EXPORTED = (
     "quadtree_refine",
     "ramlt_quadtree_workspace_size",
     "perturb_directions",
+    "ramlt_perturb_workspace_size",
 )
 
 MAX_ADAPT_REGIONS = 1 << 24
@@ -191,7 +192,9 @@ def load():
     lib.quadtree_refine.restype = ctypes.c_int
     lib.perturb_directions.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
-                                       ctypes.c_void_p]
+                                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.ramlt_perturb_workspace_size.argtypes = [ctypes.c_int32]
+    lib.ramlt_perturb_workspace_size.restype = ctypes.c_size_t
     lib.perturb_directions.restype = ctypes.c_int
     lib.ramlt_quadtree_workspace_size.argtypes = [ctypes.c_int32]
     lib.ramlt_quadtree_workspace_size.restype = ctypes.c_size_t
@@ -312,9 +315,17 @@ def quadtree_workspace_size(capacity):
     return int(load().ramlt_quadtree_workspace_size(capacity))
 
 
-def perturb_directions_status(lam, n_regions, region, omega, uv, omega_out, theta_out, n, stream=None):
-    return load().perturb_directions(lam, n_regions, region, omega, uv, omega_out, theta_out, n, stream)
+def perturb_directions_status(lam, n_regions, region, omega, uv, omega_out, theta_out, n, workspace=None,
+                              ws_bytes=0, stream=None):
+    return load().perturb_directions(lam, n_regions, region, omega, uv, omega_out, theta_out, n, workspace,
+                                     ws_bytes, stream)
 
 
-def perturb_directions(lam, n_regions, region, omega, uv, omega_out, theta_out, n, stream=None):
-    return _check(perturb_directions_status(lam, n_regions, region, omega, uv, omega_out, theta_out, n, stream))
+def perturb_directions(lam, n_regions, region, omega, uv, omega_out, theta_out, n, workspace=None, ws_bytes=0,
+                       stream=None):
+    return _check(perturb_directions_status(lam, n_regions, region, omega, uv, omega_out, theta_out, n, workspace,
+                                            ws_bytes, stream))
+
+
+def perturb_workspace_size(n_regions):
+    return int(load().ramlt_perturb_workspace_size(n_regions))

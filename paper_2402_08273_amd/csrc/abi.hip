@@ -290,7 +290,8 @@ int quadtree_refine(const ramlt_quadtree *tree, int32_t m_split, const ramlt_reg
 }
 
 int perturb_directions(const double *lambda, int32_t n_regions, const int32_t *region, const float *omega,
-                       const float *uv, float *omega_out, float *theta_out, int64_t n, void *stream) {
+                       const float *uv, float *omega_out, float *theta_out, int64_t n, void *workspace,
+                       size_t ws_bytes, void *stream) {
   if (n_regions < 1 || n_regions > RAMLT_MAX_ADAPT_REGIONS)
     return fail(RAMLT_EINVAL, "perturb_directions: n_regions %d outside 1..%d", n_regions,
                 RAMLT_MAX_ADAPT_REGIONS);
@@ -307,14 +308,26 @@ int perturb_directions(const double *lambda, int32_t n_regions, const int32_t *r
       return fail(RAMLT_EINVAL, "perturb_directions: uv must be an 8-byte aligned device pointer");
     if (theta_out && !aligned(theta_out, 4))
       return fail(RAMLT_EINVAL, "perturb_directions: theta_out is not 4-byte aligned");
+    const size_t need = ramlt::perturb_workspace_bytes(n_regions);
+    if (need > 0) {
+      if (workspace == nullptr || ws_bytes < need)
+        return fail(RAMLT_EWORKSPACE, "perturb_directions needs %zu bytes of workspace, got %zu", need,
+                    workspace == nullptr ? (size_t)0 : ws_bytes);
+      if (!aligned(workspace, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
+    }
   }
   int r = check_device();
   if (r) return r;
-  const hipError_t e =
-      ramlt::launch_perturb(lambda, n_regions, region, omega, uv, omega_out, theta_out, n, (hipStream_t)stream);
+  const hipError_t e = ramlt::launch_perturb(lambda, n_regions, region, omega, uv, omega_out, theta_out, n, workspace,
+                                             (hipStream_t)stream);
   if (e != hipSuccess) return fail(RAMLT_EHIP, "perturb_directions: %s", hipGetErrorString(e));
   g_last_error.clear();
   return RAMLT_OK;
+}
+
+size_t ramlt_perturb_workspace_size(int32_t n_regions) {
+  if (n_regions < 1 || n_regions > RAMLT_MAX_ADAPT_REGIONS) return 0;
+  return ramlt::perturb_workspace_bytes(n_regions);
 }
 
 size_t ramlt_quadtree_workspace_size(int32_t capacity) {

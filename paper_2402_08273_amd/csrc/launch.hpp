@@ -32,6 +32,7 @@ size_t quadtree_workspace_bytes(int capacity);
 
 // Direction perturbation (perturb.hip): validated arguments.
 hipError_t launch_perturb(const double *lambda, int m, const int32_t *region, const float *omega, const float *uv,
-                          float *omega_out, float *theta_out, long long n, hipStream_t st);
+                          float *omega_out, float *theta_out, long long n, void *ws, hipStream_t st);
+size_t perturb_workspace_bytes(int m);
 
 }  // namespace ramlt

@@ -343,5 +343,9 @@ def perturb_directions(lam, region, omega, uv, theta=False):
     out = torch.empty_like(omega)
     th = torch.empty(n, device=omega.device, dtype=torch.float32) if theta else None
     p = (lambda t: t.data_ptr() if (t is not None and n) else None)
-    _abi.perturb_directions(lam.data_ptr(), lam.numel(), p(region), p(omega), p(uv), p(out), p(th), n, _stream())
+    need = _abi.perturb_workspace_size(lam.numel())
+    ws = torch.empty(need + 256, device=omega.device, dtype=torch.uint8) if need else None
+    wp = (ws.data_ptr() + 255) // 256 * 256 if need else None
+    _abi.perturb_directions(lam.data_ptr(), lam.numel(), p(region), p(omega), p(uv), p(out), p(th), n, wp, need,
+                            _stream())
     return (out, th) if theta else out

@@ -354,8 +354,10 @@ def test_quadtree_validation(lib):
 
 def test_perturb_directions_validation(lib):
     ok = (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
+    need = _abi.perturb_workspace_size(400)
+    assert need >= 400 * 24 and need % 256 == 0 and _abi.perturb_workspace_size(0) == 0
     args = dict(lam=0x100000, n_regions=400, region=0x200000, omega=0x300000, uv=0x400000,
-                omega_out=0x500000, theta_out=0x600000, n=1000)
+                omega_out=0x500000, theta_out=0x600000, n=1000, workspace=FAKE_WORKSPACE, ws_bytes=need)
     st = lambda **kw: _abi.perturb_directions_status(**{**args, **kw})
     assert st() in ok, _abi.last_error()
     assert st(theta_out=None) in ok
@@ -366,3 +368,9 @@ def test_perturb_directions_validation(lib):
            dict(theta_out=0x600002)]
     for kw in bad:
         assert st(**kw) == _abi.RAMLT_EINVAL, kw
+    assert st(workspace=None, ws_bytes=0) == _abi.RAMLT_EWORKSPACE
+    assert st(ws_bytes=need - 1) == _abi.RAMLT_EWORKSPACE
+    assert st(workspace=FAKE_WORKSPACE + 8) == _abi.RAMLT_EWORKSPACE
+    # many regions: no table, no workspace
+    assert _abi.perturb_workspace_size(65537) == 0
+    assert st(n_regions=65537, workspace=None, ws_bytes=0) in ok

@@ -42,7 +42,7 @@ def _compare(name, lam, region, omega, uv):
     return out, th, want, wth
 
 
-@pytest.mark.parametrize("m,n", [(1, 1000), (400, 200_000), (70_000, 300_000)])
+@pytest.mark.parametrize("m,n", [(1, 1000), (400, 200_000), (65_536, 300_000), (70_000, 300_000)])
 def test_perturb_parity(m, n):
     print(f"perturb parity m={m} n={n}", flush=True)
     lam = make_lambda_table(m, seed=m)
