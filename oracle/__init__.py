@@ -20,7 +20,12 @@ for a reader to check against the paper by eye:
   update_lambda and step_size_n, one proposal at a time;
 * :mod:`oracle.quadtree` -- quadtree partitions (a forest: one tree for the screen, one per
   top-level grid cell for the 4-D partition), leaf lookup and the counting-based refinement
-  of Sec. 6.1-6.3, pointer-based.
+  of Sec. 6.1-6.3, pointer-based;
+* :mod:`oracle.direction_sampler` -- the perturbation of a ray direction (Sec. 3.3): the
+  polar angle from the normal truncated to [-pi, pi] by its inverse CDF, with sigma_k from
+  lambda_k, the azimuth uniform, in the Duff et al. (2017) frame;
+* :mod:`oracle.rrmse` -- the relative root-mean-square error of an image against a
+  reference, per pixel and for the image (Sec. 8.2).
 
 Parity status: every function is pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_*.py`` (brute force on tiny inputs, exact rational examples, closed forms
@@ -42,4 +47,4 @@ from .regional_filter import (  # noqa: F401
     mse_loss_seed,
     filter_backward,
 )
-from . import quadtree, region_adapt  # noqa: F401
+from . import direction_sampler, quadtree, region_adapt, rrmse  # noqa: F401
