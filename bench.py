@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="skip the batched and 4K measurements")
     p.add_argument("--no-tune", action="store_true",
                    help="use the library's default filter schedule instead of the autotuned one")
-    p.add_argument("--only", choices=["batched", "uhd", "adapt", "quadtree", "perturb"], default=None,
+    p.add_argument("--only", choices=["batched", "uhd", "adapt", "quadtree", "perturb", "rrmse"], default=None,
                    help="measure only the 32-frame batch or only the 4K frame and print that object "
                         "(for profiling one workload)")
     p.add_argument("--cpu-rows", type=int, default=0, help="rows of the frame the oracle times (0 = auto)")
@@ -379,6 +379,42 @@ def perturb_cpu_baseline(n=2_000_000, m=400):
             "sample": f"the first {n} proposals of the 400-region stream, {dt:.2f} s"}
 
 
+def measure_rrmse(steps, warmup, cpu=True):
+    """rRMSE map and image value of a rendered image against its reference at 1920x1080
+    and 3840x2160 (synth.images). Algorithmic bytes per pixel: both images read (24 B),
+    the map written (4 B)."""
+    import torch
+
+    from paper_2402_08273_amd import ops
+    from synth.images import make_image_pair
+
+    stream = torch.cuda.current_stream()
+    out = {"workload": "rRMSE map + image rRMSE, eps 1e-2", "images": []}
+    for W, H in ((1920, 1080), (3840, 2160)):
+        I, R = (torch.from_numpy(a).cuda() for a in make_image_pair(W, H, seed=7))
+        fn = lambda: ops.rrmse(I, R)
+        for _ in range(warmup):
+            fn()
+        ms = time_loop(stream, fn, steps)
+        nbytes = W * H * 28
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out["images"].append({"W": W, "H": H, "ms": round(ms, 4), "mpx_s": round(W * H / (ms * 1e-3) / 1e6, 1),
+                              "algorithmic_bytes": nbytes, "achieved_gbs": round(gbs, 1),
+                              "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+        del I, R
+    if cpu:
+        from oracle import rrmse as orr
+
+        I, R = make_image_pair(1920, 1080, seed=7)
+        t0 = time.perf_counter()
+        orr.rrmse(I, R)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(1920 * 1080 / dt / 1e6, 2), "unit": "Mpixel/s", "cores": 1,
+                               "kind": "oracle", "sample": f"the 1920x1080 pair, {dt:.3f} s"}
+    torch.cuda.empty_cache()
+    return out
+
+
 def _grow_quadtree(wl, device="cuda"):
     """The forest of a quadtree workload grown over its refinement rounds on the device
     (lookups with visit counting, then a refinement that hands lambda and n_k / 4 to the
@@ -503,6 +539,9 @@ def main():
         if args.only == "adapt":
             print(json.dumps(measure_adapt(args.steps, args.warmup, cpu=not args.no_cpu_baseline)), flush=True)
             return
+        if args.only == "rrmse":
+            print(json.dumps(measure_rrmse(args.steps, args.warmup, cpu=not args.no_cpu_baseline)), flush=True)
+            return
         if args.only == "perturb":
             print(json.dumps(measure_perturb(args.steps, args.warmup, cpu=not args.no_cpu_baseline)), flush=True)
             return
@@ -598,6 +637,7 @@ def main():
         result["adapt"] = measure_adapt(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
         result["quadtree"] = measure_quadtree(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
         result["perturb"] = measure_perturb(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
+        result["rrmse"] = measure_rrmse(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
 
     print(json.dumps(result), flush=True)
 

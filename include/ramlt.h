@@ -312,6 +312,24 @@ int perturb_directions(const double *lambda, int32_t n_regions, const int32_t *r
 /* Workspace bytes of perturb_directions (0 for an invalid n_regions). */
 size_t ramlt_perturb_workspace_size(int32_t n_regions);
 
+/* ------------------------------------------------------------------------------------
+ * rRMSE of an image against a reference (Sec. 8.2: the error measure of the paper's
+ * equal-time comparisons, shown per pixel and for the whole image; the paper gives no
+ * formula). Per pixel j of P = W H:
+ *   e_j = (1/3) sum_c (I_cj - R_cj)^2 / (R_cj^2 + eps)   (fp64; eps keeps black reference
+ *                                                         pixels finite, e.g. 1e-2)
+ *   map[j] = sqrt(e_j) (float), *rrmse_out = sqrt((1/P) sum_j e_j) (double).
+ * The image value is summed per workgroup and then in a fixed order: run-to-run identical.
+ * image, reference: DEVICE float[3][H][W] (dense planes, e.g. filter_forward's out and the
+ * frame's reference); map: DEVICE float[H][W] or NULL; rrmse_out: DEVICE double or NULL
+ * (not both NULL); W, H in 1..RAMLT_MAX_SIDE with W H <= RAMLT_MAX_PLANE_ELEMS; eps finite,
+ * >= 0. workspace: DEVICE, 256-byte aligned, >= ramlt_rrmse_workspace_size(W, H) bytes. */
+int rrmse(const float *image, const float *reference, int32_t W, int32_t H, double eps, float *map,
+          double *rrmse_out, void *workspace, size_t ws_bytes, void *stream);
+
+/* Workspace bytes of rrmse (0 for invalid sizes). */
+size_t ramlt_rrmse_workspace_size(int32_t W, int32_t H);
+
 /* Bytes of device workspace `op` needs for these frames (0 if none). Workspace is
  * caller-owned, 256-byte aligned, and may be reused across calls on one stream. */
 size_t ramlt_workspace_size(const ramlt_frame *frames_host, int32_t n_frames, int32_t op);

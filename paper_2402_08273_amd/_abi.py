@@ -57,6 +57,8 @@ EXPORTED = (
     "ramlt_quadtree_workspace_size",
     "perturb_directions",
     "ramlt_perturb_workspace_size",
+    "rrmse",
+    "ramlt_rrmse_workspace_size",
 )
 
 MAX_ADAPT_REGIONS = 1 << 24
@@ -193,6 +195,11 @@ def load():
     lib.perturb_directions.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.rrmse.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.rrmse.restype = ctypes.c_int
+    lib.ramlt_rrmse_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.ramlt_rrmse_workspace_size.restype = ctypes.c_size_t
     lib.ramlt_perturb_workspace_size.argtypes = [ctypes.c_int32]
     lib.ramlt_perturb_workspace_size.restype = ctypes.c_size_t
     lib.perturb_directions.restype = ctypes.c_int
@@ -329,3 +336,15 @@ def perturb_directions(lam, n_regions, region, omega, uv, omega_out, theta_out, 
 
 def perturb_workspace_size(n_regions):
     return int(load().ramlt_perturb_workspace_size(n_regions))
+
+
+def rrmse_status(image, reference, W, H, eps, map_, out, workspace=None, ws_bytes=0, stream=None):
+    return load().rrmse(image, reference, W, H, eps, map_, out, workspace, ws_bytes, stream)
+
+
+def rrmse(image, reference, W, H, eps, map_, out, workspace=None, ws_bytes=0, stream=None):
+    return _check(rrmse_status(image, reference, W, H, eps, map_, out, workspace, ws_bytes, stream))
+
+
+def rrmse_workspace_size(W, H):
+    return int(load().ramlt_rrmse_workspace_size(W, H))

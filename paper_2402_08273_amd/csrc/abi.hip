@@ -325,6 +325,36 @@ int perturb_directions(const double *lambda, int32_t n_regions, const int32_t *r
   return RAMLT_OK;
 }
 
+int rrmse(const float *image, const float *reference, int32_t W, int32_t H, double eps, float *map,
+          double *rrmse_out, void *workspace, size_t ws_bytes, void *stream) {
+  if (W < 1 || H < 1 || W > RAMLT_MAX_SIDE || H > RAMLT_MAX_SIDE || (long long)W * H > RAMLT_MAX_PLANE_ELEMS)
+    return fail(RAMLT_EINVAL, "rrmse: image size %d x %d out of range", W, H);
+  if (!std::isfinite(eps) || eps < 0) return fail(RAMLT_EINVAL, "rrmse: eps must be finite and >= 0");
+  if (!image || !aligned(image, 4) || !reference || !aligned(reference, 4))
+    return fail(RAMLT_EINVAL, "rrmse: image and reference must be 4-byte aligned device pointers");
+  if (!map && !rrmse_out) return fail(RAMLT_EINVAL, "rrmse: map and rrmse_out are both NULL");
+  if (map && !aligned(map, 4)) return fail(RAMLT_EINVAL, "rrmse: map is not 4-byte aligned");
+  if (rrmse_out && !aligned(rrmse_out, 8)) return fail(RAMLT_EINVAL, "rrmse: rrmse_out is not 8-byte aligned");
+  const size_t need = ramlt::rrmse_workspace_bytes((long long)W * H);
+  if (workspace == nullptr || ws_bytes < need)
+    return fail(RAMLT_EWORKSPACE, "rrmse needs %zu bytes of workspace, got %zu", need,
+                workspace == nullptr ? (size_t)0 : ws_bytes);
+  if (!aligned(workspace, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
+  int r = check_device();
+  if (r) return r;
+  const hipError_t e =
+      ramlt::launch_rrmse(image, reference, (long long)W * H, eps, map, rrmse_out, workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RAMLT_EHIP, "rrmse: %s", hipGetErrorString(e));
+  g_last_error.clear();
+  return RAMLT_OK;
+}
+
+size_t ramlt_rrmse_workspace_size(int32_t W, int32_t H) {
+  if (W < 1 || H < 1 || W > RAMLT_MAX_SIDE || H > RAMLT_MAX_SIDE || (long long)W * H > RAMLT_MAX_PLANE_ELEMS)
+    return 0;
+  return ramlt::rrmse_workspace_bytes((long long)W * H);
+}
+
 size_t ramlt_perturb_workspace_size(int32_t n_regions) {
   if (n_regions < 1 || n_regions > RAMLT_MAX_ADAPT_REGIONS) return 0;
   return ramlt::perturb_workspace_bytes(n_regions);

@@ -35,4 +35,9 @@ hipError_t launch_perturb(const double *lambda, int m, const int32_t *region, co
                           float *omega_out, float *theta_out, long long n, void *ws, hipStream_t st);
 size_t perturb_workspace_bytes(int m);
 
+// rRMSE (rrmse.hip): validated arguments; P = W H pixels.
+hipError_t launch_rrmse(const float *image, const float *reference, long long P, double eps, float *map,
+                        double *out, void *ws, hipStream_t st);
+size_t rrmse_workspace_bytes(long long P);
+
 }  // namespace ramlt

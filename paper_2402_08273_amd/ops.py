@@ -349,3 +349,21 @@ def perturb_directions(lam, region, omega, uv, theta=False):
     _abi.perturb_directions(lam.data_ptr(), lam.numel(), p(region), p(omega), p(uv), p(out), p(th), n, wp, need,
                             _stream())
     return (out, th) if theta else out
+
+
+def rrmse(image, reference, eps=1e-2, want_map=True):
+    """rRMSE of ``image`` against ``reference`` (float32 [3, H, W] device tensors, Sec. 8.2):
+    returns (map float32 [H, W] or None, rRMSE as a float64 device tensor of shape [])."""
+    for t in (image, reference):
+        if t.dtype != torch.float32 or t.dim() != 3 or t.shape[0] != 3 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("image and reference must be contiguous float32 [3, H, W] device tensors")
+    if image.shape != reference.shape:
+        raise ValueError("image and reference differ in shape")
+    _, H, W = image.shape
+    m = torch.empty((H, W), device=image.device, dtype=torch.float32) if want_map else None
+    out = torch.empty((), device=image.device, dtype=torch.float64)
+    need = _abi.rrmse_workspace_size(W, H)
+    ws = torch.empty(need + 256, device=image.device, dtype=torch.uint8)
+    _abi.rrmse(image.data_ptr(), reference.data_ptr(), W, H, float(eps), m.data_ptr() if m is not None else None,
+               out.data_ptr(), (ws.data_ptr() + 255) // 256 * 256, need, _stream())
+    return m, out

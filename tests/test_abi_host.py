@@ -374,3 +374,22 @@ def test_perturb_directions_validation(lib):
     # many regions: no table, no workspace
     assert _abi.perturb_workspace_size(65537) == 0
     assert st(n_regions=65537, workspace=None, ws_bytes=0) in ok
+
+
+def test_rrmse_validation(lib):
+    ok = (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
+    need = _abi.rrmse_workspace_size(1920, 1080)
+    assert need >= 8 * (1920 * 1080 // 1024) and need % 256 == 0
+    assert _abi.rrmse_workspace_size(0, 5) == 0 and _abi.rrmse_workspace_size(65537, 1) == 0
+    args = dict(image=0x100000, reference=0x200000, W=1920, H=1080, eps=1e-2, map_=0x300000, out=0x400000,
+                workspace=FAKE_WORKSPACE, ws_bytes=need)
+    st = lambda **kw: _abi.rrmse_status(**{**args, **kw})
+    assert st() in ok, _abi.last_error()
+    assert st(map_=None) in ok and st(out=None) in ok and st(eps=0.0) in ok
+    for kw in (dict(W=0), dict(H=-1), dict(W=65537), dict(W=40000, H=40000), dict(eps=-1.0),
+               dict(eps=float("nan")), dict(eps=float("inf")), dict(image=None), dict(reference=0x200002),
+               dict(map_=None, out=None), dict(map_=0x300001), dict(out=0x400004)):
+        assert st(**kw) == _abi.RAMLT_EINVAL, kw
+    assert st(workspace=None, ws_bytes=0) == _abi.RAMLT_EWORKSPACE
+    assert st(ws_bytes=need - 1) == _abi.RAMLT_EWORKSPACE
+    assert st(workspace=FAKE_WORKSPACE + 64) == _abi.RAMLT_EWORKSPACE
