@@ -15,7 +15,7 @@ namespace ramlt {
 namespace {
 
 constexpr int kErrBlock = 256;
-constexpr int kErrPerThread = 4;
+constexpr int kErrPerThread = 8;
 constexpr int kErrTile = kErrBlock * kErrPerThread;   // pixels per workgroup
 constexpr int kErrWaves = kErrBlock / 64;
 
@@ -66,9 +66,17 @@ __global__ __launch_bounds__(kErrBlock) void rel_error_finalize_kernel(const dou
                                                                        int nparts, long long P,
                                                                        double *__restrict__ out) {
   __shared__ double red[kErrWaves];
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += kErrBlock) acc += partial[b];
-  const double s = block_sum(acc, red);
+  // four independent chains per thread keep four loads in flight; the order of every
+  // addition is fixed by the thread and chain index
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b0 = 0; b0 < nparts; b0 += 4 * kErrBlock) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = b0 + q * kErrBlock + threadIdx.x;
+      if (b < nparts) acc[q] += partial[b];
+    }
+  }
+  const double s = block_sum((acc[0] + acc[1]) + (acc[2] + acc[3]), red);
   if (threadIdx.x == 0) *out = sqrt(s / (double)P);
 }
 
