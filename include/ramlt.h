@@ -19,6 +19,13 @@
  *   filter_backward   The exact adjoint of filter_forward composed with the per-pixel mean:
  *                     dL/dg for every radiance sample and dL/dlambda_k per region, with the
  *                     window weights recomputed from lambda.
+ *   region_adapt      Algorithm 1: regional adaptation of lambda_k from a batch of
+ *                     (region, acceptance probability) proposals.
+ *   quadtree_*        Sec. 6.1-6.3: quadtree partitions (forests for the 2-D and 4-D
+ *                     partitions), leaf lookup with visit counts, refinement.
+ *   perturb_directions  Sec. 3.3: proposed ray directions with a truncated-normal polar
+ *                     angle of scale sigma_k = sqrt(exp(lambda_k)).
+ *   rrmse             Sec. 8.2: relative RMS error map and image value.
  *
  * Conventions shared by every entry point
  *   - All pointers inside ramlt_frame are DEVICE pointers into memory the caller owns
