@@ -187,6 +187,14 @@ class SingleChain:
         return stats_bytes(self.P, self.S, self.feat_bytes) + self.P * FILTER_STEP_BYTES_PER_PX
 
 
+def hbm_roofline(nbytes, ms, note):
+    """Roofline object of an operation bound by HBM: algorithmic bytes over the measured
+    time (HIP events around the operation's launches) against 8 TB/s."""
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes": int(nbytes), "covers": note}
+
+
 def time_loop(stream, fn, steps):
     """Milliseconds per call of fn() over `steps` calls, HIP events on the launch stream,
     synchronised on both sides."""
@@ -308,7 +316,8 @@ def measure_adapt(steps, warmup, cpu=True):
         gbs = nbytes / (ms * 1e-3) / 1e9
         out["grids"].append({"regions": m, "ms_per_batch": round(ms, 4),
                              "mproposals_s": round(n / (ms * 1e-3) / 1e6, 1), "algorithmic_bytes": nbytes,
-                             "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+                             "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                             "roofline": hbm_roofline(nbytes, ms, "all kernels of one region_adapt call")})
         del rd, ad_, ad
     if cpu:
         out["cpu_baseline"] = adapt_cpu_baseline()
@@ -356,7 +365,8 @@ def measure_perturb(steps, warmup, cpu=True):
         gbs = nbytes / (ms * 1e-3) / 1e9
         out["grids"].append({"regions": m, "ms_per_batch": round(ms, 4),
                              "gproposals_s": round(n / (ms * 1e-3) / 1e9, 2), "algorithmic_bytes": nbytes,
-                             "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+                             "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                             "roofline": hbm_roofline(nbytes, ms, "scale_kernel + perturb_kernel")})
         del lam, region, omega, uv
     if cpu:
         out["cpu_baseline"] = perturb_cpu_baseline()
@@ -400,7 +410,8 @@ def measure_rrmse(steps, warmup, cpu=True):
         gbs = nbytes / (ms * 1e-3) / 1e9
         out["images"].append({"W": W, "H": H, "ms": round(ms, 4), "mpx_s": round(W * H / (ms * 1e-3) / 1e6, 1),
                               "algorithmic_bytes": nbytes, "achieved_gbs": round(gbs, 1),
-                              "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+                              "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                              "roofline": hbm_roofline(nbytes, ms, "rel_error_kernel + finalize")})
         del I, R
     if cpu:
         from oracle import rrmse as orr
@@ -487,7 +498,8 @@ def measure_quadtree(steps, warmup, cpu=True):
                              "lookup_ms": round(ms, 4), "glookups_s": round(n / (ms * 1e-3) / 1e9, 2),
                              "lookup_nocount_ms": round(ms_nc, 4),
                              "bytes_per_point": bpp, "achieved_gbs": round(gbs, 1),
-                             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "refine_ms": round(rms, 4)})
+                             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "refine_ms": round(rms, 4),
+                             "roofline": hbm_roofline(n * bpp, ms, "lookup_kernel (one launch)")})
         del t, ad, x, y, root, leaf, snap, live
     if cpu:
         out["cpu_baseline"] = quadtree_cpu_baseline()
