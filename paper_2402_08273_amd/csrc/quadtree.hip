@@ -5,7 +5,8 @@
 // depth[i]; squares are implicit (the descent carries the lower corner and the side). The
 // lookup keeps the first kCacheNodes entries of child[] in LDS (nodes are numbered in
 // creation order, so the low indices are the upper levels every descent passes through;
-// the forests of the paper's settings, a few thousand nodes, fit whole) and counts the
+// the forests of the paper's settings, a few thousand nodes, fit whole), with a jump table
+// over the top levels of forests of few trees, and counts the
 // visits of the first kBinNodes nodes in LDS, one global atomic per counter and workgroup
 // (global atomics on the same few thousand counters run at a fraction of LDS speed).
 //
@@ -29,8 +30,9 @@ namespace {
 constexpr int kMaxDepth = RAMLT_QT_MAX_DEPTH;
 constexpr int kLookupBlock = 1024;
 constexpr int kLookupBatch = 4;      // points per thread in flight
-constexpr int kCacheNodes = 10176;   // child[] of the first nodes (+1 slot), 40 KB of LDS
-constexpr int kBinNodes = 10240;     // visit counters of the first nodes, 40 KB: two workgroups per CU
+constexpr int kCacheNodes = 9712;    // child[] of the first nodes (+1 slot), 38 KB of LDS
+constexpr int kBinNodes = 9728;      // visit counters of the first nodes, 38 KB
+constexpr int kJumpEntries = 1024;   // jump table, 4 KB: 80 KB in all, two workgroups per CU
 constexpr int kRefineBlock = 1024;   // nodes per tile, one per thread
 constexpr int kRefineWaves = kRefineBlock / 64;
 constexpr int kInitBlock = 256;
@@ -92,15 +94,47 @@ __device__ __forceinline__ uint32_t encode_entry(int i, int c, ChildRange cr, in
   return (uint32_t)c - cr.lo <= cr.span ? 4u * (uint32_t)c + 3u : 4u * (uint32_t)kc;
 }
 
-__device__ __forceinline__ int descend_lds(const uint32_t *__restrict__ table, int kc, int n_roots, int nn, int r,
-                                           float x, float y) {
+// Jump table: for every tree of a forest with few trees, the table address reached after
+// the first J levels (J even) for each of the 4^J cells of the top J bits of X and Y -- the
+// leaf the descent stopped at if it was reached earlier (leaves loop to themselves).
+// Descents then start at depth J.
+__device__ __forceinline__ int jump_levels(int n_roots) {
+  return n_roots * 256 <= kJumpEntries ? 4 : (n_roots * 16 <= kJumpEntries ? 2 : 0);
+}
+
+__device__ __forceinline__ uint32_t jump_cell(uint32_t X, uint32_t Y, int J) {
+  return (X >> (20 - J)) | ((Y >> (20 - J)) << J);
+}
+
+__device__ void build_jump_table(const uint32_t *__restrict__ table, uint32_t *__restrict__ jump, int J, int n_roots,
+                                 int nn, int kc) {
+  const int cells = 1 << (2 * J);
+  const char *base = (const char *)table;
+  for (int i = threadIdx.x; i < n_roots * cells; i += kLookupBlock) {
+    const int r = i >> (2 * J);
+    const uint32_t c = (uint32_t)(i & (cells - 1));
+    uint32_t a = 4u * (uint32_t)(r < nn ? r : kc);
+    for (int t = J - 1; t >= 0; --t) {   // the cell's bits, most significant first
+      const uint32_t q = ((c >> t) & 1u) | (((c >> (J + t)) & 1u) << 1);
+      const uint32_t E = *(const uint32_t *)(base + a);
+      a = (E & ~3u) + ((q & E) << 2);
+    }
+    jump[i] = a;
+  }
+}
+
+template <int J>
+__device__ __forceinline__ int descend_lds(const uint32_t *__restrict__ table, const uint32_t *__restrict__ jump,
+                                           int kc, int n_roots, int nn, int r, float x, float y) {
   const bool ok = point_valid(r, n_roots, nn, x, y);
   const uint32_t X = ok ? grid_coord(x) : 0u;
   const uint32_t Y = ok ? grid_coord(y) : 0u;
   const char *base = (const char *)table;
-  uint32_t a = 4u * (uint32_t)(ok ? r : kc);
+  uint32_t a = !ok ? 4u * (uint32_t)kc
+                   : (J > 0 ? jump[((uint32_t)r << (2 * J)) | jump_cell(X, Y, J)] : 4u * (uint32_t)r);
   uint32_t E = *(const uint32_t *)(base + a);
-  for (int s = kMaxDepth - 1; s >= 0 && __ballot(E & 3u) != 0; s -= 2) {
+  // two levels per pass; J is even, so s stays odd and s - 1 >= 0
+  for (int s = kMaxDepth - 1 - J; s >= 0 && __ballot(E & 3u) != 0; s -= 2) {
     uint32_t q = ((X >> s) & 1u) | (((Y >> s) & 1u) << 1);
     a = (E & ~3u) + ((q & E) << 2);
     E = *(const uint32_t *)(base + a);
@@ -152,10 +186,13 @@ __device__ __forceinline__ int descend_mixed(const int32_t *__restrict__ cache, 
   return bad ? -1 : node;
 }
 
-template <bool kAllCached>
-__device__ __forceinline__ int descend(const int32_t *__restrict__ cache, int kc, const int32_t *__restrict__ child,
-                                       ChildRange cr, int nn, int n_roots, int r, float x, float y) {
-  if (kAllCached) return descend_lds((const uint32_t *)cache, kc, n_roots, nn, r, x, y);
+// kJump < 0: the forest is not held whole in LDS; else the LDS descent with kJump levels
+// taken from the jump table.
+template <int kJump>
+__device__ __forceinline__ int descend(const int32_t *__restrict__ cache, const uint32_t *__restrict__ jump, int kc,
+                                       const int32_t *__restrict__ child, ChildRange cr, int nn, int n_roots, int r,
+                                       float x, float y) {
+  if (kJump >= 0) return descend_lds<(kJump >= 0 ? kJump : 0)>((const uint32_t *)cache, jump, kc, n_roots, nn, r, x, y);
   return descend_mixed(cache, kc, child, cr, nn, n_roots, r, x, y);
 }
 
@@ -182,8 +219,9 @@ __device__ __forceinline__ void load_batch(PointBatch &b, const int32_t *__restr
   }
 }
 
-template <bool kAllCached>
-__device__ __forceinline__ void lookup_loop(const int32_t *__restrict__ cache, int kc, int32_t *__restrict__ bins,
+template <int kJump>
+__device__ __forceinline__ void lookup_loop(const int32_t *__restrict__ cache, const uint32_t *__restrict__ jump,
+                                            int kc, int32_t *__restrict__ bins,
                                             int kb, const int32_t *__restrict__ child, int32_t *__restrict__ visits,
                                             const int32_t *__restrict__ root, const float *__restrict__ xs,
                                             const float *__restrict__ ys, int32_t *__restrict__ leaf, uint32_t n,
@@ -202,7 +240,7 @@ __device__ __forceinline__ void lookup_loop(const int32_t *__restrict__ cache, i
     for (int j = 0; j < kLookupBatch; ++j) {
       const uint32_t i = p + j * stride;
       if (i < n) {
-        const int l = descend<kAllCached>(cache, kc, child, cr, nn, n_roots, cur.r[j], cur.x[j], cur.y[j]);
+        const int l = descend<kJump>(cache, jump, kc, child, cr, nn, n_roots, cur.r[j], cur.x[j], cur.y[j]);
         leaf[i] = l;
         if (count && l >= 0) {
           if (l < kb)
@@ -227,10 +265,13 @@ __global__ __launch_bounds__(kLookupBlock) void lookup_kernel(const int32_t *__r
                                                               long long n, int n_roots, int capacity, int count) {
   __shared__ int32_t cache[kCacheNodes + 1];
   __shared__ int32_t bins[kBinNodes];
+  __shared__ uint32_t jump[kJumpEntries];
   const int nn = clamp_nodes(*n_nodes, capacity);
   const int kc = min(nn, kCacheNodes);
   const int kb = count ? min(nn, kBinNodes) : 0;
-  if (kc == nn) {
+  const bool all = kc == nn;
+  const int J = all ? jump_levels(n_roots) : 0;
+  if (all) {
     const ChildRange cr = child_range(nn, n_roots);
     for (int i = threadIdx.x; i <= kc; i += kLookupBlock)
       cache[i] = (int32_t)(i < kc ? encode_entry(i, child[i], cr, kc) : 4u * (uint32_t)kc);
@@ -239,10 +280,21 @@ __global__ __launch_bounds__(kLookupBlock) void lookup_kernel(const int32_t *__r
   }
   for (int i = threadIdx.x; i < kb; i += kLookupBlock) bins[i] = 0;
   __syncthreads();
-  if (kc == nn)
-    lookup_loop<true>(cache, kc, bins, kb, child, visits, root, xs, ys, leaf, (uint32_t)n, nn, n_roots, count);
+  if (J > 0) {
+    build_jump_table((const uint32_t *)cache, jump, J, n_roots, nn, kc);
+    __syncthreads();
+  }
+#define RAMLT_LOOKUP(JJ) \
+  lookup_loop<JJ>(cache, jump, kc, bins, kb, child, visits, root, xs, ys, leaf, (uint32_t)n, nn, n_roots, count)
+  if (!all)
+    RAMLT_LOOKUP(-1);
+  else if (J == 4)
+    RAMLT_LOOKUP(4);
+  else if (J == 2)
+    RAMLT_LOOKUP(2);
   else
-    lookup_loop<false>(cache, kc, bins, kb, child, visits, root, xs, ys, leaf, (uint32_t)n, nn, n_roots, count);
+    RAMLT_LOOKUP(0);
+#undef RAMLT_LOOKUP
   if (kb > 0) {
     __syncthreads();
     for (int i = threadIdx.x; i < kb; i += kLookupBlock) {

@@ -58,7 +58,9 @@ def _lookup_both(name, t, f, root, x, y, count=True):
 @pytest.mark.parametrize("n_roots,capacity,n,m_split,rounds", [
     (1, 4096, 20_000, 100, 6),
     (3, 20_000, 50_000, 300, 6),
+    (20, 20_000, 60_000, 60, 5),
     (400, 30_000, 120_000, 40, 4),
+    (2, 40_000, 200_000, 5, 7),
 ])
 def test_quadtree_growth_parity(n_roots, capacity, n, m_split, rounds):
     print(f"quadtree growth R={n_roots} cap={capacity} n={n} M_split={m_split}", flush=True)
