@@ -8,7 +8,7 @@
 //
 //   1. stable LSD radix sort of (region, alpha) by region, 8 (or 9) bits per pass: per-tile digit
 //      histograms -> an exclusive scan (digit-major) -> a stable scatter that ranks equal
-//      digits inside each wave by ballots (one per digit bit) and across waves in LDS;
+//      digits by ballots (one per digit bit) and per-wave running counts in LDS;
 //   2. region boundaries: the first sorted position of every region;
 //   3. every position that closes a window of L visits sums that window (fp64, in
 //      proposal order, a region's first window continuing the carried A_k) and turns it
@@ -114,12 +114,48 @@ __global__ __launch_bounds__(1 << BITS) void scan_digits_kernel(uint32_t *__rest
   totals[threadIdx.x] = t[threadIdx.x];
 }
 
-// Pass p of the sort, stable scatter of (key, alpha). The tile is ranked in rounds of 256
-// proposals in index order: the rank of a proposal among equal digits is (earlier rounds)
-// + (earlier waves of the round) + (earlier lanes of its wave, from one ballot per digit
-// bit), so order follows the proposal index. Ranked proposals are first placed in LDS in
-// digit order, then written out run by run, so consecutive threads write consecutive
-// addresses of one digit's destination range.
+// Exclusive scan of v[0..kDigits) in place over the workgroup (each thread takes
+// kDigits / kSortBlock consecutive entries); the order of the additions is fixed.
+template <int kDigits>
+__device__ __forceinline__ void block_exclusive_scan(uint32_t *v) {
+  constexpr int kPer = kDigits / kSortBlock;
+  static_assert(kPer * kSortBlock == kDigits, "digits a multiple of the block");
+  __shared__ uint32_t wave_tot[kWavesPerBlock];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  uint32_t own[kPer];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    own[j] = v[threadIdx.x * kPer + j];
+    sum += own[j];
+  }
+  uint32_t incl = sum;  // inclusive scan of the per-thread sums inside the wave
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += u;
+  }
+  if (lane == 63) wave_tot[wave] = incl;
+  __syncthreads();
+  uint32_t run = incl - sum;
+  for (int w = 0; w < wave; ++w) run += wave_tot[w];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    v[threadIdx.x * kPer + j] = run;
+    run += own[j];
+  }
+  __syncthreads();
+}
+
+// Pass p of the sort, stable scatter of (key, alpha). Wave w of the workgroup ranks the
+// proposals [w kWaveChunk, (w + 1) kWaveChunk) of the tile, 64 per round in index order:
+// a proposal's rank within its wave is the wave's running count of its digit (kept in
+// LDS, advanced by the digit's first lane) plus its place among the lanes with the same
+// digit (one ballot per digit bit), so the work per round does not grow with the number
+// of digits. The waves' counts then become per-digit offsets in wave order, and the
+// ranked proposals are placed in LDS in digit order and written out run by run, so
+// consecutive threads write consecutive addresses of one digit's destination range.
 template <int BITS>
 __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(
     const int32_t *__restrict__ region, const float *__restrict__ alpha, const uint32_t *__restrict__ keys_in,
@@ -127,47 +163,34 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(
     const uint32_t *__restrict__ digit_base, int nblocks, uint32_t *__restrict__ keys_out,
     float *__restrict__ val_out) {
   constexpr int kDigits = 1 << BITS;
+  constexpr int kWaveChunk = kSortTile / kWavesPerBlock;   // proposals per wave
+  constexpr int kRounds = kWaveChunk / 64;
   __shared__ uint32_t lkey[kSortTile];
   __shared__ float lval[kSortTile];
-  __shared__ uint32_t lstart[kDigits];  // first LDS slot of each digit in this tile
-  __shared__ uint32_t gbase[kDigits];   // first destination of each digit from this tile
-  __shared__ uint32_t run[kDigits];     // proposals of each digit ranked so far
-  __shared__ uint32_t wcount[kWavesPerBlock][kDigits];
+  __shared__ uint32_t wcount[kWavesPerBlock][kDigits];  // running counts, then wave offsets
+  __shared__ uint32_t lstart[kDigits];                  // first LDS slot of each digit in this tile
+  __shared__ uint32_t gbase[kDigits];                   // first destination of each digit from this tile
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const long long tile = (long long)blockIdx.x * kSortTile;
   const int count = (int)min((long long)kSortTile, n - tile);
-  // this tile's digit counts (the same as its histogram column), their exclusive prefix
-  for (int d = threadIdx.x; d < kDigits; d += kSortBlock) run[d] = 0;
+  for (int i = threadIdx.x; i < kWavesPerBlock * kDigits; i += kSortBlock) (&wcount[0][0])[i] = 0;
   __syncthreads();
-  for (int i = threadIdx.x; i < count; i += kSortBlock) {
-    const uint32_t key = keys_in ? keys_in[tile + i] : input_key(region, tile + i, m);
-    atomicAdd(&run[(key >> shift) & (kDigits - 1)], 1u);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int d = 0; d < kDigits; ++d) {
-      lstart[d] = acc;
-      acc += run[d];
-    }
-  }
-  for (int d = threadIdx.x; d < kDigits; d += kSortBlock)
-    gbase[d] = digit_base[d] + hist[(long long)d * nblocks + blockIdx.x];
-  __syncthreads();
-  for (int d = threadIdx.x; d < kDigits; d += kSortBlock) run[d] = 0;
-  for (int r = 0; r < kSortItems; ++r) {
-    for (int d = lane; d < kDigits; d += 64) wcount[wave][d] = 0;
-    __syncthreads();
-    const int i = r * kSortBlock + threadIdx.x;  // slot in the tile, in index order
+  uint32_t key[kRounds];
+  float val[kRounds];
+  uint32_t rank[kRounds];
+  uint32_t *wc = wcount[wave];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int i = wave * kWaveChunk + r * 64 + lane;  // slot in the tile, in index order
     const bool valid = i < count;
-    uint32_t key = 0;
-    float val = 0.f;
+    key[r] = 0;
+    val[r] = 0.f;
     if (valid) {
-      key = keys_in ? keys_in[tile + i] : input_key(region, tile + i, m);
-      val = val_in ? val_in[tile + i] : alpha[tile + i];
+      key[r] = keys_in ? keys_in[tile + i] : input_key(region, tile + i, m);
+      val[r] = val_in ? val_in[tile + i] : alpha[tile + i];
     }
-    const int d = valid ? (int)((key >> shift) & (kDigits - 1)) : 0;
+    const int d = valid ? (int)((key[r] >> shift) & (kDigits - 1)) : 0;
     // lanes of this wave with the same digit: the AND over the digit's bits of the lanes
     // that agree on that bit
     unsigned long long peers = __ballot(valid);
@@ -176,37 +199,48 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(
       const unsigned long long ones = __ballot((d >> bit) & 1);
       peers &= ((d >> bit) & 1) ? ones : ~ones;
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & __lanemask_lt());
-    if (valid && rank == 0) wcount[wave][d] = (uint32_t)__popcll(peers);  // the digit's first lane
-    __syncthreads();
-    // per digit: offsets of the waves of this round, and the running count
-    for (int dd = threadIdx.x; dd < kDigits; dd += kSortBlock) {
-      uint32_t acc = run[dd];
-#pragma unroll
-      for (int w = 0; w < kWavesPerBlock; ++w) {
-        const uint32_t c = wcount[w][dd];
-        wcount[w][dd] = acc;
-        acc += c;
-      }
-      run[dd] = acc;
-    }
-    __syncthreads();
-    if (valid) {
-      const uint32_t slot = lstart[d] + wcount[wave][d] + rank;
-      if ((int)slot < count) {  // always true: the counts above are this tile's
-        lkey[slot] = key;
-        lval[slot] = val;
-      }
-    }
-    __syncthreads();  // wcount is cleared by the next round
+    const uint32_t below = (uint32_t)__popcll(peers & __lanemask_lt());
+    // every lane of the digit reads the count before the digit's first lane advances it
+    // (one wave, program order on one LDS address)
+    const uint32_t base = valid ? wc[d] : 0u;
+    rank[r] = base + below;
+    if (valid && below == 0) wc[d] = base + (uint32_t)__popcll(peers);
   }
+  __syncthreads();
+  // per digit: the waves' offsets, and the tile's count of the digit
+  for (int d = threadIdx.x; d < kDigits; d += kSortBlock) {
+    uint32_t acc = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+      const uint32_t c = wcount[w][d];
+      wcount[w][d] = acc;
+      acc += c;
+    }
+    lstart[d] = acc;
+    gbase[d] = digit_base[d] + hist[(long long)d * nblocks + blockIdx.x];
+  }
+  __syncthreads();
+  block_exclusive_scan<kDigits>(lstart);
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int i = wave * kWaveChunk + r * 64 + lane;
+    if (i < count) {
+      const int d = (int)((key[r] >> shift) & (kDigits - 1));
+      const uint32_t slot = lstart[d] + wc[d] + rank[r];
+      if ((int)slot < count) {  // always true: the counts above are this tile's
+        lkey[slot] = key[r];
+        lval[slot] = val[r];
+      }
+    }
+  }
+  __syncthreads();
   // write out in slot order: runs of equal digits go to consecutive destinations
   for (int i = threadIdx.x; i < count; i += kSortBlock) {
-    const uint32_t key = lkey[i];
-    const int d = (int)((key >> shift) & (kDigits - 1));
+    const uint32_t k = lkey[i];
+    const int d = (int)((k >> shift) & (kDigits - 1));
     const long long out = (long long)gbase[d] + (i - (int)lstart[d]);
     if (out < n) {  // always true for consistent histograms
-      keys_out[out] = key;
+      keys_out[out] = k;
       val_out[out] = lval[i];
     }
   }
@@ -372,10 +406,10 @@ __global__ __launch_bounds__(kSortBlock) void region_update_wave_kernel(const ui
 
 // Passes and digit width of the sort for keys 0..m (m marks invalid proposals): 8-bit
 // digits, except that keys of exactly 9 bits (256 <= m < 512, e.g. a 20 x 20 grid) sort
-// in one 9-bit pass. A pass reads and writes the stream once, but the scatter's ranking
-// does per-digit work in every round of its tile: measured on 16 M proposals, one 9-bit
-// pass (277 us) beats two 8-bit passes (372 us), while two 9- or 10-bit passes do not beat
-// three 8-bit ones (10-bit scatter: 408 us per pass).
+// in one 9-bit pass. A pass reads and writes the stream once, but wider digits cost
+// histogram bins, per-tile tables and LDS occupancy: measured on 16 M proposals, one
+// 9-bit pass (~230 us) beats two 8-bit passes, while 10-bit passes (~340 us each) lose to
+// the 8-bit passes they would save.
 struct SortPlan {
   int passes, bits;
 };
