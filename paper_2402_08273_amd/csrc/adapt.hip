@@ -11,11 +11,11 @@
 //      digits by ballots (one per digit bit) and per-wave running counts in LDS;
 //   2. region boundaries: the first sorted position of every region;
 //   3. every position that closes a window of L visits sums that window (fp64, in
-//      proposal order, a region's first window continuing the carried A_k) and turns it
-//      into the window's update gamma sgn(alpha_hat - alpha*);
+//      proposal order, a region's first window continuing the carried A_k) and keeps
+//      sgn(alpha_hat - alpha*);
 //   4. one thread per region (a workgroup for regions closing more than 64 windows) folds
-//      its updates, with the clamp at lambda_min, in window order, and the visits after
-//      the last closed window become the pending sum.
+//      its updates gamma(n_k + w) sgn_w, with the clamp at lambda_min, in window order, and
+//      the visits after the last closed window become the pending sum.
 //
 // Proposals with a region outside [0, m) get the key m and are sorted past every region;
 // step 3 never reads them.
@@ -262,12 +262,13 @@ __global__ void region_starts_kernel(const uint32_t *__restrict__ keys, long lon
 
 // Every sorted position that closes a window of L visits of its region computes that
 // window: its acceptance sum in proposal order (fp64; the region's first window continues
-// the carried A_k), alpha_hat, and the update delta_w = gamma(n_k + w) sgn(alpha_hat -
-// alpha*). Other positions are not written.
+// the carried A_k), alpha_hat, and sgn(alpha_hat - alpha*), stored as one byte (the fold
+// forms the update gamma(n_k + w) sgn itself: a sparse 8-byte array made every written
+// line a read-modify-write). Other positions are not written.
 __global__ void window_delta_kernel(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ start,
                                     const float *__restrict__ alpha_sorted, long long n,
                                     const ramlt_adapt_params p, const ramlt_region_state s,
-                                    double *__restrict__ delta) {
+                                    int8_t *__restrict__ sign) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const uint32_t k = keys[t];
@@ -290,9 +291,14 @@ __global__ void window_delta_kernel(const uint32_t *__restrict__ keys, const uin
 #pragma unroll 8
   for (long long q = b; q <= t; ++q) a += (double)alpha_sorted[q];  // loads issue ahead of the adds
   const double ahat = a / (double)L;
-  const int sgn = (ahat > p.alpha_target) - (ahat < p.alpha_target);
-  const double gamma = fmin(p.gamma_max, p.gamma_scale / sqrt((double)((long long)s.updates[k] + w)));
-  delta[t] = gamma * (double)sgn;
+  sign[t] = (int8_t)((ahat > p.alpha_target) - (ahat < p.alpha_target));
+}
+
+// The update of window w of region k (eq. step_size_n, eq. update_lambda): gamma(n_k + w)
+// sgn_w, with n_k the region's update count at the start of the batch.
+__device__ __forceinline__ double window_delta(const ramlt_adapt_params &p, int n_k, long long w, int8_t sgn) {
+  const double gamma = fmin(p.gamma_max, p.gamma_scale / sqrt((double)((long long)n_k + w)));
+  return gamma * (double)sgn;
 }
 
 // Region k's share of the sorted batch and the pending-window bookkeeping.
@@ -319,7 +325,7 @@ constexpr int kSmallWindows = 64;  // regions closing more windows go to the wav
 // A_k / i_k. Larger regions are listed for region_update_wave_kernel (a workgroup each).
 __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_t *__restrict__ start,
                                                                    const float *__restrict__ alpha_sorted,
-                                                                   long long n, const double *__restrict__ delta,
+                                                                   long long n, const int8_t *__restrict__ sign,
                                                                    const ramlt_adapt_params p,
                                                                    const ramlt_region_state s,
                                                                    uint32_t *__restrict__ big,
@@ -346,7 +352,9 @@ __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_
     return;
   }
   const long long rem = (c - r.need0) % L;
-  for (long long w = 0; w < nw; ++w) lam = fmax(lam + delta[r.lo + r.need0 - 1 + w * L], p.lambda_min);
+  const int n_k = s.updates[k];
+  for (long long w = 0; w < nw; ++w)
+    lam = fmax(lam + window_delta(p, n_k, w, sign[r.lo + r.need0 - 1 + w * L]), p.lambda_min);
   double a = 0.0;
   for (long long t = r.hi - rem; t < r.hi; ++t) a += (double)alpha_sorted[t];
   s.acc[k] = a;
@@ -362,7 +370,7 @@ __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_
 // 0 applies the 256 block maps in thread order.
 __global__ __launch_bounds__(kSortBlock) void region_update_wave_kernel(const uint32_t *__restrict__ start,
                                                                         const float *__restrict__ alpha_sorted,
-                                                                        long long n, const double *__restrict__ delta,
+                                                                        long long n, const int8_t *__restrict__ sign,
                                                                         const ramlt_adapt_params p,
                                                                         const ramlt_region_state s,
                                                                         const uint32_t *__restrict__ big,
@@ -379,9 +387,10 @@ __global__ __launch_bounds__(kSortBlock) void region_update_wave_kernel(const ui
     const long long per = (nw + kSortBlock - 1) / kSortBlock;
     double A = 0.0, C = -INFINITY;
     const long long w1 = min(nw, (long long)threadIdx.x * per), w2 = min(nw, w1 + per);
+    const int n_k = s.updates[k];
 #pragma unroll 16
     for (long long w = w1; w < w2; ++w) {  // loads issue ahead of the dependent fold
-      const double d = delta[r.lo + r.need0 - 1 + w * L];  // the window's closing position
+      const double d = window_delta(p, n_k, w, sign[r.lo + r.need0 - 1 + w * L]);  // at the closing position
       A += d;
       C = fmax(C + d, p.lambda_min);
     }
@@ -436,7 +445,7 @@ void launch_sort_pass(const int32_t *region, const float *alpha, const uint32_t 
 struct AdaptWorkspace {
   uint32_t *keys[2], *hist, *totals, *start, *big, *n_big;
   float *vals[2];
-  double *delta;
+  int8_t *sign;   // sgn(alpha_hat - alpha*) at each window's closing position
   size_t bytes;
 };
 
@@ -462,7 +471,7 @@ AdaptWorkspace carve(void *ws, long long n, int m) {
   w.start = take(((size_t)m + 2) * 4);
   w.big = take((size_t)m * 4);
   w.n_big = take(4);
-  w.delta = (double *)take((size_t)n * 8);
+  w.sign = (int8_t *)take((size_t)n);
   w.bytes = off;
   return w;
 }
@@ -500,11 +509,11 @@ hipError_t launch_region_adapt(const ramlt_adapt_params &p, const ramlt_region_s
   hipLaunchKernelGGL(region_starts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.keys[cur], n, m,
                      w.start, w.n_big);
   hipLaunchKernelGGL(window_delta_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.keys[cur], w.start,
-                     w.vals[cur], n, p, s, w.delta);
+                     w.vals[cur], n, p, s, w.sign);
   hipLaunchKernelGGL(region_update_kernel, dim3((unsigned)((m + kSortBlock - 1) / kSortBlock)), dim3(kSortBlock), 0,
-                     st, w.start, w.vals[cur], n, w.delta, p, s, w.big, w.n_big);
+                     st, w.start, w.vals[cur], n, w.sign, p, s, w.big, w.n_big);
   // large regions: at most n / (L kSmallWindows) of them; a fixed grid strides the list
-  hipLaunchKernelGGL(region_update_wave_kernel, dim3(256), dim3(kSortBlock), 0, st, w.start, w.vals[cur], n, w.delta,
+  hipLaunchKernelGGL(region_update_wave_kernel, dim3(256), dim3(kSortBlock), 0, st, w.start, w.vals[cur], n, w.sign,
                      p, s, w.big, w.n_big);
   return hipGetLastError();
 }

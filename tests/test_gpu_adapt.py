@@ -49,7 +49,8 @@ def _compare(name, ad, st, regions=None, updates_before=None):
 
 
 @pytest.mark.parametrize("m,n,L,batches", [(1, 50, 1, 2), (5, 997, 2, 3), (400, 200_000, 10, 3),
-                                           (3000, 150_000, 37, 2), (70_000, 300_000, 10, 2)])
+                                           (3000, 150_000, 37, 2), (70_000, 300_000, 10, 2),
+                                           (20, 80_000, 64, 2), (20, 80_000, 65, 2), (7, 300_000, 1000, 2)])
 def test_region_adapt_parity(m, n, L, batches):
     print(f"region_adapt parity m={m} n={n} L={L} batches={batches}", flush=True)
     ad = RegionAdapter(m, L=L)
