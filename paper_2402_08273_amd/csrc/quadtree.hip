@@ -2,13 +2,13 @@
 // by descent, and a deterministic refinement pass.
 //
 // Layout: node i has child[i] (first of its four consecutive children, -1 for a leaf) and
-// depth[i]; squares are implicit (the descent carries the lower corner and the side). The
-// lookup keeps the first kCacheNodes entries of child[] in LDS (nodes are numbered in
+// depth[i]; squares are implicit (a descent follows the bits of the point's coordinates).
+// The lookup keeps the first kCacheNodes entries of child[] in LDS (nodes are numbered in
 // creation order, so the low indices are the upper levels every descent passes through;
-// the forests of the paper's settings, a few thousand nodes, fit whole), with a jump table
-// over the top levels of forests of few trees, and counts the
-// visits of the first kBinNodes nodes in LDS, one global atomic per counter and workgroup
-// (global atomics on the same few thousand counters run at a fraction of LDS speed).
+// the forests of the paper's settings, a few thousand nodes, fit whole), adds a jump table
+// over the top levels of forests of few trees, and counts the visits of the first
+// kBinNodes nodes in LDS, one global atomic per counter and workgroup (global atomics on
+// the same few thousand counters run at a fraction of LDS speed).
 //
 // Refinement (one pass, split leaves numbered in node order):
 //   1. count the leaves to split per tile of kRefineBlock nodes;

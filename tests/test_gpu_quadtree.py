@@ -213,3 +213,23 @@ def test_quadtree_full_size(wl):
     want = f.lookup_many(None if R == 1 else root, x, y)
     assert np.array_equal(leaf.cpu().numpy(), want)
     _check_tree("timed batch", t, f)
+
+
+def test_quadtree_forest_larger_than_the_lds_table():
+    # more nodes than the lookup keeps in LDS: descents continue in global memory and the
+    # visits of the later nodes are counted with global atomics
+    t = Quadtree(3, 120_000)
+    f = oqt.Forest(3, 120_000)
+    r = 0
+    while len(f.nodes) <= 20_000:
+        root, x, y = make_points(300_000, 3, seed=61, batch=r)
+        _lookup_both(f"grow {r}", t, f, root, x, y)
+        t.refine(8)
+        f.refine(8)
+        _check_tree(f"refine {r}", t, f)
+        r += 1
+        assert r < 12
+    for b in range(2):
+        root, x, y = make_points(400_000, 3, seed=62, batch=b)
+        _lookup_both(f"large forest {b}", t, f, root, x, y)
+        _check_tree(f"large forest visits {b}", t, f)
