@@ -24,7 +24,8 @@ def relative_squared_error(image, reference, eps=EPS_DEFAULT):
     image = np.asarray(image, dtype=np.float64)
     reference = np.asarray(reference, dtype=np.float64)
     d = image - reference
-    return np.mean(d * d / (reference * reference + float(eps)), axis=0)
+    with np.errstate(divide="ignore", invalid="ignore"):  # eps = 0 at a black pixel: inf or NaN
+        return np.mean(d * d / (reference * reference + float(eps)), axis=0)
 
 
 def rrmse(image, reference, eps=EPS_DEFAULT):
