@@ -367,3 +367,33 @@ def rrmse(image, reference, eps=1e-2, want_map=True):
     _abi.rrmse(image.data_ptr(), reference.data_ptr(), W, H, float(eps), m.data_ptr() if m is not None else None,
                out.data_ptr(), (ws.data_ptr() + 255) // 256 * 256, need, _stream())
     return m, out
+
+
+class QuadtreeAdapter:
+    """Regional adaptation over a quadtree partition (Sec. 6.1-6.3 with Algorithm 1): every
+    batch of proposals is looked up in the forest (leaf = region, visits counted), adapted
+    region by region, and after every ``m_refine`` proposals the forest refines, handing
+    lambda and n_k / 4 to the children. Defaults: the paper's M_split = 5000,
+    M_refine = 10^7 (Sec. 8.1) and the adaptation defaults of :class:`RegionAdapter`."""
+
+    def __init__(self, n_roots, capacity, m_split=5000, m_refine=10_000_000, device="cuda", **adapt_kw):
+        self.tree = Quadtree(n_roots, capacity, device)
+        self.adapter = RegionAdapter(capacity, device=device, **adapt_kw)
+        self.m_split = int(m_split)
+        self.m_refine = int(m_refine)
+        self.pending = 0   # proposals since the last refinement
+
+    @property
+    def lam(self):
+        return self.adapter.lam
+
+    def step(self, x, y, alpha, root=None):
+        """One batch: (x, y) in the trees' unit squares (float32), alpha float32, root int32
+        or None; returns the proposals' regions (int32, -1 for none)."""
+        leaf = self.tree.lookup(x, y, root)
+        self.adapter.step(leaf, alpha)
+        self.pending += x.numel()
+        if self.pending >= self.m_refine:
+            self.tree.refine(self.m_split, self.adapter)
+            self.pending = 0
+        return leaf

@@ -233,3 +233,34 @@ def test_quadtree_forest_larger_than_the_lds_table():
         root, x, y = make_points(400_000, 3, seed=62, batch=b)
         _lookup_both(f"large forest {b}", t, f, root, x, y)
         _check_tree(f"large forest visits {b}", t, f)
+
+
+def test_quadtree_adapter_follows_the_oracle_loop():
+    # the convenience loop: lookup -> adapt -> refine every m_refine proposals
+    from paper_2402_08273_amd.ops import QuadtreeAdapter
+
+    R, cap, n = 2, 8192, 30_000
+    qa = QuadtreeAdapter(R, cap, m_split=150, m_refine=60_000)
+    f = oqt.Forest(R, cap)
+    st = ora.initial_state(cap)
+    pending = 0
+    for r in range(6):
+        root, x, y = make_points(n, R, seed=71, batch=r)
+        _, alpha = make_proposals(n, 5, seed=72, batch=r)
+        leaf = qa.step(_dev(x), _dev(y), _dev(alpha), _dev(root)).cpu().numpy()
+        want = f.lookup_many(root, x, y)
+        assert np.array_equal(leaf, want), r
+        ora.adapt(st, want, alpha)
+        pending += n
+        if pending >= 60_000:
+            f.refine(150, st)
+            pending = 0
+        _check_tree(f"round {r}", qa.tree, f)
+        nn = len(f.nodes)
+        torch.cuda.synchronize()
+        assert np.array_equal(qa.adapter.updates.cpu().numpy()[:nn], st["updates"][:nn]), r
+        assert np.array_equal(qa.adapter.acc.cpu().numpy()[:nn], st["acc"][:nn]), r
+        # rounding bound of the re-associated update sums, with every window of the run
+        # counted for every lineage (the per-lineage bound is pinned in the test above)
+        tol = lambda_tol((r + 1) * n // 10 + r + 1)
+        assert np.allclose(qa.lam.cpu().numpy()[:nn], st["lambda"][:nn], rtol=0, atol=tol), r
