@@ -120,8 +120,11 @@ class SingleChain:
         mean, var, tau = (torch.empty((3, H, W), **f32) for _ in range(3))
         fmean, fvar = torch.empty((7, H, W), **f32), torch.empty((7, H, W), **f32)
         self.out, self.U, self.G = (torch.empty((3, H, W), **f32) for _ in range(3))
-        self.grad_lam = torch.zeros(N * N, **f32)
-        self.loss = torch.zeros(1, device=dev, dtype=torch.float64)
+        # the adjoint's two accumulators share one buffer, so a step clears them with one fill
+        acc_bytes = (N * N * 4 + 7) // 8 * 8
+        self.acc = torch.zeros(acc_bytes + 8, device=dev, dtype=torch.uint8)
+        self.grad_lam = self.acc[:N * N * 4].view(torch.float32)
+        self.loss = self.acc[acc_bytes:].view(torch.float64)
         st_out = ops.Stats(mean, var, tau, None, fmean, fvar)
         fs, _ = ops.stats_frame(self.rad, self.feat, MAX_LAG, st_out, with_lag_corr=False)
         ff = ops.filter_frame(mean, self.lam, r, N)
@@ -144,7 +147,7 @@ class SingleChain:
             from paper_2402_08273_amd import tune as _tune
 
             self.call0(self.lib.stats_accumulate, self.tabs)
-            self.schedule = _tune.tune_table(self.tabf, zero=[self.grad_lam, self.loss])
+            self.schedule = _tune.tune_table(self.tabf, zero=[self.acc])
             self.tabu[0].flags = self.tabf[0].flags
         # the adjoint's workspace (per-tile partial sums), allocated once
         self.ws_t, self.ws_ptr, self.ws_bytes = ops.workspace_for([self.tabf[0]], _abi.OP_FILTER_BACKWARD, dev)
@@ -175,8 +178,7 @@ class SingleChain:
         self.forward()
         if marks is not None:
             marks[2].record(self.stream)
-        self.grad_lam.zero_()
-        self.loss.zero_()
+        self.acc.zero_()
         if fused:
             self.call(self.lib.filter_backward, self.tabf)
         else:
