@@ -8,8 +8,6 @@
 // one workgroup per planned tile, which finds its frame by binary search of the prefix.
 // Everything stays on the device and in stream order, so a batch can be captured in a
 // graph.
-#include <map>
-#include <mutex>
 #include <utility>
 
 #include "batch.hpp"
@@ -76,23 +74,6 @@ hipError_t launch_plan(const ramlt_frame *frames_dev, int n, int op, int group_s
                        hipStream_t st) {
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, st, frames_dev, n, op, group_sel, plan);
   return hipGetLastError();
-}
-
-int resident_blocks(const void *kernel, int block) {
-  static std::mutex mu;
-  static std::map<std::pair<const void *, int>, int> cache;
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  std::lock_guard<std::mutex> lock(mu);
-  const auto key = std::make_pair(kernel, dev);
-  auto it = cache.find(key);
-  if (it != cache.end()) return it->second;
-  int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
-    per_cu = 1;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-  cache[key] = per_cu * cus;
-  return per_cu * cus;
 }
 
 int distinct_groups(const ramlt_frame *fh, int n, int *groups) {

@@ -163,10 +163,6 @@ __host__ __device__ inline TileGeom *plan_geom(BatchPlan *p, int n_frames) {
 hipError_t launch_plan(const ramlt_frame *frames_dev, int n, int op, int group_sel, BatchPlan *plan,
                        hipStream_t st);
 
-// Workgroups of `kernel` (with `block` threads) that fit on the current device at once:
-// occupancy per CU times the CU count (cached per kernel and device).
-int resident_blocks(const void *kernel, int block);
-
 // Distinct filter_group values of a batch, ascending; returns their count (at most
 // kMaxFilterGroups).
 constexpr int kMaxFilterGroups = 16 * 4;
