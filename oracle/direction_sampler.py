@@ -44,14 +44,15 @@ def truncated_normal_theta(u, sigma):
     """theta' for uniforms u in [0, 1] and scales sigma > 0 (arrays broadcast)."""
     u = np.asarray(u, dtype=np.float64)
     sigma = np.asarray(sigma, dtype=np.float64)
-    a = np.pi / sigma
-    e = special.erf(a / SQRT2)
-    ec = special.erfc(a / SQRT2)
-    y = np.abs(2.0 * u - 1.0) * e                   # |2p - 1|
-    x = 2.0 * np.minimum(u, 1.0 - u) * e + ec      # 1 - |2p - 1|
-    with np.errstate(over="ignore", invalid="ignore"):
+    # sigma = 0 or inf (lambda = -inf or +inf) give 0 * inf = NaN where the limit is undefined
+    with np.errstate(divide="ignore", over="ignore", invalid="ignore"):
+        a = np.pi / sigma
+        e = special.erf(a / SQRT2)
+        ec = special.erfc(a / SQRT2)
+        y = np.abs(2.0 * u - 1.0) * e                   # |2p - 1|
+        x = 2.0 * np.minimum(u, 1.0 - u) * e + ec      # 1 - |2p - 1|
         z = np.where(y < 0.5, SQRT2 * special.erfinv(y), SQRT2 * special.erfcinv(x))
-    theta = np.sign(u - 0.5) * sigma * z
+        theta = np.sign(u - 0.5) * sigma * z
     return np.clip(theta, -np.pi, np.pi)
 
 

@@ -57,13 +57,13 @@ def test_perturb_parity(m, n):
 
 
 def test_perturb_edge_cases():
-    lam = np.array([-30.0, 0.0, 1.0, 6.0, 40.0])
+    lam = np.array([-30.0, 0.0, 1.0, 6.0, 40.0, 700.0, -745.0, np.inf, -np.inf, np.nan])
     w = [[0, 0, 1], [0, 0, -1], [0, 0, -0.0], [1, 0, 0], [0, -1, 0], [0.6, 0.8, 0], [0, 0.6, -0.8],
          [np.nan, 0, 1], [0, 0, 1], [0.36, 0.48, 0.8]]
     uvs = [[0.0, 0.0], [0.5, 0.3], [1 - 2 ** -24, 0.999], [0.25, 0.5], [2 ** -24, 0.75], [0.5, 0.0],
            [0.75, 0.1], [0.3, 0.2], [np.nan, 0.2], [0.9, np.nan]]
     region, omega, uv = [], [], []
-    for k in range(-1, 6):
+    for k in range(-1, lam.size + 1):
         for a, b in zip(w, uvs):
             region.append(k)
             omega.append(a)
@@ -72,12 +72,12 @@ def test_perturb_edge_cases():
     omega = np.array(omega, dtype=np.float32)
     uv = np.array(uv, dtype=np.float32)
     out, th, want, wth = _compare("edges", lam, region, omega, uv)
-    valid = (region >= 0) & (region < 5)
+    valid = (region >= 0) & (region < lam.size)
     assert np.all(np.isnan(out[~valid])) and np.all(np.isnan(th[~valid]))
     # u = 0: theta' = -pi exactly for every sigma; u = 1/2: omega unchanged
-    u0 = valid & (uv[:, 0] == 0.0)
+    u0 = valid & (uv[:, 0] == 0.0) & (region < 7)   # finite sigma
     assert np.all(th[u0] == np.float32(-math.pi))
-    half = valid & (uv[:, 0] == 0.5) & ~np.isnan(omega).any(axis=1)
+    half = valid & (uv[:, 0] == 0.5) & ~np.isnan(omega).any(axis=1) & (region < 7)
     assert np.array_equal(out[half], omega[half])
     # empty batch
     e = torch.empty(0, device="cuda")
