@@ -267,7 +267,8 @@ int quadtree_init(const ramlt_quadtree *tree, void *stream);
  * [0, n_roots), x or y is outside [0, 1] or NaN, or the stored links are inconsistent (a
  * first child outside [n_roots, capacity - 4], or more than RAMLT_QT_MAX_DEPTH levels).
  * count != 0 also adds 1 to visits[leaf] for every point with a region (integer atomics,
- * so the counts do not depend on the order).
+ * so the counts do not depend on the order; int32, so more than 2^31 - 1 visits of one
+ * leaf between refinements wrap).
  * root: DEVICE int32[n] or NULL; x, y: DEVICE float[n]; leaf: DEVICE int32[n]; n in
  * 0..RAMLT_MAX_QT_POINTS. Errors: RAMLT_EINVAL for bad sizes or pointers. */
 int quadtree_lookup(const ramlt_quadtree *tree, const int32_t *root, const float *x, const float *y,
