@@ -527,7 +527,7 @@ def quadtree_cpu_baseline(n=2_000_000):
     f.lookup_many(None, x, y)
     dt = time.perf_counter() - t0
     return {"value": round(n / dt / 1e6, 3), "unit": "Mlookups/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} points on a {len(f.nodes)}-node tree (10^6 growth points per round, "
+            "sample": f"{n} points on a {len(f.nodes)}-node tree (10^6 growth points per refinement, "
                       f"M_split 500), {dt:.2f} s"}
 
 

@@ -69,7 +69,7 @@ def test_quadtree_growth_parity(n_roots, capacity, n, m_split, rounds):
     _check_tree("init", t, f)
     for r in range(rounds):
         root, x, y = make_points(n, n_roots, seed=11 + n_roots, batch=r)
-        _lookup_both(f"round {r}", t, f, None if n_roots == 1 else root, x, y)
+        _lookup_both(f"refinement {r}", t, f, None if n_roots == 1 else root, x, y)
         _check_tree(f"visits {r}", t, f)
         t.refine(m_split)
         f.refine(m_split)
@@ -90,7 +90,7 @@ def test_quadtree_with_region_adaptation():
     for r in range(6):
         root, x, y = make_points(n, R, seed=21, batch=r)
         _, alpha = make_proposals(n, 7, seed=22, batch=r)
-        leaf = _lookup_both(f"round {r}", t, f, root, x, y)
+        leaf = _lookup_both(f"refinement {r}", t, f, root, x, y)
         ad.step(_dev(leaf), _dev(alpha))
         before = st["updates"].copy()
         ora.adapt(st, leaf, alpha, L=L)
@@ -123,7 +123,7 @@ def test_quadtree_capacity_limit():
     x = np.array([0.1, 0.6, 0.1, 0.6] * 10, dtype=np.float32)
     y = np.array([0.1, 0.1, 0.6, 0.6] * 10, dtype=np.float32)
     for r in range(3):
-        _lookup_both(f"round {r}", t, f, None, x, y)
+        _lookup_both(f"refinement {r}", t, f, None, x, y)
         t.refine(5)
         f.refine(5)
         _check_tree(f"refine {r}", t, f)
@@ -136,7 +136,7 @@ def test_quadtree_depth_limit():
     x = np.full(7, 0.3, dtype=np.float32)
     y = np.full(7, 0.7, dtype=np.float32)
     for r in range(oqt.MAX_DEPTH + 3):
-        _lookup_both(f"round {r}", t, f, None, x, y)
+        _lookup_both(f"refinement {r}", t, f, None, x, y)
         t.refine(0)
         f.refine(0)
     _check_tree("deep", t, f)
@@ -206,7 +206,7 @@ def test_quadtree_full_size(wl):
         assert np.array_equal(leaf.cpu().numpy(), want), r
         t.refine(wl["m_split"])
         f.refine(wl["m_split"])
-        _check_tree(f"round {r}", t, f)
+        _check_tree(f"refinement {r}", t, f)
     print(f"  nodes {len(f.nodes)} depth {max(f.depth_array())}", flush=True)
     root, x, y = make_points(wl["lookup_points"], R, seed=wl["seed"], batch=1)
     leaf = t.lookup(_dev(x), _dev(y), None if R == 1 else _dev(root))
@@ -255,7 +255,7 @@ def test_quadtree_adapter_follows_the_oracle_loop():
         if pending >= 60_000:
             f.refine(150, st)
             pending = 0
-        _check_tree(f"round {r}", qa.tree, f)
+        _check_tree(f"refinement {r}", qa.tree, f)
         nn = len(f.nodes)
         torch.cuda.synchronize()
         assert np.array_equal(qa.adapter.updates.cpu().numpy()[:nn], st["updates"][:nn]), r
