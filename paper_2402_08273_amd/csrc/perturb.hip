@@ -5,10 +5,13 @@
 //
 // theta' is the inverse CDF of N(0, sigma^2) truncated to [-pi, pi] at u, evaluated in fp64
 // through erf: with e = erf(a / sqrt 2), a = pi / sigma, 2p - 1 = (2u - 1) e, so
-// |Phi^-1(p)| = sqrt 2 erfinv(|2u - 1| e) = sqrt 2 erfcinv(2 min(u, 1 - u) e + erfc(a / sqrt 2))
-// (the complement formed without cancellation). phi' = 2 pi v. The new direction is
+// |Phi^-1(p)| = sqrt 2 erfinv(y), y = |2u - 1| e, whose complement 1 - y =
+// 2 min(u, 1 - u) e + erfc(a / sqrt 2) is formed without cancellation. erfinv comes from
+// polynomials in log(1 - y^2) and its square root (erfinv_poly.hpp, relative error below
+// 1e-9, a fraction of the float32 rounding of theta'). phi' = 2 pi v. The new direction is
 // sin theta' (cos phi' t + sin phi' b) + cos theta' omega in the Duff et al. (2017) basis
 // (t, b) of omega, in fp32.
+#include "erfinv_poly.hpp"
 #include "launch.hpp"
 
 #include <math.h>
@@ -39,19 +42,36 @@ __device__ __forceinline__ Scale scale_of(double lam) {
   return Scale{sigma, erf(h), erfc(h)};
 }
 
-// theta' = sgn(2u - 1) sigma sqrt 2 erfinv(y), y = |2u - 1| e = |2p - 1|. Evaluated as
-// sqrt 2 erfcinv(x) with x = 1 - y = 2 min(u, 1 - u) e + ec formed from the complements
-// (no cancellation at either tail); below y = 2^-20, where x = 1 - y would keep too few
-// digits of y, as erfinv(y). Every lane of a wave takes the erfcinv form unless sigma is
-// beyond ~10^6 or u = 1/2, so the waves do not diverge.
+template <int N>
+__device__ __forceinline__ double horner(const double (&c)[N], double t) {
+  double p = c[0];
+#pragma unroll
+  for (int k = 1; k < N; ++k) p = fma(p, t, c[k]);
+  return p;
+}
+
+// erfinv(y) for y in [0, 1], given y and its complement x = 1 - y, each to full relative
+// precision: y P(w) with w = -log(x (2 - x)) = -log(1 - y^2) (Giles, GPU Computing Gems Jade
+// Edition, 2011), P a polynomial in w below w = 6.25 and in sqrt(w) on three intervals up to
+// sqrt(w) = 10.2 (x ~ 2^-148, the smallest complement a float32 u in (0, 1) can give). Below
+// that (x = 0, or NaN) the library's erfcinv answers. Almost every lane of a wave takes the
+// first form: the tail needs x < 0.001 (w >= 6.25).
+__device__ __forceinline__ double erfinv_from_complement(double y, double x) {
+  namespace ep = erfinv_poly;
+  const double w = -log(x * (2.0 - x));
+  if (w < ep::kCentralHi) return y * horner(ep::kCentral, fma(w, ep::kCentralScale, ep::kCentralShift));
+  const double s = sqrt(w);
+  if (s < ep::kTail1Hi) return y * horner(ep::kTail1, fma(s, ep::kTail1Scale, ep::kTail1Shift));
+  if (s < ep::kTail2Hi) return y * horner(ep::kTail2, fma(s, ep::kTail2Scale, ep::kTail2Shift));
+  if (s <= ep::kTail3Hi) return y * horner(ep::kTail3, fma(s, ep::kTail3Scale, ep::kTail3Shift));
+  return erfcinv(x);
+}
+
+// theta' = sgn(2u - 1) sigma sqrt 2 erfinv(y), y = |2u - 1| e.
 __device__ __forceinline__ double theta_of(double u, const Scale &sc) {
   const double y = fabs(2.0 * u - 1.0) * sc.e;
-  double z;
-  if (y >= 0x1p-20) {
-    z = kSqrt2 * erfcinv(2.0 * fmin(u, 1.0 - u) * sc.e + sc.ec);
-  } else {
-    z = kSqrt2 * erfinv(y);
-  }
+  const double x = 2.0 * fmin(u, 1.0 - u) * sc.e + sc.ec;
+  const double z = kSqrt2 * erfinv_from_complement(y, x);
   const double sgn = u > 0.5 ? 1.0 : (u < 0.5 ? -1.0 : 0.0);
   const double t = sgn * sc.sigma * z;
   return t < -kPi ? -kPi : (t > kPi ? kPi : t);   // the support; NaN passes through
