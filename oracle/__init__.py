@@ -25,7 +25,10 @@ for a reader to check against the paper by eye:
   polar angle from the normal truncated to [-pi, pi] by its inverse CDF, with sigma_k from
   lambda_k, the azimuth uniform, in the Duff et al. (2017) frame;
 * :mod:`oracle.rrmse` -- the relative root-mean-square error of an image against a
-  reference, per pixel and for the image (Sec. 8.2).
+  reference, per pixel and for the image (Sec. 8.2);
+* :mod:`oracle.lens_chain` -- one Metropolis step of screen-space chains under the regional
+  adaptive lens perturbation (Sec. 3.3, Sec. 6.1, Alg. 1 lines 8-13), with an image's
+  luminance standing in for the path contribution.
 
 Parity status: every function is pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_*.py`` (brute force on tiny inputs, exact rational examples, closed forms
@@ -47,4 +50,4 @@ from .regional_filter import (  # noqa: F401
     mse_loss_seed,
     filter_backward,
 )
-from . import direction_sampler, quadtree, region_adapt, rrmse  # noqa: F401
+from . import direction_sampler, lens_chain, quadtree, region_adapt, rrmse  # noqa: F401
