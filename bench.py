@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="skip the batched and 4K measurements")
     p.add_argument("--no-tune", action="store_true",
                    help="use the library's default filter schedule instead of the autotuned one")
-    p.add_argument("--only", choices=["batched", "uhd", "adapt", "quadtree", "perturb", "rrmse"], default=None,
+    p.add_argument("--only", choices=["batched", "uhd", "adapt", "quadtree", "perturb", "rrmse", "lens"], default=None,
                    help="measure only the 32-frame batch or only the 4K frame and print that object "
                         "(for profiling one workload)")
     p.add_argument("--cpu-rows", type=int, default=0, help="rows of the frame the oracle times (0 = auto)")
@@ -391,6 +391,80 @@ def perturb_cpu_baseline(n=2_000_000, m=400):
             "sample": f"the first {n} proposals of the 400-region stream, {dt:.2f} s"}
 
 
+LENS_CHAINS = 1 << 24
+LENS_CAMERA = (1920, 1080, 0.6, 20)   # luminance W, H; tan of half the horizontal field of view; grid N
+
+
+def measure_lens(steps, warmup, cpu=True):
+    """Screen-space chains under the regional adaptive lens perturbation on a 1920x1080
+    luminance image, 20x20 regions, 16 M chains: one Metropolis step per chain
+    (lens_chain_step), and the closed loop (step, then region_adapt of its (region, alpha)
+    stream). Algorithmic bytes per chain of the step: omega 12 + noise 12 read, region 4 +
+    alpha 4 written, the luminance at both pixels 8, omega 12 written on acceptance (times the
+    batch's mean alpha)."""
+    import torch
+
+    from paper_2402_08273_amd import ops
+    from paper_2402_08273_amd.ops import RegionAdapter
+    from synth.lens import make_lens_chains, make_lens_noise, make_luminance
+
+    W, H, tx, N = LENS_CAMERA
+    n = LENS_CHAINS
+    stream = torch.cuda.current_stream()
+    L = torch.from_numpy(make_luminance(W, H, seed=5)).cuda()
+    om = torch.from_numpy(make_lens_chains(n, W, H, tx, seed=8)).cuda()
+    noise = torch.from_numpy(make_lens_noise(n, seed=9)).cuda()
+    ad = RegionAdapter(N * N, L=10)
+    last = {}
+
+    def step():
+        last["ra"] = ops.lens_chain_step(L, tx, ad.lam, N, om, noise)
+
+    def loop():
+        step()
+        ad.step(*last["ra"])
+
+    for _ in range(warmup):
+        loop()
+    ms_loop = time_loop(stream, loop, steps)
+    ms = time_loop(stream, step, steps)
+    region, alpha = last["ra"]
+    ok = region >= 0
+    acc = float(alpha[ok].double().mean())
+    nbytes = int(n * (40 + 12 * acc))
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out = {"workload": f"lens-perturbation chains, {n} chains, {W}x{H} luminance, {N}x{N} regions, "
+                       f"tan(fov/2) = {tx}",
+           "chains": n, "ms_per_step": round(ms, 4), "gchains_s": round(n / (ms * 1e-3) / 1e9, 2),
+           "ms_per_adaptive_step": round(ms_loop, 4), "mean_alpha": round(acc, 4), "algorithmic_bytes": nbytes,
+           "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+           "roofline": hbm_roofline(nbytes, ms, "scale_kernel + lens_step_kernel")}
+    del L, om, noise, ad, last
+    if cpu:
+        out["cpu_baseline"] = lens_cpu_baseline()
+    torch.cuda.empty_cache()
+    return out
+
+
+def lens_cpu_baseline(n=2_000_000):
+    """The oracle step (NumPy/SciPy) on a bounded sample of the chains, on one host thread."""
+    import numpy as np
+
+    from oracle import lens_chain as olc
+    from synth.lens import make_lens_chains, make_lens_noise, make_luminance
+
+    W, H, tx, N = LENS_CAMERA
+    L = make_luminance(W, H, seed=5)
+    om = make_lens_chains(n, W, H, tx, seed=8)
+    noise = make_lens_noise(n, seed=9)
+    lam = np.ones(N * N)
+    t0 = time.perf_counter()
+    olc.step(L, tx, lam, N, om, noise)
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt / 1e6, 3), "unit": "Mchains/s", "cores": 1, "kind": "oracle",
+            "sample": f"one step of {n} chains (lambda = 1 everywhere), {dt:.2f} s"}
+
+
 def measure_rrmse(steps, warmup, cpu=True):
     """rRMSE map and image value of a rendered image against its reference at 1920x1080
     and 3840x2160 (synth.images). Algorithmic bytes per pixel: both images read (24 B),
@@ -559,6 +633,9 @@ def main():
         if args.only == "perturb":
             print(json.dumps(measure_perturb(args.steps, args.warmup, cpu=not args.no_cpu_baseline)), flush=True)
             return
+        if args.only == "lens":
+            print(json.dumps(measure_lens(args.steps, args.warmup, cpu=not args.no_cpu_baseline)), flush=True)
+            return
         if args.only == "quadtree":
             print(json.dumps(measure_quadtree(args.steps, args.warmup, cpu=not args.no_cpu_baseline)), flush=True)
             return
@@ -652,6 +729,7 @@ def main():
         result["quadtree"] = measure_quadtree(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
         result["perturb"] = measure_perturb(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
         result["rrmse"] = measure_rrmse(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
+        result["lens"] = measure_lens(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
 
     print(json.dumps(result), flush=True)
 

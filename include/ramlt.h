@@ -26,6 +26,8 @@
  *   perturb_directions  Sec. 3.3: proposed ray directions with a truncated-normal polar
  *                     angle of scale sigma_k = sqrt(exp(lambda_k)).
  *   rrmse             Sec. 8.2: relative RMS error map and image value.
+ *   lens_chain_step   Sec. 3.3 / 6.1 / Alg. 1: one Metropolis step of screen-space chains
+ *                     under the regional adaptive lens perturbation (luminance target).
  *
  * Conventions shared by every entry point
  *   - All pointers inside ramlt_frame are DEVICE pointers into memory the caller owns
@@ -319,6 +321,42 @@ int perturb_directions(const double *lambda, int32_t n_regions, const int32_t *r
 
 /* Workspace bytes of perturb_directions (0 for an invalid n_regions). */
 size_t ramlt_perturb_workspace_size(int32_t n_regions);
+
+/* ------------------------------------------------------------------------------------
+ * Screen-space chains of the regional adaptive lens perturbation (Sec. 3.3 "Lens
+ * Perturbation", "Perturbing Ray Directions"; Sec. 6.1 "2d Partition for the Lens
+ * Perturbation"; Alg. 1 lines 8-13), with an image's luminance standing in for the path
+ * contribution: one Metropolis step per chain, producing the (region, alpha) stream that
+ * region_adapt consumes.
+ *
+ * The state of chain i is its primary ray direction omega_i of a pinhole camera looking along
+ * +z. Its raster position is sx = 1/2 + (1/2)(x / z) / tx, sy = 1/2 + (1/2)(y / z) / ty,
+ * tx = tan_half_fov_x, ty = (float)(tx H / W) (from double); it is in the frame iff z > 0
+ * and sx, sy in [0, 1), its pixel is (min(floor(sx W), W - 1), min(floor(sy H), H - 1)), and
+ * its region the cell of that pixel on the n_regions x n_regions screen grid (the map of
+ * filter_forward). Every one of these float operations rounds to nearest on its own.
+ *   proposal: omega' as perturb_directions gives it for (u, v) = noise[i][0..1] with
+ *             sigma_k = sqrt(exp(lambda[k])) of the current region k;
+ *   alpha:    0 if omega' is outside the frame, else 1 if L' >= L, else L' / L (float), with
+ *             L, L' the luminance at the two pixels (pi(omega) = L[pixel] is the target
+ *             density over directions; the proposal is symmetric);
+ *   move:     omega_i = omega' iff noise[i][2] < alpha.
+ * region[i] = k, alpha[i] = alpha (Alg. 1 line 8: the region of the state before the move).
+ * A chain whose state is outside the frame (or NaN) gets region -1 and alpha NaN and does not
+ * move. luminance: DEVICE float[H][W] (>= 0; NaN gives alpha NaN, never a move); lambda:
+ * DEVICE double[n_regions^2], 8-byte aligned (e.g. ramlt_region_state.lambda); omega: DEVICE
+ * float[n][3], read and updated in place; noise: DEVICE float[n][3]; region: DEVICE int32[n];
+ * alpha: DEVICE float[n]; omega_prop: DEVICE float[n][3] or NULL (the proposals). W, H as for
+ * rrmse; tan_half_fov_x finite, > 0; n_regions in 1..RAMLT_MAX_REGIONS; n in
+ * 0..RAMLT_MAX_PROPOSALS. workspace: DEVICE, 256-byte aligned, at least
+ * ramlt_lens_workspace_size(n_regions) bytes (0, and NULL allowed, above 65536 regions or for
+ * n = 0). Errors: RAMLT_EINVAL, RAMLT_EWORKSPACE. */
+int lens_chain_step(const float *luminance, int32_t W, int32_t H, float tan_half_fov_x, const double *lambda,
+                    int32_t n_regions, float *omega, const float *noise, int32_t *region, float *alpha,
+                    float *omega_prop, int64_t n, void *workspace, size_t ws_bytes, void *stream);
+
+/* Workspace bytes of lens_chain_step (0 for an invalid n_regions). */
+size_t ramlt_lens_workspace_size(int32_t n_regions);
 
 /* ------------------------------------------------------------------------------------
  * rRMSE of an image against a reference (Sec. 8.2: the error measure of the paper's

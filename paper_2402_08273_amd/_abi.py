@@ -57,6 +57,8 @@ EXPORTED = (
     "ramlt_quadtree_workspace_size",
     "perturb_directions",
     "ramlt_perturb_workspace_size",
+    "lens_chain_step",
+    "ramlt_lens_workspace_size",
     "rrmse",
     "ramlt_rrmse_workspace_size",
 )
@@ -200,6 +202,13 @@ def load():
     lib.rrmse.restype = ctypes.c_int
     lib.ramlt_rrmse_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.ramlt_rrmse_workspace_size.restype = ctypes.c_size_t
+    lib.lens_chain_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p,
+                                    ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_size_t, ctypes.c_void_p]
+    lib.lens_chain_step.restype = ctypes.c_int
+    lib.ramlt_lens_workspace_size.argtypes = [ctypes.c_int32]
+    lib.ramlt_lens_workspace_size.restype = ctypes.c_size_t
     lib.ramlt_perturb_workspace_size.argtypes = [ctypes.c_int32]
     lib.ramlt_perturb_workspace_size.restype = ctypes.c_size_t
     lib.perturb_directions.restype = ctypes.c_int
@@ -336,6 +345,22 @@ def perturb_directions(lam, n_regions, region, omega, uv, omega_out, theta_out, 
 
 def perturb_workspace_size(n_regions):
     return int(load().ramlt_perturb_workspace_size(n_regions))
+
+
+def lens_chain_step_status(luminance, W, H, tan_half_fov_x, lam, n_regions, omega, noise, region, alpha,
+                           omega_prop, n, workspace=None, ws_bytes=0, stream=None):
+    return load().lens_chain_step(luminance, W, H, tan_half_fov_x, lam, n_regions, omega, noise, region, alpha,
+                                  omega_prop, n, workspace, ws_bytes, stream)
+
+
+def lens_chain_step(luminance, W, H, tan_half_fov_x, lam, n_regions, omega, noise, region, alpha, omega_prop, n,
+                    workspace=None, ws_bytes=0, stream=None):
+    return _check(lens_chain_step_status(luminance, W, H, tan_half_fov_x, lam, n_regions, omega, noise, region,
+                                         alpha, omega_prop, n, workspace, ws_bytes, stream))
+
+
+def lens_workspace_size(n_regions):
+    return int(load().ramlt_lens_workspace_size(n_regions))
 
 
 def rrmse_status(image, reference, W, H, eps, map_, out, workspace=None, ws_bytes=0, stream=None):

@@ -325,6 +325,54 @@ int perturb_directions(const double *lambda, int32_t n_regions, const int32_t *r
   return RAMLT_OK;
 }
 
+int lens_chain_step(const float *luminance, int32_t W, int32_t H, float tan_half_fov_x, const double *lambda,
+                    int32_t n_regions, float *omega, const float *noise, int32_t *region, float *alpha,
+                    float *omega_prop, int64_t n, void *workspace, size_t ws_bytes, void *stream) {
+  if (W < 1 || H < 1 || W > RAMLT_MAX_SIDE || H > RAMLT_MAX_SIDE || (long long)W * H > RAMLT_MAX_PLANE_ELEMS)
+    return fail(RAMLT_EINVAL, "lens_chain_step: image size %d x %d out of range", W, H);
+  if (!std::isfinite(tan_half_fov_x) || !(tan_half_fov_x > 0.0f))
+    return fail(RAMLT_EINVAL, "lens_chain_step: tan_half_fov_x must be finite and > 0");
+  const float ty = (float)((double)tan_half_fov_x * H / W);
+  if (!(ty > 0.0f) || !std::isfinite(ty))
+    return fail(RAMLT_EINVAL, "lens_chain_step: tan_half_fov_x * H / W is not a positive float");
+  if (n_regions < 1 || n_regions > RAMLT_MAX_REGIONS)
+    return fail(RAMLT_EINVAL, "lens_chain_step: n_regions %d outside 1..%d", n_regions, RAMLT_MAX_REGIONS);
+  if (!luminance || !aligned(luminance, 4))
+    return fail(RAMLT_EINVAL, "lens_chain_step: luminance must be a 4-byte aligned device pointer");
+  if (!lambda || !aligned(lambda, 8))
+    return fail(RAMLT_EINVAL, "lens_chain_step: lambda must be an 8-byte aligned device pointer");
+  if (n < 0 || n > RAMLT_MAX_PROPOSALS)
+    return fail(RAMLT_EINVAL, "lens_chain_step: n %lld outside 0..%lld", (long long)n,
+                (long long)RAMLT_MAX_PROPOSALS);
+  if (n > 0) {
+    if (!omega || !aligned(omega, 4) || !noise || !aligned(noise, 4) || !region || !aligned(region, 4) || !alpha ||
+        !aligned(alpha, 4))
+      return fail(RAMLT_EINVAL, "lens_chain_step: omega, noise, region and alpha must be 4-byte aligned device "
+                                "pointers");
+    if (omega_prop && !aligned(omega_prop, 4))
+      return fail(RAMLT_EINVAL, "lens_chain_step: omega_prop is not 4-byte aligned");
+    const size_t need = ramlt::perturb_workspace_bytes(n_regions * n_regions);
+    if (need > 0) {
+      if (workspace == nullptr || ws_bytes < need)
+        return fail(RAMLT_EWORKSPACE, "lens_chain_step needs %zu bytes of workspace, got %zu", need,
+                    workspace == nullptr ? (size_t)0 : ws_bytes);
+      if (!aligned(workspace, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
+    }
+  }
+  int r = check_device();
+  if (r) return r;
+  const hipError_t e = ramlt::launch_lens_step(luminance, W, H, tan_half_fov_x, ty, lambda, n_regions, omega, noise,
+                                               region, alpha, omega_prop, n, workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RAMLT_EHIP, "lens_chain_step: %s", hipGetErrorString(e));
+  g_last_error.clear();
+  return RAMLT_OK;
+}
+
+size_t ramlt_lens_workspace_size(int32_t n_regions) {
+  if (n_regions < 1 || n_regions > RAMLT_MAX_REGIONS) return 0;
+  return ramlt::perturb_workspace_bytes(n_regions * n_regions);
+}
+
 int rrmse(const float *image, const float *reference, int32_t W, int32_t H, double eps, float *map,
           double *rrmse_out, void *workspace, size_t ws_bytes, void *stream) {
   if (W < 1 || H < 1 || W > RAMLT_MAX_SIDE || H > RAMLT_MAX_SIDE || (long long)W * H > RAMLT_MAX_PLANE_ELEMS)

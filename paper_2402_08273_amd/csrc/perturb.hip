@@ -77,6 +77,25 @@ __device__ __forceinline__ double theta_of(double u, const Scale &sc) {
   return t < -kPi ? -kPi : (t > kPi ? kPi : t);   // the support; NaN passes through
 }
 
+// omega' = sin th (cos phi t + sin phi b) + cos th omega, phi = 2 pi v, in the Duff et al.
+// (2017) basis of omega: s = sign(z), a = -1 / (s + z), c = x y a,
+// t = (1 + s x^2 a, s c, -s x), b = (c, s + y^2 a, -y).
+__device__ __forceinline__ void propose(float wx, float wy, float wz, float th, float v, float &ox, float &oy,
+                                        float &oz) {
+  float st, ct, sp, cp;
+  sincosf(th, &st, &ct);
+  sincospif(2.0f * v, &sp, &cp);   // phi' = 2 pi v (2v is exact)
+  const float s = copysignf(1.0f, wz);
+  const float aa = -1.0f / (s + wz);
+  const float bb = wx * wy * aa;
+  const float tx = 1.0f + s * wx * wx * aa, ty = s * bb, tz = -s * wx;
+  const float bx = bb, by = s + wy * wy * aa, bz = -wy;
+  const float c1 = st * cp, c2 = st * sp;
+  ox = c1 * tx + c2 * bx + ct * wx;
+  oy = c1 * ty + c2 * by + ct * wy;
+  oz = c1 * tz + c2 * bz + ct * wz;
+}
+
 __global__ __launch_bounds__(kPerturbBlock) void scale_kernel(const double *__restrict__ lambda, int m,
                                                               Scale *__restrict__ table) {
   const int j = blockIdx.x * kPerturbBlock + threadIdx.x;
@@ -100,27 +119,79 @@ __global__ __launch_bounds__(kPerturbBlock) void perturb_kernel(const Scale *__r
   if (k < 0 || k >= m) {
     ox = oy = oz = th = __builtin_nanf("");
   } else {
-    const double theta = theta_of((double)r.x, kTable ? table[k] : scale_of(lambda[k]));
-    th = (float)theta;
-    float st, ct, sp, cp;
-    sincosf(th, &st, &ct);
-    sincospif(2.0f * r.y, &sp, &cp);   // phi' = 2 pi v (2v is exact)
-    // Duff et al. 2017: s = sign(z), a = -1 / (s + z), b = x y a,
-    // t = (1 + s x^2 a, s b, -s x), b' = (b, s + y^2 a, -y)
-    const float s = copysignf(1.0f, wz);
-    const float aa = -1.0f / (s + wz);
-    const float bb = wx * wy * aa;
-    const float tx = 1.0f + s * wx * wx * aa, ty = s * bb, tz = -s * wx;
-    const float bx = bb, by = s + wy * wy * aa, bz = -wy;
-    const float c1 = st * cp, c2 = st * sp;
-    ox = c1 * tx + c2 * bx + ct * wx;
-    oy = c1 * ty + c2 * by + ct * wy;
-    oz = c1 * tz + c2 * bz + ct * wz;
+    th = (float)theta_of((double)r.x, kTable ? table[k] : scale_of(lambda[k]));
+    propose(wx, wy, wz, th, r.y, ox, oy, oz);
   }
   omega_out[3 * i] = ox;
   omega_out[3 * i + 1] = oy;
   omega_out[3 * i + 2] = oz;
   if (theta_out) theta_out[i] = th;
+}
+
+// ------------------------------------------------------------------------ lens chains
+// Raster position of a primary ray direction of a pinhole camera looking along +z, in
+// canonical screen space: sx = 1/2 + (1/2) (x / z) / tx, sy likewise with ty; in the frame
+// iff z > 0 and sx, sy in [0, 1). Every operation rounds to nearest on its own (no fused
+// multiply-add), so the pixel and every decision taken from it are reproducible one IEEE
+// operation at a time.
+struct Raster {
+  bool inside;
+  int ix, iy;
+};
+
+__device__ __forceinline__ Raster raster_of(float wx, float wy, float wz, float tx, float ty, int W, int H) {
+  const float sx = __fadd_rn(0.5f, __fmul_rn(0.5f, __fdiv_rn(__fdiv_rn(wx, wz), tx)));
+  const float sy = __fadd_rn(0.5f, __fmul_rn(0.5f, __fdiv_rn(__fdiv_rn(wy, wz), ty)));
+  Raster r;
+  r.inside = wz > 0.0f && sx >= 0.0f && sx < 1.0f && sy >= 0.0f && sy < 1.0f;
+  r.ix = r.inside ? min((int)__fmul_rn(sx, (float)W), W - 1) : 0;
+  r.iy = r.inside ? min((int)__fmul_rn(sy, (float)H), H - 1) : 0;
+  return r;
+}
+
+// One Metropolis step per chain (Alg. 1 lines 8-13 with the lens perturbation of Sec. 3.3):
+// region k of the current state's pixel on the N x N screen grid (Sec. 6.1, the filter's
+// map), proposal by the direction perturbation with sigma_k, alpha = min(1, L' / L) from
+// the luminance at both pixels (0 outside the frame), move iff the uniform is below alpha.
+template <bool kTable>
+__global__ __launch_bounds__(kPerturbBlock) void lens_step_kernel(
+    const Scale *__restrict__ table, const double *__restrict__ lambda, int N, const float *__restrict__ lum, int W,
+    int H, float tx, float ty, float *__restrict__ omega, const float *__restrict__ noise, int32_t *__restrict__ region,
+    float *__restrict__ alpha, float *__restrict__ omega_prop, long long n) {
+  const long long i = (long long)blockIdx.x * kPerturbBlock + threadIdx.x;
+  if (i >= n) return;
+  const float wx = omega[3 * i], wy = omega[3 * i + 1], wz = omega[3 * i + 2];
+  const float u = noise[3 * i], v = noise[3 * i + 1], ua = noise[3 * i + 2];
+  const Raster c = raster_of(wx, wy, wz, tx, ty, W, H);
+  int k = -1;
+  float a = __builtin_nanf(""), ox = a, oy = a, oz = a;
+  if (c.inside) {
+    const int kx = ((2 * c.ix + 1) * N) / (2 * W);
+    const int ky = ((2 * c.iy + 1) * N) / (2 * H);
+    k = ky * N + kx;
+    const float th = (float)theta_of((double)u, kTable ? table[k] : scale_of(lambda[k]));
+    propose(wx, wy, wz, th, v, ox, oy, oz);
+    const Raster p = raster_of(ox, oy, oz, tx, ty, W, H);
+    const float lc = lum[(long long)c.iy * W + c.ix];
+    if (p.inside) {
+      const float lp = lum[(long long)p.iy * W + p.ix];
+      a = lp >= lc ? 1.0f : __fdiv_rn(lp, lc);
+    } else {
+      a = 0.0f;
+    }
+    if (ua < a) {
+      omega[3 * i] = ox;
+      omega[3 * i + 1] = oy;
+      omega[3 * i + 2] = oz;
+    }
+  }
+  region[i] = k;
+  alpha[i] = a;
+  if (omega_prop) {
+    omega_prop[3 * i] = ox;
+    omega_prop[3 * i + 1] = oy;
+    omega_prop[3 * i + 2] = oz;
+  }
 }
 
 }  // namespace
@@ -141,6 +212,24 @@ hipError_t launch_perturb(const double *lambda, int m, const int32_t *region, co
   } else {
     perturb_kernel<false><<<(unsigned)blocks, kPerturbBlock, 0, st>>>(nullptr, lambda, m, region, omega,
                                                                       (const float2 *)uv, omega_out, theta_out, n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lens_step(const float *lum, int W, int H, float tx, float ty, const double *lambda, int N,
+                            float *omega, const float *noise, int32_t *region, float *alpha, float *omega_prop,
+                            long long n, void *ws, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int m = N * N;
+  const long long blocks = (n + kPerturbBlock - 1) / kPerturbBlock;
+  if (m <= kMaxTableRegions) {
+    Scale *table = (Scale *)ws;
+    scale_kernel<<<(m + kPerturbBlock - 1) / kPerturbBlock, kPerturbBlock, 0, st>>>(lambda, m, table);
+    lens_step_kernel<true><<<(unsigned)blocks, kPerturbBlock, 0, st>>>(table, lambda, N, lum, W, H, tx, ty, omega,
+                                                                       noise, region, alpha, omega_prop, n);
+  } else {
+    lens_step_kernel<false><<<(unsigned)blocks, kPerturbBlock, 0, st>>>(nullptr, lambda, N, lum, W, H, tx, ty, omega,
+                                                                        noise, region, alpha, omega_prop, n);
   }
   return hipGetLastError();
 }

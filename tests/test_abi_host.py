@@ -376,6 +376,31 @@ def test_perturb_directions_validation(lib):
     assert st(n_regions=65537, workspace=None, ws_bytes=0) in ok
 
 
+def test_lens_chain_step_validation(lib):
+    ok = (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
+    need = _abi.lens_workspace_size(20)
+    assert need == _abi.perturb_workspace_size(400) and _abi.lens_workspace_size(0) == 0
+    assert _abi.lens_workspace_size(4097) == 0 and _abi.lens_workspace_size(257) == 0   # 66049 regions: no table
+    args = dict(luminance=0x100000, W=1920, H=1080, tan_half_fov_x=0.6, lam=0x200000, n_regions=20,
+                omega=0x300000, noise=0x400000, region=0x500000, alpha=0x600000, omega_prop=0x700000, n=1000,
+                workspace=FAKE_WORKSPACE, ws_bytes=need)
+    st = lambda **kw: _abi.lens_chain_step_status(**{**args, **kw})
+    assert st() in ok, _abi.last_error()
+    assert st(omega_prop=None) in ok
+    assert st(omega=None, noise=None, region=None, alpha=None, omega_prop=None, n=0) in ok
+    bad = [dict(W=0), dict(H=0), dict(W=65537), dict(tan_half_fov_x=0.0), dict(tan_half_fov_x=-1.0),
+           dict(tan_half_fov_x=float("inf")), dict(tan_half_fov_x=float("nan")), dict(tan_half_fov_x=1e-45, H=1),
+           dict(n_regions=0), dict(n_regions=4097), dict(luminance=None), dict(luminance=0x100002), dict(lam=None),
+           dict(lam=0x200004), dict(n=-1), dict(n=(1 << 30) + 1), dict(omega=None), dict(omega=0x300001),
+           dict(noise=None), dict(region=None), dict(alpha=0x600002), dict(omega_prop=0x700001)]
+    for kw in bad:
+        assert st(**kw) == _abi.RAMLT_EINVAL, kw
+    assert st(workspace=None, ws_bytes=0) == _abi.RAMLT_EWORKSPACE
+    assert st(ws_bytes=need - 1) == _abi.RAMLT_EWORKSPACE
+    assert st(workspace=FAKE_WORKSPACE + 8) == _abi.RAMLT_EWORKSPACE
+    assert st(n_regions=257, workspace=None, ws_bytes=0) in ok
+
+
 def test_rrmse_validation(lib):
     ok = (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
     need = _abi.rrmse_workspace_size(1920, 1080)
