@@ -747,8 +747,8 @@ def _oracle_chain(rad_b, feat_b, ref_b, lam_h, S, r, N, W, H):
 def cpu_baseline(rad, feat, ref, lam, W, H, S, r, N, rows, target_s=15.0):
     """The FP64 oracle, as it stands, on a band of rows of the same frame (same chain:
     stats -> filter -> loss seed -> adjoint, with the frame's regions), timed on the host.
-    Rate in Mpixel/s. The band height is chosen from a 16-row probe so the timed run takes
-    about target_s."""
+    Rate in Mpixel/s. The band height is chosen from two probes (8 and 24 rows: their
+    difference removes the fixed cost of a call) so the timed run takes about target_s."""
     lam_h = lam.cpu().numpy()
 
     def band(n):
@@ -756,11 +756,14 @@ def cpu_baseline(rad, feat, ref, lam, W, H, S, r, N, rows, target_s=15.0):
         return rad[:, :, sl].cpu().numpy(), feat[:, :, sl].cpu().numpy(), ref[:, sl].cpu().numpy()
 
     if not rows:
-        probe = min(16, H)
-        t0 = time.perf_counter()
-        _oracle_chain(*band(probe), lam_h, S, r, N, W, H)
-        per_row = (time.perf_counter() - t0) / probe
-        rows = int(max(probe, min(H, target_s / max(per_row, 1e-6))))
+        times = []
+        for probe in (min(8, H), min(24, H)):
+            t0 = time.perf_counter()
+            _oracle_chain(*band(probe), lam_h, S, r, N, W, H)
+            times.append((probe, time.perf_counter() - t0))
+        (p0, t0_), (p1, t1_) = times
+        per_row = (t1_ - t0_) / (p1 - p0) if p1 > p0 and t1_ > t0_ else t1_ / p1
+        rows = int(max(p1, min(H, target_s / max(per_row, 1e-6))))
     data = band(rows)
     t0 = time.perf_counter()
     _oracle_chain(*data, lam_h, S, r, N, W, H)
