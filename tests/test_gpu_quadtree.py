@@ -61,6 +61,8 @@ def _lookup_both(name, t, f, root, x, y, count=True):
     (20, 20_000, 60_000, 60, 5),
     (400, 30_000, 120_000, 40, 4),
     (2, 40_000, 200_000, 5, 7),
+    (100, 20_000, 80_000, 30, 4),
+    (600, 30_000, 150_000, 30, 4),
 ])
 def test_quadtree_growth_parity(n_roots, capacity, n, m_split, rounds):
     print(f"quadtree growth R={n_roots} cap={capacity} n={n} M_split={m_split}", flush=True)
