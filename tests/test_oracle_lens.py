@@ -2,8 +2,8 @@
 perturbation, Sec. 6.1 screen partition, Alg. 1 lines 8-13): the raster map against pixel
 centres and the frame's edges; the Metropolis step's stationary distribution against the
 closed form (luminance times each pixel's solid angle, by the exact rectangle formula) with a
-chi-square test; and the degenerate cases (tiny sigma, states outside the frame, black
-pixels)."""
+chi-square test; the degenerate cases (tiny sigma, states outside the frame, black
+pixels); and, closing the loop with the adaptation, the direction of the lambda update."""
 
 import math
 
@@ -84,3 +84,37 @@ def test_degenerate_cases():
                                        rng.random((200, 3)).astype(F32))
     ins, _, _ = lc.raster(prop, W, H, tx)
     assert np.all(alpha[ins] == 1) and np.all(alpha[~ins] == 0) and (~ins).any()
+
+
+def test_closed_loop_pins_the_direction_of_the_update():
+    # Reading A2: eq. update_lambda raises lambda when the estimated acceptance is above the
+    # target, while the prose states the opposite. Closing the loop with the lens chains shows
+    # which one adapts: with the equation every region settles near alpha* = 1/2; with the
+    # prose's direction (the same update fed 1 - alpha, which flips sgn(alpha_hat - 1/2)) the
+    # scales run away (here upwards, from an initial sigma of 1.6 rad that already accepts
+    # less than half) and the acceptance with them.
+    from oracle import region_adapt as ora
+
+    W, H, tx, N, n, rounds = 64, 40, 0.5, 2, 8192, 60
+    rng = np.random.default_rng(21)
+    L = rng.uniform(0.2, 3.0, size=(H, W)).astype(F32)
+
+    def run(flip):
+        st = ora.initial_state(N * N)
+        omega = lc.pixel_centre_directions(W, H, tx)[rng.integers(0, W * H, n)]
+        acc = np.zeros(N * N)
+        cnt = np.zeros(N * N)
+        for r in range(rounds):
+            omega, region, alpha, _ = lc.step(L, tx, st["lambda"], N, omega, rng.random((n, 3)).astype(F32))
+            ora.adapt(st, region, (F32(1) - alpha) if flip else alpha, L=10)
+            if r >= rounds - 20:
+                ok = region >= 0
+                np.add.at(acc, region[ok], alpha[ok])
+                np.add.at(cnt, region[ok], 1)
+        return acc / np.maximum(cnt, 1), st["lambda"]
+
+    acc, lam = run(False)
+    assert np.all(np.abs(acc - 0.5) < 0.1), (acc, lam)
+    with np.errstate(over="ignore", invalid="ignore"):
+        acc_f, lam_f = run(True)
+    assert np.all(np.abs(acc_f - 0.5) > 0.4) and np.all(np.abs(lam_f) > 20), (acc_f, lam_f)
