@@ -9,12 +9,15 @@
  *                                 quadtree_refine (children inherit lambda and n_k / 4);
  *                                 then quadtree_lookup -> perturb_directions with the
  *                                 leaves' lambda
+ *   lens chains:                  lens_chain_step on a luminance image with the screen
+ *                                 grid's adapted lambda
  *
- * Usage: gpu_chain DIR W H S N r max_lag n_prop capacity n_pts m_split rounds
+ * Usage: gpu_chain DIR W H S N r max_lag n_prop capacity n_pts m_split rounds n_chains tan_half_fov_x
  * Inputs are raw little-endian arrays in DIR (radiance.f32 [3][S][H][W], features.f32
  * [7][S][H][W], reference.f32 [3][H][W], region.i32 / alpha.f32 [n_prop], px.f32 / py.f32 /
- * qalpha.f32 [n_pts], omega.f32 [n_pts][3], uv.f32 [n_pts][2]); every output is written to
- * DIR as out_<name>.<type>. Exit status 0 on success, 2 for a HIP error, 3 for a library
+ * qalpha.f32 [n_pts], omega.f32 [n_pts][3], uv.f32 [n_pts][2], luminance.f32 [H][W],
+ * chains.f32 / noise.f32 [n_chains][3]); every output is written to DIR as
+ * out_<name>.<type>. Exit status 0 on success, 2 for a HIP error, 3 for a library
  * status, 4 for a file or argument error. */
 #include <hip/hip_runtime_api.h>
 #include <stdio.h>
@@ -151,8 +154,9 @@ static void adapt(const ramlt_region_state *st, int32_t m, const int32_t *region
 }
 
 int main(int argc, char **argv) {
-  if (argc != 13) {
-    fprintf(stderr, "usage: %s DIR W H S N r max_lag n_prop capacity n_pts m_split rounds\n", argv[0]);
+  if (argc != 15) {
+    fprintf(stderr, "usage: %s DIR W H S N r max_lag n_prop capacity n_pts m_split rounds n_chains tan_half_fov_x\n",
+            argv[0]);
     return 4;
   }
   g_dir = argv[1];
@@ -162,8 +166,10 @@ int main(int argc, char **argv) {
   const int32_t capacity = atoi(argv[9]);
   const int64_t n_pts = atoll(argv[10]);
   const int32_t m_split = atoi(argv[11]), rounds = atoi(argv[12]);
+  const int64_t n_chains = atoll(argv[13]);
+  const float tan_half = (float)atof(argv[14]);
   if (W < 1 || H < 1 || S < 1 || N < 1 || r < 0 || max_lag < 0 || n_prop < 1 || capacity < 1 || n_pts < 1 ||
-      m_split < 0 || rounds < 1 || (int64_t)W * H * S > (1 << 26)) {
+      m_split < 0 || rounds < 1 || n_chains < 1 || !(tan_half > 0.0f) || (int64_t)W * H * S > (1 << 26)) {
     fprintf(stderr, "bad sizes\n");
     return 4;
   }
@@ -295,6 +301,23 @@ int main(int argc, char **argv) {
   download("out_leaf_ivisits.i32", leaves.visits, sizeof(int32_t) * (size_t)nn);
   download("out_omega.f32", omega_out, sizeof(float) * 3 * (size_t)n_pts);
   download("out_theta.f32", theta, sizeof(float) * (size_t)n_pts);
+
+  /* lens chains on the luminance, with the screen grid's adapted lambda */
+  float *lum = upload("luminance.f32", sizeof(float) * P);
+  float *chains = upload("chains.f32", sizeof(float) * 3 * (size_t)n_chains);
+  float *noise = upload("noise.f32", sizeof(float) * 3 * (size_t)n_chains);
+  int32_t *lregion = dev_alloc(sizeof(int32_t) * (size_t)n_chains);
+  float *lalpha = dev_alloc(sizeof(float) * (size_t)n_chains);
+  float *lprop = dev_alloc(sizeof(float) * 3 * (size_t)n_chains);
+  size_t lws = ramlt_lens_workspace_size(N);
+  void *lw = dev_alloc(lws);
+  RAMLT_OK_(lens_chain_step(lum, W, H, tan_half, grid.lambda, N, chains, noise, lregion, lalpha, lprop, n_chains, lw,
+                            lws, NULL));
+  HIP_OK(hipDeviceSynchronize());
+  download("out_lens_region.i32", lregion, sizeof(int32_t) * (size_t)n_chains);
+  download("out_lens_alpha.f32", lalpha, sizeof(float) * (size_t)n_chains);
+  download("out_lens_prop.f32", lprop, sizeof(float) * 3 * (size_t)n_chains);
+  download("out_lens_chains.f32", chains, sizeof(float) * 3 * (size_t)n_chains);
   printf("chain done: %d nodes\n", nn);
   return 0;
 }

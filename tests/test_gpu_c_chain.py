@@ -6,7 +6,8 @@ Screen grid: region_adapt (Algorithm 1) -> stats_accumulate (Appendix A) ->
 filter_forward with the adapted lambda (Sec. 3.1, 5.3) -> filter_backward with the loss
 seed fused -> rrmse (Sec. 8.2). Quadtree: lookups, adaptation keyed by leaf and
 refinement with inheritance (Sec. 6.1-6.2), then the direction perturbation (Sec. 3.3)
-with the leaves' lambda.
+with the leaves' lambda. Lens chains: one step on a luminance image with the screen grid's
+adapted lambda (Sec. 3.3, 6.1).
 
 Tolerances are those of the per-entry-point parity tests. The grid's lambda is compared
 exactly: every region there applies at most 25 updates, and gamma = min(1, 5 / sqrt(n)) is
@@ -24,13 +25,16 @@ import pytest
 
 import oracle
 from oracle import direction_sampler as ods
+from oracle import lens_chain as olc
 from oracle import quadtree as oqt
 from oracle import region_adapt as ora
 from oracle import rrmse as orr
 from paper_2402_08273_amd import _abi
 from parity import TOL, backward_scales, check, filter_scale, stats_scales
+from test_gpu_lens import _safe
 from synth import make_frame, make_reference
 from synth.directions import make_perturb_inputs
+from synth.lens import make_lens_chains, make_lens_noise, make_luminance
 from synth.numpy_gen import NOISE_CONST
 from synth.points import make_points
 from synth.proposals import make_proposals
@@ -43,6 +47,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 W, H, S, N, R, MAX_LAG = 75, 41, 6, 3, 2, 8
 N_PROP = 600
 CAPACITY, N_PTS, M_SPLIT, ROUNDS, L = 256, 20_000, 500, 4, 10
+N_CHAINS, TAN = 50_000, 0.6
 EPS = 1e-2
 DIR_TOL = 4e-6
 
@@ -80,7 +85,8 @@ def _inputs(d):
     _, omega, uv = make_perturb_inputs(N_PTS, CAPACITY, seed=45)
     arrays = {"radiance.f32": rad, "features.f32": feats, "reference.f32": ref, "region.i32": region,
               "alpha.f32": alpha, "px.f32": px, "py.f32": py, "qalpha.f32": qalpha, "omega.f32": omega,
-              "uv.f32": uv}
+              "uv.f32": uv, "luminance.f32": make_luminance(W, H, seed=46),
+              "chains.f32": make_lens_chains(N_CHAINS, W, H, TAN, seed=47), "noise.f32": make_lens_noise(N_CHAINS, seed=48)}
     for name, a in arrays.items():
         np.ascontiguousarray(a).tofile(os.path.join(d, name))
     return arrays
@@ -94,7 +100,8 @@ def test_c_program_runs_the_path(tmp_path):
     exe = _build(tmp_path)
     d = str(tmp_path)
     a = _inputs(d)
-    args = [exe, d] + [str(v) for v in (W, H, S, N, R, MAX_LAG, N_PROP, CAPACITY, N_PTS, M_SPLIT, ROUNDS)]
+    args = [exe, d] + [str(v) for v in (W, H, S, N, R, MAX_LAG, N_PROP, CAPACITY, N_PTS, M_SPLIT, ROUNDS, N_CHAINS,
+                                        TAN)]
     print("C chain:", " ".join(args[2:]), flush=True)
     run = subprocess.run(args, capture_output=True, text=True, timeout=120)
     assert run.returncode == 0, (run.returncode, run.stdout, run.stderr)
@@ -182,3 +189,22 @@ def test_c_program_runs_the_path(tmp_path):
     okd = ~np.isnan(want)
     assert np.array_equal(np.isnan(om), np.isnan(want))
     assert np.max(np.abs(om[okd] - want[okd])) <= DIR_TOL
+
+    # lens chains with the grid's adapted lambda: regions exact, proposals within 4e-6, alpha
+    # and the move exactly where the proposal's pixel is decided (as in test_gpu_lens.py)
+    ch, nz = a["chains.f32"], a["noise.f32"]
+    _, o_reg, o_alpha, o_prop = olc.step(a["luminance.f32"], TAN, st["lambda"], N, ch, nz)
+    g_reg = _out(d, "lens_region.i32", np.int32)
+    g_alpha = _out(d, "lens_alpha.f32", np.float32)
+    g_prop = _out(d, "lens_prop.f32", np.float32).reshape(N_CHAINS, 3)
+    g_next = _out(d, "lens_chains.f32", np.float32).reshape(N_CHAINS, 3)
+    assert np.array_equal(g_reg, o_reg)
+    ok = o_reg >= 0
+    assert np.max(np.abs(g_prop[ok] - o_prop[ok])) <= DIR_TOL
+    safe = ok & _safe(o_prop, g_prop, W, H, TAN)
+    assert safe.sum() >= 0.99 * ok.sum()
+    assert np.array_equal(g_alpha[safe], o_alpha[safe])
+    moved = safe & (nz[:, 2] < o_alpha)
+    stay = safe & ~moved
+    assert np.array_equal(g_next[moved], g_prop[moved]) and np.array_equal(g_next[stay], ch[stay])
+    assert moved.any() and stay.any()
