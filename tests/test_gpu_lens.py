@@ -145,3 +145,41 @@ def test_lens_adaptation_loop_reaches_the_target_acceptance():
     assert lam.max() - lam.min() > 1.0, lam                  # the scales differ by region
     assert np.all(lam > -30) and np.all(np.isfinite(lam))
     assert math.isfinite(float(acc[busy].mean()))
+
+
+def test_lens_step_edge_cases():
+    print("lens edge cases", flush=True)
+    # no chains
+    L = _dev(make_luminance(64, 40, seed=1))
+    lam = _dev(np.zeros(4))
+    region, alpha = ops.lens_chain_step(L, 0.5, lam, 2, _dev(np.zeros((0, 3), np.float32)),
+                                        _dev(np.zeros((0, 3), np.float32)))
+    assert region.numel() == 0 and alpha.numel() == 0
+    # a black image: every proposal inside the frame is accepted, every one outside rejected;
+    # NaN luminance: alpha NaN and no move, on both sides
+    for name, img in (("black", np.zeros((40, 64), np.float32)),
+                      ("nan", np.where(np.arange(64 * 40).reshape(40, 64) % 7 == 0, np.nan, 1.0).astype(np.float32))):
+        om = make_lens_chains(20_000, 64, 40, 0.5, seed=2)
+        nz = make_lens_noise(20_000, seed=3)
+        lam_h = np.array([-2.0, 0.0, -1.0, -3.0])
+        g_om = _dev(om)
+        region, alpha, prop = ops.lens_chain_step(_dev(img), 0.5, _dev(lam_h), 2, g_om, _dev(nz), want_proposals=True)
+        torch.cuda.synchronize()
+        o_next, o_reg, o_alpha, o_prop = olc.step(img, 0.5, lam_h, 2, om, nz)
+        g_reg, g_alpha, g_prop, g_next = (t.cpu().numpy() for t in (region, alpha, prop, g_om))
+        assert np.array_equal(g_reg, o_reg), name
+        ok = o_reg >= 0
+        safe = ok & _safe(o_prop, g_prop, 64, 40, 0.5)
+        assert safe.sum() >= 0.99 * ok.sum(), name
+        assert np.array_equal(g_alpha[safe], o_alpha[safe], equal_nan=True), name
+        moved = safe & (nz[:, 2] < o_alpha)
+        assert np.array_equal(g_next[moved], g_prop[moved]) and np.array_equal(g_next[safe & ~moved], om[safe & ~moved])
+        if name == "black":
+            assert set(np.unique(g_alpha[ok]).tolist()) == {0.0, 1.0}
+        else:
+            assert np.isnan(g_alpha[ok]).any() and not moved[np.isnan(o_alpha)].any()
+    # a one-row image with a wide field of view
+    W, H, tx = 3000, 1, 2.0
+    img = make_luminance(W, H, seed=4)
+    lam_h = make_lambda_table(9, seed=5)
+    _compare("one row", img, tx, lam_h, 3, make_lens_chains(50_000, W, H, tx, seed=6), make_lens_noise(50_000, seed=7))
