@@ -399,9 +399,10 @@ def measure_lens(steps, warmup, cpu=True):
     """Screen-space chains under the regional adaptive lens perturbation on a 1920x1080
     luminance image, 20x20 regions, 16 M chains: one Metropolis step per chain
     (lens_chain_step), and the closed loop (step, then region_adapt of its (region, alpha)
-    stream). Algorithmic bytes per chain of the step: omega 12 + noise 12 read, region 4 +
-    alpha 4 written, the luminance at both pixels 8, omega 12 written on acceptance (times the
-    batch's mean alpha)."""
+    stream). The chains carry the luminance of their pixel between steps. Algorithmic bytes
+    per chain of the step: omega 12 + noise 12 + carried luminance 4 read, region 4 + alpha 4
+    + carried luminance 4 written, the luminance at the proposal 4, omega 12 written on
+    acceptance (times the batch's mean alpha)."""
     import torch
 
     from paper_2402_08273_amd import ops
@@ -415,10 +416,11 @@ def measure_lens(steps, warmup, cpu=True):
     om = torch.from_numpy(make_lens_chains(n, W, H, tx, seed=8)).cuda()
     noise = torch.from_numpy(make_lens_noise(n, seed=9)).cuda()
     ad = RegionAdapter(N * N, L=10)
+    dens = torch.full((n,), -1.0, dtype=torch.float32, device=om.device)   # carried luminance
     last = {}
 
     def step():
-        last["ra"] = ops.lens_chain_step(L, tx, ad.lam, N, om, noise)
+        last["ra"] = ops.lens_chain_step(L, tx, ad.lam, N, om, noise, density=dens)
 
     def loop():
         step()
@@ -431,7 +433,7 @@ def measure_lens(steps, warmup, cpu=True):
     region, alpha = last["ra"]
     ok = region >= 0
     acc = float(alpha[ok].double().mean())
-    nbytes = int(n * (40 + 12 * acc))
+    nbytes = int(n * (44 + 12 * acc))
     gbs = nbytes / (ms * 1e-3) / 1e9
     out = {"workload": f"lens-perturbation chains, {n} chains, {W}x{H} luminance, {N}x{N} regions, "
                        f"tan(fov/2) = {tx}",
@@ -439,7 +441,7 @@ def measure_lens(steps, warmup, cpu=True):
            "ms_per_adaptive_step": round(ms_loop, 4), "mean_alpha": round(acc, 4), "algorithmic_bytes": nbytes,
            "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
            "roofline": hbm_roofline(nbytes, ms, "scale_kernel + lens_step_kernel")}
-    del L, om, noise, ad, last
+    del L, om, noise, ad, last, dens
     if cpu:
         out["cpu_baseline"] = lens_cpu_baseline()
     torch.cuda.empty_cache()

@@ -343,7 +343,13 @@ size_t ramlt_perturb_workspace_size(int32_t n_regions);
  *   move:     omega_i = omega' iff noise[i][2] < alpha.
  * region[i] = k, alpha[i] = alpha (Alg. 1 line 8: the region of the state before the move).
  * A chain whose state is outside the frame (or NaN) gets region -1 and alpha NaN and does not
- * move. luminance: DEVICE float[H][W] (>= 0; NaN gives alpha NaN, never a move); lambda:
+ * move. density: DEVICE float[n] or NULL, read and updated in place: the luminance of each
+ * chain's current pixel, carried between steps so that a step reads the image once per chain
+ * (at the proposal) instead of twice; an entry below 0 or NaN (e.g. -1 before the first
+ * step) is read from the image, and after the step every entry holds the luminance of the
+ * chain's pixel (-1 for a chain outside the frame). Results equal those without it as long
+ * as the image does not change between steps (reset the entries to -1 when it does).
+ * luminance: DEVICE float[H][W] (>= 0; NaN gives alpha NaN, never a move); lambda:
  * DEVICE double[n_regions^2], 8-byte aligned (e.g. ramlt_region_state.lambda); omega: DEVICE
  * float[n][3], read and updated in place; noise: DEVICE float[n][3]; region: DEVICE int32[n];
  * alpha: DEVICE float[n]; omega_prop: DEVICE float[n][3] or NULL (the proposals). W, H as for
@@ -352,8 +358,8 @@ size_t ramlt_perturb_workspace_size(int32_t n_regions);
  * ramlt_lens_workspace_size(n_regions) bytes (0, and NULL allowed, above 65536 regions or for
  * n = 0). Errors: RAMLT_EINVAL, RAMLT_EWORKSPACE. */
 int lens_chain_step(const float *luminance, int32_t W, int32_t H, float tan_half_fov_x, const double *lambda,
-                    int32_t n_regions, float *omega, const float *noise, int32_t *region, float *alpha,
-                    float *omega_prop, int64_t n, void *workspace, size_t ws_bytes, void *stream);
+                    int32_t n_regions, float *omega, float *density, const float *noise, int32_t *region,
+                    float *alpha, float *omega_prop, int64_t n, void *workspace, size_t ws_bytes, void *stream);
 
 /* Workspace bytes of lens_chain_step (0 for an invalid n_regions). */
 size_t ramlt_lens_workspace_size(int32_t n_regions);

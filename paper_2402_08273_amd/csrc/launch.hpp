@@ -37,8 +37,8 @@ size_t perturb_workspace_bytes(int m);
 // Lens-perturbation chain step (perturb.hip): validated arguments; ty = tx H / W; the
 // workspace is perturb_workspace_bytes(N * N).
 hipError_t launch_lens_step(const float *lum, int W, int H, float tx, float ty, const double *lambda, int N,
-                            float *omega, const float *noise, int32_t *region, float *alpha, float *omega_prop,
-                            long long n, void *ws, hipStream_t st);
+                            float *omega, float *density, const float *noise, int32_t *region, float *alpha,
+                            float *omega_prop, long long n, void *ws, hipStream_t st);
 
 // rRMSE (rrmse.hip): validated arguments; P = W H pixels.
 hipError_t launch_rrmse(const float *image, const float *reference, long long P, double eps, float *map,

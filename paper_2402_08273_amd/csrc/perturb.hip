@@ -153,18 +153,21 @@ __device__ __forceinline__ Raster raster_of(float wx, float wy, float wz, float 
 // region k of the current state's pixel on the N x N screen grid (Sec. 6.1, the filter's
 // map), proposal by the direction perturbation with sigma_k, alpha = min(1, L' / L) from
 // the luminance at both pixels (0 outside the frame), move iff the uniform is below alpha.
+// With `density`, each chain carries the luminance of its current pixel between steps (an
+// entry below 0 or NaN is read from the image), so a step reads the image once per chain,
+// at the proposal, instead of twice.
 template <bool kTable>
 __global__ __launch_bounds__(kPerturbBlock) void lens_step_kernel(
     const Scale *__restrict__ table, const double *__restrict__ lambda, int N, const float *__restrict__ lum, int W,
-    int H, float tx, float ty, float *__restrict__ omega, const float *__restrict__ noise, int32_t *__restrict__ region,
-    float *__restrict__ alpha, float *__restrict__ omega_prop, long long n) {
+    int H, float tx, float ty, float *__restrict__ omega, float *__restrict__ density, const float *__restrict__ noise,
+    int32_t *__restrict__ region, float *__restrict__ alpha, float *__restrict__ omega_prop, long long n) {
   const long long i = (long long)blockIdx.x * kPerturbBlock + threadIdx.x;
   if (i >= n) return;
   const float wx = omega[3 * i], wy = omega[3 * i + 1], wz = omega[3 * i + 2];
   const float u = noise[3 * i], v = noise[3 * i + 1], ua = noise[3 * i + 2];
   const Raster c = raster_of(wx, wy, wz, tx, ty, W, H);
   int k = -1;
-  float a = __builtin_nanf(""), ox = a, oy = a, oz = a;
+  float a = __builtin_nanf(""), ox = a, oy = a, oz = a, dens = -1.0f;
   if (c.inside) {
     const int kx = ((2 * c.ix + 1) * N) / (2 * W);
     const int ky = ((2 * c.iy + 1) * N) / (2 * H);
@@ -172,21 +175,26 @@ __global__ __launch_bounds__(kPerturbBlock) void lens_step_kernel(
     const float th = (float)theta_of((double)u, kTable ? table[k] : scale_of(lambda[k]));
     propose(wx, wy, wz, th, v, ox, oy, oz);
     const Raster p = raster_of(ox, oy, oz, tx, ty, W, H);
-    const float lc = lum[(long long)c.iy * W + c.ix];
+    const float carried = density ? density[i] : -1.0f;
+    const float lc = carried >= 0.0f ? carried : lum[(long long)c.iy * W + c.ix];
+    float lp = 0.0f;
     if (p.inside) {
-      const float lp = lum[(long long)p.iy * W + p.ix];
+      lp = lum[(long long)p.iy * W + p.ix];
       a = lp >= lc ? 1.0f : __fdiv_rn(lp, lc);
     } else {
       a = 0.0f;
     }
+    dens = lc;
     if (ua < a) {
       omega[3 * i] = ox;
       omega[3 * i + 1] = oy;
       omega[3 * i + 2] = oz;
+      dens = lp;
     }
   }
   region[i] = k;
   alpha[i] = a;
+  if (density) density[i] = dens;
   if (omega_prop) {
     omega_prop[3 * i] = ox;
     omega_prop[3 * i + 1] = oy;
@@ -217,8 +225,8 @@ hipError_t launch_perturb(const double *lambda, int m, const int32_t *region, co
 }
 
 hipError_t launch_lens_step(const float *lum, int W, int H, float tx, float ty, const double *lambda, int N,
-                            float *omega, const float *noise, int32_t *region, float *alpha, float *omega_prop,
-                            long long n, void *ws, hipStream_t st) {
+                            float *omega, float *density, const float *noise, int32_t *region, float *alpha,
+                            float *omega_prop, long long n, void *ws, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int m = N * N;
   const long long blocks = (n + kPerturbBlock - 1) / kPerturbBlock;
@@ -226,10 +234,10 @@ hipError_t launch_lens_step(const float *lum, int W, int H, float tx, float ty, 
     Scale *table = (Scale *)ws;
     scale_kernel<<<(m + kPerturbBlock - 1) / kPerturbBlock, kPerturbBlock, 0, st>>>(lambda, m, table);
     lens_step_kernel<true><<<(unsigned)blocks, kPerturbBlock, 0, st>>>(table, lambda, N, lum, W, H, tx, ty, omega,
-                                                                       noise, region, alpha, omega_prop, n);
+                                                                       density, noise, region, alpha, omega_prop, n);
   } else {
     lens_step_kernel<false><<<(unsigned)blocks, kPerturbBlock, 0, st>>>(nullptr, lambda, N, lum, W, H, tx, ty, omega,
-                                                                        noise, region, alpha, omega_prop, n);
+                                                                        density, noise, region, alpha, omega_prop, n);
   }
   return hipGetLastError();
 }

@@ -183,3 +183,28 @@ def test_lens_step_edge_cases():
     img = make_luminance(W, H, seed=4)
     lam_h = make_lambda_table(9, seed=5)
     _compare("one row", img, tx, lam_h, 3, make_lens_chains(50_000, W, H, tx, seed=6), make_lens_noise(50_000, seed=7))
+
+
+def test_lens_carried_density_gives_the_same_steps():
+    # carrying each chain's luminance between steps (read once, at the proposal) changes
+    # nothing in the results: five steps with and without it agree bit for bit, and the
+    # carried value is the luminance at the chain's pixel
+    W, H, tx, N, n = 320, 200, 0.6, 20, 100_000
+    print("lens carried density", flush=True)
+    img = make_luminance(W, H, seed=8)
+    L = _dev(img)
+    lam = _dev(make_lambda_table(N * N, seed=9))
+    om_a = _dev(make_lens_chains(n, W, H, tx, seed=10))
+    om_b = om_a.clone()
+    dens = torch.full((n,), -1.0, dtype=torch.float32, device="cuda")
+    for r in range(5):
+        nz = _dev(make_lens_noise(n, seed=11, batch=r))
+        ra, aa = ops.lens_chain_step(L, tx, lam, N, om_a, nz)
+        rb, ab = ops.lens_chain_step(L, tx, lam, N, om_b, nz, density=dens)
+        torch.cuda.synchronize()
+        assert torch.equal(ra, rb), r
+        assert np.array_equal(aa.cpu().numpy(), ab.cpu().numpy(), equal_nan=True), r
+        assert np.array_equal(om_a.cpu().numpy(), om_b.cpu().numpy(), equal_nan=True), r
+    inside, ix, iy = olc.raster(om_b.cpu().numpy(), W, H, tx)
+    d = dens.cpu().numpy()
+    assert np.array_equal(d[inside], img[iy[inside], ix[inside]]) and np.all(d[~inside] == -1.0)
