@@ -73,18 +73,37 @@ def step(luminance, tan_half_x, lam, n_regions, omega, noise):
     region = np.where(inside, kmap[iy, ix], -1)
     prop64, _ = ds.perturb_directions(lam, region, omega.astype(np.float64), noise[:, :2].astype(np.float64))
     prop = prop64.astype(F32)
-    inside2, ix2, iy2 = raster(np.where(inside[:, None], prop, F32(0)), W, H, tan_half_x)
-    inside2 &= inside
-    cur = L[iy, ix]
-    new = np.where(inside2, L[iy2, ix2], F32(0))
-    with np.errstate(divide="ignore", invalid="ignore"):
-        alpha = np.where(inside2, np.where(new >= cur, F32(1), new / cur), F32(0)).astype(F32)
-    alpha = np.where(inside, alpha, F32(np.nan))
+    alpha = acceptance(L, tan_half_x, omega, prop)
     accept = noise[:, 2] < alpha
     nxt = np.where(accept[:, None], prop, omega)
     prop = np.where(inside[:, None], prop, F32(np.nan))
     assert nxt.shape == (n, 3)
     return nxt, region, alpha, prop
+
+
+def ratio(new, cur):
+    """alpha = min(1, new / cur) of luminances (float32): 1 if new >= cur, else the quotient."""
+    new = np.asarray(new, dtype=F32)
+    cur = np.asarray(cur, dtype=F32)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(new >= cur, F32(1), new / cur).astype(F32)
+
+
+def acceptance(luminance, tan_half_x, omega, prop):
+    """alpha of moving from each state omega [n, 3] to its proposal prop [n, 3] (float32):
+    NaN for a state outside the frame, 0 for a proposal outside it, else
+    min(1, pi(prop) / pi(omega)) with pi the luminance of the pixel."""
+    L = np.asarray(luminance, dtype=F32)
+    H, W = L.shape
+    omega = np.asarray(omega, dtype=F32)
+    prop = np.asarray(prop, dtype=F32)
+    inside, ix, iy = raster(omega, W, H, tan_half_x)
+    inside2, ix2, iy2 = raster(np.where(inside[:, None], prop, F32(0)), W, H, tan_half_x)
+    inside2 &= inside
+    cur = L[iy, ix]
+    new = np.where(inside2, L[iy2, ix2], F32(0))
+    alpha = np.where(inside2, ratio(new, cur), F32(0)).astype(F32)
+    return np.where(inside, alpha, F32(np.nan)).astype(F32)
 
 
 def pixel_solid_angles(W, H, tan_half_x):

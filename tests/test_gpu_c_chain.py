@@ -31,7 +31,7 @@ from oracle import region_adapt as ora
 from oracle import rrmse as orr
 from paper_2402_08273_amd import _abi
 from parity import TOL, backward_scales, check, filter_scale, stats_scales
-from test_gpu_lens import _safe
+import lens_check
 from synth import make_frame, make_reference
 from synth.directions import make_perturb_inputs
 from synth.lens import make_lens_chains, make_lens_noise, make_luminance
@@ -191,20 +191,13 @@ def test_c_program_runs_the_path(tmp_path):
     assert np.max(np.abs(om[okd] - want[okd])) <= DIR_TOL
 
     # lens chains with the grid's adapted lambda: regions exact, proposals within 4e-6, alpha
-    # and the move exactly where the proposal's pixel is decided (as in test_gpu_lens.py)
+    # and the move checked as in test_gpu_lens.py (tests/lens_check.py)
     ch, nz = a["chains.f32"], a["noise.f32"]
-    _, o_reg, o_alpha, o_prop = olc.step(a["luminance.f32"], TAN, st["lambda"], N, ch, nz)
+    o = olc.step(a["luminance.f32"], TAN, st["lambda"], N, ch, nz)
     g_reg = _out(d, "lens_region.i32", np.int32)
     g_alpha = _out(d, "lens_alpha.f32", np.float32)
     g_prop = _out(d, "lens_prop.f32", np.float32).reshape(N_CHAINS, 3)
     g_next = _out(d, "lens_chains.f32", np.float32).reshape(N_CHAINS, 3)
-    assert np.array_equal(g_reg, o_reg)
-    ok = o_reg >= 0
-    assert np.max(np.abs(g_prop[ok] - o_prop[ok])) <= DIR_TOL
-    safe = ok & _safe(o_prop, g_prop, W, H, TAN)
-    assert safe.sum() >= 0.99 * ok.sum()
-    assert np.array_equal(g_alpha[safe], o_alpha[safe])
-    moved = safe & (nz[:, 2] < o_alpha)
-    stay = safe & ~moved
-    assert np.array_equal(g_next[moved], g_prop[moved]) and np.array_equal(g_next[stay], ch[stay])
-    assert moved.any() and stay.any()
+    lens_check.check_step(a["luminance.f32"], TAN, ch, nz, o, [g_next, g_reg, g_alpha, g_prop], name="C chain")
+    moved = (o[1] >= 0) & (nz[:, 2] < g_alpha)
+    assert moved.any() and ((o[1] >= 0) & ~moved).any()
