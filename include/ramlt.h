@@ -80,11 +80,22 @@ enum ramlt_op {
  *   bits 0-1: output tile of the filter kernels (filter_forward, filter_backward);
  *   bit 2:    RAMLT_SCHED_DIRECT: the filter gathers each (2r+1)^2 window directly instead of
  *             a pass over rows then columns.
- * Other bits must be 0. Frames of one batch with different tiles run in separate launches. */
+ * Frames of one batch with different tiles run in separate launches.
+ *
+ * Where the loss is formed, also in ramlt_frame.flags:
+ *   bit 3:    RAMLT_LOSS_IN_FORWARD: filter_forward forms, besides out, the MSE loss seed
+ *             (writes grad_out = U = 2 (out - reference) / (3 W H), accumulates *loss) and the
+ *             parameter half of the adjoint (accumulates grad_lambda), from the window sums it
+ *             holds for out; filter_backward then forms grad_radiance only, from grad_out
+ *             (reference, loss and grad_lambda are left alone). Over the pair the results are
+ *             those of filter_forward followed by filter_backward with the seed fused, up to
+ *             fp32 rounding order; the per-pixel planes are read and written fewer times.
+ * Other bits must be 0. */
 enum ramlt_tile { RAMLT_TILE_DEFAULT = 0, RAMLT_TILE_32X8 = 1, RAMLT_TILE_32X16 = 2, RAMLT_TILE_64X8 = 3 };
 #define RAMLT_TILE_MASK 3
 #define RAMLT_SCHED_DIRECT 4
-#define RAMLT_FLAGS_KNOWN (RAMLT_TILE_MASK | RAMLT_SCHED_DIRECT)
+#define RAMLT_LOSS_IN_FORWARD 8
+#define RAMLT_FLAGS_KNOWN (RAMLT_TILE_MASK | RAMLT_SCHED_DIRECT | RAMLT_LOSS_IN_FORWARD)
 
 #define RAMLT_N_RADIANCE 3
 #define RAMLT_N_FEATURES 7
@@ -149,7 +160,12 @@ int stats_accumulate(const ramlt_frame *frames_host, const ramlt_frame *frames_d
  *   k(x,y) = floor((2y+1)N/(2H)) * N + floor((2x+1)N/(2W)),
  *   h_jp = exp(-(dx^2+dy^2) / (2 exp(max(lambda_k(j), lambda_min)))),
  *   out_j = sum_{p in window(j), inside} h_jp mean_p / sum h_jp   (fp32).
- * Requires per frame: mean, lambda, out, n_regions >= 1, 0 <= radius <= 15. */
+ * (A NaN lambda_k gives NaN outputs for its region.)
+ * Requires per frame: mean, lambda, out, n_regions >= 1, 0 <= radius <= 15.
+ * With RAMLT_LOSS_IN_FORWARD in flags also: reference and grad_out (loss and grad_lambda
+ * optional), and a workspace of ramlt_workspace_size(..., RAMLT_OP_FILTER_FORWARD) bytes for
+ * the per-tile partial sums of the loss and dL/dlambda, added in a fixed order as
+ * filter_backward adds its own (see there). */
 int filter_forward(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
                    int32_t n_frames, void *workspace, size_t ws_bytes, void *stream);
 
@@ -161,8 +177,11 @@ int loss_seed(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
 /* Adjoint of filter_forward o per-pixel mean, for U = grad_out:
  *   grad_radiance_p = (1/S) sum_{j : p in window(j)} U_j h_jp / D_j,
  *   grad_lambda_k  += sum_{k(j)=k} sum_c U_jc sum_p h'_jp (mean_pc - out_jc) / D_j,
- *   h'_jp = h_jp (dx^2+dy^2) / (2 sigma^2) if lambda_k >= lambda_min else 0.
- * Requires: mean, out, lambda, grad_radiance, and either grad_out, or (grad_out NULL)
+ *   h'_jp = h_jp (dx^2+dy^2) / (2 sigma^2) if lambda_k >= lambda_min else 0
+ *   (and NaN for a NaN lambda_k, which propagates as in filter_forward).
+ * With RAMLT_LOSS_IN_FORWARD in flags: grad_radiance only (filter_forward has formed the
+ * rest); requires lambda, grad_out, grad_radiance.
+ * Otherwise requires: mean, out, lambda, grad_radiance, and either grad_out, or (grad_out NULL)
  * reference: then U = 2 (out - reference) / (3 W H) is formed inside the kernel (the
  * loss seed fused into the adjoint, nothing written to grad_out) and *loss, if not
  * NULL, accumulates the MSE as loss_seed would. grad_lambda may be NULL.

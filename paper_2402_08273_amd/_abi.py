@@ -11,7 +11,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libramlt.so")
+# RAMLT_LIBRARY names another build of the same library (the host tests load the
+# AddressSanitizer build this way); the default is the in-tree libramlt.so
+LIB_PATH = os.environ.get("RAMLT_LIBRARY") or os.path.join(_HERE, "libramlt.so")
 
 RAMLT_OK = 0
 RAMLT_EINVAL = 1
@@ -29,6 +31,7 @@ RAMLT_TILE_32X16 = 2
 RAMLT_TILE_64X8 = 3
 RAMLT_TILE_MASK = 3
 RAMLT_SCHED_DIRECT = 4
+RAMLT_LOSS_IN_FORWARD = 8  # the MSE seed and dL/dlambda in filter_forward; filter_backward: G only
 TILE_SHAPES = {RAMLT_TILE_32X8: (32, 8), RAMLT_TILE_32X16: (32, 16), RAMLT_TILE_64X8: (64, 8)}
 
 OP_STATS = 0

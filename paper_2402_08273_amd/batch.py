@@ -43,11 +43,18 @@ class FrameBatch:
     when the frames share one tensor), and one fp64 loss = sum over frames of each
     frame's MSE."""
 
-    def __init__(self, frames: Sequence[FrameInput], device="cuda"):
+    def __init__(self, frames: Sequence[FrameInput], device="cuda", loss_in_forward=False):
+        """``loss_in_forward``: the forward launch also forms the MSE seed (U, kept per
+        frame as ``grad_out``), the loss and dL/dlambda (RAMLT_LOSS_IN_FORWARD); the
+        backward launch then forms the radiance gradient only. Every frame needs a
+        reference."""
         if not frames:
             raise ValueError("empty batch")
         self.device = torch.device(device)
         self.inputs = list(frames)
+        self.loss_in_forward = bool(loss_in_forward)
+        if self.loss_in_forward and any(fi.reference is None for fi in self.inputs):
+            raise ValueError("loss_in_forward needs a reference for every frame")
         f32 = dict(device=self.device, dtype=torch.float32)
         self.loss = torch.zeros(1, device=self.device, dtype=torch.float64)
         self.outputs = []
@@ -92,8 +99,11 @@ class FrameBatch:
             d.mean, d.var, d.tau = o["mean"].data_ptr(), o["var"].data_ptr(), o["tau"].data_ptr()
             d.lambda_ = fi.lam.data_ptr()
             d.n_regions, d.radius, d.lambda_min = fi.n_regions, fi.radius, fi.lambda_min
-            d.flags = fi.schedule
+            d.flags = fi.schedule | (_abi.RAMLT_LOSS_IN_FORWARD if self.loss_in_forward else 0)
             d.out = o["out"].data_ptr()
+            if self.loss_in_forward:
+                o["grad_out"] = torch.empty((3, H, W), **f32)
+                d.grad_out = o["grad_out"].data_ptr()
             if fi.reference is not None:
                 d.reference = fi.reference.data_ptr()
                 d.loss = self.loss.data_ptr()
@@ -152,14 +162,21 @@ class FrameBatch:
         self.loss.zero_()
 
     def backward(self):
-        """Fused MSE seed + adjoint (every frame needs a reference)."""
+        """Fused MSE seed + adjoint (every frame needs a reference); with loss_in_forward,
+        the radiance gradient from the seed the forward launch formed."""
         self._call("filter_backward")
 
     def step(self):
-        """stats -> filter -> (zero accumulators) -> fused loss seed + adjoint."""
+        """stats -> filter -> (zero accumulators) -> fused loss seed + adjoint; with
+        loss_in_forward: stats -> (zero accumulators) -> filter with the seed, the loss and
+        dL/dlambda -> radiance gradient."""
         self.stats()
-        self.forward()
-        self.zero_grads()
+        if self.loss_in_forward:
+            self.zero_grads()
+            self.forward()
+        else:
+            self.forward()
+            self.zero_grads()
         self.backward()
 
     # ------------------------------------------------------------------ graphs

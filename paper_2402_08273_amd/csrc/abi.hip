@@ -109,6 +109,12 @@ int validate_forward(const ramlt_frame &f, int i) {
   if (r) return r;
   REQUIRE_PTR(i, f, mean, 4);
   REQUIRE_PTR(i, f, out, 4);
+  if (f.flags & RAMLT_LOSS_IN_FORWARD) {  // the MSE seed and dL/dlambda in the same pass
+    REQUIRE_PTR(i, f, reference, 4);
+    REQUIRE_PTR(i, f, grad_out, 4);
+    OPTIONAL_PTR(i, f, loss, 8);
+    OPTIONAL_PTR(i, f, grad_lambda, 4);
+  }
   return RAMLT_OK;
 }
 
@@ -124,6 +130,11 @@ int validate_backward(const ramlt_frame &f, int i) {
   if (f.S < 1) return fail(RAMLT_EINVAL, "frame %d: S must be >= 1 (got %d)", i, f.S);
   int r = check_filter_params(i, f);
   if (r) return r;
+  if (f.flags & RAMLT_LOSS_IN_FORWARD) {  // grad_radiance only, from grad_out
+    REQUIRE_PTR(i, f, grad_out, 4);
+    REQUIRE_PTR(i, f, grad_radiance, 4);
+    return RAMLT_OK;
+  }
   if (f.grad_out == nullptr && f.reference == nullptr)
     return fail(RAMLT_EINVAL, "frame %d: filter_backward needs grad_out, or reference for the fused MSE seed", i);
   OPTIONAL_PTR(i, f, grad_out, 4);

@@ -31,8 +31,13 @@ static_assert(tile_w(RAMLT_TILE_64X8) == kTileShapes[RAMLT_TILE_64X8].w &&
                   tile_h(RAMLT_TILE_32X8) == kTileShapes[RAMLT_TILE_32X8].h,
               "tile table and accessors agree");
 
-// Batched filter launches group frames by (radius, tile kind).
-__host__ __device__ constexpr int filter_group(const ramlt_frame &f) { return f.radius + 16 * tile_kind(f.flags); }
+// Batched filter launches group frames by (radius, tile kind, loss in the forward pass).
+__host__ __device__ constexpr int filter_group(const ramlt_frame &f) {
+  return f.radius + 16 * tile_kind(f.flags) + ((f.flags & RAMLT_LOSS_IN_FORWARD) ? 64 : 0);
+}
+__host__ __device__ constexpr int group_radius(int group) { return group % 16; }
+__host__ __device__ constexpr int group_kind(int group) { return (group / 16) % 4; }
+__host__ __device__ constexpr bool group_loss_in_forward(int group) { return group >= 64; }
 constexpr int kLossTilePixels = 1024;
 
 // 256-pixel statistics tiles per batched work unit: enough that a unit reads >= 64
@@ -165,7 +170,7 @@ hipError_t launch_plan(const ramlt_frame *frames_dev, int n, int op, int group_s
 
 // Distinct filter_group values of a batch, ascending; returns their count (at most
 // kMaxFilterGroups).
-constexpr int kMaxFilterGroups = 16 * 4;
+constexpr int kMaxFilterGroups = 16 * 4 * 2;
 int distinct_groups(const ramlt_frame *fh, int n, int *groups);
 
 }  // namespace ramlt

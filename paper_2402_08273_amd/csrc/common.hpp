@@ -20,10 +20,15 @@ __device__ __forceinline__ int region_of(int x, int y, int W, int H, int N) {
   return cell_of(y, H, N) * N + cell_of(x, W, N);
 }
 
+// lambda clamped below at lambda_min; a NaN lambda stays NaN (fmaxf would return the bound).
+__device__ __forceinline__ float clamp_lambda(float lam, float lambda_min) {
+  return lam < lambda_min ? lambda_min : lam;
+}
+
 // 1/(2 sigma^2) for the region parameter lambda = log sigma^2 (Sec. 5.3), with lambda
-// clamped below at lambda_min.
+// clamped below at lambda_min (NaN propagates).
 __device__ __forceinline__ float half_inv_var(float lam, float lambda_min) {
-  return 0.5f * expf(-fmaxf(lam, lambda_min));
+  return 0.5f * expf(-clamp_lambda(lam, lambda_min));
 }
 
 __device__ __forceinline__ float wave_sum(float v) {

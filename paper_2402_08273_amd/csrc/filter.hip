@@ -19,10 +19,12 @@ constexpr int kFinalizeWaves = kFinalizeBlock / kWave;
 
 __host__ __device__ inline int finalize_lam_blocks(int N) { return (N * N + kFinalizeWaves - 1) / kFinalizeWaves; }
 
+// after_forward: the partials of the forward pass with the loss (RAMLT_LOSS_IN_FORWARD
+// frames only), else those of the adjoint (the other frames).
 __global__ __launch_bounds__(kFinalizeBlock) void backward_finalize_kernel(const ramlt_frame single,
                                                                         const ramlt_frame *__restrict__ frames,
                                                                         BatchPlan *plan, const float *lam_part,
-                                                                        const double *loss_part) {
+                                                                        const double *loss_part, int after_forward) {
   __shared__ double red[kFinalizeWaves];
   ramlt_frame f;
   long long base = 0;
@@ -35,6 +37,8 @@ __global__ __launch_bounds__(kFinalizeBlock) void backward_finalize_kernel(const
   } else {
     f = single;
   }
+  const bool lif = (f.flags & RAMLT_LOSS_IN_FORWARD) != 0;
+  if (lif != (after_forward != 0)) return;
   const int N = f.n_regions;
   const bool al = aligned_tiling(f);
   const int tw = tile_w(tile_kind(f.flags)), th = tile_h(tile_kind(f.flags));
@@ -56,7 +60,7 @@ __global__ __launch_bounds__(kFinalizeBlock) void backward_finalize_kernel(const
     if (lane == 0 && v != 0.f) unsafeAtomicAdd(f.grad_lambda + k, v);
     return;
   }
-  if ((int)blockIdx.x != nlb || f.grad_out != nullptr || !f.loss) return;
+  if ((int)blockIdx.x != nlb || !f.loss || (!lif && f.grad_out != nullptr)) return;
   const long long nt = (long long)ntx * nty;
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   long long t = threadIdx.x;
@@ -131,6 +135,19 @@ hipError_t launch_tiles(K kernel, int block, long long tiles, hipStream_t st, co
   return hipSuccess;
 }
 
+// Partial-sum slots (dL/dlambda float[nt], loss double[nt]) at the start of ws.
+void partial_slots(void *ws, long long nt, float **lam_part, double **loss_part) {
+  *lam_part = (float *)ws;
+  *loss_part = (double *)((char *)ws + (((size_t)nt * sizeof(float) + 7) & ~(size_t)7));
+}
+
+hipError_t launch_finalize(const ramlt_frame &single, const ramlt_frame *fd, BatchPlan *plan, int n, int nmax,
+                           float *lam_part, double *loss_part, bool after_forward, hipStream_t st) {
+  hipLaunchKernelGGL(backward_finalize_kernel, dim3(finalize_lam_blocks(nmax) + 1, n), dim3(kFinalizeBlock), 0, st,
+                     single, fd, plan, lam_part, loss_part, after_forward ? 1 : 0);
+  return hipGetLastError();
+}
+
 hipError_t launch_filter(bool bwd, const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws,
                          hipStream_t st) {
   if (n == 1) {
@@ -138,52 +155,56 @@ hipError_t launch_filter(bool bwd, const ramlt_frame *fh, const ramlt_frame *fd,
     const KindKernels K = kernels_of(tile_kind(f.flags));
     const TileGeom g = make_geom(f);
     const long long nt = filter_tiles(f);
-    if (!bwd)
+    const bool lif = (f.flags & RAMLT_LOSS_IN_FORWARD) != 0;
+    if (!bwd && !lif)
       return launch_tiles(K.forward[f.radius], K.block, nt, st, f, g, (const ramlt_frame *)nullptr,
                           (BatchPlan *)nullptr, nt);
-    float *lam_part = (float *)ws;
-    double *loss_part = (double *)((char *)ws + (((size_t)nt * sizeof(float) + 7) & ~(size_t)7));
-    hipError_t e = launch_tiles(K.backward[f.radius], K.block, nt, st, f, g, (const ramlt_frame *)nullptr,
-                                (BatchPlan *)nullptr, nt, lam_part, loss_part);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(backward_finalize_kernel, dim3(finalize_lam_blocks(f.n_regions) + 1), dim3(kFinalizeBlock),
-                       0, st, f, (const ramlt_frame *)nullptr, (BatchPlan *)nullptr, lam_part, loss_part);
-    return hipGetLastError();
+    float *lam_part;
+    double *loss_part;
+    partial_slots(ws, nt, &lam_part, &loss_part);
+    hipError_t e = launch_tiles(bwd ? K.backward[f.radius] : K.forward_loss[f.radius], K.block, nt, st, f, g,
+                                (const ramlt_frame *)nullptr, (BatchPlan *)nullptr, nt, lam_part, loss_part);
+    if (e != hipSuccess || (bwd && lif)) return e;  // the adjoint of such a frame leaves no partials
+    return launch_finalize(f, nullptr, nullptr, 1, f.n_regions, lam_part, loss_part, !bwd, st);
   }
   int groups[kMaxFilterGroups];
   const int ng = distinct_groups(fh, n, groups);
   const size_t pb = plan_bytes(n);
-  const size_t part = bwd ? partials_bytes(fh, n) : 0;
+  bool any_lif = false;
+  for (int i = 0; i < n; ++i) any_lif |= (fh[i].flags & RAMLT_LOSS_IN_FORWARD) != 0;
+  const bool parts = bwd || any_lif;
+  const size_t part = parts ? partials_bytes(fh, n) : 0;
   long long T = 0;
   for (int i = 0; i < n; ++i) T += filter_tiles(fh[i]);
+  int nmax = 1;
+  for (int i = 0; i < n; ++i) nmax = max(nmax, fh[i].n_regions);
   const ramlt_frame none{};
   const TileGeom none_g{};
   for (int q = 0; q < ng; ++q) {
-    const int radius = groups[q] % 16;
-    const KindKernels K = kernels_of(groups[q] / 16);
+    const int radius = group_radius(groups[q]);
+    const bool lif = group_loss_in_forward(groups[q]);
+    const KindKernels K = kernels_of(group_kind(groups[q]));
     char *base = (char *)ws + (size_t)q * (pb + part);
     BatchPlan *plan = (BatchPlan *)base;
-    float *lam_part = bwd ? (float *)(base + pb) : nullptr;
-    double *loss_part = bwd ? (double *)(base + pb + (((size_t)T * sizeof(float) + 7) & ~(size_t)7)) : nullptr;
+    float *lam_part = nullptr;
+    double *loss_part = nullptr;
+    if (parts) partial_slots(base + pb, T, &lam_part, &loss_part);
     hipError_t e = launch_plan(fd, n, bwd ? RAMLT_OP_FILTER_BACKWARD : RAMLT_OP_FILTER_FORWARD, groups[q], plan, st);
     if (e != hipSuccess) return e;
     long long tiles = 0;  // the planner counts the same tiles on the device
     for (int i = 0; i < n; ++i)
       if (filter_group(fh[i]) == groups[q]) tiles += filter_tiles(fh[i]);
     if (tiles == 0) continue;
-    if (!bwd) {
+    if (!bwd && !lif) {
       e = launch_tiles(K.forward_batched[radius], K.block, tiles, st, none, none_g, fd, plan, 0LL);
       if (e != hipSuccess) return e;
       continue;
     }
-    e = launch_tiles(K.backward_batched[radius], K.block, tiles, st, none, none_g, fd, plan, 0LL, lam_part,
-                     loss_part);
+    e = launch_tiles(bwd ? K.backward_batched[radius] : K.forward_loss_batched[radius], K.block, tiles, st, none,
+                     none_g, fd, plan, 0LL, lam_part, loss_part);
     if (e != hipSuccess) return e;
-    int nmax = 1;
-    for (int i = 0; i < n; ++i) nmax = max(nmax, fh[i].n_regions);
-    hipLaunchKernelGGL(backward_finalize_kernel, dim3(finalize_lam_blocks(nmax) + 1, n), dim3(kFinalizeBlock), 0, st,
-                       none, fd, plan, lam_part, loss_part);
-    e = hipGetLastError();
+    if (bwd && lif) continue;
+    e = launch_finalize(none, fd, plan, n, nmax, lam_part, loss_part, !bwd, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -220,7 +241,9 @@ hipError_t launch_loss_seed(const ramlt_frame *fh, const ramlt_frame *fd, int n,
 }
 
 size_t workspace_bytes(const ramlt_frame *fh, int n, int op) {
-  if (op == RAMLT_OP_FILTER_BACKWARD) {
+  bool any_lif = false;
+  for (int i = 0; i < n; ++i) any_lif |= (fh[i].flags & RAMLT_LOSS_IN_FORWARD) != 0;
+  if (op == RAMLT_OP_FILTER_BACKWARD || (op == RAMLT_OP_FILTER_FORWARD && any_lif)) {
     if (n == 1) {
       const long long nt = filter_tiles(fh[0]);
       const size_t b = (((size_t)nt * sizeof(float) + 7) & ~(size_t)7) + (size_t)nt * sizeof(double);

@@ -393,6 +393,175 @@ __device__ __forceinline__ void reduce_lambda(float *grad_lambda, int key, float
   }
 }
 
+// ------------------------------------------------------------------------ forward + loss
+// With RAMLT_LOSS_IN_FORWARD the forward tile also forms the MSE seed U_j = 2 (out_j - R_j)
+// / (3P) and the parameter adjoint
+//   dL/dlambda_k(j) += beta_j sum_c U_jc (N2_jc - out_jc H2_j) / D_j,
+//   N2_jc = sum_p h_jp d^2 mean_pc, H2_j = sum_p h_jp d^2, beta = 1 / (2 sigma^2),
+// from the mean halo it holds for out: the separable passes carry the d^2-weighted sums
+// beside the plain ones (a tile in one region), or the direct gather does (a tile that
+// spans regions). Per-tile partials of the loss and of dL/dlambda go to the same slots as
+// the adjoint's.
+template <int R, class SH>
+struct FwdLossLds {
+  float4 stage[(SH::TX + 2 * R) * (SH::TY + 2 * R)];
+  float4 hb1[(SH::TY + 2 * R) * SH::TX];
+  float4 hb2[(SH::TY + 2 * R) * SH::TX];
+  float wtab[R + 1];
+  double red[SH::BLOCK / kWave];
+};
+
+// uniform: the separable passes (one sigma for the tile, and the schedule allows them);
+// one_region: every pixel of the tile is in one region (one partial sum of dL/dlambda).
+template <int R, class SH>
+__device__ __forceinline__ void forward_loss_compute(const ramlt_frame &f, const TileGeom &g, const Rect &r,
+                                                     bool uniform, bool one_region, long long slot,
+                                                     float *lam_part, double *loss_part, FwdLossLds<R, SH> &L) {
+  constexpr int kTX = SH::TX, kTY = SH::TY, kFilterBlock = SH::BLOCK;
+  constexpr int HX = kTX + 2 * R;
+  constexpr int HY = kTY + 2 * R;
+  const float4 *stage = L.stage;
+  const long long P = (long long)f.W * f.H;
+  const float useed = (float)(2.0 / (3.0 * (double)P));
+  const int tx = threadIdx.x % kTX;
+  const int ty = threadIdx.x / kTX;
+  const int x = r.x0 + tx;
+  const int y = r.y0 + ty;
+  const bool inside = x < r.x1 && y < r.y1;
+  const long long o = (long long)y * f.W + x;
+  // the own pixel's reference, in flight during the passes
+  float4 ref = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (inside) ref = load3(f.reference, P, o);
+  const int k_own = inside ? region_at(g, x, y) : tile_region(g, r);
+  const float lam = f.lambda[k_own];
+  // the gradient passes the clamp for lambda >= lambda_min; NaN counts as live
+  const bool live = !(lam < f.lambda_min);
+  float w[R + 1], wd2[R + 1];
+  float beta;
+  float ax = 0.f, ay = 0.f, az = 0.f;  // sum h mean
+  float nx = 0.f, ny = 0.f, nz = 0.f;  // sum h d^2 mean
+  if (uniform) {
+    // one sigma for the whole tile: rows, then columns, plain and d^2-weighted
+#pragma unroll
+    for (int d = 0; d <= R; ++d) w[d] = L.wtab[d];
+#pragma unroll
+    for (int d = 0; d <= R; ++d) wd2[d] = w[d] * (float)(d * d);
+    beta = half_inv_var(lam, f.lambda_min);
+    for (int i = threadIdx.x; i < HY * kTX; i += kFilterBlock) {
+      const int hy = i / kTX;
+      const int hx = i - hy * kTX;
+      const float4 *row = stage + hy * HX + hx + R;
+      float4 a1 = make_float4(0.f, 0.f, 0.f, 0.f), a2 = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int dx = -R; dx <= R; ++dx) {
+        const float4 m = row[dx];
+        const int ad = dx < 0 ? -dx : dx;
+        a1.x = fmaf(w[ad], m.x, a1.x);
+        a1.y = fmaf(w[ad], m.y, a1.y);
+        a1.z = fmaf(w[ad], m.z, a1.z);
+        a2.x = fmaf(wd2[ad], m.x, a2.x);
+        a2.y = fmaf(wd2[ad], m.y, a2.y);
+        a2.z = fmaf(wd2[ad], m.z, a2.z);
+      }
+      L.hb1[i] = a1;
+      L.hb2[i] = a2;
+    }
+    __syncthreads();
+    if (inside) {
+#pragma unroll
+      for (int dy = -R; dy <= R; ++dy) {
+        const int ad = dy < 0 ? -dy : dy;
+        const float4 h1 = L.hb1[(ty + R + dy) * kTX + tx];
+        const float4 h2 = L.hb2[(ty + R + dy) * kTX + tx];
+        ax = fmaf(w[ad], h1.x, ax);
+        ay = fmaf(w[ad], h1.y, ay);
+        az = fmaf(w[ad], h1.z, az);
+        nx = fmaf(w[ad], h2.x, fmaf(wd2[ad], h1.x, nx));
+        ny = fmaf(w[ad], h2.y, fmaf(wd2[ad], h1.y, ny));
+        nz = fmaf(w[ad], h2.z, fmaf(wd2[ad], h1.z, nz));
+      }
+    }
+  } else {
+    // per-pixel sigma: direct (2R+1)^2 gather
+    beta = half_inv_var(lam, f.lambda_min);
+    gauss_weights<R>(beta, w);
+#pragma unroll
+    for (int d = 0; d <= R; ++d) wd2[d] = w[d] * (float)(d * d);
+    if (inside) {
+#pragma unroll
+      for (int dy = -R; dy <= R; ++dy) {
+        const float4 *row = stage + (ty + R + dy) * HX + tx + R;
+        float r1x = 0.f, r1y = 0.f, r1z = 0.f, r2x = 0.f, r2y = 0.f, r2z = 0.f;
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx) {
+          const float4 m = row[dx];
+          const int ad = dx < 0 ? -dx : dx;
+          r1x = fmaf(w[ad], m.x, r1x);
+          r1y = fmaf(w[ad], m.y, r1y);
+          r1z = fmaf(w[ad], m.z, r1z);
+          r2x = fmaf(wd2[ad], m.x, r2x);
+          r2y = fmaf(wd2[ad], m.y, r2y);
+          r2z = fmaf(wd2[ad], m.z, r2z);
+        }
+        const int ad = dy < 0 ? -dy : dy;
+        ax = fmaf(w[ad], r1x, ax);
+        ay = fmaf(w[ad], r1y, ay);
+        az = fmaf(w[ad], r1z, az);
+        nx = fmaf(w[ad], r2x, fmaf(wd2[ad], r1x, nx));
+        ny = fmaf(w[ad], r2y, fmaf(wd2[ad], r1y, ny));
+        nz = fmaf(w[ad], r2z, fmaf(wd2[ad], r1z, nz));
+      }
+    }
+  }
+  double lacc = 0.0;
+  float contrib = 0.f;
+  if (inside) {
+    const float Z0 = window_sum<R>(w), Z2 = window_moment2<R>(w);
+    const float sx0 = axis_sum<R, 0>(w, Z0, x, f.W), sy0 = axis_sum<R, 0>(w, Z0, y, f.H);
+    const float D = sx0 * sy0;
+    const float4 out = make_float4(ax / D, ay / D, az / D, 0.f);
+    f.out[o] = out.x;
+    f.out[P + o] = out.y;
+    f.out[2 * P + o] = out.z;
+    const float dx_ = out.x - ref.x, dy_ = out.y - ref.y, dz_ = out.z - ref.z;
+    const float4 u = make_float4(useed * dx_, useed * dy_, useed * dz_, 0.f);
+    f.grad_out[o] = u.x;
+    f.grad_out[P + o] = u.y;
+    f.grad_out[2 * P + o] = u.z;
+    lacc = fma((double)dx_, (double)dx_, lacc);
+    lacc = fma((double)dy_, (double)dy_, lacc);
+    lacc = fma((double)dz_, (double)dz_, lacc);
+    if (live) {
+      const float sx2 = axis_sum<R, 2>(w, Z2, x, f.W), sy2 = axis_sum<R, 2>(w, Z2, y, f.H);
+      const float H2 = sx2 * sy0 + sx0 * sy2;
+      const float t = u.x * (nx - out.x * H2) + u.y * (ny - out.y * H2) + u.z * (nz - out.z * H2);
+      contrib = beta * t / D;
+    }
+  }
+  if (f.loss) {
+    const double s = block_sum(lacc, L.red);
+    if (threadIdx.x == 0) {
+      if (loss_part)
+        loss_part[slot] = s;
+      else
+        unsafeAtomicAdd(f.loss, s / (3.0 * (double)P));
+    }
+  }
+  if (!f.grad_lambda) return;
+  if (one_region) {
+    // one region for the whole tile: block reduction, one partial (or atomic)
+    const double s = block_sum((double)contrib, L.red);
+    if (threadIdx.x == 0) {
+      if (lam_part && g.aligned)  // the finalize kernel reads region-aligned partials
+        lam_part[slot] = live ? (float)s : 0.f;
+      else if (live)
+        unsafeAtomicAdd(f.grad_lambda + k_own, (float)s);
+    }
+  } else {
+    reduce_lambda(f.grad_lambda, inside && live ? k_own : -1, contrib);
+  }
+}
+
 template <int R, class SH>
 struct BwdLds {
   static constexpr int HX = SH::TX + 2 * R;
@@ -677,15 +846,18 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const TileGe
     }
   }
 
-  // ---- dL/dlambda_k(j) += beta_j sum_c U_jc (N2_jc - out_jc H2_j) / D_j
-  if (!f.grad_lambda) return;
+  // ---- dL/dlambda_k(j) += beta_j sum_c U_jc (N2_jc - out_jc H2_j) / D_j (formed by the
+  // forward pass instead under RAMLT_LOSS_IN_FORWARD)
+  if (!f.grad_lambda || (f.flags & RAMLT_LOSS_IN_FORWARD)) return;
   __syncthreads();  // stage and hb2 are reused below
   float4 *smu = stage;
   stage_halo<R, SH>(f, r.x0, r.y0, smu, [&](long long q) { return load3(f.mean, P, q); });
   __syncthreads();
   const int k_own = inside ? region_at(g, x, y) : k0;
   const float lam = f.lambda[k_own];
-  const bool live = lam >= f.lambda_min;
+  // the gradient passes the clamp for lambda >= lambda_min; a NaN lambda counts as live, so
+  // its NaN reaches dL/dlambda as it reaches out and G
+  const bool live = !(lam < f.lambda_min);
   const float beta = half_inv_var(lam, f.lambda_min);
   float w[R + 1], wd2[R + 1];
   if (sep) {
@@ -843,6 +1015,38 @@ __device__ __forceinline__ void empty_tile_partials(long long slot, float *lam_p
   }
 }
 
+// Forward filter with the MSE seed and dL/dlambda (RAMLT_LOSS_IN_FORWARD), one tile per
+// workgroup; per-tile partials go to slot t.
+template <int R, class SH, bool BATCH>
+__global__ __launch_bounds__(SH::BLOCK) void forward_loss_kernel(const ramlt_frame single, const TileGeom single_g,
+                                                                    const ramlt_frame *__restrict__ frames,
+                                                                    BatchPlan *plan, long long ntiles, long long t0,
+                                                                    float *lam_part, double *loss_part) {
+  __shared__ FwdLossLds<R, SH> s;
+  const long long total = BATCH ? (long long)plan->total_tiles : ntiles;
+  const long long t = t0 + xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= total) return;
+  ramlt_frame f;
+  TileGeom g;
+  Rect r;
+  fetch_tile<SH, BATCH>(single, single_g, frames, plan, t, f, g, r);
+  if (r.x0 >= r.x1 || r.y0 >= r.y1) {  // block-uniform
+    empty_tile_partials(t, lam_part, loss_part);
+    return;
+  }
+  const bool one_region = tile_uniform(g, r);
+  const bool uniform = one_region && !(f.flags & RAMLT_SCHED_DIRECT);
+  Halo<R, SH> h;
+  halo_load<R, SH>(f, r.x0, r.y0, h, [&](long long q) { return load3(f.mean, (long long)f.W * f.H, q); });
+  if (uniform && threadIdx.x <= R) {
+    const float beta = half_inv_var(f.lambda[tile_region(g, r)], f.lambda_min);
+    s.wtab[threadIdx.x] = threadIdx.x == 0 ? 1.0f : expf(-(float)(threadIdx.x * threadIdx.x) * beta);
+  }
+  halo_store<R, SH>(f, r.x0, r.y0, h, s.stage);
+  __syncthreads();
+  forward_loss_compute<R, SH>(f, g, r, uniform, one_region, t, lam_part, loss_part, s);
+}
+
 // Adjoint, one tile per workgroup; per-tile partials go to slot t.
 template <int R, class SH, bool BATCH>
 __global__ __launch_bounds__(SH::BLOCK) void backward_kernel(const ramlt_frame single, const TileGeom single_g,
@@ -867,12 +1071,15 @@ using FwdKernel = void (*)(const ramlt_frame, const TileGeom, const ramlt_frame 
                            long long);
 using BwdKernel = void (*)(const ramlt_frame, const TileGeom, const ramlt_frame *, BatchPlan *, long long, long long,
                            float *, double *);
+using FwdLossKernel = BwdKernel;
 
 template <class SH, int... Rs>
 struct KernelTables {
   static constexpr int kCount = sizeof...(Rs);
   static constexpr FwdKernel forward[kCount] = {forward_kernel<Rs, SH, false>...};
   static constexpr FwdKernel forward_batched[kCount] = {forward_kernel<Rs, SH, true>...};
+  static constexpr FwdLossKernel forward_loss[kCount] = {forward_loss_kernel<Rs, SH, false>...};
+  static constexpr FwdLossKernel forward_loss_batched[kCount] = {forward_loss_kernel<Rs, SH, true>...};
   static constexpr BwdKernel backward[kCount] = {backward_kernel<Rs, SH, false>...};
   static constexpr BwdKernel backward_batched[kCount] = {backward_kernel<Rs, SH, true>...};
 };
@@ -883,6 +1090,7 @@ using TablesFor = KernelTables<SH, 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13,
 // Kernels of one tile kind: forward/backward, single frame/batch, by radius.
 struct KindKernels {
   const FwdKernel *forward, *forward_batched;
+  const FwdLossKernel *forward_loss, *forward_loss_batched;
   const BwdKernel *backward, *backward_batched;
   int block;
 };
@@ -890,7 +1098,8 @@ struct KindKernels {
 template <class SH>
 KindKernels kind_kernels() {
   using T = TablesFor<SH>;
-  return KindKernels{T::forward, T::forward_batched, T::backward, T::backward_batched, SH::BLOCK};
+  return KindKernels{T::forward,  T::forward_batched,  T::forward_loss, T::forward_loss_batched,
+                     T::backward, T::backward_batched, SH::BLOCK};
 }
 
 // The kernel tables of each tile kind, one per translation unit.

@@ -36,9 +36,36 @@ def _check_samples(t, name, channels, dtypes):
         raise ValueError(f"{name} must have unit x stride")
 
 
-def _check_plane(t, name, channels=3):
-    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous() or t.dim() != 3 or t.shape[0] != channels:
+def _check_plane(t, name, channels=3, hw=None):
+    """A dense float32 device plane [channels, H, W] (and [.., H, W] == hw when given)."""
+    if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous()
+            or t.dim() != 3 or t.shape[0] != channels):
         raise ValueError(f"{name} must be a contiguous float32 device tensor [{channels}, H, W]")
+    if hw is not None and tuple(t.shape[1:]) != tuple(hw):
+        raise ValueError(f"{name} must be [{channels}, {hw[0]}, {hw[1]}], got {tuple(t.shape)}")
+
+
+def _check_vector(t, name, n, dtype):
+    if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous()
+            or t.numel() != n):
+        raise ValueError(f"{name} must be a contiguous {dtype} device tensor with {n} entries")
+
+
+def _check_stats_out(out, K_L, H, W, features):
+    """Every output plane a caller passes in must hold what the kernel writes into it."""
+    for name in ("mean", "var", "tau"):
+        _check_plane(getattr(out, name), f"out.{name}", 3, (H, W))
+    if out.lag_corr is not None:
+        t = out.lag_corr
+        if (not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous()
+                or tuple(t.shape) != (3, K_L, H, W)):
+            raise ValueError(f"out.lag_corr must be a contiguous float32 device tensor [3, {K_L}, {H}, {W}]")
+    if features is not None:
+        for name in ("feat_mean", "feat_var"):
+            t = getattr(out, name)
+            if t is None:
+                raise ValueError(f"out.{name} is required with features")
+            _check_plane(t, f"out.{name}", 7, (H, W))
 
 
 def workspace_for(frames, op, device):
@@ -65,7 +92,9 @@ def stats_frame(radiance, features=None, max_lag=8, out: Optional[Stats] = None,
     _check_samples(radiance, "radiance", 3, (torch.float32,))
     _, S, H, W = radiance.shape
     dev = radiance.device
-    K_L = min(int(max_lag), S - 1)
+    K_L = max(0, min(int(max_lag), S - 1))
+    if out is not None:
+        _check_stats_out(out, K_L, H, W, features)
     if out is None:
         mk = lambda c: torch.empty((c, H, W), device=dev, dtype=torch.float32)  # noqa: E731
         out = Stats(
@@ -121,6 +150,7 @@ def filter_forward(mean, lam, radius, n_regions=None, lambda_min=LAMBDA_MIN_DEFA
     f = filter_frame(mean, lam, radius, n_regions, lambda_min, schedule)
     if out is None:
         out = torch.empty_like(mean)
+    _check_plane(out, "out", 3, mean.shape[1:])
     f.out = out.data_ptr()
     _abi.filter_forward([f], stream=_stream())
     return out
@@ -129,11 +159,13 @@ def filter_forward(mean, lam, radius, n_regions=None, lambda_min=LAMBDA_MIN_DEFA
 def loss_seed(out, reference, grad_out=None, loss=None):
     """MSE loss (accumulated into a float64 [1] tensor) and its gradient w.r.t. ``out``."""
     _check_plane(out, "out")
-    _check_plane(reference, "reference")
+    _check_plane(reference, "reference", 3, out.shape[1:])
     if grad_out is None:
         grad_out = torch.empty_like(out)
+    _check_plane(grad_out, "grad_out", 3, out.shape[1:])
     if loss is None:
         loss = torch.zeros(1, device=out.device, dtype=torch.float64)
+    _check_vector(loss, "loss", 1, torch.float64)
     f = RamltFrame()
     f.W, f.H = out.shape[2], out.shape[1]
     f.out, f.reference, f.grad_out, f.loss = out.data_ptr(), reference.data_ptr(), grad_out.data_ptr(), loss.data_ptr()
@@ -150,21 +182,27 @@ def filter_backward(grad_out, mean, out, lam, radius, S, n_regions=None, lambda_
     adjoint (U is never written); ``loss`` (fp64 [1]), if given, accumulates the MSE.
     ``schedule``: as for :func:`filter_forward`."""
     f = filter_frame(mean, lam, radius, n_regions, lambda_min, schedule)
-    _check_plane(out, "out")
+    hw = mean.shape[1:]
+    _check_plane(out, "out", 3, hw)
     if grad_out is None:
         if reference is None:
             raise ValueError("filter_backward needs grad_out or a reference image")
-        _check_plane(reference, "reference")
+        _check_plane(reference, "reference", 3, hw)
         f.reference = reference.data_ptr()
+        if loss is not None:
+            _check_vector(loss, "loss", 1, torch.float64)
         f.loss = _ptr(loss)
     else:
-        _check_plane(grad_out, "grad_out")
+        _check_plane(grad_out, "grad_out", 3, hw)
         f.grad_out = grad_out.data_ptr()
     f.S = int(S)
     if grad_radiance is None:
         grad_radiance = torch.empty_like(mean)
+    _check_plane(grad_radiance, "grad_radiance", 3, hw)
     if want_grad_lambda and grad_lambda is None:
         grad_lambda = torch.zeros_like(lam)
+    if want_grad_lambda:
+        _check_vector(grad_lambda, "grad_lambda", f.n_regions * f.n_regions, torch.float32)
     f.out = out.data_ptr()
     f.grad_radiance = grad_radiance.data_ptr()
     f.grad_lambda = _ptr(grad_lambda) if want_grad_lambda else None
@@ -172,6 +210,51 @@ def filter_backward(grad_out, mean, out, lam, radius, S, n_regions=None, lambda_
     _abi.filter_backward([f], workspace=ws_ptr, ws_bytes=ws_bytes, stream=_stream())
     del ws  # freed blocks are reused in stream order, after this launch
     return grad_radiance, grad_lambda
+
+
+def filter_forward_loss(mean, lam, radius, reference, n_regions=None, lambda_min=LAMBDA_MIN_DEFAULT, out=None,
+                        grad_out=None, loss=None, grad_lambda=None, want_grad_lambda=True, schedule=0):
+    """The filter with the MSE loss seed and dL/dlambda formed in the same pass
+    (RAMLT_LOSS_IN_FORWARD): returns (out, U = dL/dout, loss, grad_lambda); ``loss`` (fp64
+    [1]) and ``grad_lambda`` are accumulated into (zeros when not given). The radiance
+    gradient then comes from :func:`filter_backward_radiance` on U."""
+    f = filter_frame(mean, lam, radius, n_regions, lambda_min, schedule | _abi.RAMLT_LOSS_IN_FORWARD)
+    hw = mean.shape[1:]
+    _check_plane(reference, "reference", 3, hw)
+    out = torch.empty_like(mean) if out is None else out
+    grad_out = torch.empty_like(mean) if grad_out is None else grad_out
+    loss = torch.zeros(1, device=mean.device, dtype=torch.float64) if loss is None else loss
+    _check_plane(out, "out", 3, hw)
+    _check_plane(grad_out, "grad_out", 3, hw)
+    _check_vector(loss, "loss", 1, torch.float64)
+    if want_grad_lambda:
+        grad_lambda = torch.zeros_like(lam) if grad_lambda is None else grad_lambda
+        _check_vector(grad_lambda, "grad_lambda", f.n_regions * f.n_regions, torch.float32)
+    f.out, f.reference, f.grad_out, f.loss = out.data_ptr(), reference.data_ptr(), grad_out.data_ptr(), loss.data_ptr()
+    f.grad_lambda = _ptr(grad_lambda) if want_grad_lambda else None
+    ws, ws_ptr, ws_bytes = workspace_for([f], _abi.OP_FILTER_FORWARD, mean.device)
+    _abi.filter_forward([f], workspace=ws_ptr, ws_bytes=ws_bytes, stream=_stream())
+    del ws  # freed blocks are reused in stream order, after this launch
+    return out, grad_out, loss, (grad_lambda if want_grad_lambda else None)
+
+
+def filter_backward_radiance(grad_out, lam, radius, S, n_regions=None, lambda_min=LAMBDA_MIN_DEFAULT,
+                             grad_radiance=None, schedule=0):
+    """The radiance half of the adjoint: G [3, H, W] = dL/dg for every sample, from U
+    (RAMLT_LOSS_IN_FORWARD: dL/dlambda and the loss come from :func:`filter_forward_loss`)."""
+    _check_plane(grad_out, "grad_out")
+    f = filter_frame(grad_out, lam, radius, n_regions, lambda_min, schedule | _abi.RAMLT_LOSS_IN_FORWARD)
+    f.mean = 0
+    f.grad_out = grad_out.data_ptr()
+    f.S = int(S)
+    if grad_radiance is None:
+        grad_radiance = torch.empty_like(grad_out)
+    _check_plane(grad_radiance, "grad_radiance", 3, grad_out.shape[1:])
+    f.grad_radiance = grad_radiance.data_ptr()
+    ws, ws_ptr, ws_bytes = workspace_for([f], _abi.OP_FILTER_BACKWARD, grad_out.device)
+    _abi.filter_backward([f], workspace=ws_ptr, ws_bytes=ws_bytes, stream=_stream())
+    del ws
+    return grad_radiance
 
 
 class RegionalFilter(torch.autograd.Function):
@@ -183,11 +266,11 @@ class RegionalFilter(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, radiance, features, lam, radius, n_regions=None, lambda_min=LAMBDA_MIN_DEFAULT, max_lag=8):
-        st = stats(radiance, features, max_lag)
+        # the lag correlations are not needed by the filter or its adjoint: not written
+        st = stats(radiance, features, max_lag, with_lag_corr=False)
         out = filter_forward(st.mean, lam, radius, n_regions, lambda_min)
         ctx.save_for_backward(st.mean, out, lam)
         ctx.cfg = (int(radius), n_regions, float(lambda_min), radiance.shape)
-        ctx.mark_non_differentiable()
         return out
 
     @staticmethod

@@ -80,9 +80,10 @@ def device_arch(device=None) -> str:
 
 def workload_key(descs: Iterable, arch: str) -> str:
     """Key of a list of frame descriptors: architecture + each frame's (W, H, S, radius,
-    regions), in order (S matters to the adjoint only through its scale, but is kept so a
-    key names one workload)."""
-    parts = [f"{d.W}x{d.H}x{d.S}/r{d.radius}/N{d.n_regions}" for d in descs]
+    regions, whether the loss is formed in the forward pass), in order (S matters to the
+    adjoint only through its scale, but is kept so a key names one workload)."""
+    parts = [f"{d.W}x{d.H}x{d.S}/r{d.radius}/N{d.n_regions}"
+             + ("/loss-in-forward" if getattr(d, "flags", 0) & _abi.RAMLT_LOSS_IN_FORWARD else "") for d in descs]
     return arch + "|" + ";".join(parts)
 
 

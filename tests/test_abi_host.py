@@ -111,7 +111,7 @@ def test_valid_arguments_reach_the_device_check(lib):
         (lambda f: setattr(f, "lag_corr", 0x40003), _abi.RAMLT_EINVAL),
         (lambda f: setattr(f, "rad_stride_y", 7), _abi.RAMLT_EINVAL),
         (lambda f: setattr(f, "rad_stride_s", 0), _abi.RAMLT_EINVAL),
-        (lambda f: setattr(f, "flags", 8), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "flags", 16), _abi.RAMLT_EINVAL),
         (lambda f: setattr(f, "flags", -1), _abi.RAMLT_EINVAL),
         (lambda f: (setattr(f, "H", 1 << 16), setattr(f, "rad_stride_y", 1 << 15)), _abi.RAMLT_EUNSUPPORTED),
         (lambda f: (setattr(f, "features", 0x100000), setattr(f, "feat_dtype", 7),
@@ -419,3 +419,38 @@ def test_rrmse_validation(lib):
     assert st(workspace=None, ws_bytes=0) == _abi.RAMLT_EWORKSPACE
     assert st(ws_bytes=need - 1) == _abi.RAMLT_EWORKSPACE
     assert st(workspace=FAKE_WORKSPACE + 64) == _abi.RAMLT_EWORKSPACE
+
+
+def test_loss_in_forward_flag(lib):
+    # RAMLT_LOSS_IN_FORWARD: filter_forward needs the reference, grad_out and a workspace for
+    # its per-tile partial sums; filter_backward then needs only grad_out and grad_radiance
+    f = _valid_filter_frame()
+    f.W, f.H, f.n_regions = 1920, 1080, 20
+    f.flags = _abi.RAMLT_LOSS_IN_FORWARD | _abi.RAMLT_TILE_32X16
+    need = _abi.workspace_size([f], _abi.OP_FILTER_FORWARD)
+    assert need == _abi.workspace_size([f], _abi.OP_FILTER_BACKWARD) > 0
+    fwd = lambda g, **kw: _abi.status_of("filter_forward", [g], **kw)  # noqa: E731
+    assert fwd(f) == _abi.RAMLT_EWORKSPACE
+    assert fwd(f, workspace=FAKE_WORKSPACE, ws_bytes=need - 1) == _abi.RAMLT_EWORKSPACE
+    assert fwd(f, workspace=FAKE_WORKSPACE, ws_bytes=need) in (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
+    for field in ("reference", "grad_out", "mean", "out"):
+        g = _abi.RamltFrame.from_buffer_copy(f)
+        setattr(g, field, None)
+        assert fwd(g, workspace=FAKE_WORKSPACE, ws_bytes=need) == _abi.RAMLT_EINVAL, field
+    for field, value in (("loss", 0xB0004), ("grad_lambda", 0x90002)):
+        g = _abi.RamltFrame.from_buffer_copy(f)
+        setattr(g, field, value)
+        assert fwd(g, workspace=FAKE_WORKSPACE, ws_bytes=need) == _abi.RAMLT_EINVAL, field
+    # the radiance-only adjoint: mean, out and reference are not needed
+    b = _abi.RamltFrame.from_buffer_copy(f)
+    b.mean = b.out = b.reference = None
+    assert _status("filter_backward", [b]) in (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
+    for field in ("grad_out", "grad_radiance", "lambda_"):
+        g = _abi.RamltFrame.from_buffer_copy(b)
+        setattr(g, field, None)
+        assert _status("filter_backward", [g]) == _abi.RAMLT_EINVAL, field
+    # a batch groups frames by the flag as well (one plan and partials per group)
+    a, c = _valid_filter_frame(), _valid_filter_frame()
+    base = _abi.workspace_size([a, c], _abi.OP_FILTER_FORWARD)
+    c.flags = _abi.RAMLT_LOSS_IN_FORWARD
+    assert _abi.workspace_size([a, c], _abi.OP_FILTER_FORWARD) > 2 * base

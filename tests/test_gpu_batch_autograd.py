@@ -115,13 +115,40 @@ def test_batched_matches_single_frames_and_oracle():
     assert abs(_h(b.loss)[0] - loss_total) <= 1e-5 * loss_total
 
 
+def test_batched_loss_in_forward_matches_oracle():
+    # the six uneven frames (fp32 / fp16 / no features, S from 1 to 64, shared lambda and
+    # gradient) with the loss formed in the forward launch
+    lam = make_lambda(20, seed=99)
+    lam_d = _dev(lam)
+    frames, host = _batch_inputs(SPECS, lam_d)
+    b = FrameBatch(frames, loss_in_forward=True)
+    b.step()
+    torch.cuda.synchronize()
+    loss_total, gl_sum, gl_scale = 0.0, np.zeros(400), np.zeros(400)
+    for i, (rad, feats, ref, r) in enumerate(host):
+        o = b.outputs[i]
+        S = rad.shape[1]
+        gl_s = _check_chain(f"frame {i}", rad, feats, ref, lam, 20, r, S,
+                            {k: _h(o[k]) for k in ("mean", "var", "tau")}, _h(o["out"]), None,
+                            _h(o["grad_radiance"]), None)
+        ch = _oracle_chain(rad, feats, ref, lam, 20, r, S)
+        n = ch[1].size
+        check(f"frame {i} U", _h(o["grad_out"]), ch[3], 2.0 * (np.abs(ch[1]) + np.abs(ref)) / n)
+        loss_total += ch[2]
+        gl_sum += ch[5]
+        gl_scale += gl_s
+    check("batch grad_lambda", _h(b.outputs[0]["grad_lambda"]), gl_sum, gl_scale)
+    assert abs(_h(b.loss)[0] - loss_total) <= 1e-5 * loss_total
+
+
 # Frames large enough for region-aligned tiling (>= 16 N x 4 N pixels), each with its own
 # lambda table, grid size and gradient buffer; three radii, so the batch runs three plans.
 ALIGNED_SPECS = [(96, 40, 4, 3, 4), (130, 37, 8, 5, 4), (64, 16, 2, 0, 4), (200, 90, 5, 5, 6),
                  (320, 80, 3, 3, 20)]
 
 
-def test_batched_region_aligned_frames():
+@pytest.mark.parametrize("loss_in_forward", [False, True])
+def test_batched_region_aligned_frames(loss_in_forward):
     frames, host = [], []
     for i, (W, H, S, r, N) in enumerate(ALIGNED_SPECS):
         rad, _ = make_frame(W, H, S, seed=30 + i, frame=i, with_features=False)
@@ -132,7 +159,7 @@ def test_batched_region_aligned_frames():
         sched = [0, _abi.RAMLT_TILE_32X16, _abi.RAMLT_TILE_64X8, _abi.RAMLT_SCHED_DIRECT,
                  _abi.RAMLT_TILE_32X16 | _abi.RAMLT_SCHED_DIRECT][i]
         frames.append(FrameInput(_dev(rad), None, _dev(ref), _dev(lam), radius=r, n_regions=N, schedule=sched))
-    b = FrameBatch(frames)
+    b = FrameBatch(frames, loss_in_forward=loss_in_forward)
     b.step()
     torch.cuda.synchronize()
     loss_total = 0.0
@@ -165,10 +192,11 @@ def test_single_frame_adjoint_is_deterministic():
         assert np.array_equal(loss, runs[0][2])
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("loss_in_forward", [False, True])
+def test_graph_replay_matches_eager(loss_in_forward):
     lam_d = _dev(make_lambda(20, seed=99))
     frames, _ = _batch_inputs(SPECS[:4], lam_d)
-    b = FrameBatch(frames)
+    b = FrameBatch(frames, loss_in_forward=loss_in_forward)
     b.step()
     torch.cuda.synchronize()
     eager = [{k: _h(v).copy() for k, v in o.items()} for o in b.outputs]
@@ -181,7 +209,7 @@ def test_graph_replay_matches_eager():
         b.replay()
         torch.cuda.synchronize()
         for i, o in enumerate(b.outputs):
-            for k in ("mean", "var", "tau", "out"):
+            for k in ("mean", "var", "tau", "out") + (("grad_out",) if loss_in_forward else ()):
                 assert np.array_equal(_h(o[k]), eager[i][k]), (rep, i, k)
             np.testing.assert_allclose(_h(o["grad_radiance"]), eager[i]["grad_radiance"], rtol=0, atol=0)
             np.testing.assert_allclose(_h(o["grad_lambda"]), eager[i]["grad_lambda"], rtol=1e-5, atol=1e-12)

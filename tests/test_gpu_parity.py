@@ -209,3 +209,81 @@ def test_chain_parity_small_frame():
     G_s, gl_s = backward_scales(u_scale, o["mean"], out_o, lam, N, r, -30.0, S)
     check("G", _host(G), G_o, G_s)
     check("grad_lambda", _host(gl), gl_o, gl_s)
+
+
+@pytest.mark.parametrize("schedule", [0, _abi.RAMLT_TILE_32X8 | _abi.RAMLT_SCHED_DIRECT])
+@pytest.mark.parametrize("W,H,N,r", [(96, 54, 4, 5), (70, 37, 20, 3)])
+def test_filter_nan_and_infinite_lambda(W, H, N, r, schedule):
+    # A NaN lambda propagates as the oracle's exp(max(lambda, lambda_min)) propagates it: out
+    # of that region, G within r of it, its dL/dlambda and the loss are NaN, the rest is as
+    # for finite lambda; lambda = +inf is a box filter (sigma^2 = inf), -inf is clamped.
+    print(f"nan lambda W={W} H={H} N={N} r={r} schedule={schedule}", flush=True)
+    _, mean32, lam = _filter_inputs(W, H, 4, N, seed=W + H)
+    lam[[1, N + 2]] = np.nan
+    lam[N * N - 1] = np.inf
+    lam[N] = -np.inf
+    out = _host(ops.filter_forward(_dev(mean32), _dev(lam), r, N, -30.0, schedule=schedule))
+    ref, _ = oracle.filter_forward(mean32, lam, N, r, -30.0)
+    assert np.array_equal(np.isnan(out), np.isnan(ref)) and np.isnan(ref).any()
+    ok = ~np.isnan(ref)
+    check("out", np.where(ok, out, 0), np.where(ok, ref, 0), np.nan_to_num(filter_scale(mean32, lam, N, r, -30.0)))
+    out32 = ref.astype(np.float32)
+    S = 4
+    U32 = (np.random.default_rng(W).standard_normal((3, H, W)) * 1e-3).astype(np.float32)
+    G, gl = (_host(t) for t in ops.filter_backward(_dev(U32), _dev(mean32), _dev(out32), _dev(lam), r, S, N,
+                                                   schedule=schedule))
+    G_ref, gl_ref = oracle.filter_backward(U32, mean32, out32, lam, N, r, -30.0, S)
+    G_s, gl_s = backward_scales(np.abs(U32), mean32, out32, lam, N, r, -30.0, S)
+    for name, a, b, s in (("G", G, G_ref, G_s), ("grad_lambda", gl, gl_ref, gl_s)):
+        nan = np.isnan(b)
+        assert np.array_equal(np.isnan(a), nan), name
+        assert nan.any() and not nan.all(), name
+        check(name, np.where(nan, 0, a), np.where(nan, 0, b), np.nan_to_num(s))
+    # the fused seed: U = 2 (out - R) / (3P) is NaN where out is
+    R32 = (mean32 + np.float32(0.01)).astype(np.float32)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    G2, gl2 = (_host(t) for t in ops.filter_backward(None, _dev(mean32), _dev(out32), _dev(lam), r, S, N,
+                                                     reference=_dev(R32), loss=loss, schedule=schedule))
+    L_o, U_o = oracle.mse_loss_seed(out32, R32)
+    G2_ref, gl2_ref = oracle.filter_backward(U_o, mean32, out32, lam, N, r, -30.0, S)
+    assert np.isnan(_host(loss)[0]) and np.isnan(L_o)
+    assert np.array_equal(np.isnan(G2), np.isnan(G2_ref)) and np.array_equal(np.isnan(gl2), np.isnan(gl2_ref))
+    # the loss formed in the forward pass: the same NaN pattern
+    out3, U3, loss3, gl3 = ops.filter_forward_loss(_dev(mean32), _dev(lam), r, _dev(R32), N, schedule=schedule)
+    G3 = _host(ops.filter_backward_radiance(U3, _dev(lam), r, S, N, schedule=schedule))
+    assert np.array_equal(np.isnan(_host(out3)), np.isnan(ref)) and np.isnan(_host(loss3)[0])
+    assert np.array_equal(np.isnan(G3), np.isnan(G2_ref)) and np.array_equal(np.isnan(_host(gl3)), np.isnan(gl2_ref))
+
+
+@pytest.mark.parametrize("schedule", [0] + SCHEDULES)
+@pytest.mark.parametrize("W,H,N,r,S", [(130, 70, 4, 3, 8), (96, 54, 40, 5, 4), (333, 190, 3, 7, 16),
+                                       (41, 9, 5, 15, 2), (67, 31, 1, 0, 2), (1, 1, 1, 2, 3), (96, 54, 4, 5, 64)])
+def test_loss_in_forward_parity(W, H, N, r, S, schedule):
+    # RAMLT_LOSS_IN_FORWARD: the forward pass forms out, U, the loss and dL/dlambda; the
+    # adjoint then forms G from U alone. Against the oracle's chain, and against the plain
+    # forward followed by the adjoint with the seed fused (the same results up to rounding).
+    print(f"loss in forward W={W} H={H} N={N} r={r} S={S} schedule={schedule}", flush=True)
+    _, mean32, lam = _filter_inputs(W, H, 4, N, seed=W * 5 + H)
+    lam[:: max(1, N)] = -35.0
+    ref32 = (mean32 * np.float32(0.9) + np.float32(0.05)).astype(np.float32)
+    out, U, loss, gl = ops.filter_forward_loss(_dev(mean32), _dev(lam), r, _dev(ref32), N, schedule=schedule)
+    G = ops.filter_backward_radiance(U, _dev(lam), r, S, N, schedule=schedule)
+    out_o, _ = oracle.filter_forward(mean32, lam, N, r, -30.0)
+    L_o, U_o = oracle.mse_loss_seed(out_o, ref32)
+    G_o, gl_o = oracle.filter_backward(U_o, mean32, out_o, lam, N, r, -30.0, S)
+    check("out", _host(out), out_o, filter_scale(mean32, lam, N, r, -30.0))
+    n = out_o.size
+    u_scale = 2.0 * (np.abs(out_o) + np.abs(ref32)) / n
+    check("U", _host(U), U_o, u_scale)
+    d = np.abs(out_o - ref32)
+    check("loss", _host(loss)[0], L_o, L_o + (2 * d * (np.abs(out_o) + np.abs(ref32))).sum() / n)
+    G_s, gl_s = backward_scales(u_scale, mean32, out_o, lam, N, r, -30.0, S)
+    check("G", _host(G), G_o, G_s)
+    check("grad_lambda", _host(gl), gl_o, gl_s)
+    # the two-kernel split against the fused adjoint on the same GPU out
+    loss2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    G2, gl2 = ops.filter_backward(None, _dev(mean32), out, _dev(lam), r, S, N, reference=_dev(ref32), loss=loss2,
+                                  schedule=schedule)
+    check("G vs fused adjoint", _host(G), _host(G2), G_s)
+    check("grad_lambda vs fused adjoint", _host(gl), _host(gl2), gl_s)
+    assert abs(_host(loss)[0] - _host(loss2)[0]) <= 1e-12 * max(L_o, 1e-300)
