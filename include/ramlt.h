@@ -194,6 +194,21 @@ int loss_seed(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
 int filter_backward(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
                     int32_t n_frames, void *workspace, size_t ws_bytes, void *stream);
 
+/* filter_backward for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same operation and
+ * results, with the workspace taken from a device array the library owns, so the caller
+ * passes no workspace. The array holds RAMLT_NOALLOC_WORKSPACE_BYTES on every GPU the
+ * library runs on, until the process ends; a call whose ramlt_workspace_size(...,
+ * RAMLT_OP_FILTER_BACKWARD) exceeds it returns RAMLT_EWORKSPACE (a single 3840x2160 frame
+ * needs about 400 KB). The call allocates nothing. Every call on one GPU uses that GPU's
+ * one array: calls that overlap on one GPU (on different streams, or from different host
+ * threads without ordering) race and must not be made; calls ordered on one stream are
+ * fine. No part of the array needs to start at zero (each call writes every entry it
+ * reads). Other arguments and errors as for filter_backward. */
+#define RAMLT_NOALLOC_WORKSPACE_BYTES (4u << 20)
+int filter_backward_noalloc(const ramlt_frame *frames_host, const ramlt_frame *frames_dev, int32_t n_frames,
+                            void *stream);
+
 /* ---------------------------------------------------------------------------------
  * Regional adaptation of the scaling parameters (Algorithm 1 with eqs. est_exp_acc,
  * update_lambda and step_size_n; parameters of Sec. 8.1).

@@ -49,6 +49,7 @@ EXPORTED = (
     "filter_forward",
     "loss_seed",
     "filter_backward",
+    "filter_backward_noalloc",
     "ramlt_workspace_size",
     "ramlt_last_error",
     "ramlt_abi_version",
@@ -176,6 +177,9 @@ def load():
         fn = getattr(lib, name)
         fn.argtypes = sig
         fn.restype = ctypes.c_int
+    lib.filter_backward_noalloc.argtypes = [ctypes.POINTER(RamltFrame), ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_void_p]
+    lib.filter_backward_noalloc.restype = ctypes.c_int
     lib.ramlt_workspace_size.argtypes = [ctypes.POINTER(RamltFrame), ctypes.c_int32, ctypes.c_int32]
     lib.ramlt_workspace_size.restype = ctypes.c_size_t
     lib.ramlt_last_error.argtypes = []
@@ -254,6 +258,16 @@ def loss_seed(frames, frames_dev=None, workspace=None, ws_bytes=0, stream=None):
 
 def filter_backward(frames, frames_dev=None, workspace=None, ws_bytes=0, stream=None):
     return _call("filter_backward", frames, frames_dev, workspace, ws_bytes, stream)
+
+
+def filter_backward_noalloc(frames, frames_dev=None, stream=None):
+    """filter_backward with the library's own device workspace (no workspace argument)."""
+    lib = load()
+    arr, n = _table(frames)
+    st = lib.filter_backward_noalloc(arr, frames_dev, n, stream)
+    if st != RAMLT_OK:
+        raise RamltError(st, lib.ramlt_last_error().decode())
+    return st
 
 
 def workspace_size(frames, op):

@@ -477,6 +477,29 @@ int filter_backward(const ramlt_frame *frames_host, const ramlt_frame *frames_de
                 frames_host, frames_dev, n_frames, workspace, ws_bytes, stream);
 }
 
+int filter_backward_noalloc(const ramlt_frame *frames_host, const ramlt_frame *frames_dev, int32_t n_frames,
+                            void *stream) {
+  int r = check_common(frames_host, frames_dev, n_frames);
+  if (r) return r;
+  for (int i = 0; i < n_frames; ++i) {
+    r = validate_backward(frames_host[i], i);
+    if (r) return r;
+  }
+  const size_t need = ramlt::workspace_bytes(frames_host, n_frames, RAMLT_OP_FILTER_BACKWARD);
+  if (need > ramlt::kNoallocWorkspaceBytes)
+    return fail(RAMLT_EWORKSPACE, "filter_backward_noalloc needs %zu bytes of workspace; the library's own holds %zu",
+                need, (size_t)ramlt::kNoallocWorkspaceBytes);
+  r = check_device();
+  if (r) return r;
+  void *ws = nullptr;
+  hipError_t e = ramlt::noalloc_workspace(&ws);
+  if (e != hipSuccess) return fail(RAMLT_EHIP, "filter_backward_noalloc: workspace address: %s", hipGetErrorString(e));
+  e = ramlt::launch_filter_backward(frames_host, frames_dev, n_frames, ws, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RAMLT_EHIP, "filter_backward_noalloc: %s", hipGetErrorString(e));
+  g_last_error.clear();
+  return RAMLT_OK;
+}
+
 size_t ramlt_workspace_size(const ramlt_frame *frames_host, int32_t n_frames, int32_t op) {
   if (frames_host == nullptr || n_frames < 1 || n_frames > RAMLT_MAX_FRAMES) return 0;
   return ramlt::workspace_bytes(frames_host, n_frames, op);

@@ -17,6 +17,11 @@ hipError_t launch_filter_backward(const ramlt_frame *fh, const ramlt_frame *fd, 
                                   hipStream_t st);
 size_t workspace_bytes(const ramlt_frame *fh, int n, int op);
 
+// The library's own device workspace of filter_backward_noalloc (noalloc.hip): this many
+// bytes per GPU; *ptr = the current device's copy (resolved once per device).
+constexpr size_t kNoallocWorkspaceBytes = RAMLT_NOALLOC_WORKSPACE_BYTES;
+hipError_t noalloc_workspace(void **ptr);
+
 // Regional adaptation (adapt.hip): n proposals, validated parameters and state.
 hipError_t launch_region_adapt(const ramlt_adapt_params &p, const ramlt_region_state &s, const int32_t *region,
                                const float *alpha, long long n, void *ws, hipStream_t st);

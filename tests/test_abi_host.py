@@ -454,3 +454,19 @@ def test_loss_in_forward_flag(lib):
     base = _abi.workspace_size([a, c], _abi.OP_FILTER_FORWARD)
     c.flags = _abi.RAMLT_LOSS_IN_FORWARD
     assert _abi.workspace_size([a, c], _abi.OP_FILTER_FORWARD) > 2 * base
+
+
+def test_noalloc_adjoint_validation(lib):
+    # filter_backward_noalloc validates like filter_backward and refuses, before any device
+    # work, a call whose workspace would exceed the library's own array
+    f = _valid_filter_frame()
+    assert lib.filter_backward_noalloc((_abi.RamltFrame * 1)(f), None, 1, None) in (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
+    g = _abi.RamltFrame.from_buffer_copy(f)
+    g.grad_radiance = None
+    assert lib.filter_backward_noalloc((_abi.RamltFrame * 1)(g), None, 1, None) == _abi.RAMLT_EINVAL
+    big = _abi.RamltFrame.from_buffer_copy(f)
+    big.W, big.H, big.n_regions = 32768, 32768, 1
+    assert _abi.workspace_size([big], _abi.OP_FILTER_BACKWARD) > 4 << 20
+    assert lib.filter_backward_noalloc((_abi.RamltFrame * 1)(big), None, 1, None) == _abi.RAMLT_EWORKSPACE
+    assert "workspace" in _abi.last_error()
+    assert lib.filter_backward_noalloc(None, None, 1, None) == _abi.RAMLT_EINVAL
