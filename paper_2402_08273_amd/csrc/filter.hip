@@ -157,13 +157,14 @@ hipError_t launch_filter(bool bwd, const ramlt_frame *fh, const ramlt_frame *fd,
     const long long nt = filter_tiles(f);
     const bool lif = (f.flags & RAMLT_LOSS_IN_FORWARD) != 0;
     if (!bwd && !lif)
-      return launch_tiles(K.forward[f.radius], K.block, nt, st, f, g, (const ramlt_frame *)nullptr,
-                          (BatchPlan *)nullptr, nt);
+      return launch_tiles(K.forward[f.radius], K.fwd_block, nt, st, f, g, (const ramlt_frame *)nullptr,
+                          (BatchPlan *)nullptr, nt, (float *)nullptr, (double *)nullptr);
     float *lam_part;
     double *loss_part;
     partial_slots(ws, nt, &lam_part, &loss_part);
-    hipError_t e = launch_tiles(bwd ? K.backward[f.radius] : K.forward_loss[f.radius], K.block, nt, st, f, g,
-                                (const ramlt_frame *)nullptr, (BatchPlan *)nullptr, nt, lam_part, loss_part);
+    hipError_t e = launch_tiles(bwd ? K.backward[f.radius] : K.forward_loss[f.radius], bwd ? K.block : K.fwd_block,
+                                nt, st, f, g, (const ramlt_frame *)nullptr, (BatchPlan *)nullptr, nt, lam_part,
+                                loss_part);
     if (e != hipSuccess || (bwd && lif)) return e;  // the adjoint of such a frame leaves no partials
     return launch_finalize(f, nullptr, nullptr, 1, f.n_regions, lam_part, loss_part, !bwd, st);
   }
@@ -196,12 +197,13 @@ hipError_t launch_filter(bool bwd, const ramlt_frame *fh, const ramlt_frame *fd,
       if (filter_group(fh[i]) == groups[q]) tiles += filter_tiles(fh[i]);
     if (tiles == 0) continue;
     if (!bwd && !lif) {
-      e = launch_tiles(K.forward_batched[radius], K.block, tiles, st, none, none_g, fd, plan, 0LL);
+      e = launch_tiles(K.forward_batched[radius], K.fwd_block, tiles, st, none, none_g, fd, plan, 0LL,
+                       (float *)nullptr, (double *)nullptr);
       if (e != hipSuccess) return e;
       continue;
     }
-    e = launch_tiles(bwd ? K.backward_batched[radius] : K.forward_loss_batched[radius], K.block, tiles, st, none,
-                     none_g, fd, plan, 0LL, lam_part, loss_part);
+    e = launch_tiles(bwd ? K.backward_batched[radius] : K.forward_loss_batched[radius],
+                     bwd ? K.block : K.fwd_block, tiles, st, none, none_g, fd, plan, 0LL, lam_part, loss_part);
     if (e != hipSuccess) return e;
     if (bwd && lif) continue;
     e = launch_finalize(none, fd, plan, n, nmax, lam_part, loss_part, !bwd, st);

@@ -208,140 +208,6 @@ __device__ __forceinline__ float window_moment2(const float (&w)[R + 1]) {
   return 2.0f * z;
 }
 
-// Halo values of one tile held in registers between their loads and their LDS stores, so
-// that a workgroup loads the next tile's halo while it computes the current one.
-template <int R, class SH>
-struct Halo {
-  float4 v[halo_iters<R, SH>()];
-};
-
-// Issue the loads of value(q) for every halo pixel of the tile at (x0, y0) (addresses
-// clamped into the image, so every load is in bounds).
-template <int R, class SH, typename F>
-__device__ __forceinline__ void halo_load(const ramlt_frame &f, int x0, int y0, Halo<R, SH> &h, F value) {
-  constexpr int kTX = SH::TX, kTY = SH::TY, kFilterBlock = SH::BLOCK;
-  constexpr int HX = kTX + 2 * R;
-#pragma unroll
-  for (int it = 0; it < halo_iters<R, SH>(); ++it) {
-    const int i = threadIdx.x + it * kFilterBlock;
-    const int hy = i / HX;
-    const int hx = i - hy * HX;
-    const int cx = min(max(x0 - R + hx, 0), f.W - 1);
-    const int cy = min(max(y0 - R + hy, 0), f.H - 1);
-    h.v[it] = value((long long)cy * f.W + cx);
-  }
-}
-
-// Store loaded halo values to LDS, zero for pixels outside the image.
-template <int R, class SH>
-__device__ __forceinline__ void halo_store(const ramlt_frame &f, int x0, int y0, const Halo<R, SH> &h, float4 *lds) {
-  constexpr int kTX = SH::TX, kTY = SH::TY, kFilterBlock = SH::BLOCK;
-  constexpr int HX = kTX + 2 * R;
-  constexpr int HY = kTY + 2 * R;
-#pragma unroll
-  for (int it = 0; it < halo_iters<R, SH>(); ++it) {
-    const int i = threadIdx.x + it * kFilterBlock;
-    const int hy = i / HX;
-    const int hx = i - hy * HX;
-    const int gx = x0 - R + hx;
-    const int gy = y0 - R + hy;
-    const bool in = gx >= 0 && gx < f.W && gy >= 0 && gy < f.H;
-    if (i < HX * HY) lds[i] = in ? h.v[it] : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-}
-
-template <int R, class SH>
-struct FwdLds {
-  float4 stage[(SH::TX + 2 * R) * (SH::TY + 2 * R)];
-  float4 hb1[(SH::TY + 2 * R) * SH::TX];
-  float wtab[R + 1];
-};
-
-// The filter of one tile whose mean halo is in LDS (and, for a tile in one region, the
-// weights w(d) in wtab).
-template <int R, class SH>
-__device__ __forceinline__ void forward_compute(const ramlt_frame &f, const TileGeom &g, const Rect &r, bool uniform,
-                                                FwdLds<R, SH> &L) {
-  constexpr int kTX = SH::TX, kTY = SH::TY, kFilterBlock = SH::BLOCK;
-  constexpr int HX = kTX + 2 * R;
-  constexpr int HY = kTY + 2 * R;
-  float4 *stage = L.stage, *hbuf = L.hb1;
-  const long long P = (long long)f.W * f.H;
-  const int tx = threadIdx.x % kTX;
-  const int ty = threadIdx.x / kTX;
-  const int x = r.x0 + tx;
-  const int y = r.y0 + ty;
-  const bool inside = x < r.x1 && y < r.y1;
-  if (uniform) {
-    // one sigma for the whole tile: rows, then columns
-    float w[R + 1];
-#pragma unroll
-    for (int d = 0; d <= R; ++d) w[d] = L.wtab[d];
-    for (int i = threadIdx.x; i < HY * kTX; i += kFilterBlock) {
-      const int hy = i / kTX;
-      const int hx = i - hy * kTX;
-      const float4 *row = stage + hy * HX + hx + R;
-      float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-      for (int dx = -R; dx <= R; ++dx) {
-        const float4 m = row[dx];
-        const float ww = w[dx < 0 ? -dx : dx];
-        a.x = fmaf(ww, m.x, a.x);
-        a.y = fmaf(ww, m.y, a.y);
-        a.z = fmaf(ww, m.z, a.z);
-      }
-      hbuf[i] = a;
-    }
-    __syncthreads();
-    if (inside) {
-      float ax = 0.f, ay = 0.f, az = 0.f;
-#pragma unroll
-      for (int dy = -R; dy <= R; ++dy) {
-        const float4 h = hbuf[(ty + R + dy) * kTX + tx];
-        const float wy = w[dy < 0 ? -dy : dy];
-        ax = fmaf(wy, h.x, ax);
-        ay = fmaf(wy, h.y, ay);
-        az = fmaf(wy, h.z, az);
-      }
-      const float Z = window_sum<R>(w);
-      const float D = axis_sum<R, 0>(w, Z, x, f.W) * axis_sum<R, 0>(w, Z, y, f.H);
-      const long long o = (long long)y * f.W + x;
-      f.out[o] = ax / D;
-      f.out[P + o] = ay / D;
-      f.out[2 * P + o] = az / D;
-    }
-  } else if (inside) {
-    // per-pixel sigma: direct (2R+1)^2 gather
-    const int k = region_at(g, x, y);
-    const float beta = half_inv_var(f.lambda[k], f.lambda_min);
-    float w[R + 1];
-    gauss_weights<R>(beta, w);
-    float ax = 0.f, ay = 0.f, az = 0.f;
-#pragma unroll
-    for (int dy = -R; dy <= R; ++dy) {
-      const float4 *row = stage + (ty + R + dy) * HX + tx + R;
-      float rx = 0.f, ry = 0.f, rz = 0.f;
-#pragma unroll
-      for (int dx = -R; dx <= R; ++dx) {
-        const float4 m = row[dx];
-        const float ww = w[dx < 0 ? -dx : dx];
-        rx = fmaf(ww, m.x, rx);
-        ry = fmaf(ww, m.y, ry);
-        rz = fmaf(ww, m.z, rz);
-      }
-      const float wy = w[dy < 0 ? -dy : dy];
-      ax = fmaf(wy, rx, ax);
-      ay = fmaf(wy, ry, ay);
-      az = fmaf(wy, rz, az);
-    }
-    const float D = clipped_sum<R, 0>(w, x, f.W) * clipped_sum<R, 0>(w, y, f.H);
-    const long long o = (long long)y * f.W + x;
-    f.out[o] = ax / D;
-    f.out[P + o] = ay / D;
-    f.out[2 * P + o] = az / D;
-  }
-}
-
 // ------------------------------------------------------------------------ loss seed
 constexpr int kLossBlock = 256;
 
@@ -390,175 +256,6 @@ __device__ __forceinline__ void reduce_lambda(float *grad_lambda, int key, float
     v = wave_sum(v);
     if (lane == lead) unsafeAtomicAdd(grad_lambda + kk, v);
     if (key == kk) key = -1;
-  }
-}
-
-// ------------------------------------------------------------------------ forward + loss
-// With RAMLT_LOSS_IN_FORWARD the forward tile also forms the MSE seed U_j = 2 (out_j - R_j)
-// / (3P) and the parameter adjoint
-//   dL/dlambda_k(j) += beta_j sum_c U_jc (N2_jc - out_jc H2_j) / D_j,
-//   N2_jc = sum_p h_jp d^2 mean_pc, H2_j = sum_p h_jp d^2, beta = 1 / (2 sigma^2),
-// from the mean halo it holds for out: the separable passes carry the d^2-weighted sums
-// beside the plain ones (a tile in one region), or the direct gather does (a tile that
-// spans regions). Per-tile partials of the loss and of dL/dlambda go to the same slots as
-// the adjoint's.
-template <int R, class SH>
-struct FwdLossLds {
-  float4 stage[(SH::TX + 2 * R) * (SH::TY + 2 * R)];
-  float4 hb1[(SH::TY + 2 * R) * SH::TX];
-  float4 hb2[(SH::TY + 2 * R) * SH::TX];
-  float wtab[R + 1];
-  double red[SH::BLOCK / kWave];
-};
-
-// uniform: the separable passes (one sigma for the tile, and the schedule allows them);
-// one_region: every pixel of the tile is in one region (one partial sum of dL/dlambda).
-template <int R, class SH>
-__device__ __forceinline__ void forward_loss_compute(const ramlt_frame &f, const TileGeom &g, const Rect &r,
-                                                     bool uniform, bool one_region, long long slot,
-                                                     float *lam_part, double *loss_part, FwdLossLds<R, SH> &L) {
-  constexpr int kTX = SH::TX, kTY = SH::TY, kFilterBlock = SH::BLOCK;
-  constexpr int HX = kTX + 2 * R;
-  constexpr int HY = kTY + 2 * R;
-  const float4 *stage = L.stage;
-  const long long P = (long long)f.W * f.H;
-  const float useed = (float)(2.0 / (3.0 * (double)P));
-  const int tx = threadIdx.x % kTX;
-  const int ty = threadIdx.x / kTX;
-  const int x = r.x0 + tx;
-  const int y = r.y0 + ty;
-  const bool inside = x < r.x1 && y < r.y1;
-  const long long o = (long long)y * f.W + x;
-  // the own pixel's reference, in flight during the passes
-  float4 ref = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (inside) ref = load3(f.reference, P, o);
-  const int k_own = inside ? region_at(g, x, y) : tile_region(g, r);
-  const float lam = f.lambda[k_own];
-  // the gradient passes the clamp for lambda >= lambda_min; NaN counts as live
-  const bool live = !(lam < f.lambda_min);
-  float w[R + 1], wd2[R + 1];
-  float beta;
-  float ax = 0.f, ay = 0.f, az = 0.f;  // sum h mean
-  float nx = 0.f, ny = 0.f, nz = 0.f;  // sum h d^2 mean
-  if (uniform) {
-    // one sigma for the whole tile: rows, then columns, plain and d^2-weighted
-#pragma unroll
-    for (int d = 0; d <= R; ++d) w[d] = L.wtab[d];
-#pragma unroll
-    for (int d = 0; d <= R; ++d) wd2[d] = w[d] * (float)(d * d);
-    beta = half_inv_var(lam, f.lambda_min);
-    for (int i = threadIdx.x; i < HY * kTX; i += kFilterBlock) {
-      const int hy = i / kTX;
-      const int hx = i - hy * kTX;
-      const float4 *row = stage + hy * HX + hx + R;
-      float4 a1 = make_float4(0.f, 0.f, 0.f, 0.f), a2 = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-      for (int dx = -R; dx <= R; ++dx) {
-        const float4 m = row[dx];
-        const int ad = dx < 0 ? -dx : dx;
-        a1.x = fmaf(w[ad], m.x, a1.x);
-        a1.y = fmaf(w[ad], m.y, a1.y);
-        a1.z = fmaf(w[ad], m.z, a1.z);
-        a2.x = fmaf(wd2[ad], m.x, a2.x);
-        a2.y = fmaf(wd2[ad], m.y, a2.y);
-        a2.z = fmaf(wd2[ad], m.z, a2.z);
-      }
-      L.hb1[i] = a1;
-      L.hb2[i] = a2;
-    }
-    __syncthreads();
-    if (inside) {
-#pragma unroll
-      for (int dy = -R; dy <= R; ++dy) {
-        const int ad = dy < 0 ? -dy : dy;
-        const float4 h1 = L.hb1[(ty + R + dy) * kTX + tx];
-        const float4 h2 = L.hb2[(ty + R + dy) * kTX + tx];
-        ax = fmaf(w[ad], h1.x, ax);
-        ay = fmaf(w[ad], h1.y, ay);
-        az = fmaf(w[ad], h1.z, az);
-        nx = fmaf(w[ad], h2.x, fmaf(wd2[ad], h1.x, nx));
-        ny = fmaf(w[ad], h2.y, fmaf(wd2[ad], h1.y, ny));
-        nz = fmaf(w[ad], h2.z, fmaf(wd2[ad], h1.z, nz));
-      }
-    }
-  } else {
-    // per-pixel sigma: direct (2R+1)^2 gather
-    beta = half_inv_var(lam, f.lambda_min);
-    gauss_weights<R>(beta, w);
-#pragma unroll
-    for (int d = 0; d <= R; ++d) wd2[d] = w[d] * (float)(d * d);
-    if (inside) {
-#pragma unroll
-      for (int dy = -R; dy <= R; ++dy) {
-        const float4 *row = stage + (ty + R + dy) * HX + tx + R;
-        float r1x = 0.f, r1y = 0.f, r1z = 0.f, r2x = 0.f, r2y = 0.f, r2z = 0.f;
-#pragma unroll
-        for (int dx = -R; dx <= R; ++dx) {
-          const float4 m = row[dx];
-          const int ad = dx < 0 ? -dx : dx;
-          r1x = fmaf(w[ad], m.x, r1x);
-          r1y = fmaf(w[ad], m.y, r1y);
-          r1z = fmaf(w[ad], m.z, r1z);
-          r2x = fmaf(wd2[ad], m.x, r2x);
-          r2y = fmaf(wd2[ad], m.y, r2y);
-          r2z = fmaf(wd2[ad], m.z, r2z);
-        }
-        const int ad = dy < 0 ? -dy : dy;
-        ax = fmaf(w[ad], r1x, ax);
-        ay = fmaf(w[ad], r1y, ay);
-        az = fmaf(w[ad], r1z, az);
-        nx = fmaf(w[ad], r2x, fmaf(wd2[ad], r1x, nx));
-        ny = fmaf(w[ad], r2y, fmaf(wd2[ad], r1y, ny));
-        nz = fmaf(w[ad], r2z, fmaf(wd2[ad], r1z, nz));
-      }
-    }
-  }
-  double lacc = 0.0;
-  float contrib = 0.f;
-  if (inside) {
-    const float Z0 = window_sum<R>(w), Z2 = window_moment2<R>(w);
-    const float sx0 = axis_sum<R, 0>(w, Z0, x, f.W), sy0 = axis_sum<R, 0>(w, Z0, y, f.H);
-    const float D = sx0 * sy0;
-    const float4 out = make_float4(ax / D, ay / D, az / D, 0.f);
-    f.out[o] = out.x;
-    f.out[P + o] = out.y;
-    f.out[2 * P + o] = out.z;
-    const float dx_ = out.x - ref.x, dy_ = out.y - ref.y, dz_ = out.z - ref.z;
-    const float4 u = make_float4(useed * dx_, useed * dy_, useed * dz_, 0.f);
-    f.grad_out[o] = u.x;
-    f.grad_out[P + o] = u.y;
-    f.grad_out[2 * P + o] = u.z;
-    lacc = fma((double)dx_, (double)dx_, lacc);
-    lacc = fma((double)dy_, (double)dy_, lacc);
-    lacc = fma((double)dz_, (double)dz_, lacc);
-    if (live) {
-      const float sx2 = axis_sum<R, 2>(w, Z2, x, f.W), sy2 = axis_sum<R, 2>(w, Z2, y, f.H);
-      const float H2 = sx2 * sy0 + sx0 * sy2;
-      const float t = u.x * (nx - out.x * H2) + u.y * (ny - out.y * H2) + u.z * (nz - out.z * H2);
-      contrib = beta * t / D;
-    }
-  }
-  if (f.loss) {
-    const double s = block_sum(lacc, L.red);
-    if (threadIdx.x == 0) {
-      if (loss_part)
-        loss_part[slot] = s;
-      else
-        unsafeAtomicAdd(f.loss, s / (3.0 * (double)P));
-    }
-  }
-  if (!f.grad_lambda) return;
-  if (one_region) {
-    // one region for the whole tile: block reduction, one partial (or atomic)
-    const double s = block_sum((double)contrib, L.red);
-    if (threadIdx.x == 0) {
-      if (lam_part && g.aligned)  // the finalize kernel reads region-aligned partials
-        lam_part[slot] = live ? (float)s : 0.f;
-      else if (live)
-        unsafeAtomicAdd(f.grad_lambda + k_own, (float)s);
-    }
-  } else {
-    reduce_lambda(f.grad_lambda, inside && live ? k_own : -1, contrib);
   }
 }
 
@@ -979,50 +676,191 @@ __device__ __forceinline__ void fetch_tile(const ramlt_frame &single, const Tile
   }
 }
 
-// Forward filter, one tile per workgroup: tile t0 + (the XCD-aware order of the workgroup)
-// of the single frame, or of a batch's plan. (A loop over several tiles per workgroup
-// kept more values live and cost occupancy; large launches are split by the host.)
-template <int R, class SH, bool BATCH>
-__global__ __launch_bounds__(SH::BLOCK) void forward_kernel(const ramlt_frame single, const TileGeom single_g,
-                                                               const ramlt_frame *__restrict__ frames,
-                                                               BatchPlan *plan, long long ntiles, long long t0) {
-  __shared__ FwdLds<R, SH> s;
-  const long long total = BATCH ? (long long)plan->total_tiles : ntiles;
-  const long long t = t0 + xcd_tile(blockIdx.x, gridDim.x);
-  if (t >= total) return;
-  ramlt_frame f;
-  TileGeom g;
-  Rect r;
-  fetch_tile<SH, BATCH>(single, single_g, frames, plan, t, f, g, r);
-  if (r.x0 >= r.x1 || r.y0 >= r.y1) return;  // block-uniform
-  // one sigma for the whole tile: rows then columns, unless the schedule asks for the direct gather
-  const bool uniform = tile_uniform(g, r) && !(f.flags & RAMLT_SCHED_DIRECT);
-  Halo<R, SH> h;
-  halo_load<R, SH>(f, r.x0, r.y0, h, [&](long long q) { return load3(f.mean, (long long)f.W * f.H, q); });
-  if (uniform && threadIdx.x <= R) {
-    const float beta = half_inv_var(f.lambda[tile_region(g, r)], f.lambda_min);
-    s.wtab[threadIdx.x] = threadIdx.x == 0 ? 1.0f : expf(-(float)(threadIdx.x * threadIdx.x) * beta);
+// ------------------------------------------------------------------------ forward
+// The forward tile, register-blocked. kFwdBlock threads per tile; thread u owns output
+// column u % TX and kFwdV consecutive output rows, so the column pass reads each row sum
+// once for kFwdV outputs, and a row-pass item covers 4 consecutive columns, so it reads each
+// staged mean once for 4 outputs. The mean halo and the row sums are held in LDS channel by
+// channel (structure of arrays, rows padded to a multiple of 4 floats), so a row-pass item
+// reads 4 columns of a channel with one 16-byte LDS read and lanes read consecutive words.
+// The sums are taken in the same order as a per-pixel gather: along x from -R to R, then
+// along y from -R to R.
+//
+// With LOSS (RAMLT_LOSS_IN_FORWARD) the tile also forms the MSE seed U_j = 2 (out_j - R_j)
+// / (3P) and the parameter adjoint
+//   dL/dlambda_k(j) += beta_j sum_c U_jc (N2_jc - out_jc H2_j) / D_j,
+//   N2_jc = sum_p h_jp d^2 mean_pc, H2_j = sum_p h_jp d^2, beta = 1 / (2 sigma^2),
+// with d^2 = dx^2 + dy^2 split over the two passes: the row pass carries sum w(dx) dx^2 mean
+// beside sum w(dx) mean, and N2 = sum_dy w(dy) (row d^2 sum) + w(dy) dy^2 (row sum).
+// Per-tile partials of the loss and of dL/dlambda go to the same slots as the adjoint's.
+constexpr int kFwdBlock = 256;
+
+template <int R, class SH>
+struct FwdGeom {
+  static constexpr int TX = SH::TX, TY = SH::TY;
+  static constexpr int HX = TX + 2 * R, HY = TY + 2 * R;
+  static constexpr int HXP = (HX + 3) & ~3;  // LDS row stride (16-byte rows)
+  static constexpr int PLANE = HY * HXP;      // one channel of the staged halo
+  static constexpr int RPLANE = HY * TX;      // one channel of the row sums
+  static constexpr int V = TX * TY / kFwdBlock;  // output rows per thread
+  static constexpr int NQ = (4 + 2 * R + 3) / 4;  // 16-byte reads per row-pass item and channel
+  static_assert(V >= 1 && TX * TY == V * kFwdBlock && TY % V == 0, "one column unit per thread");
+  static_assert(TX % 4 == 0, "row-pass items of 4 columns");
+  static_assert(4 * NQ <= HXP, "row-pass reads stay inside an LDS row");
+};
+
+template <int R, class SH, bool LOSS>
+struct FwdLds {
+  using G = FwdGeom<R, SH>;
+  alignas(16) float stage[3 * G::PLANE];
+  alignas(16) float rows[(LOSS ? 6 : 3) * G::RPLANE];  // row sums: plain (3 channels), then d^2-weighted
+  float wtab[R + 1];
+  double red[kFwdBlock / kWave];
+};
+
+// Stage the mean over tile + halo, channel planes, zero outside the image. All loads are
+// issued before the first LDS store (addresses clamped into the image).
+template <int R, class SH>
+__device__ __forceinline__ void stage_mean_soa(const ramlt_frame &f, int x0, int y0, float *stage) {
+  using G = FwdGeom<R, SH>;
+  constexpr int NIT = (G::HX * G::HY + kFwdBlock - 1) / kFwdBlock;
+  const long long P = (long long)f.W * f.H;
+  float4 v[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int i = threadIdx.x + it * kFwdBlock;
+    const int hy = i / G::HX;
+    const int hx = i - hy * G::HX;
+    const int cx = min(max(x0 - R + hx, 0), f.W - 1);
+    const int cy = min(max(y0 - R + hy, 0), f.H - 1);
+    v[it] = load3(f.mean, P, (long long)cy * f.W + cx);
   }
-  halo_store<R, SH>(f, r.x0, r.y0, h, s.stage);
-  __syncthreads();
-  forward_compute<R, SH>(f, g, r, uniform, s);
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int i = threadIdx.x + it * kFwdBlock;
+    if (i < G::HX * G::HY) {
+      const int hy = i / G::HX;
+      const int hx = i - hy * G::HX;
+      const int gx = x0 - R + hx, gy = y0 - R + hy;
+      const bool in = gx >= 0 && gx < f.W && gy >= 0 && gy < f.H;
+      const int o = hy * G::HXP + hx;
+      stage[o] = in ? v[it].x : 0.f;
+      stage[G::PLANE + o] = in ? v[it].y : 0.f;
+      stage[2 * G::PLANE + o] = in ? v[it].z : 0.f;
+    }
+  }
 }
 
-__device__ __forceinline__ void empty_tile_partials(long long slot, float *lam_part, double *loss_part) {
-  if (threadIdx.x == 0) {
-    if (lam_part) lam_part[slot] = 0.f;
-    if (loss_part) loss_part[slot] = 0.0;
+// Row pass of a tile in one region: rows[c][hy][x] = sum_dx w(|dx|) mean_c(hy, x + dx) and,
+// with LOSS, rows[3 + c][hy][x] = sum_dx w(|dx|) dx^2 mean_c(hy, x + dx).
+template <int R, class SH, bool LOSS>
+__device__ __forceinline__ void forward_rows(const float *stage, float *rows, const float (&w)[R + 1],
+                                             const float (&wd2)[R + 1]) {
+  using G = FwdGeom<R, SH>;
+  constexpr int NG = G::TX / 4;
+  for (int u = threadIdx.x; u < G::HY * NG; u += kFwdBlock) {
+    const int hy = u / NG;
+    const int x0 = 4 * (u - hy * NG);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float4 *src = (const float4 *)(stage + c * G::PLANE + hy * G::HXP + x0);
+      float m[4 * G::NQ];
+#pragma unroll
+      for (int q = 0; q < G::NQ; ++q) {
+        const float4 t = src[q];
+        m[4 * q] = t.x;
+        m[4 * q + 1] = t.y;
+        m[4 * q + 2] = t.z;
+        m[4 * q + 3] = t.w;
+      }
+      float a1[4] = {0.f, 0.f, 0.f, 0.f}, a2[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < 4 + 2 * R; ++j) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int d = j - k - R;  // tap offset of output x0 + k
+          if (d >= -R && d <= R) {
+            const int ad = d < 0 ? -d : d;
+            a1[k] = fmaf(w[ad], m[j], a1[k]);
+            if (LOSS) a2[k] = fmaf(wd2[ad], m[j], a2[k]);
+          }
+        }
+      }
+      *(float4 *)(rows + c * G::RPLANE + hy * G::TX + x0) = make_float4(a1[0], a1[1], a1[2], a1[3]);
+      if (LOSS)
+        *(float4 *)(rows + (3 + c) * G::RPLANE + hy * G::TX + x0) = make_float4(a2[0], a2[1], a2[2], a2[3]);
+    }
   }
 }
 
-// Forward filter with the MSE seed and dL/dlambda (RAMLT_LOSS_IN_FORWARD), one tile per
-// workgroup; per-tile partials go to slot t.
-template <int R, class SH, bool BATCH>
-__global__ __launch_bounds__(SH::BLOCK) void forward_loss_kernel(const ramlt_frame single, const TileGeom single_g,
-                                                                    const ramlt_frame *__restrict__ frames,
-                                                                    BatchPlan *plan, long long ntiles, long long t0,
-                                                                    float *lam_part, double *loss_part) {
-  __shared__ FwdLossLds<R, SH> s;
+// Column pass for the thread's column tx and rows ty0 .. ty0 + V - 1: a[k][c] = sum_dy w(|dy|)
+// rows[c] and, with LOSS, n[k][c] = sum_dy w(|dy|) rows[3 + c] + w(|dy|) dy^2 rows[c].
+template <int R, class SH, bool LOSS>
+__device__ __forceinline__ void forward_columns(const float *rows, int tx, int ty0, const float (&w)[R + 1],
+                                                const float (&wd2)[R + 1], float (&a)[FwdGeom<R, SH>::V][3],
+                                                float (&n)[FwdGeom<R, SH>::V][3]) {
+  using G = FwdGeom<R, SH>;
+  constexpr int V = G::V;
+#pragma unroll
+  for (int j = 0; j < V + 2 * R; ++j) {
+    float h1[3], h2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      h1[c] = rows[c * G::RPLANE + (ty0 + j) * G::TX + tx];
+      h2[c] = LOSS ? rows[(3 + c) * G::RPLANE + (ty0 + j) * G::TX + tx] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const int d = j - k - R;
+      if (d >= -R && d <= R) {
+        const int ad = d < 0 ? -d : d;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          a[k][c] = fmaf(w[ad], h1[c], a[k][c]);
+          if (LOSS) n[k][c] = fmaf(w[ad], h2[c], fmaf(wd2[ad], h1[c], n[k][c]));
+        }
+      }
+    }
+  }
+}
+
+// Direct (2R+1)^2 gather for output (tx, ty) with its own weights w (and wd2 for N2).
+template <int R, class SH, bool LOSS>
+__device__ __forceinline__ void forward_direct(const float *stage, int tx, int ty, const float (&w)[R + 1],
+                                               const float (&wd2)[R + 1], float (&a)[3], float (&n)[3]) {
+  using G = FwdGeom<R, SH>;
+#pragma unroll
+  for (int dy = -R; dy <= R; ++dy) {
+    const int ay = dy < 0 ? -dy : dy;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float *row = stage + c * G::PLANE + (ty + R + dy) * G::HXP + tx + R;
+      float r1 = 0.f, r2 = 0.f;
+#pragma unroll
+      for (int dx = -R; dx <= R; ++dx) {
+        const int ax = dx < 0 ? -dx : dx;
+        const float m = row[dx];
+        r1 = fmaf(w[ax], m, r1);
+        if (LOSS) r2 = fmaf(wd2[ax], m, r2);
+      }
+      a[c] = fmaf(w[ay], r1, a[c]);
+      if (LOSS) n[c] = fmaf(w[ay], r2, fmaf(wd2[ay], r1, n[c]));
+    }
+  }
+}
+
+// Forward filter of one tile per workgroup: tile t0 + (the XCD-aware order of the workgroup)
+// of the single frame, or of a batch's plan. With LOSS, per-tile partials go to slot t.
+// (A loop over several tiles per workgroup kept more values live and cost occupancy; large
+// launches are split by the host.)
+template <int R, class SH, bool BATCH, bool LOSS>
+__global__ __launch_bounds__(kFwdBlock) void forward_kernel(const ramlt_frame single, const TileGeom single_g,
+                                                            const ramlt_frame *__restrict__ frames, BatchPlan *plan,
+                                                            long long ntiles, long long t0, float *lam_part,
+                                                            double *loss_part) {
+  using G = FwdGeom<R, SH>;
+  constexpr int V = G::V;
+  __shared__ FwdLds<R, SH, LOSS> L;
   const long long total = BATCH ? (long long)plan->total_tiles : ntiles;
   const long long t = t0 + xcd_tile(blockIdx.x, gridDim.x);
   if (t >= total) return;
@@ -1031,20 +869,133 @@ __global__ __launch_bounds__(SH::BLOCK) void forward_loss_kernel(const ramlt_fra
   Rect r;
   fetch_tile<SH, BATCH>(single, single_g, frames, plan, t, f, g, r);
   if (r.x0 >= r.x1 || r.y0 >= r.y1) {  // block-uniform
-    empty_tile_partials(t, lam_part, loss_part);
+    if (LOSS && threadIdx.x == 0) {
+      if (lam_part) lam_part[t] = 0.f;
+      if (loss_part) loss_part[t] = 0.0;
+    }
     return;
   }
+  const long long P = (long long)f.W * f.H;
+  // one region for the whole tile: one sigma, separable passes (unless the schedule asks for
+  // the direct gather) and one partial sum of dL/dlambda
   const bool one_region = tile_uniform(g, r);
   const bool uniform = one_region && !(f.flags & RAMLT_SCHED_DIRECT);
-  Halo<R, SH> h;
-  halo_load<R, SH>(f, r.x0, r.y0, h, [&](long long q) { return load3(f.mean, (long long)f.W * f.H, q); });
+  const int tx = threadIdx.x % G::TX;
+  const int ty0 = (threadIdx.x / G::TX) * V;
+  const int x = r.x0 + tx;
+  stage_mean_soa<R, SH>(f, r.x0, r.y0, L.stage);
   if (uniform && threadIdx.x <= R) {
     const float beta = half_inv_var(f.lambda[tile_region(g, r)], f.lambda_min);
-    s.wtab[threadIdx.x] = threadIdx.x == 0 ? 1.0f : expf(-(float)(threadIdx.x * threadIdx.x) * beta);
+    L.wtab[threadIdx.x] = threadIdx.x == 0 ? 1.0f : expf(-(float)(threadIdx.x * threadIdx.x) * beta);
   }
-  halo_store<R, SH>(f, r.x0, r.y0, h, s.stage);
+  // the own pixels' reference values, in flight during the passes
+  float ref[V][3];
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    const int y = r.y0 + ty0 + k;
+    const bool in = x < r.x1 && y < r.y1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ref[k][c] = (LOSS && in) ? f.reference[c * P + (long long)y * f.W + x] : 0.f;
+  }
   __syncthreads();
-  forward_loss_compute<R, SH>(f, g, r, uniform, one_region, t, lam_part, loss_part, s);
+  float a[V][3], n[V][3];
+#pragma unroll
+  for (int k = 0; k < V; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a[k][c] = n[k][c] = 0.f;
+  float w[R + 1], wd2[R + 1];
+  if (uniform) {
+#pragma unroll
+    for (int d = 0; d <= R; ++d) w[d] = L.wtab[d];
+#pragma unroll
+    for (int d = 0; d <= R; ++d) wd2[d] = w[d] * (float)(d * d);
+    forward_rows<R, SH, LOSS>(L.stage, L.rows, w, wd2);
+    __syncthreads();
+    forward_columns<R, SH, LOSS>(L.rows, tx, ty0, w, wd2, a, n);
+  }
+  double lacc = 0.0;
+  float contrib = 0.f;
+  int k_last = tile_region(g, r);
+  bool live_last = false;
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    const int y = r.y0 + ty0 + k;
+    const bool inside = x < r.x1 && y < r.y1;
+    const int kr = inside ? region_at(g, x, y) : tile_region(g, r);
+    const float lam = f.lambda[kr];
+    const bool live = !(lam < f.lambda_min);  // NaN counts as live: it reaches dL/dlambda
+    const float beta = half_inv_var(lam, f.lambda_min);
+    if (!uniform) {
+      gauss_weights<R>(beta, w);
+#pragma unroll
+      for (int d = 0; d <= R; ++d) wd2[d] = w[d] * (float)(d * d);
+      if (inside) forward_direct<R, SH, LOSS>(L.stage, tx, ty0 + k, w, wd2, a[k], n[k]);
+    }
+    float ck = 0.f;
+    if (inside) {
+      const float Z0 = window_sum<R>(w);
+      const float sx0 = uniform ? axis_sum<R, 0>(w, Z0, x, f.W) : clipped_sum<R, 0>(w, x, f.W);
+      const float sy0 = uniform ? axis_sum<R, 0>(w, Z0, y, f.H) : clipped_sum<R, 0>(w, y, f.H);
+      const float D = sx0 * sy0;
+      const long long o = (long long)y * f.W + x;
+      float out[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        out[c] = a[k][c] / D;
+        f.out[c * P + o] = out[c];
+      }
+      if (LOSS) {
+        const float useed = (float)(2.0 / (3.0 * (double)P));
+        float u[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float dd = out[c] - ref[k][c];
+          u[c] = useed * dd;
+          f.grad_out[c * P + o] = u[c];
+          lacc = fma((double)dd, (double)dd, lacc);
+        }
+        if (live) {
+          const float Z2 = window_moment2<R>(w);
+          const float sx2 = axis_sum<R, 2>(w, Z2, x, f.W), sy2 = axis_sum<R, 2>(w, Z2, y, f.H);
+          const float H2 = sx2 * sy0 + sx0 * sy2;
+          const float tt = u[0] * (n[k][0] - out[0] * H2) + u[1] * (n[k][1] - out[1] * H2) +
+                           u[2] * (n[k][2] - out[2] * H2);
+          ck = beta * tt / D;
+        }
+      }
+    }
+    if (LOSS && !one_region && f.grad_lambda) reduce_lambda(f.grad_lambda, inside && live ? kr : -1, ck);
+    contrib += ck;
+    k_last = kr;
+    live_last = live;
+  }
+  if (!LOSS) return;
+  if (f.loss) {
+    const double s = block_sum(lacc, L.red);
+    if (threadIdx.x == 0) {
+      if (loss_part)
+        loss_part[t] = s;
+      else
+        unsafeAtomicAdd(f.loss, s / (3.0 * (double)P));
+    }
+  }
+  if (f.grad_lambda && one_region) {
+    // one region for the whole tile: block reduction, one partial (or atomic)
+    const double s = block_sum((double)contrib, L.red);
+    if (threadIdx.x == 0) {
+      if (lam_part && g.aligned)  // the finalize kernel reads region-aligned partials
+        lam_part[t] = live_last ? (float)s : 0.f;
+      else if (live_last)
+        unsafeAtomicAdd(f.grad_lambda + k_last, (float)s);
+    }
+  }
+}
+
+__device__ __forceinline__ void empty_tile_partials(long long slot, float *lam_part, double *loss_part) {
+  if (threadIdx.x == 0) {
+    if (lam_part) lam_part[slot] = 0.f;
+    if (loss_part) loss_part[slot] = 0.0;
+  }
 }
 
 // Adjoint, one tile per workgroup; per-tile partials go to slot t.
@@ -1067,19 +1018,18 @@ __global__ __launch_bounds__(SH::BLOCK) void backward_kernel(const ramlt_frame s
     empty_tile_partials(t, lam_part, loss_part);
 }
 
-using FwdKernel = void (*)(const ramlt_frame, const TileGeom, const ramlt_frame *, BatchPlan *, long long,
-                           long long);
 using BwdKernel = void (*)(const ramlt_frame, const TileGeom, const ramlt_frame *, BatchPlan *, long long, long long,
                            float *, double *);
+using FwdKernel = BwdKernel;  // the forward takes the partial-sum slots too (used with the loss)
 using FwdLossKernel = BwdKernel;
 
 template <class SH, int... Rs>
 struct KernelTables {
   static constexpr int kCount = sizeof...(Rs);
-  static constexpr FwdKernel forward[kCount] = {forward_kernel<Rs, SH, false>...};
-  static constexpr FwdKernel forward_batched[kCount] = {forward_kernel<Rs, SH, true>...};
-  static constexpr FwdLossKernel forward_loss[kCount] = {forward_loss_kernel<Rs, SH, false>...};
-  static constexpr FwdLossKernel forward_loss_batched[kCount] = {forward_loss_kernel<Rs, SH, true>...};
+  static constexpr FwdKernel forward[kCount] = {forward_kernel<Rs, SH, false, false>...};
+  static constexpr FwdKernel forward_batched[kCount] = {forward_kernel<Rs, SH, true, false>...};
+  static constexpr FwdLossKernel forward_loss[kCount] = {forward_kernel<Rs, SH, false, true>...};
+  static constexpr FwdLossKernel forward_loss_batched[kCount] = {forward_kernel<Rs, SH, true, true>...};
   static constexpr BwdKernel backward[kCount] = {backward_kernel<Rs, SH, false>...};
   static constexpr BwdKernel backward_batched[kCount] = {backward_kernel<Rs, SH, true>...};
 };
@@ -1092,14 +1042,15 @@ struct KindKernels {
   const FwdKernel *forward, *forward_batched;
   const FwdLossKernel *forward_loss, *forward_loss_batched;
   const BwdKernel *backward, *backward_batched;
-  int block;
+  int block;      // threads per workgroup of the adjoint
+  int fwd_block;  // of the forward
 };
 
 template <class SH>
 KindKernels kind_kernels() {
   using T = TablesFor<SH>;
   return KindKernels{T::forward,  T::forward_batched,  T::forward_loss, T::forward_loss_batched,
-                     T::backward, T::backward_batched, SH::BLOCK};
+                     T::backward, T::backward_batched, SH::BLOCK, kFwdBlock};
 }
 
 // The kernel tables of each tile kind, one per translation unit.
