@@ -21,24 +21,35 @@ NOISE_CONST = 0
 NOISE_UNIFORM = 1
 
 
-def _pixel_grid(W, H):
-    y, x = np.meshgrid(np.arange(H, dtype=np.uint64), np.arange(W, dtype=np.uint64), indexing="ij")
+def _pixel_grid(W, H, rows=None):
+    """x, y and pixel index of rows [y0, y1) of a W x H frame (all rows by default)."""
+    y0, y1 = (0, H) if rows is None else rows
+    y, x = np.meshgrid(np.arange(y0, y1, dtype=np.uint64), np.arange(W, dtype=np.uint64), indexing="ij")
     return x, y, y * np.uint64(W) + x
 
 
-def pixel_sigma(W, H, seed, frame=0, noise=NOISE_UNIFORM, sigma=0.1):
-    """Per-pixel noise scale sigma_p [H, W] (float64)."""
+def _rows(H, rows):
+    y0, y1 = (0, H) if rows is None else (int(rows[0]), int(rows[1]))
+    if not 0 <= y0 < y1 <= H:
+        raise ValueError("rows outside the frame")
+    return y0, y1
+
+
+def pixel_sigma(W, H, seed, frame=0, noise=NOISE_UNIFORM, sigma=0.1, rows=None):
+    """Per-pixel noise scale sigma_p [H, W] (float64); [y1 - y0, W] for rows = (y0, y1)."""
+    y0, y1 = _rows(H, rows)
     if noise == NOISE_CONST:
-        return np.full((H, W), float(sigma))
-    _, _, pix = _pixel_grid(W, H)
+        return np.full((y1 - y0, W), float(sigma))
+    _, _, pix = _pixel_grid(W, H, (y0, y1))
     fk = frame_key(seed, frame)
     ua, _ = uniform_pair(draw(sample_key(fk, pix, SAMPLE_PIXEL), 0))
     return 0.02 + 0.48 * ua
 
 
-def _sample_values(W, H, s, fk, sig, firefly_p):
-    """Radiance (3,H,W) and features (7,H,W), float64, for sample index s."""
-    x, y, pix = _pixel_grid(W, H)
+def _sample_values(W, H, s, fk, sig, firefly_p, rows=None):
+    """Radiance (3,H,W) and features (7,H,W), float64, for sample index s (rows [y0, y1)
+    only when given)."""
+    x, y, pix = _pixel_grid(W, H, rows)
     sk = sample_key(fk, pix, np.uint64(s))
     xi_x, xi_y = uniform_pair(draw(sk, 0))
     u1, u2 = uniform_pair(draw(sk, 1))
@@ -59,19 +70,21 @@ def _sample_values(W, H, s, fk, sig, firefly_p):
 
 
 def make_frame(W, H, S, seed, frame=0, noise=NOISE_UNIFORM, sigma=0.1, firefly_p=1e-3,
-               feature_dtype=np.float32, with_features=True):
+               feature_dtype=np.float32, with_features=True, rows=None):
     """Sample planes of one frame.
 
-    Returns ``(radiance float32 [3,S,H,W], features [7,S,H,W] or None)``.
+    Returns ``(radiance float32 [3,S,H,W], features [7,S,H,W] or None)``; with
+    ``rows = (y0, y1)`` only those rows of the frame ([.., y1 - y0, W], the same values).
     """
     if not (1 <= S <= MAX_SPP):
         raise ValueError("S out of range")
+    y0, y1 = _rows(H, rows)
     fk = frame_key(seed, frame)
-    sig = pixel_sigma(W, H, seed, frame, noise, sigma)
-    rad = np.empty((3, S, H, W), dtype=np.float32)
-    feat = np.empty((7, S, H, W), dtype=feature_dtype) if with_features else None
+    sig = pixel_sigma(W, H, seed, frame, noise, sigma, (y0, y1))
+    rad = np.empty((3, S, y1 - y0, W), dtype=np.float32)
+    feat = np.empty((7, S, y1 - y0, W), dtype=feature_dtype) if with_features else None
     for s in range(S):
-        g, f = _sample_values(W, H, s, fk, sig, firefly_p)
+        g, f = _sample_values(W, H, s, fk, sig, firefly_p, (y0, y1))
         rad[:, s] = g.astype(np.float32)
         if with_features:
             # fp16 storage rounds through fp32 (the GPU generator does the same)
@@ -79,14 +92,16 @@ def make_frame(W, H, S, seed, frame=0, noise=NOISE_UNIFORM, sigma=0.1, firefly_p
     return rad, feat
 
 
-def make_reference(W, H, seed, frame=0, spp=4096, noise=NOISE_UNIFORM, sigma=0.1, firefly_p=1e-3):
+def make_reference(W, H, seed, frame=0, spp=4096, noise=NOISE_UNIFORM, sigma=0.1, firefly_p=1e-3, rows=None):
     """High-spp reference image [3,H,W] float32: the float64 mean of ``spp`` float32-rounded
-    radiance samples drawn from the independent stream ``seed``."""
+    radiance samples drawn from the independent stream ``seed`` (rows [y0, y1) only when
+    given)."""
+    y0, y1 = _rows(H, rows)
     fk = frame_key(seed, frame)
-    sig = pixel_sigma(W, H, seed, frame, noise, sigma)
-    acc = np.zeros((3, H, W), dtype=np.float64)
+    sig = pixel_sigma(W, H, seed, frame, noise, sigma, (y0, y1))
+    acc = np.zeros((3, y1 - y0, W), dtype=np.float64)
     for s in range(spp):
-        g, _ = _sample_values(W, H, s, fk, sig, firefly_p)
+        g, _ = _sample_values(W, H, s, fk, sig, firefly_p, (y0, y1))
         acc += g.astype(np.float32).astype(np.float64)
     return (acc / float(spp)).astype(np.float32)
 
