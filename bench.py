@@ -44,7 +44,8 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="skip the batched and 4K measurements")
     p.add_argument("--no-tune", action="store_true",
                    help="use the library's default filter schedule instead of the autotuned one")
-    p.add_argument("--only", choices=["batched", "uhd", "adapt", "quadtree", "perturb", "rrmse", "lens"], default=None,
+    p.add_argument("--only", choices=["batched", "uhd", "adapt", "quadtree", "perturb", "rrmse", "lens", "small",
+                                      "leaf_grad", "copy"], default=None,
                    help="measure only the 32-frame batch or only the 4K frame and print that object "
                         "(for profiling one workload)")
     p.add_argument("--cpu-rows", type=int, default=0, help="rows of the frame the oracle times (0 = auto)")
@@ -90,7 +91,9 @@ def stats_bytes(P, S, feat_bytes=4):
     return P * S * (3 * 4 + 7 * feat_bytes) + P * 23 * 4
 
 
-# filter forward (mean read, out write) + fused adjoint (mean, out, reference read; G write)
+# the filter's part of a step, 72 B per pixel in both forms: forward with the loss (mean,
+# reference read; out, U written) + radiance adjoint (U read, G written), or plain forward
+# (mean read, out written) + adjoint with the seed fused (mean, out, reference read; G written)
 FILTER_STEP_BYTES_PER_PX = 24 + 48
 
 
@@ -134,23 +137,32 @@ class SingleChain:
         # fused: the MSE seed is formed inside the adjoint (grad_out NULL)
         fu = _abi.RamltFrame.from_buffer_copy(ff)
         fu.grad_out = self.U.data_ptr()  # unfused variant: loss_seed writes U, the adjoint reads it
+        # loss in the forward pass: the forward writes out and U and accumulates the loss and
+        # dL/dlambda; the adjoint forms G from U
+        fl = _abi.RamltFrame.from_buffer_copy(fu)
+        fl.flags = _abi.RAMLT_LOSS_IN_FORWARD
         self.stream = torch.cuda.current_stream()
         self.sh = self.stream.cuda_stream
         self.tabs = (_abi.RamltFrame * 1)(fs)
         self.tabf = (_abi.RamltFrame * 1)(ff)
         self.tabu = (_abi.RamltFrame * 1)(fu)
+        self.tabl = (_abi.RamltFrame * 1)(fl)
         self.lib = _abi.load()
         self._abi = _abi
-        self.schedule = 0
         if tune:
-            # filter schedule (tile shape, window schedule) timed on this frame, untimed here
+            # filter schedule (tile shape, window schedule) timed on this frame for each form of
+            # the step, untimed here
             from paper_2402_08273_amd import tune as _tune
 
             self.call0(self.lib.stats_accumulate, self.tabs)
-            self.schedule = _tune.tune_table(self.tabf, zero=[self.acc])
+            _tune.tune_table(self.tabf, zero=[self.acc])
             self.tabu[0].flags = self.tabf[0].flags
-        # the adjoint's workspace (per-tile partial sums), allocated once
-        self.ws_t, self.ws_ptr, self.ws_bytes = ops.workspace_for([self.tabf[0]], _abi.OP_FILTER_BACKWARD, dev)
+            _tune.tune_table(self.tabl, zero=[self.acc])
+        # the filter's workspace (per-tile partial sums), allocated once
+        need = max(_abi.workspace_size([t[0]], op) for t in (self.tabf, self.tabl)
+                   for op in (_abi.OP_FILTER_FORWARD, _abi.OP_FILTER_BACKWARD))
+        self.ws_t = torch.empty(need + 256, device=dev, dtype=torch.uint8)
+        self.ws_ptr, self.ws_bytes = (self.ws_t.data_ptr() + 255) // 256 * 256, need
         torch.cuda.synchronize()
 
     def call0(self, fn, tab):
@@ -169,17 +181,27 @@ class SingleChain:
     def forward(self):
         self.call(self.lib.filter_forward, self.tabf)
 
-    def step(self, marks=None, fused=True):
+    def step(self, marks=None, form="loss_in_forward"):
+        """One step: stats -> filter -> loss seed -> adjoint. ``form``: "loss_in_forward" (the
+        forward forms out, U, the loss and dL/dlambda; the adjoint G), "fused" (plain forward;
+        the seed fused into the adjoint) or "unfused" (plain forward, loss_seed, adjoint)."""
         if marks is not None:
             marks[0].record(self.stream)
         self.stats()
         if marks is not None:
             marks[1].record(self.stream)
+        if form == "loss_in_forward":
+            self.acc.zero_()
+            self.call(self.lib.filter_forward, self.tabl)
+            if marks is not None:
+                marks[2].record(self.stream)
+            self.call(self.lib.filter_backward, self.tabl)
+            return
         self.forward()
         if marks is not None:
             marks[2].record(self.stream)
         self.acc.zero_()
-        if fused:
+        if form == "fused":
             self.call(self.lib.filter_backward, self.tabf)
         else:
             self.call(self.lib.loss_seed, self.tabu)
@@ -234,7 +256,7 @@ def measure_uhd(steps, warmup, tune=True):
         "fwd_mpx_s": round(c.P / (ms_fwd * 1e-3) / 1e6, 2),
         "algorithmic_bytes": b,
         "hbm_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "filter_schedule": schedule_name(c.tabf[0].flags),
+        "filter_schedule": schedule_name(c.tabl[0].flags),
     }
     del c
     torch.cuda.empty_cache()
@@ -259,7 +281,7 @@ def measure_batch32(steps, warmup, tune=True):
         rad, feat = sgpu.make_frame(sp.W, sp.H, sp.S, seed=sp.seed, frame=sp.frame)
         ref = sgpu.make_reference(sp.W, sp.H, seed=sp.seed + 1000, frame=sp.frame, spp=REFERENCE_SPP)
         frames.append(FrameInput(rad, feat, ref, lam, radius=sp.radius, n_regions=N_REGIONS, max_lag=MAX_LAG))
-    b = FrameBatch(frames)
+    b = FrameBatch(frames, loss_in_forward=True)
     if tune:
         b.stats()
         b.tune()
@@ -285,6 +307,80 @@ def measure_batch32(steps, warmup, tune=True):
     del b, frames
     torch.cuda.empty_cache()
     return res
+
+
+def measure_copy_ceiling(steps, mib=4096):
+    """The streaming-copy ceiling of this GPU: a device-to-device copy of ``mib`` MiB
+    (torch's copy_, a HIP blit kernel), bytes read + written per second."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, device="cuda:0", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        dst.copy_(src)
+    ms = time_loop(stream, lambda: dst.copy_(src), max(steps, 10))
+    del src, dst
+    torch.cuda.empty_cache()
+    gbs = 2 * n * 4 / (ms * 1e-3) / 1e9
+    return {"copy_gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes": 2 * n * 4,
+            "ms": round(ms, 4), "how": f"torch copy_ of {mib} MiB on the device (read + write)"}
+
+
+def measure_small(steps, warmup, tune=True):
+    """The 128 x 128, 16 spp frame with a 7 x 7 window, forward only (stats + filter): it
+    fits in the caches, so it is reported per call (launch- and latency-bound)."""
+    from synth.workloads import N_REGIONS, SMALL
+
+    c = SingleChain(SMALL.W, SMALL.H, SMALL.S, SMALL.radius, N_REGIONS, SMALL.seed, SMALL.frame, False, tune)
+    fwd = lambda: (c.stats(), c.forward())  # noqa: E731
+    for _ in range(max(warmup, 10)):
+        fwd()
+    reps = max(steps, 200)
+    ms = time_loop(c.stream, fwd, reps)
+    ms_stats = time_loop(c.stream, c.stats, reps)
+    return {"workload": f"stats+filter fwd, {SMALL.W}x{SMALL.H}, {SMALL.S} spp, fp32 radiance+features, "
+                        f"{2 * SMALL.radius + 1}x{2 * SMALL.radius + 1} window, {N_REGIONS}x{N_REGIONS} regions",
+            "us_per_call": round(ms * 1e3, 2), "stats_us": round(ms_stats * 1e3, 2),
+            "mpx_s": round(c.P / (ms * 1e-3) / 1e6, 2), "calls_timed": reps,
+            "note": "two launches per call, back to back on one stream; the 12.4 MB of inputs stay in the caches"}
+
+
+def measure_leaf_grad(steps, warmup):
+    """The autograd form at 1080p / 64 spp: RegionalFilter.apply on radiance that requires
+    grad, MSELoss, backward. Autograd materialises dL/dg for every sample (+12 B per sample
+    written: 1.59 GB here), which the algorithmic step does not."""
+    import torch
+
+    from paper_2402_08273_amd import ops
+    from synth import gpu as sgpu
+    from synth import make_lambda
+    from synth.workloads import HD, LAMBDA_SEED, N_REGIONS, REFERENCE_SPP
+
+    rad, feat = sgpu.make_frame(HD.W, HD.H, HD.S, seed=HD.seed, frame=HD.frame)
+    ref = sgpu.make_reference(HD.W, HD.H, seed=HD.seed + 1000, frame=HD.frame, spp=REFERENCE_SPP)
+    lam = torch.from_numpy(make_lambda(N_REGIONS, seed=LAMBDA_SEED)).cuda().requires_grad_(True)
+    rad.requires_grad_(True)
+
+    def step():
+        rad.grad = None
+        lam.grad = None
+        out = ops.RegionalFilter.apply(rad, feat, lam, HD.radius, N_REGIONS)
+        ops.MSELoss.apply(out, ref).backward()
+
+    for _ in range(warmup):
+        step()
+    ms = time_loop(torch.cuda.current_stream(), step, steps)
+    P = HD.W * HD.H
+    extra = P * HD.S * 12
+    del rad, feat, ref, lam
+    torch.cuda.empty_cache()
+    return {"workload": "torch autograd: RegionalFilter -> MSELoss -> backward, 1920x1080, 64 spp, 11x11 window",
+            "mpx_s": round(P / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
+            "materialised_grad_bytes": extra,
+            "note": "the per-sample gradient is written by autograd (expand of G accumulated into radiance.grad); "
+                    "the loss seed runs as its own kernel"}
 
 
 ADAPT_PROPOSALS = 1 << 24
@@ -638,6 +734,15 @@ def main():
         if args.only == "lens":
             print(json.dumps(measure_lens(args.steps, args.warmup, cpu=not args.no_cpu_baseline)), flush=True)
             return
+        if args.only == "small":
+            print(json.dumps(measure_small(args.steps, args.warmup, not args.no_tune)), flush=True)
+            return
+        if args.only == "leaf_grad":
+            print(json.dumps(measure_leaf_grad(args.steps, args.warmup)), flush=True)
+            return
+        if args.only == "copy":
+            print(json.dumps(measure_copy_ceiling(args.steps)), flush=True)
+            return
         if args.only == "quadtree":
             print(json.dumps(measure_quadtree(args.steps, args.warmup, cpu=not args.no_cpu_baseline)), flush=True)
             return
@@ -669,8 +774,10 @@ def main():
     torch.cuda.synchronize()
     step_ms_median = float(np.median([e[0].elapsed_time(e[1]) for e in ev]))
 
-    # unfused step (separate loss_seed kernel writing U), and forward only (stats + filter)
-    unfused_ms = time_loop(c.stream, lambda: c.step(fused=False), args.steps)
+    # the other forms of the step: plain forward + adjoint with the seed fused; separate
+    # loss_seed kernel writing U; forward only (stats + filter)
+    fused_ms = time_loop(c.stream, lambda: c.step(form="fused"), args.steps)
+    unfused_ms = time_loop(c.stream, lambda: c.step(form="unfused"), args.steps)
     fwd_only_ms = time_loop(c.stream, lambda: (c.stats(), c.forward()), args.steps)
 
     sb = stats_bytes(P, S)
@@ -696,12 +803,15 @@ def main():
                                f"{2 * r + 1}x{2 * r + 1} window, {N}x{N} regions",
                    "width": W, "height": H, "spp": S, "radius": r, "regions": N, "max_lag": MAX_LAG},
         "ms_per_step_median": round(step_ms_median, 4),
+        "step_form": "loss in the forward pass (stats -> filter with seed, loss, dL/dlambda -> radiance adjoint)",
         "fwd_mpx_s": round(P / (fwd_only_ms * 1e-3) / 1e6, 2),
+        "fused_adjoint_fwd_bwd_mpx_s": round(P / (fused_ms * 1e-3) / 1e6, 2),
         "unfused_fwd_bwd_mpx_s": round(P / (unfused_ms * 1e-3) / 1e6, 2),
         "fwd_ms": round(fwd_only_ms, 4),
         "stats_ms": round(stats_ms, 4),
-        "filter_forward_ms": round(fwd_ms - stats_ms, 4),
-        "filter_schedule": schedule_name(c.tabf[0].flags),
+        "filter_forward_with_loss_ms": round(fwd_ms - stats_ms, 4),
+        "filter_schedule": schedule_name(c.tabl[0].flags),
+        "filter_schedule_fwd_only": schedule_name(c.tabf[0].flags),
         "roofline": {
             "kernel": "stats_accumulate",
             "bound": "hbm",
@@ -718,13 +828,23 @@ def main():
         "step_hbm_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
 
+    one_thread = None
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(c.rad, c.feat, c.ref, c.lam, W, H, S, r, N, args.cpu_rows)
+        one_thread = cpu_baseline(c.rad, c.feat, c.ref, c.lam, W, H, S, r, N, args.cpu_rows)
     del c
     torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        par = cpu_baseline_parallel(W, H, S, r, N, HD.seed, HD.frame)
+        par["single_thread"] = {k: one_thread[k] for k in ("value", "unit", "sample", "seconds")}
+        result["cpu_baseline"] = par
+    result["copy_ceiling"] = measure_copy_ceiling(args.steps)
+    result["roofline"]["frac_of_copy_ceiling"] = round(achieved / result["copy_ceiling"]["copy_gbs"], 4)
 
     if not args.no_extra:
-        print("measuring the 32-frame batch and the 4K frame", file=sys.stderr, flush=True)
+        print("measuring the small frame, the autograd form, the 32-frame batch and the 4K frame", file=sys.stderr,
+              flush=True)
+        result["small"] = measure_small(args.steps, args.warmup, not args.no_tune)
+        result["leaf_grad"] = measure_leaf_grad(args.steps, args.warmup)
         result["batched"] = measure_batch32(args.steps, args.warmup, not args.no_tune)
         result["uhd"] = measure_uhd(args.steps, args.warmup, not args.no_tune)
         result["adapt"] = measure_adapt(args.steps, args.warmup, cpu=not args.no_cpu_baseline)
@@ -736,10 +856,10 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def _oracle_chain(rad_b, feat_b, ref_b, lam_h, S, r, N, W, H):
+def _oracle_chain(rad_b, feat_b, ref_b, lam_h, S, r, N, W, H, y0=0):
     import oracle
 
-    crop = dict(origin=(0, 0), image_size=(W, H))
+    crop = dict(origin=(0, y0), image_size=(W, H))
     st = oracle.stats_accumulate(rad_b, feat_b, 8)
     out, _ = oracle.filter_forward(st["mean"], lam_h, N, r, -30.0, **crop)
     _, U = oracle.mse_loss_seed(out, ref_b, count=3 * W * H)
@@ -779,6 +899,94 @@ def cpu_baseline(rad, feat, ref, lam, W, H, S, r, N, rows, target_s=15.0):
         "sample": f"rows 0..{rows - 1} of the {W}x{H} frame ({px} px, {S} spp, features), full "
                   f"stats+filter+loss+adjoint chain in numpy fp64 on one thread, {dt:.2f} s",
         "seconds": round(dt, 3),
+    }
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or "unknown"."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores(cap=16):
+    """Threads the CPU baseline may use: the CPU share of this process (at most ``cap``, the
+    share of one GPU on the GPU hosts)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, cap))
+
+
+def _band_worker(W, H, S, r, N, seed, frame, y0, y1, ref_spp, barrier, queue):
+    """One band of rows [y0, y1) of the frame: its inputs with a 2r-row halo on each side
+    (generated here, untimed), then the oracle chain on that crop, timed between two
+    barriers shared with the other bands."""
+    import numpy as np
+
+    from synth import numpy_gen
+    from synth.workloads import LAMBDA_SEED
+
+    a, b = max(0, y0 - 2 * r), min(H, y1 + 2 * r)
+    rad, feat = numpy_gen.make_frame(W, H, S, seed, frame, rows=(a, b))
+    ref = numpy_gen.make_reference(W, H, seed + 1000, frame, spp=ref_spp, rows=(a, b))
+    lam = numpy_gen.make_lambda(N, seed=LAMBDA_SEED).astype(np.float64)
+    barrier.wait()
+    t0 = time.monotonic()
+    _oracle_chain(rad, feat, ref, lam, S, r, N, W, H, y0=a)
+    queue.put((y0, y1, t0, time.monotonic()))
+
+
+def cpu_baseline_parallel(W, H, S, r, N, seed, frame, cores=None, ref_spp=64, timeout=600):
+    """The FP64 oracle, as it stands, band-parallel over the host cores: the frame's rows
+    split into one band per core, each band (plus the 2r-row halo its filter and adjoint
+    read) run through the whole chain (stats -> filter -> loss seed -> adjoint) by one
+    process, all bands timed together (wall clock from the first start to the last end).
+    The bands' inputs come from the NumPy twin of the input recipe (the reference from
+    ``ref_spp`` samples: the oracle's work does not depend on its values)."""
+    import multiprocessing as mp
+
+    cores = cores or host_cores()
+    ctx = mp.get_context("spawn")  # fresh interpreters: nothing of this process's GPU state
+    barrier = ctx.Barrier(cores)
+    queue = ctx.Queue()
+    edges = [round(i * H / cores) for i in range(cores + 1)]
+    procs = [ctx.Process(target=_band_worker, args=(W, H, S, r, N, seed, frame, edges[i], edges[i + 1], ref_spp,
+                                                    barrier, queue), daemon=True) for i in range(cores)]
+    for p in procs:
+        p.start()
+    import queue as _q
+
+    got = []
+    t_end = time.monotonic() + timeout
+    try:
+        while len(got) < cores:
+            try:
+                got.append(queue.get(timeout=2))
+            except _q.Empty:
+                dead = [p.exitcode for p in procs if p.exitcode not in (None, 0)]
+                if dead or time.monotonic() > t_end:
+                    raise RuntimeError(f"CPU baseline band failed (exit codes {dead})")
+    finally:
+        for p in procs:
+            p.join(timeout=30)
+            if p.is_alive():
+                p.kill()
+    wall = max(g[3] for g in got) - min(g[2] for g in got)
+    return {
+        "value": round(W * H / wall / 1e6, 5),
+        "unit": "Mpixel/s",
+        "cores": cores,
+        "cpu": cpu_model(),
+        "kind": "oracle",
+        "sample": f"the whole {W}x{H} frame ({W * H} px, {S} spp, features) in {cores} row bands, one process "
+                  f"each, full stats+filter+loss+adjoint chain in numpy fp64, {wall:.2f} s wall",
+        "seconds": round(wall, 3),
     }
 
 
