@@ -162,10 +162,13 @@ hipError_t launch_filter(bool bwd, const ramlt_frame *fh, const ramlt_frame *fd,
     float *lam_part;
     double *loss_part;
     partial_slots(ws, nt, &lam_part, &loss_part);
+    if (bwd && lif)  // the radiance adjoint alone: no partial sums
+      return launch_tiles(K.radiance[f.radius], K.fwd_block, nt, st, f, g, (const ramlt_frame *)nullptr,
+                          (BatchPlan *)nullptr, nt, (float *)nullptr, (double *)nullptr);
     hipError_t e = launch_tiles(bwd ? K.backward[f.radius] : K.forward_loss[f.radius], bwd ? K.block : K.fwd_block,
                                 nt, st, f, g, (const ramlt_frame *)nullptr, (BatchPlan *)nullptr, nt, lam_part,
                                 loss_part);
-    if (e != hipSuccess || (bwd && lif)) return e;  // the adjoint of such a frame leaves no partials
+    if (e != hipSuccess) return e;
     return launch_finalize(f, nullptr, nullptr, 1, f.n_regions, lam_part, loss_part, !bwd, st);
   }
   int groups[kMaxFilterGroups];
@@ -202,10 +205,15 @@ hipError_t launch_filter(bool bwd, const ramlt_frame *fh, const ramlt_frame *fd,
       if (e != hipSuccess) return e;
       continue;
     }
+    if (bwd && lif) {  // the radiance adjoint alone: no partial sums
+      e = launch_tiles(K.radiance_batched[radius], K.fwd_block, tiles, st, none, none_g, fd, plan, 0LL,
+                       (float *)nullptr, (double *)nullptr);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     e = launch_tiles(bwd ? K.backward_batched[radius] : K.forward_loss_batched[radius],
                      bwd ? K.block : K.fwd_block, tiles, st, none, none_g, fd, plan, 0LL, lam_part, loss_part);
     if (e != hipSuccess) return e;
-    if (bwd && lif) continue;
     e = launch_finalize(none, fd, plan, n, nmax, lam_part, loss_part, !bwd, st);
     if (e != hipSuccess) return e;
   }

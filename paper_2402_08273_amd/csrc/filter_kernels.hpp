@@ -543,9 +543,8 @@ __device__ __forceinline__ void backward_tile(const ramlt_frame &f, const TileGe
     }
   }
 
-  // ---- dL/dlambda_k(j) += beta_j sum_c U_jc (N2_jc - out_jc H2_j) / D_j (formed by the
-  // forward pass instead under RAMLT_LOSS_IN_FORWARD)
-  if (!f.grad_lambda || (f.flags & RAMLT_LOSS_IN_FORWARD)) return;
+  // ---- dL/dlambda_k(j) += beta_j sum_c U_jc (N2_jc - out_jc H2_j) / D_j
+  if (!f.grad_lambda) return;
   __syncthreads();  // stage and hb2 are reused below
   float4 *smu = stage;
   stage_halo<R, SH>(f, r.x0, r.y0, smu, [&](long long q) { return load3(f.mean, P, q); });
@@ -678,11 +677,12 @@ __device__ __forceinline__ void fetch_tile(const ramlt_frame &single, const Tile
 
 // ------------------------------------------------------------------------ forward
 // The forward tile, register-blocked. kFwdBlock threads per tile; thread u owns output
-// column u % TX and kFwdV consecutive output rows, so the column pass reads each row sum
-// once for kFwdV outputs, and a row-pass item covers 4 consecutive columns, so it reads each
-// staged mean once for 4 outputs. The mean halo and the row sums are held in LDS channel by
-// channel (structure of arrays, rows padded to a multiple of 4 floats), so a row-pass item
-// reads 4 columns of a channel with one 16-byte LDS read and lanes read consecutive words.
+// column u % TX and V consecutive output rows, so the column pass reads each row sum once for
+// V outputs, and a row-pass item covers 4 consecutive columns, so it reads each staged mean
+// once for 4 outputs. The mean halo is held in LDS channel by channel (structure of arrays,
+// rows padded to a multiple of 4 floats), so a row-pass item reads 4 columns of a channel
+// with one 16-byte LDS read and lanes read consecutive words; the passes run one channel at
+// a time, so only one channel's row sums take LDS space.
 // The sums are taken in the same order as a per-pixel gather: along x from -R to R, then
 // along y from -R to R.
 //
@@ -713,8 +713,11 @@ template <int R, class SH, bool LOSS>
 struct FwdLds {
   using G = FwdGeom<R, SH>;
   alignas(16) float stage[3 * G::PLANE];
-  alignas(16) float rows[(LOSS ? 6 : 3) * G::RPLANE];  // row sums: plain (3 channels), then d^2-weighted
+  alignas(16) float rows[(LOSS ? 2 : 1) * G::RPLANE];  // row sums of one channel: plain, then d^2-weighted
   float wtab[R + 1];
+  // a tile in one region: the in-image sums of w (and w d^2) along x for each output column
+  // and along y for each output row, so D = cx0 ry0 and H2 = cx2 ry0 + cx0 ry2
+  float cx0[G::TX], cx2[G::TX], ry0[G::TY], ry2[G::TY];
   double red[kFwdBlock / kWave];
 };
 
@@ -751,74 +754,63 @@ __device__ __forceinline__ void stage_mean_soa(const ramlt_frame &f, int x0, int
   }
 }
 
-// Row pass of a tile in one region: rows[c][hy][x] = sum_dx w(|dx|) mean_c(hy, x + dx) and,
-// with LOSS, rows[3 + c][hy][x] = sum_dx w(|dx|) dx^2 mean_c(hy, x + dx).
+// Row pass of channel c of a tile in one region: rows[0][hy][x] = sum_dx w(|dx|)
+// mean_c(hy, x + dx) and, with LOSS, rows[1][hy][x] = sum_dx w(|dx|) dx^2 mean_c(hy, x + dx).
 template <int R, class SH, bool LOSS>
 __device__ __forceinline__ void forward_rows(const float *stage, float *rows, const float (&w)[R + 1],
-                                             const float (&wd2)[R + 1]) {
+                                             const float (&wd2)[R + 1], int c) {
   using G = FwdGeom<R, SH>;
   constexpr int NG = G::TX / 4;
   for (int u = threadIdx.x; u < G::HY * NG; u += kFwdBlock) {
     const int hy = u / NG;
     const int x0 = 4 * (u - hy * NG);
+    const float4 *src = (const float4 *)(stage + c * G::PLANE + hy * G::HXP + x0);
+    float m[4 * G::NQ];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float4 *src = (const float4 *)(stage + c * G::PLANE + hy * G::HXP + x0);
-      float m[4 * G::NQ];
+    for (int q = 0; q < G::NQ; ++q) {
+      const float4 t = src[q];
+      m[4 * q] = t.x;
+      m[4 * q + 1] = t.y;
+      m[4 * q + 2] = t.z;
+      m[4 * q + 3] = t.w;
+    }
+    float a1[4] = {0.f, 0.f, 0.f, 0.f}, a2[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int q = 0; q < G::NQ; ++q) {
-        const float4 t = src[q];
-        m[4 * q] = t.x;
-        m[4 * q + 1] = t.y;
-        m[4 * q + 2] = t.z;
-        m[4 * q + 3] = t.w;
-      }
-      float a1[4] = {0.f, 0.f, 0.f, 0.f}, a2[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 4 + 2 * R; ++j) {
 #pragma unroll
-      for (int j = 0; j < 4 + 2 * R; ++j) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int d = j - k - R;  // tap offset of output x0 + k
-          if (d >= -R && d <= R) {
-            const int ad = d < 0 ? -d : d;
-            a1[k] = fmaf(w[ad], m[j], a1[k]);
-            if (LOSS) a2[k] = fmaf(wd2[ad], m[j], a2[k]);
-          }
+      for (int k = 0; k < 4; ++k) {
+        const int d = j - k - R;  // tap offset of output x0 + k
+        if (d >= -R && d <= R) {
+          const int ad = d < 0 ? -d : d;
+          a1[k] = fmaf(w[ad], m[j], a1[k]);
+          if (LOSS) a2[k] = fmaf(wd2[ad], m[j], a2[k]);
         }
       }
-      *(float4 *)(rows + c * G::RPLANE + hy * G::TX + x0) = make_float4(a1[0], a1[1], a1[2], a1[3]);
-      if (LOSS)
-        *(float4 *)(rows + (3 + c) * G::RPLANE + hy * G::TX + x0) = make_float4(a2[0], a2[1], a2[2], a2[3]);
     }
+    *(float4 *)(rows + hy * G::TX + x0) = make_float4(a1[0], a1[1], a1[2], a1[3]);
+    if (LOSS) *(float4 *)(rows + G::RPLANE + hy * G::TX + x0) = make_float4(a2[0], a2[1], a2[2], a2[3]);
   }
 }
 
-// Column pass for the thread's column tx and rows ty0 .. ty0 + V - 1: a[k][c] = sum_dy w(|dy|)
-// rows[c] and, with LOSS, n[k][c] = sum_dy w(|dy|) rows[3 + c] + w(|dy|) dy^2 rows[c].
+// Column pass of channel c for the thread's column tx and rows ty0 .. ty0 + V - 1: a[k] +=
+// sum_dy w(|dy|) rows[0] and, with LOSS, n[k] += sum_dy w(|dy|) rows[1] + w(|dy|) dy^2 rows[0].
 template <int R, class SH, bool LOSS>
 __device__ __forceinline__ void forward_columns(const float *rows, int tx, int ty0, const float (&w)[R + 1],
                                                 const float (&wd2)[R + 1], float (&a)[FwdGeom<R, SH>::V][3],
-                                                float (&n)[FwdGeom<R, SH>::V][3]) {
+                                                float (&n)[FwdGeom<R, SH>::V][3], int c) {
   using G = FwdGeom<R, SH>;
   constexpr int V = G::V;
 #pragma unroll
   for (int j = 0; j < V + 2 * R; ++j) {
-    float h1[3], h2[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      h1[c] = rows[c * G::RPLANE + (ty0 + j) * G::TX + tx];
-      h2[c] = LOSS ? rows[(3 + c) * G::RPLANE + (ty0 + j) * G::TX + tx] : 0.f;
-    }
+    const float h1 = rows[(ty0 + j) * G::TX + tx];
+    const float h2 = LOSS ? rows[G::RPLANE + (ty0 + j) * G::TX + tx] : 0.f;
 #pragma unroll
     for (int k = 0; k < V; ++k) {
       const int d = j - k - R;
       if (d >= -R && d <= R) {
         const int ad = d < 0 ? -d : d;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          a[k][c] = fmaf(w[ad], h1[c], a[k][c]);
-          if (LOSS) n[k][c] = fmaf(w[ad], h2[c], fmaf(wd2[ad], h1[c], n[k][c]));
-        }
+        a[k][c] = fmaf(w[ad], h1, a[k][c]);
+        if (LOSS) n[k][c] = fmaf(w[ad], h2, fmaf(wd2[ad], h1, n[k][c]));
       }
     }
   }
@@ -884,9 +876,29 @@ __global__ __launch_bounds__(kFwdBlock) void forward_kernel(const ramlt_frame si
   const int ty0 = (threadIdx.x / G::TX) * V;
   const int x = r.x0 + tx;
   stage_mean_soa<R, SH>(f, r.x0, r.y0, L.stage);
-  if (uniform && threadIdx.x <= R) {
-    const float beta = half_inv_var(f.lambda[tile_region(g, r)], f.lambda_min);
-    L.wtab[threadIdx.x] = threadIdx.x == 0 ? 1.0f : expf(-(float)(threadIdx.x * threadIdx.x) * beta);
+  // the tile's region, and (one region) its weights and per-column / per-row axis sums
+  const int k_tile = tile_region(g, r);
+  const float lam_tile = f.lambda[k_tile];
+  const float beta_tile = half_inv_var(lam_tile, f.lambda_min);
+  if (one_region) {
+    const int tt = threadIdx.x;
+    if (tt <= R) L.wtab[tt] = tt == 0 ? 1.0f : expf(-(float)(tt * tt) * beta_tile);
+    if (tt < G::TX + G::TY) {
+      float w[R + 1];
+      gauss_weights<R>(beta_tile, w);
+      const bool col = tt < G::TX;
+      const int c = col ? r.x0 + tt : r.y0 + (tt - G::TX);
+      const int n = col ? f.W : f.H;
+      const float s0 = axis_sum<R, 0>(w, window_sum<R>(w), c, n);
+      const float s2 = axis_sum<R, 2>(w, window_moment2<R>(w), c, n);
+      if (col) {
+        L.cx0[tt] = s0;
+        L.cx2[tt] = s2;
+      } else {
+        L.ry0[tt - G::TX] = s0;
+        L.ry2[tt - G::TX] = s2;
+      }
+    }
   }
   // the own pixels' reference values, in flight during the passes
   float ref[V][3];
@@ -909,39 +921,62 @@ __global__ __launch_bounds__(kFwdBlock) void forward_kernel(const ramlt_frame si
     for (int d = 0; d <= R; ++d) w[d] = L.wtab[d];
 #pragma unroll
     for (int d = 0; d <= R; ++d) wd2[d] = w[d] * (float)(d * d);
-    forward_rows<R, SH, LOSS>(L.stage, L.rows, w, wd2);
-    __syncthreads();
-    forward_columns<R, SH, LOSS>(L.rows, tx, ty0, w, wd2, a, n);
+    // channel by channel, so the row sums of one channel fit in LDS (more resident tiles)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (c > 0) __syncthreads();  // the previous channel's column pass is done with rows
+      forward_rows<R, SH, LOSS>(L.stage, L.rows, w, wd2, c);
+      __syncthreads();
+      forward_columns<R, SH, LOSS>(L.rows, tx, ty0, w, wd2, a, n, c);
+    }
   }
   double lacc = 0.0;
   float contrib = 0.f;
-  int k_last = tile_region(g, r);
-  bool live_last = false;
+  const bool live_tile = !(lam_tile < f.lambda_min);  // NaN counts as live: it reaches dL/dlambda
+  if (one_region && !uniform) {  // the direct schedule on a tile in one region: its weights
+#pragma unroll
+    for (int d = 0; d <= R; ++d) w[d] = L.wtab[d];
+#pragma unroll
+    for (int d = 0; d <= R; ++d) wd2[d] = w[d] * (float)(d * d);
+  }
 #pragma unroll
   for (int k = 0; k < V; ++k) {
-    const int y = r.y0 + ty0 + k;
+    const int ty = ty0 + k;
+    const int y = r.y0 + ty;
     const bool inside = x < r.x1 && y < r.y1;
-    const int kr = inside ? region_at(g, x, y) : tile_region(g, r);
-    const float lam = f.lambda[kr];
-    const bool live = !(lam < f.lambda_min);  // NaN counts as live: it reaches dL/dlambda
-    const float beta = half_inv_var(lam, f.lambda_min);
-    if (!uniform) {
+    int kr = k_tile;
+    bool live = live_tile;
+    float beta = beta_tile;
+    if (!one_region) {  // per-pixel region, weights and window sums
+      kr = inside ? region_at(g, x, y) : k_tile;
+      const float lam = f.lambda[kr];
+      live = !(lam < f.lambda_min);
+      beta = half_inv_var(lam, f.lambda_min);
       gauss_weights<R>(beta, w);
 #pragma unroll
       for (int d = 0; d <= R; ++d) wd2[d] = w[d] * (float)(d * d);
-      if (inside) forward_direct<R, SH, LOSS>(L.stage, tx, ty0 + k, w, wd2, a[k], n[k]);
     }
+    if (!uniform && inside) forward_direct<R, SH, LOSS>(L.stage, tx, ty, w, wd2, a[k], n[k]);
     float ck = 0.f;
     if (inside) {
-      const float Z0 = window_sum<R>(w);
-      const float sx0 = uniform ? axis_sum<R, 0>(w, Z0, x, f.W) : clipped_sum<R, 0>(w, x, f.W);
-      const float sy0 = uniform ? axis_sum<R, 0>(w, Z0, y, f.H) : clipped_sum<R, 0>(w, y, f.H);
+      // out is rounded on its own before out - R is formed (no fused multiply-add across
+      // them): U and the loss come from the value written to out
+#pragma clang fp contract(off)
+      float sx0, sy0;
+      if (one_region) {
+        sx0 = L.cx0[tx];
+        sy0 = L.ry0[ty];
+      } else {
+        sx0 = clipped_sum<R, 0>(w, x, f.W);
+        sy0 = clipped_sum<R, 0>(w, y, f.H);
+      }
       const float D = sx0 * sy0;
+      const float invD = 1.0f / D;
       const long long o = (long long)y * f.W + x;
       float out[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        out[c] = a[k][c] / D;
+        out[c] = a[k][c] * invD;
         f.out[c * P + o] = out[c];
       }
       if (LOSS) {
@@ -955,19 +990,23 @@ __global__ __launch_bounds__(kFwdBlock) void forward_kernel(const ramlt_frame si
           lacc = fma((double)dd, (double)dd, lacc);
         }
         if (live) {
-          const float Z2 = window_moment2<R>(w);
-          const float sx2 = axis_sum<R, 2>(w, Z2, x, f.W), sy2 = axis_sum<R, 2>(w, Z2, y, f.H);
+          float sx2, sy2;
+          if (one_region) {
+            sx2 = L.cx2[tx];
+            sy2 = L.ry2[ty];
+          } else {
+            sx2 = clipped_sum<R, 2>(w, x, f.W);
+            sy2 = clipped_sum<R, 2>(w, y, f.H);
+          }
           const float H2 = sx2 * sy0 + sx0 * sy2;
           const float tt = u[0] * (n[k][0] - out[0] * H2) + u[1] * (n[k][1] - out[1] * H2) +
                            u[2] * (n[k][2] - out[2] * H2);
-          ck = beta * tt / D;
+          ck = beta * tt * invD;
         }
       }
     }
     if (LOSS && !one_region && f.grad_lambda) reduce_lambda(f.grad_lambda, inside && live ? kr : -1, ck);
     contrib += ck;
-    k_last = kr;
-    live_last = live;
   }
   if (!LOSS) return;
   if (f.loss) {
@@ -984,9 +1023,305 @@ __global__ __launch_bounds__(kFwdBlock) void forward_kernel(const ramlt_frame si
     const double s = block_sum((double)contrib, L.red);
     if (threadIdx.x == 0) {
       if (lam_part && g.aligned)  // the finalize kernel reads region-aligned partials
-        lam_part[t] = live_last ? (float)s : 0.f;
-      else if (live_last)
-        unsafeAtomicAdd(f.grad_lambda + k_last, (float)s);
+        lam_part[t] = live_tile ? (float)s : 0.f;
+      else if (live_tile)
+        unsafeAtomicAdd(f.grad_lambda + k_tile, (float)s);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------ radiance adjoint
+// The radiance half of the adjoint on its own (RAMLT_LOSS_IN_FORWARD: the forward pass has
+// formed U, the loss and dL/dlambda), register-blocked like the forward: kFwdBlock threads,
+// V output rows per thread, 4 columns per row-pass item, channel planes in LDS.
+//   G_p = sum_{j : p in window(j)} a_j h_j(p - j),  a_j = U_j / (S D_j),
+// each source j with its own sigma. A region-aligned tile's outputs lie in one region column;
+// its window's sources lie in that column ("own") or in the <= R columns of a neighbouring
+// region column on either side ("strips"), in at most three region rows. G is the own
+// sources' separable sum (row pass with each source row's weights, then the column pass with
+// the same source row's weights) plus the strips' (row sums over the <= R strip columns for
+// the <= R output columns they reach, then the same column pass). Other tiles gather the
+// window directly, each source with its own weight.
+template <int R, class SH>
+struct AdjLds {
+  using G = FwdGeom<R, SH>;
+  static constexpr int RS = R > 0 ? R : 1;   // strip width
+  static constexpr int SPLANE = G::HY * RS;   // one channel of one strip
+  // the own row sums and the strip row sums (separable tiles), or the sources' beta log2(e)
+  // (direct gather): never both
+  static constexpr int SEPAUX = 3 * G::RPLANE + 2 * 3 * SPLANE;
+  static constexpr int AUX = SEPAUX > G::PLANE ? SEPAUX : G::PLANE;
+  alignas(16) float stage[3 * G::PLANE];     // a_j by channel
+  alignas(16) float aux[AUX];
+  float strip[2 * 3 * SPLANE];               // left / right strip sources, by channel
+  float tab[9 * (R + 1)];                    // weights of the (<= 3 x 3) regions around the tile
+  float ztab[9];                             // their full window sums
+  float inv_zz[9];                           // 1 / (S z^2): a_j / U_j of a source away from the border
+  int rowslot[G::HY];                        // region row of each halo row, from the first
+  int colslot[G::HX];                        // same for halo columns
+};
+
+template <int R, class SH, bool BATCH>
+__global__ __launch_bounds__(kFwdBlock) void radiance_adjoint_kernel(const ramlt_frame single,
+                                                                     const TileGeom single_g,
+                                                                     const ramlt_frame *__restrict__ frames,
+                                                                     BatchPlan *plan, long long ntiles, long long t0,
+                                                                     float *, double *) {
+  using G = FwdGeom<R, SH>;
+  using A = AdjLds<R, SH>;
+  constexpr int V = G::V, TX = G::TX, HX = G::HX, HY = G::HY, HXP = G::HXP;
+  constexpr int PLANE = G::PLANE, RS = A::RS, SPLANE = A::SPLANE;
+  __shared__ A L;
+  float *rows = L.aux;                  // own row sums by channel (separable)
+  float *srow = L.aux + 3 * G::RPLANE;  // left / right strip row sums by channel
+  float *tagp = L.aux;                  // beta log2(e) of every source (direct)
+  const long long total = BATCH ? (long long)plan->total_tiles : ntiles;
+  const long long t = t0 + xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= total) return;
+  ramlt_frame f;
+  TileGeom g;
+  Rect r;
+  fetch_tile<SH, BATCH>(single, single_g, frames, plan, t, f, g, r);
+  if (r.x0 >= r.x1 || r.y0 >= r.y1) return;  // block-uniform
+  const int W = f.W, H = f.H, N = f.n_regions;
+  const long long P = (long long)W * H;
+  const float invS = 1.0f / (float)f.S;
+
+  // region columns / rows reachable from the tile's window
+  const int gx_lo = max(r.x0 - R, 0), gx_hi = min(r.x1 + R, W) - 1;
+  const int gy_lo = max(r.y0 - R, 0), gy_hi = min(r.y1 + R, H) - 1;
+  const int kx_lo = cell_x(gx_lo, g), kx_hi = cell_x(gx_hi, g);
+  const int ky_lo = cell_y(gy_lo, g), nsy = cell_y(gy_hi, g) - ky_lo + 1;
+  const int kx_own = r.kx >= 0 ? r.kx : cell_x(r.x0, g);
+  const bool direct = (f.flags & RAMLT_SCHED_DIRECT) != 0;
+  // block-uniform: separable when the outputs share a region column and only one neighbour
+  // column lies within R on each side
+  const bool sep = tile_uniform(g, r) && !direct && kx_lo >= kx_own - 1 && kx_hi <= kx_own + 1 && nsy <= 3;
+  const int so = kx_own - kx_lo;  // own slot among the (<= 3) region columns
+  const int rs = region_begin(g, kx_own, W), re = region_begin(g, kx_own + 1, W);
+  const int nL = sep ? rs - gx_lo : 0;                    // left strip width (<= R)
+  const int nR = sep ? gx_hi + 1 - re : 0;                // right strip width (<= R)
+  const int mL = nL > 0 ? min(r.x1, rs + R) - r.x0 : 0;  // outputs the left strip reaches
+  const int xR0 = max(r.x0, re - R);                      // first output the right strip reaches
+  const int mR = nR > 0 ? r.x1 - xR0 : 0;
+
+  // U over tile + halo: every load first (clamped, in-bounds addresses)
+  constexpr int NIT = (HX * HY + kFwdBlock - 1) / kFwdBlock;
+  float4 uv[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int i = threadIdx.x + it * kFwdBlock;
+    const int hy = i / HX;
+    const int hx = i - hy * HX;
+    const int cx = min(max(r.x0 - R + hx, 0), W - 1);
+    const int cy = min(max(r.y0 - R + hy, 0), H - 1);
+    uv[it] = load3(f.grad_out, P, (long long)cy * W + cx);
+  }
+  if (sep) {
+    if (threadIdx.x < 9) {
+      const int sx = threadIdx.x % 3, sy = threadIdx.x / 3;
+      const int kx = min(kx_lo + sx, N - 1), ky = min(ky_lo + sy, N - 1);
+      const float beta = half_inv_var(f.lambda[ky * N + kx], f.lambda_min);
+      float w[R + 1];
+      gauss_weights<R>(beta, w);
+#pragma unroll
+      for (int d = 0; d <= R; ++d) L.tab[threadIdx.x * (R + 1) + d] = w[d];
+      const float z = window_sum<R>(w);
+      L.ztab[threadIdx.x] = z;
+      L.inv_zz[threadIdx.x] = invS / (z * z);
+    }
+    for (int i = threadIdx.x; i < HY; i += kFwdBlock)
+      L.rowslot[i] = cell_y(min(max(r.y0 - R + i, 0), H - 1), g) - ky_lo;
+    for (int i = threadIdx.x; i < HX; i += kFwdBlock)
+      L.colslot[i] = cell_x(min(max(r.x0 - R + i, 0), W - 1), g) - kx_lo;
+    __syncthreads();
+  }
+
+  // stage a_j = U_j / (S D_j): own-column sources in `stage` (others zero), neighbour
+  // columns in the strips; the direct path keeps every source, with beta log2(e)
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int i = threadIdx.x + it * kFwdBlock;
+    if (i < HX * HY) {
+      const int hy = i / HX;
+      const int hx = i - hy * HX;
+      const int gx = r.x0 - R + hx;
+      const int gy = r.y0 - R + hy;
+      float a[3] = {0.f, 0.f, 0.f};
+      float tag = 0.f;
+      if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+        float sc;  // 1 / (S D_j)
+        if (sep) {
+          const int sl = L.rowslot[hy] * 3 + L.colslot[hx];
+          if (gx < R || gx + R >= W || gy < R || gy + R >= H) {
+            const float z = L.ztab[sl];
+            float w[R + 1];
+#pragma unroll
+            for (int d = 0; d <= R; ++d) w[d] = L.tab[sl * (R + 1) + d];
+            sc = invS / (axis_sum<R, 0>(w, z, gx, W) * axis_sum<R, 0>(w, z, gy, H));
+          } else {
+            sc = L.inv_zz[sl];  // the full window: D = z^2
+          }
+        } else {
+          const float beta = half_inv_var(f.lambda[region_at(g, gx, gy)], f.lambda_min);
+          float w[R + 1];
+          gauss_weights<R>(beta, w);
+          sc = invS / (clipped_sum<R, 0>(w, gx, W) * clipped_sum<R, 0>(w, gy, H));
+          tag = beta * kLog2e;
+        }
+        a[0] = uv[it].x * sc;
+        a[1] = uv[it].y * sc;
+        a[2] = uv[it].z * sc;
+      }
+      if (sep) {  // every strip entry is written, zero for rows outside the image
+        int side = -1, col = 0;
+        if (gx < rs) {
+          if (gx >= rs - nL) side = 0, col = gx - (rs - nL);
+        } else if (gx >= re) {
+          if (gx < re + nR) side = 1, col = gx - re;
+        }
+        if (gx < rs || gx >= re) {
+          if (side >= 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) L.strip[(side * 3 + c) * SPLANE + hy * RS + col] = a[c];
+          }
+          a[0] = a[1] = a[2] = 0.f;
+        }
+      }
+      const int o = hy * HXP + hx;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) L.stage[c * PLANE + o] = a[c];
+      if (!sep) tagp[o] = tag;
+    }
+  }
+  __syncthreads();
+
+  const int tx = threadIdx.x % TX;
+  const int ty0 = (threadIdx.x / TX) * V;
+  const int x = r.x0 + tx;
+  float gacc[V][3];
+#pragma unroll
+  for (int k = 0; k < V; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gacc[k][c] = 0.f;
+  if (sep) {
+    // own row pass, 4 columns per item, each source row with its own region's weights
+    constexpr int NG = TX / 4;
+    for (int u = threadIdx.x; u < HY * NG; u += kFwdBlock) {
+      const int hy = u / NG;
+      const int x0 = 4 * (u - hy * NG);
+      const float *wt = L.tab + (L.rowslot[hy] * 3 + so) * (R + 1);
+      float w[R + 1];
+#pragma unroll
+      for (int d = 0; d <= R; ++d) w[d] = wt[d];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float4 *src = (const float4 *)(L.stage + c * PLANE + hy * HXP + x0);
+        float m[4 * G::NQ];
+#pragma unroll
+        for (int q = 0; q < G::NQ; ++q) {
+          const float4 v4 = src[q];
+          m[4 * q] = v4.x;
+          m[4 * q + 1] = v4.y;
+          m[4 * q + 2] = v4.z;
+          m[4 * q + 3] = v4.w;
+        }
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < 4 + 2 * R; ++j) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int d = j - k - R;
+            if (d >= -R && d <= R) acc[k] = fmaf(w[d < 0 ? -d : d], m[j], acc[k]);
+          }
+        }
+        *(float4 *)(rows + c * G::RPLANE + hy * TX + x0) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+      }
+    }
+    // strip row sums at the output columns each strip reaches
+    const int nLitems = HY * mL, nRitems = HY * mR;
+    for (int i = threadIdx.x; i < nLitems + nRitems; i += kFwdBlock) {
+      const bool left = i < nLitems;
+      const int ii = left ? i : i - nLitems;
+      const int m = left ? mL : mR;
+      const int hy = ii / m;
+      const int cc = ii - hy * m;
+      const float *wt = L.tab + (L.rowslot[hy] * 3 + (left ? so - 1 : so + 1)) * (R + 1);
+      const int xo = left ? r.x0 + cc : xR0 + cc;  // output column
+      const int s0 = left ? rs - nL : re;          // first strip column
+      const int ns = left ? nL : nR;
+      const int side = left ? 0 : 1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float *sp = L.strip + (side * 3 + c) * SPLANE + hy * RS;
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < RS; ++j) {
+          const int d = abs(s0 + j - xo);
+          if (j < ns && d <= R) acc = fmaf(wt[d], sp[j], acc);
+        }
+        srow[(side * 3 + c) * SPLANE + hy * RS + cc] = acc;
+      }
+    }
+    __syncthreads();
+    // column pass: V outputs per thread, each source row with its region's weights (not
+    // unrolled: the weights come from LDS per source row anyway, and unrolling lets every
+    // row's loads be hoisted, three times the registers)
+    const bool lreach = x - r.x0 < mL;                 // (mL <= the tile's width)
+    const bool rreach = mR > 0 && x >= xR0 && x < r.x1;
+#pragma unroll 1
+    for (int j = 0; j < V + 2 * R; ++j) {
+      const int hy = ty0 + j;
+      const int rb = L.rowslot[hy] * 3;
+      float ho[3], hl[3], hr[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        ho[c] = rows[c * G::RPLANE + hy * TX + tx];
+        hl[c] = lreach ? srow[c * SPLANE + hy * RS + (x - r.x0)] : 0.f;
+        hr[c] = rreach ? srow[(3 + c) * SPLANE + hy * RS + (x - xR0)] : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const int d = j - k - R;
+        if (d >= -R && d <= R) {
+          const int ad = d < 0 ? -d : d;
+          const float wo = L.tab[(rb + so) * (R + 1) + ad];
+          const float wl = lreach ? L.tab[(rb + so - 1) * (R + 1) + ad] : 0.f;
+          const float wr = rreach ? L.tab[(rb + so + 1) * (R + 1) + ad] : 0.f;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            gacc[k][c] = fmaf(wo, ho[c], gacc[k][c]);
+            if (lreach) gacc[k][c] = fmaf(wl, hl[c], gacc[k][c]);
+            if (rreach) gacc[k][c] = fmaf(wr, hr[c], gacc[k][c]);
+          }
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const int ty = ty0 + k;
+      if (x < r.x1 && r.y0 + ty < r.y1) {
+#pragma unroll
+        for (int dy = -R; dy <= R; ++dy) {
+          const int base = (ty + R + dy) * HXP + tx + R;
+#pragma unroll
+          for (int dx = -R; dx <= R; ++dx) {
+            const float h = __builtin_amdgcn_exp2f(-(float)(dx * dx + dy * dy) * tagp[base + dx]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gacc[k][c] = fmaf(h, L.stage[c * PLANE + base + dx], gacc[k][c]);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    const int y = r.y0 + ty0 + k;
+    if (x < r.x1 && y < r.y1) {
+      const long long o = (long long)y * W + x;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) f.grad_radiance[c * P + o] = gacc[k][c];
     }
   }
 }
@@ -1032,6 +1367,8 @@ struct KernelTables {
   static constexpr FwdLossKernel forward_loss_batched[kCount] = {forward_kernel<Rs, SH, true, true>...};
   static constexpr BwdKernel backward[kCount] = {backward_kernel<Rs, SH, false>...};
   static constexpr BwdKernel backward_batched[kCount] = {backward_kernel<Rs, SH, true>...};
+  static constexpr BwdKernel radiance[kCount] = {radiance_adjoint_kernel<Rs, SH, false>...};
+  static constexpr BwdKernel radiance_batched[kCount] = {radiance_adjoint_kernel<Rs, SH, true>...};
 };
 
 template <class SH>
@@ -1042,6 +1379,7 @@ struct KindKernels {
   const FwdKernel *forward, *forward_batched;
   const FwdLossKernel *forward_loss, *forward_loss_batched;
   const BwdKernel *backward, *backward_batched;
+  const BwdKernel *radiance, *radiance_batched;  // the radiance adjoint alone (loss in the forward pass)
   int block;      // threads per workgroup of the adjoint
   int fwd_block;  // of the forward
 };
@@ -1050,7 +1388,8 @@ template <class SH>
 KindKernels kind_kernels() {
   using T = TablesFor<SH>;
   return KindKernels{T::forward,  T::forward_batched,  T::forward_loss, T::forward_loss_batched,
-                     T::backward, T::backward_batched, SH::BLOCK, kFwdBlock};
+                     T::backward, T::backward_batched, T::radiance,     T::radiance_batched,
+                     SH::BLOCK,   kFwdBlock};
 }
 
 // The kernel tables of each tile kind, one per translation unit.

@@ -140,6 +140,9 @@ struct Raster {
 };
 
 __device__ __forceinline__ Raster raster_of(float wx, float wy, float wz, float tx, float ty, int W, int H) {
+  // HIP's *_rn helpers are plain operators here: the pragma keeps the compiler from fusing
+  // a product into the following sum
+#pragma clang fp contract(off)
   const float sx = __fadd_rn(0.5f, __fmul_rn(0.5f, __fdiv_rn(__fdiv_rn(wx, wz), tx)));
   const float sy = __fadd_rn(0.5f, __fmul_rn(0.5f, __fdiv_rn(__fdiv_rn(wy, wz), ty)));
   Raster r;
