@@ -683,8 +683,9 @@ __device__ __forceinline__ void fetch_tile(const ramlt_frame &single, const Tile
 // rows padded to a multiple of 4 floats), so a row-pass item reads 4 columns of a channel
 // with one 16-byte LDS read and lanes read consecutive words; the passes run one channel at
 // a time, so only one channel's row sums take LDS space.
-// The sums are taken in the same order as a per-pixel gather: along x from -R to R, then
-// along y from -R to R.
+// The plain sums are taken in the same order as a per-pixel gather: along x from -R to R,
+// then along y from -R to R; with the loss, the taps at -d and +d are added first (the
+// plain and d^2-weighted sums share those pairs).
 //
 // With LOSS (RAMLT_LOSS_IN_FORWARD) the tile also forms the MSE seed U_j = 2 (out_j - R_j)
 // / (3P) and the parameter adjoint
@@ -775,15 +776,25 @@ __device__ __forceinline__ void forward_rows(const float *stage, float *rows, co
       m[4 * q + 3] = t.w;
     }
     float a1[4] = {0.f, 0.f, 0.f, 0.f}, a2[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int j = 0; j < 4 + 2 * R; ++j) {
+    if (LOSS) {
+      // the two sums share the tap pairs m(x - d) + m(x + d) (w and w d^2 are even in d)
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int d = j - k - R;  // tap offset of output x0 + k
-        if (d >= -R && d <= R) {
-          const int ad = d < 0 ? -d : d;
-          a1[k] = fmaf(w[ad], m[j], a1[k]);
-          if (LOSS) a2[k] = fmaf(wd2[ad], m[j], a2[k]);
+        a1[k] = w[0] * m[k + R];
+#pragma unroll
+        for (int d = 1; d <= R; ++d) {
+          const float pr = m[k + R - d] + m[k + R + d];
+          a1[k] = fmaf(w[d], pr, a1[k]);
+          a2[k] = fmaf(wd2[d], pr, a2[k]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4 + 2 * R; ++j) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int d = j - k - R;  // tap offset of output x0 + k
+          if (d >= -R && d <= R) a1[k] = fmaf(w[d < 0 ? -d : d], m[j], a1[k]);
         }
       }
     }
@@ -800,18 +811,36 @@ __device__ __forceinline__ void forward_columns(const float *rows, int tx, int t
                                                 float (&n)[FwdGeom<R, SH>::V][3], int c) {
   using G = FwdGeom<R, SH>;
   constexpr int V = G::V;
+  if (LOSS) {
+    // tap pairs of rows ty0 + k + R -+ d share w(d) and w(d) d^2
+    float h1[V + 2 * R], h2[V + 2 * R];
+#pragma unroll
+    for (int j = 0; j < V + 2 * R; ++j) {
+      h1[j] = rows[(ty0 + j) * G::TX + tx];
+      h2[j] = rows[G::RPLANE + (ty0 + j) * G::TX + tx];
+    }
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      float ak = w[0] * h1[k + R], nk = w[0] * h2[k + R];
+#pragma unroll
+      for (int d = 1; d <= R; ++d) {
+        const float p1 = h1[k + R - d] + h1[k + R + d];
+        const float p2 = h2[k + R - d] + h2[k + R + d];
+        ak = fmaf(w[d], p1, ak);
+        nk = fmaf(w[d], p2, fmaf(wd2[d], p1, nk));
+      }
+      a[k][c] = ak;
+      n[k][c] = nk;
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < V + 2 * R; ++j) {
     const float h1 = rows[(ty0 + j) * G::TX + tx];
-    const float h2 = LOSS ? rows[G::RPLANE + (ty0 + j) * G::TX + tx] : 0.f;
 #pragma unroll
     for (int k = 0; k < V; ++k) {
       const int d = j - k - R;
-      if (d >= -R && d <= R) {
-        const int ad = d < 0 ? -d : d;
-        a[k][c] = fmaf(w[ad], h1, a[k][c]);
-        if (LOSS) n[k][c] = fmaf(w[ad], h2, fmaf(wd2[ad], h1, n[k][c]));
-      }
+      if (d >= -R && d <= R) a[k][c] = fmaf(w[d < 0 ? -d : d], h1, a[k][c]);
     }
   }
 }
@@ -1057,6 +1086,7 @@ struct AdjLds {
   float tab[9 * (R + 1)];                    // weights of the (<= 3 x 3) regions around the tile
   float ztab[9];                             // their full window sums
   float inv_zz[9];                           // 1 / (S z^2): a_j / U_j of a source away from the border
+  float wrow[3 * G::HY * (R + 1)];           // by halo row: the weights of its own / left / right region
   int rowslot[G::HY];                        // region row of each halo row, from the first
   int colslot[G::HX];                        // same for halo columns
 };
@@ -1194,6 +1224,16 @@ __global__ __launch_bounds__(kFwdBlock) void radiance_adjoint_kernel(const ramlt
       if (!sep) tagp[o] = tag;
     }
   }
+  if (sep) {  // each halo row's weights for the own column and the two strips
+    for (int i = threadIdx.x; i < 3 * HY * (R + 1); i += kFwdBlock) {
+      const int side = i / (HY * (R + 1));  // 0 own, 1 left, 2 right
+      const int rest = i - side * HY * (R + 1);
+      const int hy = rest / (R + 1);
+      const int d = rest - hy * (R + 1);
+      const int col = side == 0 ? so : (side == 1 ? so - 1 : so + 1);
+      L.wrow[i] = (col >= 0 && col < 3) ? L.tab[(L.rowslot[hy] * 3 + col) * (R + 1) + d] : 0.f;
+    }
+  }
   __syncthreads();
 
   const int tx = threadIdx.x % TX;
@@ -1264,35 +1304,56 @@ __global__ __launch_bounds__(kFwdBlock) void radiance_adjoint_kernel(const ramlt
       }
     }
     __syncthreads();
-    // column pass: V outputs per thread, each source row with its region's weights (not
-    // unrolled: the weights come from LDS per source row anyway, and unrolling lets every
-    // row's loads be hoisted, three times the registers)
+    // column pass: V outputs per thread, each source row with its region's weights (from the
+    // per-row tables: with j and k unrolled every LDS address is the thread's base plus a
+    // constant); the strips only in waves with a lane they reach
     const bool lreach = x - r.x0 < mL;                 // (mL <= the tile's width)
     const bool rreach = mR > 0 && x >= xR0 && x < r.x1;
-#pragma unroll 1
-    for (int j = 0; j < V + 2 * R; ++j) {
-      const int hy = ty0 + j;
-      const int rb = L.rowslot[hy] * 3;
-      float ho[3], hl[3], hr[3];
+    constexpr int NJ = V + 2 * R;
+    {
+      float wj[NJ][V];  // own-column weight of source row ty0 + j for output row ty0 + k
+      const float *wb = L.wrow + ty0 * (R + 1);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          const int d = j - k - R;
+          wj[j][k] = (d >= -R && d <= R) ? wb[j * (R + 1) + (d < 0 ? -d : d)] : 0.f;
+        }
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        ho[c] = rows[c * G::RPLANE + hy * TX + tx];
-        hl[c] = lreach ? srow[c * SPLANE + hy * RS + (x - r.x0)] : 0.f;
-        hr[c] = rreach ? srow[(3 + c) * SPLANE + hy * RS + (x - xR0)] : 0.f;
+        const float *hb = rows + c * G::RPLANE + ty0 * TX + tx;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const float h = hb[j * TX];
+#pragma unroll
+          for (int k = 0; k < V; ++k) {
+            const int d = j - k - R;
+            if (d >= -R && d <= R) gacc[k][c] = fmaf(wj[j][k], h, gacc[k][c]);
+          }
+        }
       }
+    }
 #pragma unroll
-      for (int k = 0; k < V; ++k) {
-        const int d = j - k - R;
-        if (d >= -R && d <= R) {
-          const int ad = d < 0 ? -d : d;
-          const float wo = L.tab[(rb + so) * (R + 1) + ad];
-          const float wl = lreach ? L.tab[(rb + so - 1) * (R + 1) + ad] : 0.f;
-          const float wr = rreach ? L.tab[(rb + so + 1) * (R + 1) + ad] : 0.f;
+    for (int side = 1; side <= 2; ++side) {
+      const bool reach = side == 1 ? lreach : rreach;
+      if (__ballot(reach) == 0ULL) continue;  // wave-uniform
+      const float *wb = L.wrow + (side * HY + ty0) * (R + 1);
+      const int col = side == 1 ? x - r.x0 : x - xR0;
+      const float *hb = srow + (side - 1) * 3 * SPLANE + ty0 * RS + (reach ? col : 0);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            gacc[k][c] = fmaf(wo, ho[c], gacc[k][c]);
-            if (lreach) gacc[k][c] = fmaf(wl, hl[c], gacc[k][c]);
-            if (rreach) gacc[k][c] = fmaf(wr, hr[c], gacc[k][c]);
+      for (int j = 0; j < NJ; ++j) {
+        float h[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) h[c] = reach ? hb[c * SPLANE + j * RS] : 0.f;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          const int d = j - k - R;
+          if (d >= -R && d <= R) {
+            // zero weight where the strip does not reach (a NaN weight times 0 is NaN)
+            const float wgt = reach ? wb[j * (R + 1) + (d < 0 ? -d : d)] : 0.f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gacc[k][c] = fmaf(wgt, h[c], gacc[k][c]);
           }
         }
       }
