@@ -49,9 +49,9 @@ def parse():
                    help="measure only the 32-frame batch or only the 4K frame and print that object "
                         "(for profiling one workload)")
     p.add_argument("--cpu-rows", type=int, default=0, help="rows of the frame the oracle times (0 = auto)")
-    p.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "stats_accumulate_traffic.txt"),
-                   help="rocprofv3 HBM byte count of the statistics kernel (JSON); ignored if the kernel "
-                        "source changed since it was taken")
+    p.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "hbm_traffic.json"),
+                   help="rocprofv3 HBM byte counts of the measured kernels (JSON records); a record is "
+                        "ignored if a source it names changed since it was taken")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of MIB MiB (counter calibration) and exit")
     return p.parse_args()
@@ -70,20 +70,25 @@ def calibrate_copy(mib):
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}), flush=True)
 
 
-def measured_traffic(path, W, H, S):
-    """HBM bytes per statistics launch from a committed rocprofv3 count, or None if the
-    count is for another workload or the kernel source has changed since."""
+TRAFFIC_RECORDS = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def measured_traffic(path, key):
+    """HBM bytes per launch of the kernel of workload ``key`` from the committed rocprofv3
+    counts (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration), or None if there is no
+    record for it or a source it names has changed since the counters were taken."""
     import hashlib
 
     if not path or not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    if (W, H, S) != (1920, 1080, 64):
-        return None
-    src = os.path.join(ROOT, rec["source"])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec["source_sha256_16"]:
-        return None
-    return rec["bytes_per_launch"]
+    for rec in json.load(open(path))["records"]:
+        if rec["key"] != key:
+            continue
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        return rec["bytes_per_launch"] if h.hexdigest()[:16] == rec["sources_sha256_16"] else None
+    return None
 
 
 def stats_bytes(P, S, feat_bytes=4):
@@ -235,8 +240,17 @@ def time_loop(stream, fn, steps):
     return t0.elapsed_time(t1) / steps
 
 
-def measure_uhd(steps, warmup, tune=True):
-    """The 3840x2160, 256 spp, fp16-feature frame with a 15x15 window: fused fwd+bwd step."""
+def stats_roofline(nbytes, ms, traffic, note):
+    """Roofline object of a statistics launch: algorithmic bytes over its duration (HIP
+    events on the launch stream) against 8 TB/s, and the committed counter bytes."""
+    r = hbm_roofline(nbytes, ms, note)
+    r["traffic"] = traffic
+    return r
+
+
+def measure_uhd(steps, warmup, tune=True, traffic_path=TRAFFIC_RECORDS):
+    """The 3840x2160, 256 spp, fp16-feature frame with a 15x15 window: fwd+bwd step (the loss
+    formed in the forward pass)."""
     import torch
 
     from paper_2402_08273_amd.tune import schedule_name
@@ -247,7 +261,9 @@ def measure_uhd(steps, warmup, tune=True):
         c.step()
     ms = time_loop(c.stream, c.step, steps)
     ms_fwd = time_loop(c.stream, lambda: (c.stats(), c.forward()), steps)
+    ms_stats = time_loop(c.stream, c.stats, steps)
     b = c.algorithmic_bytes()
+    sb = stats_bytes(c.P, c.S, c.feat_bytes)
     res = {
         "workload": f"stats+filter fwd+bwd, {UHD.W}x{UHD.H}, {UHD.S} spp, fp32 radiance + fp16 features, "
                     f"{2 * UHD.radius + 1}x{2 * UHD.radius + 1} window, {N_REGIONS}x{N_REGIONS} regions",
@@ -257,13 +273,16 @@ def measure_uhd(steps, warmup, tune=True):
         "algorithmic_bytes": b,
         "hbm_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "filter_schedule": schedule_name(c.tabl[0].flags),
+        "stats_ms": round(ms_stats, 4),
+        "roofline": stats_roofline(sb, ms_stats, measured_traffic(traffic_path, f"stats {UHD.W}x{UHD.H}x{UHD.S} fp16"),
+                                   "stats_kernel (one launch)"),
     }
     del c
     torch.cuda.empty_cache()
     return res
 
 
-def measure_batch32(steps, warmup, tune=True):
+def measure_batch32(steps, warmup, tune=True, traffic_path=TRAFFIC_RECORDS):
     """32 frames of uneven size and spp; each step is one HIP graph replay of one launch
     per operation over the whole batch (stats, filter, zeroing, fused loss seed + adjoint)."""
     import torch
@@ -290,8 +309,10 @@ def measure_batch32(steps, warmup, tune=True):
         b.replay()
     stream = torch.cuda.current_stream()
     ms = time_loop(stream, b.replay, steps)
+    ms_stats = time_loop(stream, b.stats, steps)  # the batched statistics launch alone (eager)
     P = sum(sp.W * sp.H for sp in specs)
     nbytes = sum(sample_bytes(sp) + sp.W * sp.H * (23 * 4 + FILTER_STEP_BYTES_PER_PX) for sp in specs)
+    sbytes = sum(sample_bytes(sp) + sp.W * sp.H * 23 * 4 for sp in specs)
     res = {
         "workload": "32 frames 256x256..2048x1152, spp {4,16,64,256}, fp32 radiance+features, 11x11 window, "
                     "20x20 regions; stats+filter fwd+bwd as one HIP graph replay per step",
@@ -303,6 +324,9 @@ def measure_batch32(steps, warmup, tune=True):
         "algorithmic_bytes": nbytes,
         "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "filter_schedule": schedule_name(b.table[0].flags),
+        "stats_ms": round(ms_stats, 4),
+        "roofline": stats_roofline(sbytes, ms_stats, measured_traffic(traffic_path, "stats batch32"),
+                                   "plan_kernel + stats_batched_kernel (the batch's statistics launch)"),
     }
     del b, frames
     torch.cuda.empty_cache()
@@ -782,7 +806,7 @@ def main():
 
     sb = stats_bytes(P, S)
     achieved = sb / (stats_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.traffic, W, H, S)
+    traffic = measured_traffic(args.traffic, f"stats {W}x{H}x{S}") if (W, H, S) == (HD.W, HD.H, HD.S) else None
     step_bytes = c.algorithmic_bytes()
 
     result = {

@@ -19,16 +19,25 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in run.stderr and run.stdout == ""
 
 
-def test_statistics_bytes_and_traffic_record():
+def test_statistics_bytes_and_traffic_records():
     P, S = 1920 * 1080, 64
     # every sample read once (3 radiance fp32 + 7 features) and 23 fp32 output planes
     assert bench.stats_bytes(P, S) == P * S * 40 + P * 23 * 4 == 5_499_187_200
     assert bench.stats_bytes(P, S, feat_bytes=2) == P * S * 26 + P * 23 * 4
-    path = os.path.join(ROOT, "profiles", "stats_accumulate_traffic.txt")
-    rec = json.load(open(path))
-    scaled = rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"]
-    assert rec["bytes_per_launch"] == int(scaled)
-    # the record counts for the 1080p workload and the current kernel source only
-    assert bench.measured_traffic(path, 1920, 1080, 64) == rec["bytes_per_launch"]
-    assert bench.measured_traffic(path, 3840, 2160, 256) is None
-    assert bench.measured_traffic("", 1920, 1080, 64) is None
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    data = json.load(open(path))
+    cal = data["copy_calibration"]
+    import hashlib
+
+    for rec in data["records"]:
+        # scaled counter bytes: FETCH_SIZE and WRITE_SIZE (KiB) times the copy calibration
+        scaled = rec["fetch_kib"] * 1024 * cal["fetch_scale"] + rec["write_kib"] * 1024 * cal["write_scale"]
+        assert rec["bytes_per_launch"] == int(scaled), rec["key"]
+        # a record counts for the kernel sources it was taken on only
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        same = h.hexdigest()[:16] == rec["sources_sha256_16"]
+        assert bench.measured_traffic(path, rec["key"]) == (rec["bytes_per_launch"] if same else None)
+    assert bench.measured_traffic(path, "no such workload") is None
+    assert bench.measured_traffic("", "stats 1920x1080x64") is None
