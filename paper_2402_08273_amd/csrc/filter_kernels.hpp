@@ -722,13 +722,15 @@ struct FwdLds {
   double red[kFwdBlock / kWave];
 };
 
-// Stage the mean over tile + halo, channel planes, zero outside the image. All loads are
-// issued before the first LDS store (addresses clamped into the image).
+// Stage the mean over tile + halo, channel planes, zero outside the image: the first hy_n
+// (<= HY) halo rows. All loads are issued before the first LDS store (addresses clamped
+// into the image).
 template <int R, class SH>
-__device__ __forceinline__ void stage_mean_soa(const ramlt_frame &f, int x0, int y0, float *stage) {
+__device__ __forceinline__ void stage_mean_soa(const ramlt_frame &f, int x0, int y0, int hy_n, float *stage) {
   using G = FwdGeom<R, SH>;
   constexpr int NIT = (G::HX * G::HY + kFwdBlock - 1) / kFwdBlock;
   const long long P = (long long)f.W * f.H;
+  const int n = G::HX * hy_n;
   float4 v[NIT];
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
@@ -737,12 +739,12 @@ __device__ __forceinline__ void stage_mean_soa(const ramlt_frame &f, int x0, int
     const int hx = i - hy * G::HX;
     const int cx = min(max(x0 - R + hx, 0), f.W - 1);
     const int cy = min(max(y0 - R + hy, 0), f.H - 1);
-    v[it] = load3(f.mean, P, (long long)cy * f.W + cx);
+    if (i < n) v[it] = load3(f.mean, P, (long long)cy * f.W + cx);
   }
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int i = threadIdx.x + it * kFwdBlock;
-    if (i < G::HX * G::HY) {
+    if (i < n) {
       const int hy = i / G::HX;
       const int hx = i - hy * G::HX;
       const int gx = x0 - R + hx, gy = y0 - R + hy;
@@ -755,14 +757,15 @@ __device__ __forceinline__ void stage_mean_soa(const ramlt_frame &f, int x0, int
   }
 }
 
-// Row pass of channel c of a tile in one region: rows[0][hy][x] = sum_dx w(|dx|)
-// mean_c(hy, x + dx) and, with LOSS, rows[1][hy][x] = sum_dx w(|dx|) dx^2 mean_c(hy, x + dx).
+// Row pass of channel c of a tile in one region, halo rows 0 .. hy_n - 1: rows[0][hy][x] =
+// sum_dx w(|dx|) mean_c(hy, x + dx) and, with LOSS, rows[1][hy][x] = sum_dx w(|dx|) dx^2
+// mean_c(hy, x + dx).
 template <int R, class SH, bool LOSS>
 __device__ __forceinline__ void forward_rows(const float *stage, float *rows, const float (&w)[R + 1],
-                                             const float (&wd2)[R + 1], int c) {
+                                             const float (&wd2)[R + 1], int c, int hy_n) {
   using G = FwdGeom<R, SH>;
   constexpr int NG = G::TX / 4;
-  for (int u = threadIdx.x; u < G::HY * NG; u += kFwdBlock) {
+  for (int u = threadIdx.x; u < hy_n * NG; u += kFwdBlock) {
     const int hy = u / NG;
     const int x0 = 4 * (u - hy * NG);
     const float4 *src = (const float4 *)(stage + c * G::PLANE + hy * G::HXP + x0);
@@ -904,7 +907,11 @@ __global__ __launch_bounds__(kFwdBlock) void forward_kernel(const ramlt_frame si
   const int tx = threadIdx.x % G::TX;
   const int ty0 = (threadIdx.x / G::TX) * V;
   const int x = r.x0 + tx;
-  stage_mean_soa<R, SH>(f, r.x0, r.y0, L.stage);
+  // a tile clipped at a region edge has fewer rows: only the halo rows its row groups read
+  // are staged and filtered, and row groups past its last row skip the column pass
+  const int nrows = r.y1 - r.y0;
+  const int hy_n = min(G::HY, (nrows + V - 1) / V * V + 2 * R);
+  stage_mean_soa<R, SH>(f, r.x0, r.y0, hy_n, L.stage);
   // the tile's region, and (one region) its weights and per-column / per-row axis sums
   const int k_tile = tile_region(g, r);
   const float lam_tile = f.lambda[k_tile];
@@ -954,9 +961,9 @@ __global__ __launch_bounds__(kFwdBlock) void forward_kernel(const ramlt_frame si
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (c > 0) __syncthreads();  // the previous channel's column pass is done with rows
-      forward_rows<R, SH, LOSS>(L.stage, L.rows, w, wd2, c);
+      forward_rows<R, SH, LOSS>(L.stage, L.rows, w, wd2, c, hy_n);
       __syncthreads();
-      forward_columns<R, SH, LOSS>(L.rows, tx, ty0, w, wd2, a, n, c);
+      if (ty0 < nrows) forward_columns<R, SH, LOSS>(L.rows, tx, ty0, w, wd2, a, n, c);
     }
   }
   double lacc = 0.0;
@@ -1134,6 +1141,11 @@ __global__ __launch_bounds__(kFwdBlock) void radiance_adjoint_kernel(const ramlt
   const int mL = nL > 0 ? min(r.x1, rs + R) - r.x0 : 0;  // outputs the left strip reaches
   const int xR0 = max(r.x0, re - R);                      // first output the right strip reaches
   const int mR = nR > 0 ? r.x1 - xR0 : 0;
+  // a tile clipped at a region edge has fewer rows: only the halo rows its row groups read
+  // are staged and summed, and row groups past its last row skip the column pass
+  const int nrows = r.y1 - r.y0;
+  const int hy_n = min(HY, (nrows + V - 1) / V * V + 2 * R);
+  const int nstage = HX * hy_n;
 
   // U over tile + halo: every load first (clamped, in-bounds addresses)
   constexpr int NIT = (HX * HY + kFwdBlock - 1) / kFwdBlock;
@@ -1145,7 +1157,7 @@ __global__ __launch_bounds__(kFwdBlock) void radiance_adjoint_kernel(const ramlt
     const int hx = i - hy * HX;
     const int cx = min(max(r.x0 - R + hx, 0), W - 1);
     const int cy = min(max(r.y0 - R + hy, 0), H - 1);
-    uv[it] = load3(f.grad_out, P, (long long)cy * W + cx);
+    if (i < nstage) uv[it] = load3(f.grad_out, P, (long long)cy * W + cx);
   }
   if (sep) {
     if (threadIdx.x < 9) {
@@ -1172,7 +1184,7 @@ __global__ __launch_bounds__(kFwdBlock) void radiance_adjoint_kernel(const ramlt
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int i = threadIdx.x + it * kFwdBlock;
-    if (i < HX * HY) {
+    if (i < nstage) {
       const int hy = i / HX;
       const int hx = i - hy * HX;
       const int gx = r.x0 - R + hx;
@@ -1247,7 +1259,7 @@ __global__ __launch_bounds__(kFwdBlock) void radiance_adjoint_kernel(const ramlt
   if (sep) {
     // own row pass, 4 columns per item, each source row with its own region's weights
     constexpr int NG = TX / 4;
-    for (int u = threadIdx.x; u < HY * NG; u += kFwdBlock) {
+    for (int u = threadIdx.x; u < hy_n * NG; u += kFwdBlock) {
       const int hy = u / NG;
       const int x0 = 4 * (u - hy * NG);
       const float *wt = L.tab + (L.rowslot[hy] * 3 + so) * (R + 1);
@@ -1279,7 +1291,7 @@ __global__ __launch_bounds__(kFwdBlock) void radiance_adjoint_kernel(const ramlt
       }
     }
     // strip row sums at the output columns each strip reaches
-    const int nLitems = HY * mL, nRitems = HY * mR;
+    const int nLitems = hy_n * mL, nRitems = hy_n * mR;
     for (int i = threadIdx.x; i < nLitems + nRitems; i += kFwdBlock) {
       const bool left = i < nLitems;
       const int ii = left ? i : i - nLitems;
@@ -1307,10 +1319,11 @@ __global__ __launch_bounds__(kFwdBlock) void radiance_adjoint_kernel(const ramlt
     // column pass: V outputs per thread, each source row with its region's weights (from the
     // per-row tables: with j and k unrolled every LDS address is the thread's base plus a
     // constant); the strips only in waves with a lane they reach
-    const bool lreach = x - r.x0 < mL;                 // (mL <= the tile's width)
-    const bool rreach = mR > 0 && x >= xR0 && x < r.x1;
+    const bool active = ty0 < nrows;
+    const bool lreach = active && x - r.x0 < mL;       // (mL <= the tile's width)
+    const bool rreach = active && mR > 0 && x >= xR0 && x < r.x1;
     constexpr int NJ = V + 2 * R;
-    {
+    if (active) {
       float wj[NJ][V];  // own-column weight of source row ty0 + j for output row ty0 + k
       const float *wb = L.wrow + ty0 * (R + 1);
 #pragma unroll
