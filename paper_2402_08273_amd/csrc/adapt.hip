@@ -17,6 +17,13 @@
 //      its updates gamma(n_k + w) sgn_w, with the clamp at lambda_min, in window order, and
 //      the visits after the last closed window become the pending sum.
 //
+// Keys of at most 9 bits (m < 512, e.g. the 2-D grid) sort in one pass, and the batch then
+// takes a shorter path: the pass writes only the sorted alphas (the digit bases of its scan
+// are the regions' first positions), one thread per closed window (windows numbered region
+// by region) sums it and forms its update gamma(n_k + w) sgn_w, and one workgroup per
+// region folds the updates. The sums, signs and updates are the same operations in the
+// same order as above, so both paths give the same state.
+//
 // Proposals with a region outside [0, m) get the key m and are sorted past every region;
 // step 3 never reads them.
 #include "launch.hpp"
@@ -96,8 +103,11 @@ __global__ __launch_bounds__(kScanBlock) void scan_rows_kernel(uint32_t *__restr
   if (threadIdx.x == kScanBlock - 1) totals[blockIdx.x] = part[kScanBlock - 1];
 }
 
+// With start (a single pass over keys 0..m, m < 2^BITS): the digit bases are the regions'
+// first sorted positions, start[k] for k = 0..m, and start[m + 1] = n.
 template <int BITS>
-__global__ __launch_bounds__(1 << BITS) void scan_digits_kernel(uint32_t *__restrict__ totals) {
+__global__ __launch_bounds__(1 << BITS) void scan_digits_kernel(uint32_t *__restrict__ totals,
+                                                                uint32_t *__restrict__ start, int m, long long n) {
   constexpr int kDigits = 1 << BITS;
   __shared__ uint32_t t[kDigits];
   t[threadIdx.x] = totals[threadIdx.x];
@@ -112,6 +122,10 @@ __global__ __launch_bounds__(1 << BITS) void scan_digits_kernel(uint32_t *__rest
   }
   __syncthreads();
   totals[threadIdx.x] = t[threadIdx.x];
+  if (start) {
+    if ((int)threadIdx.x <= m) start[threadIdx.x] = t[threadIdx.x];
+    if (threadIdx.x == 0) start[m + 1] = (uint32_t)n;
+  }
 }
 
 // Exclusive scan of v[0..kDigits) in place over the workgroup (each thread takes
@@ -156,7 +170,8 @@ __device__ __forceinline__ void block_exclusive_scan(uint32_t *v) {
 // of digits. The waves' counts then become per-digit offsets in wave order, and the
 // ranked proposals are placed in LDS in digit order and written out run by run, so
 // consecutive threads write consecutive addresses of one digit's destination range.
-template <int BITS>
+// KEYS false: only the values are written (the single pass of the small-grid path).
+template <int BITS, bool KEYS>
 __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(
     const int32_t *__restrict__ region, const float *__restrict__ alpha, const uint32_t *__restrict__ keys_in,
     const float *__restrict__ val_in, long long n, int m, int shift, const uint32_t *__restrict__ hist,
@@ -240,7 +255,7 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(
     const int d = (int)((k >> shift) & (kDigits - 1));
     const long long out = (long long)gbase[d] + (i - (int)lstart[d]);
     if (out < n) {  // always true for consistent histograms
-      keys_out[out] = k;
+      if (KEYS) keys_out[out] = k;
       val_out[out] = lval[i];
     }
   }
@@ -413,6 +428,185 @@ __global__ __launch_bounds__(kSortBlock) void region_update_wave_kernel(const ui
   }
 }
 
+// ---------------------------------------------------------------- small-grid path (m < 512)
+constexpr int kSmallGrid = 1 << kMaxDigitBits;  // regions of the single-pass path: m < kSmallGrid
+constexpr int kPlanBlock = kSmallGrid;
+
+// Windows closed by region k's visits in this batch (0 if the pending window stays open).
+__device__ __forceinline__ long long closed_windows(const RegionSpan &r, int L) {
+  const long long c = r.hi - r.lo;
+  return c < r.need0 ? 0 : 1 + (c - r.need0) / L;
+}
+
+// A window update is the map lambda -> max(lambda + A, C) (A = delta_w, C = lambda_min);
+// maps compose to the same form, (A1, C1) then (A2, C2) = (A1 + A2, max(C1 + A2, C2)), with
+// the identity (0, -inf). A region's closed windows are folded in chunks of kFoldChunk.
+constexpr int kFoldPer = 8;                         // windows per thread of a chunk
+constexpr int kFoldChunk = kSortBlock * kFoldPer;   // windows per chunk (one workgroup)
+
+struct WinMap {
+  double A, C;
+};
+__device__ __forceinline__ WinMap then(WinMap f, WinMap g) { return WinMap{f.A + g.A, fmax(f.C + g.A, g.C)}; }
+
+// wbase[k] = closed windows of the regions before k, wbase[m] = all of them; cbase the same
+// for the regions' chunks of windows (one workgroup, a thread per region; one scan of both
+// counts packed in 64 bits).
+__global__ __launch_bounds__(kPlanBlock) void window_plan_kernel(const uint32_t *__restrict__ start, long long n,
+                                                                 const ramlt_adapt_params p,
+                                                                 const ramlt_region_state s,
+                                                                 uint32_t *__restrict__ wbase,
+                                                                 uint32_t *__restrict__ cbase) {
+  __shared__ unsigned long long v[kPlanBlock];
+  const int k = threadIdx.x;
+  const int m = p.n_regions;
+  const unsigned long long nw = k < m ? (unsigned long long)closed_windows(region_span(start, n, k, p, s), p.L) : 0ull;
+  const unsigned long long own = (nw << 32) | ((nw + kFoldChunk - 1) / kFoldChunk);
+  v[k] = own;
+  __syncthreads();
+  for (int off = 1; off < kPlanBlock; off <<= 1) {  // inclusive scan
+    const unsigned long long add = k >= off ? v[k - off] : 0ull;
+    __syncthreads();
+    v[k] += add;
+    __syncthreads();
+  }
+  const unsigned long long ex = v[k] - own;
+  if (k < m) {
+    wbase[k] = (uint32_t)(ex >> 32);
+    cbase[k] = (uint32_t)ex;
+  }
+  if (k == m - 1) {
+    wbase[m] = (uint32_t)(v[k] >> 32);
+    cbase[m] = (uint32_t)v[k];
+  }
+}
+
+// One thread per closed window g (windows numbered region by region): its region k and
+// ordinal w from wbase, the window's acceptance sum in proposal order (fp64; the region's
+// first window continues the carried A_k), and its update gamma(n_k + w) sgn(alpha_hat -
+// alpha*) into delta[g].
+__global__ __launch_bounds__(kSortBlock) void window_sums_kernel(const uint32_t *__restrict__ start,
+                                                                 const uint32_t *__restrict__ wbase,
+                                                                 const float *__restrict__ alpha_sorted, long long n,
+                                                                 const ramlt_adapt_params p,
+                                                                 const ramlt_region_state s,
+                                                                 double *__restrict__ delta) {
+  __shared__ uint32_t wb[kSmallGrid + 1];
+  const int m = p.n_regions;
+  for (int i = threadIdx.x; i <= m; i += kSortBlock) wb[i] = wbase[i];
+  __syncthreads();
+  const uint32_t g = blockIdx.x * kSortBlock + threadIdx.x;
+  if (g >= wb[m]) return;
+  int lo = 0, hi = m - 1;  // the last region whose first window is <= g (it closes window g)
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (wb[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const int k = lo;
+  const long long w = (long long)(g - wb[k]);
+  const RegionSpan r = region_span(start, n, k, p, s);
+  const int L = p.L;
+  double a;
+  long long b, e;
+  if (w == 0) {
+    a = s.acc[k];
+    b = r.lo;
+    e = r.lo + r.need0 - 1;
+  } else {
+    a = 0.0;
+    b = r.lo + r.need0 + (w - 1) * L;
+    e = b + L - 1;
+  }
+#pragma unroll 8
+  for (long long q = b; q <= e; ++q) a += (double)alpha_sorted[q];
+  const double ahat = a / (double)L;
+  const int8_t sgn = (int8_t)((ahat > p.alpha_target) - (ahat < p.alpha_target));
+  delta[g] = window_delta(p, s.updates[k], w, sgn);
+}
+
+// One workgroup per chunk of a region's closed windows: each thread composes kFoldPer
+// consecutive windows in order, then the threads' maps are combined pairwise in a fixed
+// tree (neighbours first), and the chunk's map goes to chunk_map[c].
+__global__ __launch_bounds__(kSortBlock) void fold_chunks_kernel(const uint32_t *__restrict__ wbase,
+                                                                 const uint32_t *__restrict__ cbase,
+                                                                 const double *__restrict__ delta,
+                                                                 const ramlt_adapt_params p,
+                                                                 WinMap *__restrict__ chunk_map) {
+  __shared__ uint32_t cb[kSmallGrid + 1];
+  __shared__ WinMap red[kSortBlock];
+  const int m = p.n_regions;
+  for (int i = threadIdx.x; i <= m; i += kSortBlock) cb[i] = cbase[i];
+  __syncthreads();
+  const uint32_t c = blockIdx.x;
+  if (c >= cb[m]) return;  // block-uniform
+  int lo = 0, hi = m - 1;  // the region of chunk c
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cb[mid] <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  const int k = lo;
+  const long long w0 = (long long)(c - cb[k]) * kFoldChunk;
+  const long long nw = (long long)wbase[k + 1] - wbase[k];
+  const double *d = delta + wbase[k];
+  WinMap f{0.0, -INFINITY};
+  const long long b = w0 + (long long)threadIdx.x * kFoldPer;
+#pragma unroll
+  for (int j = 0; j < kFoldPer; ++j) {
+    if (b + j < nw) {
+      const double x = d[b + j];
+      f.A += x;
+      f.C = fmax(f.C + x, p.lambda_min);
+    }
+  }
+  red[threadIdx.x] = f;
+  __syncthreads();
+  for (int h = 1; h < kSortBlock; h <<= 1) {
+    if ((threadIdx.x & (2 * h - 1)) == 0) red[threadIdx.x] = then(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) chunk_map[c] = red[0];
+}
+
+// One thread per region: the chunk maps applied to lambda in order, the visits after the
+// last closed window summed into the new A_k / i_k (or, when no window closes, the visits
+// added to the pending A_k).
+__global__ __launch_bounds__(kSortBlock) void region_fold_kernel(const uint32_t *__restrict__ start,
+                                                                 const uint32_t *__restrict__ wbase,
+                                                                 const uint32_t *__restrict__ cbase,
+                                                                 const float *__restrict__ alpha_sorted, long long n,
+                                                                 const WinMap *__restrict__ chunk_map,
+                                                                 const ramlt_adapt_params p,
+                                                                 const ramlt_region_state s) {
+  const int k = blockIdx.x * kSortBlock + threadIdx.x;
+  if (k >= p.n_regions) return;
+  const RegionSpan r = region_span(start, n, k, p, s);
+  const long long c = r.hi - r.lo;
+  if (c < r.need0) {  // no window closes: only the pending sum grows
+    if (c > 0) {
+      double a = s.acc[k];
+      for (long long t = r.lo; t < r.hi; ++t) a += (double)alpha_sorted[t];
+      s.acc[k] = a;
+      s.visits[k] = r.i0 + (int)c;
+    }
+    if (s.lambda_f32) s.lambda_f32[k] = (float)s.lambda[k];
+    return;
+  }
+  const int L = p.L;
+  const long long nw = (long long)wbase[k + 1] - wbase[k];
+  const long long rem = (c - r.need0) % L;
+  double lam = s.lambda[k];
+  for (uint32_t j = cbase[k]; j < cbase[k + 1]; ++j) lam = fmax(lam + chunk_map[j].A, chunk_map[j].C);
+  double a = 0.0;
+  for (long long t = r.hi - rem; t < r.hi; ++t) a += (double)alpha_sorted[t];
+  s.acc[k] = a;
+  s.visits[k] = (int)rem;
+  s.lambda[k] = lam;
+  s.updates[k] = s.updates[k] + (int)nw;
+  if (s.lambda_f32) s.lambda_f32[k] = (float)lam;
+}
+
 // Passes and digit width of the sort for keys 0..m (m marks invalid proposals): 8-bit
 // digits, except that keys of exactly 9 bits (256 <= m < 512, e.g. a 20 x 20 grid) sort
 // in one 9-bit pass. A pass reads and writes the stream once, but wider digits cost
@@ -430,22 +624,30 @@ SortPlan sort_plan(int m) {
   return SortPlan{(bits + 7) / 8, 8};
 }
 
+// One pass of the sort; start non-null: the single pass of the small-grid path (values only,
+// region starts from the digit scan).
 template <int BITS>
 void launch_sort_pass(const int32_t *region, const float *alpha, const uint32_t *kin, const float *vin, long long n,
                       int m, int shift, uint32_t *hist, uint32_t *totals, int nblocks, uint32_t *kout, float *vout,
-                      hipStream_t st) {
+                      uint32_t *start, hipStream_t st) {
   hipLaunchKernelGGL(sort_hist_kernel<BITS>, dim3(nblocks), dim3(kSortBlock), 0, st, region, kin, n, m, shift, hist,
                      nblocks);
   hipLaunchKernelGGL(scan_rows_kernel, dim3(1 << BITS), dim3(kScanBlock), 0, st, hist, nblocks, totals);
-  hipLaunchKernelGGL(scan_digits_kernel<BITS>, dim3(1), dim3(1 << BITS), 0, st, totals);
-  hipLaunchKernelGGL(sort_scatter_kernel<BITS>, dim3(nblocks), dim3(kSortBlock), 0, st, region, alpha, kin, vin, n, m,
-                     shift, hist, totals, nblocks, kout, vout);
+  hipLaunchKernelGGL(scan_digits_kernel<BITS>, dim3(1), dim3(1 << BITS), 0, st, totals, start, m, n);
+  if (start)
+    hipLaunchKernelGGL((sort_scatter_kernel<BITS, false>), dim3(nblocks), dim3(kSortBlock), 0, st, region, alpha, kin,
+                       vin, n, m, shift, hist, totals, nblocks, kout, vout);
+  else
+    hipLaunchKernelGGL((sort_scatter_kernel<BITS, true>), dim3(nblocks), dim3(kSortBlock), 0, st, region, alpha, kin,
+                       vin, n, m, shift, hist, totals, nblocks, kout, vout);
 }
 
 struct AdaptWorkspace {
-  uint32_t *keys[2], *hist, *totals, *start, *big, *n_big;
+  uint32_t *keys[2], *hist, *totals, *start, *big, *n_big, *wbase, *cbase;
   float *vals[2];
-  int8_t *sign;   // sgn(alpha_hat - alpha*) at each window's closing position
+  int8_t *sign;    // sgn(alpha_hat - alpha*) at each window's closing position
+  double *delta;   // small-grid path: the update of each closed window, by window number
+  WinMap *chunk_map;  // small-grid path: the map of each chunk of a region's windows
   size_t bytes;
 };
 
@@ -472,6 +674,13 @@ AdaptWorkspace carve(void *ws, long long n, int m) {
   w.big = take((size_t)m * 4);
   w.n_big = take(4);
   w.sign = (int8_t *)take((size_t)n);
+  if (m < kSmallGrid) {
+    // closed windows <= n / L + m <= n + m; chunks <= (n + m) / kFoldChunk + m
+    w.wbase = take(((size_t)m + 1) * 4);
+    w.cbase = take(((size_t)m + 1) * 4);
+    w.delta = (double *)take(((size_t)n + (size_t)m) * 8);
+    w.chunk_map = (WinMap *)take((((size_t)n + (size_t)m) / kFoldChunk + (size_t)m + 1) * sizeof(WinMap));
+  }
   w.bytes = off;
   return w;
 }
@@ -490,6 +699,25 @@ hipError_t launch_region_adapt(const ramlt_adapt_params &p, const ramlt_region_s
   const AdaptWorkspace w = carve(ws, n, m);
   const int nblocks = (int)((n + kSortTile - 1) / kSortTile);
   const SortPlan plan = sort_plan(m);
+  if (m < kSmallGrid) {  // keys of at most 9 bits: one pass
+    if (plan.passes != 1) return hipErrorInvalidValue;  // (sort_plan gives one pass here)
+    if (plan.bits == 8)
+      launch_sort_pass<8>(region, alpha, nullptr, nullptr, n, m, 0, w.hist, w.totals, nblocks, nullptr, w.vals[0],
+                          w.start, st);
+    else
+      launch_sort_pass<9>(region, alpha, nullptr, nullptr, n, m, 0, w.hist, w.totals, nblocks, nullptr, w.vals[0],
+                          w.start, st);
+    hipLaunchKernelGGL(window_plan_kernel, dim3(1), dim3(kPlanBlock), 0, st, w.start, n, p, s, w.wbase, w.cbase);
+    // closed windows <= n / L + m, their chunks <= wmax / kFoldChunk + m
+    const long long wmax = n / p.L + m;
+    hipLaunchKernelGGL(window_sums_kernel, dim3((unsigned)((wmax + kSortBlock - 1) / kSortBlock)), dim3(kSortBlock),
+                       0, st, w.start, w.wbase, w.vals[0], n, p, s, w.delta);
+    hipLaunchKernelGGL(fold_chunks_kernel, dim3((unsigned)(wmax / kFoldChunk + m)), dim3(kSortBlock), 0, st, w.wbase,
+                       w.cbase, w.delta, p, w.chunk_map);
+    hipLaunchKernelGGL(region_fold_kernel, dim3((unsigned)((m + kSortBlock - 1) / kSortBlock)), dim3(kSortBlock), 0,
+                       st, w.start, w.wbase, w.cbase, w.vals[0], n, w.chunk_map, p, s);
+    return hipGetLastError();
+  }
   int cur = 0;  // buffers holding the keys of the previous pass (none before pass 0)
   for (int q = 0; q < plan.passes; ++q) {
     const uint32_t *kin = q ? w.keys[cur] : nullptr;
@@ -498,10 +726,10 @@ hipError_t launch_region_adapt(const ramlt_adapt_params &p, const ramlt_region_s
     const int shift = q * plan.bits;
     if (plan.bits == 8)
       launch_sort_pass<8>(region, alpha, kin, vin, n, m, shift, w.hist, w.totals, nblocks, w.keys[out], w.vals[out],
-                          st);
+                          nullptr, st);
     else
       launch_sort_pass<9>(region, alpha, kin, vin, n, m, shift, w.hist, w.totals, nblocks, w.keys[out], w.vals[out],
-                          st);
+                          nullptr, st);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     cur = out;

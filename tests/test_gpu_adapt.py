@@ -1,7 +1,8 @@
 """GPU parity of region_adapt (regional adaptation, Algorithm 1) against the sequential
 FP64 oracle: integer state and every update decision exactly, A_k exactly (the same fp64
 additions in the same order), lambda_k within the rounding bound of summing its updates
-in a different association (lambda_tol), on streams spanning one to three radix passes,
+in a different association (lambda_tol), on streams spanning one to three radix passes
+(both paths: the single-pass one of grids under 512 regions and the multi-pass one),
 several batches in a row, and the edge cases (L = 1, one region, out-of-range keys,
 acceptance exactly at the target, NaN acceptance, empty batches)."""
 
@@ -50,9 +51,13 @@ def _compare(name, ad, st, regions=None, updates_before=None, extra=0):
     assert np.array_equal(lam32, lam.astype(np.float32)), name
 
 
+# m < 512 takes the single-pass path (8-bit keys up to m = 255, 9-bit from 256 to 511);
+# m = 512 is the first grid of the multi-pass path
 @pytest.mark.parametrize("m,n,L,batches", [(1, 50, 1, 2), (5, 997, 2, 3), (400, 200_000, 10, 3),
                                            (3000, 150_000, 37, 2), (70_000, 300_000, 10, 2),
-                                           (20, 80_000, 64, 2), (20, 80_000, 65, 2), (7, 300_000, 1000, 2)])
+                                           (20, 80_000, 64, 2), (20, 80_000, 65, 2), (7, 300_000, 1000, 2),
+                                           (255, 100_000, 3, 2), (256, 100_000, 10, 2), (511, 100_000, 1, 2),
+                                           (512, 100_000, 10, 2)])
 def test_region_adapt_parity(m, n, L, batches):
     print(f"region_adapt parity m={m} n={n} L={L} batches={batches}", flush=True)
     ad = RegionAdapter(m, L=L)
