@@ -10,19 +10,20 @@
 //      histograms -> an exclusive scan (digit-major) -> a stable scatter that ranks equal
 //      digits by ballots (one per digit bit) and per-wave running counts in LDS;
 //   2. region boundaries: the first sorted position of every region;
-//   3. every position that closes a window of L visits sums that window (fp64, in
-//      proposal order, a region's first window continuing the carried A_k) and keeps
-//      sgn(alpha_hat - alpha*);
-//   4. one thread per region (a workgroup for regions closing more than 64 windows) folds
-//      its updates gamma(n_k + w) sgn_w, with the clamp at lambda_min, in window order, and
-//      the visits after the last closed window become the pending sum.
+//   3. one thread per region (a workgroup for regions closing more than 64 windows) sums
+//      each window of L visits it closes (fp64, in proposal order, the region's first
+//      window continuing the carried A_k), forms sgn(alpha_hat - alpha*) and the update
+//      gamma(n_k + w) sgn_w, folds the updates with the clamp at lambda_min in window order,
+//      and the visits after the last closed window become the pending sum.
 //
 // Keys of at most 9 bits (m < 512, e.g. the 2-D grid) sort in one pass, and the batch then
 // takes a shorter path: the pass writes only the sorted alphas (the digit bases of its scan
 // are the regions' first positions), one thread per closed window (windows numbered region
-// by region) sums it and forms its update gamma(n_k + w) sgn_w, and one workgroup per
-// region folds the updates. The sums, signs and updates are the same operations in the
-// same order as above, so both paths give the same state.
+// by region) sums it and forms its update, workgroups compose the updates of chunks of a
+// region's windows, and one thread per region applies its chunks in order. The window sums,
+// signs and updates are the same operations in the same order on both paths; the fold of
+// a region's updates into lambda_k is associated differently (within the same rounding
+// bound of the sequential fold).
 //
 // Proposals with a region outside [0, m) get the key m and are sorted past every region;
 // step 3 never reads them.
@@ -275,40 +276,6 @@ __global__ void region_starts_kernel(const uint32_t *__restrict__ keys, long lon
     for (long long k = cur + 1; k <= (long long)m + 1; ++k) start[k] = (uint32_t)n;
 }
 
-// Every sorted position that closes a window of L visits of its region computes that
-// window: its acceptance sum in proposal order (fp64; the region's first window continues
-// the carried A_k), alpha_hat, and sgn(alpha_hat - alpha*), stored as one byte (the fold
-// forms the update gamma(n_k + w) sgn itself: a sparse 8-byte array made every written
-// line a read-modify-write). Other positions are not written.
-__global__ void window_delta_kernel(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ start,
-                                    const float *__restrict__ alpha_sorted, long long n,
-                                    const ramlt_adapt_params p, const ramlt_region_state s,
-                                    int8_t *__restrict__ sign) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const uint32_t k = keys[t];
-  if ((int)k >= p.n_regions) return;  // out-of-range proposals, sorted last
-  const int L = p.L;
-  const long long r = t - (long long)start[k];  // visit number within the batch, from 0
-  const int i0 = pending_visits(s.visits[k], L);
-  const long long v = (long long)i0 + r + 1;    // visits of the pending window after this one
-  if (v % L != 0) return;
-  const long long w = v / L - 1;                 // window ordinal in this batch
-  double a;
-  long long b;
-  if (w == 0) {
-    a = s.acc[k];
-    b = start[k];
-  } else {
-    a = 0.0;
-    b = t - L + 1;
-  }
-#pragma unroll 8
-  for (long long q = b; q <= t; ++q) a += (double)alpha_sorted[q];  // loads issue ahead of the adds
-  const double ahat = a / (double)L;
-  sign[t] = (int8_t)((ahat > p.alpha_target) - (ahat < p.alpha_target));
-}
-
 // The update of window w of region k (eq. step_size_n, eq. update_lambda): gamma(n_k + w)
 // sgn_w, with n_k the region's update count at the start of the batch.
 __device__ __forceinline__ double window_delta(const ramlt_adapt_params &p, int n_k, long long w, int8_t sgn) {
@@ -332,6 +299,31 @@ __device__ __forceinline__ RegionSpan region_span(const uint32_t *start, long lo
   return r;
 }
 
+// The update of closed window w of region k: the window's acceptance sum in proposal order
+// (fp64; the region's first window continues the carried A_k), alpha_hat = sum / L, and
+// gamma(n_k + w) sgn(alpha_hat - alpha*).
+__device__ __forceinline__ double closed_window_update(const ramlt_adapt_params &p, const ramlt_region_state &s,
+                                                       const float *__restrict__ alpha_sorted, const RegionSpan &r,
+                                                       int k, int n_k, long long w) {
+  const int L = p.L;
+  double a;
+  long long b, e;
+  if (w == 0) {
+    a = s.acc[k];
+    b = r.lo;
+    e = r.lo + r.need0;
+  } else {
+    a = 0.0;
+    b = r.lo + r.need0 + (w - 1) * L;
+    e = b + L;
+  }
+#pragma unroll 8
+  for (long long q = b; q < e; ++q) a += (double)alpha_sorted[q];  // loads issue ahead of the adds
+  const double ahat = a / (double)L;
+  const int8_t sgn = (int8_t)((ahat > p.alpha_target) - (ahat < p.alpha_target));
+  return window_delta(p, n_k, w, sgn);
+}
+
 constexpr int kSmallWindows = 64;  // regions closing more windows go to the wave kernel
 
 // One thread per region. A region whose batch closes at most kSmallWindows windows is
@@ -340,8 +332,7 @@ constexpr int kSmallWindows = 64;  // regions closing more windows go to the wav
 // A_k / i_k. Larger regions are listed for region_update_wave_kernel (a workgroup each).
 __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_t *__restrict__ start,
                                                                    const float *__restrict__ alpha_sorted,
-                                                                   long long n, const int8_t *__restrict__ sign,
-                                                                   const ramlt_adapt_params p,
+                                                                   long long n, const ramlt_adapt_params p,
                                                                    const ramlt_region_state s,
                                                                    uint32_t *__restrict__ big,
                                                                    uint32_t *__restrict__ n_big) {
@@ -369,7 +360,7 @@ __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_
   const long long rem = (c - r.need0) % L;
   const int n_k = s.updates[k];
   for (long long w = 0; w < nw; ++w)
-    lam = fmax(lam + window_delta(p, n_k, w, sign[r.lo + r.need0 - 1 + w * L]), p.lambda_min);
+    lam = fmax(lam + closed_window_update(p, s, alpha_sorted, r, k, n_k, w), p.lambda_min);
   double a = 0.0;
   for (long long t = r.hi - rem; t < r.hi; ++t) a += (double)alpha_sorted[t];
   s.acc[k] = a;
@@ -385,8 +376,7 @@ __global__ __launch_bounds__(kSortBlock) void region_update_kernel(const uint32_
 // 0 applies the 256 block maps in thread order.
 __global__ __launch_bounds__(kSortBlock) void region_update_wave_kernel(const uint32_t *__restrict__ start,
                                                                         const float *__restrict__ alpha_sorted,
-                                                                        long long n, const int8_t *__restrict__ sign,
-                                                                        const ramlt_adapt_params p,
+                                                                        long long n, const ramlt_adapt_params p,
                                                                         const ramlt_region_state s,
                                                                         const uint32_t *__restrict__ big,
                                                                         const uint32_t *__restrict__ n_big) {
@@ -403,9 +393,8 @@ __global__ __launch_bounds__(kSortBlock) void region_update_wave_kernel(const ui
     double A = 0.0, C = -INFINITY;
     const long long w1 = min(nw, (long long)threadIdx.x * per), w2 = min(nw, w1 + per);
     const int n_k = s.updates[k];
-#pragma unroll 16
-    for (long long w = w1; w < w2; ++w) {  // loads issue ahead of the dependent fold
-      const double d = window_delta(p, n_k, w, sign[r.lo + r.need0 - 1 + w * L]);  // at the closing position
+    for (long long w = w1; w < w2; ++w) {
+      const double d = closed_window_update(p, s, alpha_sorted, r, k, n_k, w);
       A += d;
       C = fmax(C + d, p.lambda_min);
     }
@@ -482,9 +471,7 @@ __global__ __launch_bounds__(kPlanBlock) void window_plan_kernel(const uint32_t 
 }
 
 // One thread per closed window g (windows numbered region by region): its region k and
-// ordinal w from wbase, the window's acceptance sum in proposal order (fp64; the region's
-// first window continues the carried A_k), and its update gamma(n_k + w) sgn(alpha_hat -
-// alpha*) into delta[g].
+// ordinal w from wbase, and the window's update into delta[g].
 __global__ __launch_bounds__(kSortBlock) void window_sums_kernel(const uint32_t *__restrict__ start,
                                                                  const uint32_t *__restrict__ wbase,
                                                                  const float *__restrict__ alpha_sorted, long long n,
@@ -504,25 +491,8 @@ __global__ __launch_bounds__(kSortBlock) void window_sums_kernel(const uint32_t 
     else hi = mid - 1;
   }
   const int k = lo;
-  const long long w = (long long)(g - wb[k]);
   const RegionSpan r = region_span(start, n, k, p, s);
-  const int L = p.L;
-  double a;
-  long long b, e;
-  if (w == 0) {
-    a = s.acc[k];
-    b = r.lo;
-    e = r.lo + r.need0 - 1;
-  } else {
-    a = 0.0;
-    b = r.lo + r.need0 + (w - 1) * L;
-    e = b + L - 1;
-  }
-#pragma unroll 8
-  for (long long q = b; q <= e; ++q) a += (double)alpha_sorted[q];
-  const double ahat = a / (double)L;
-  const int8_t sgn = (int8_t)((ahat > p.alpha_target) - (ahat < p.alpha_target));
-  delta[g] = window_delta(p, s.updates[k], w, sgn);
+  delta[g] = closed_window_update(p, s, alpha_sorted, r, k, s.updates[k], (long long)(g - wb[k]));
 }
 
 // One workgroup per chunk of a region's closed windows: each thread composes kFoldPer
@@ -645,7 +615,6 @@ void launch_sort_pass(const int32_t *region, const float *alpha, const uint32_t 
 struct AdaptWorkspace {
   uint32_t *keys[2], *hist, *totals, *start, *big, *n_big, *wbase, *cbase;
   float *vals[2];
-  int8_t *sign;    // sgn(alpha_hat - alpha*) at each window's closing position
   double *delta;   // small-grid path: the update of each closed window, by window number
   WinMap *chunk_map;  // small-grid path: the map of each chunk of a region's windows
   size_t bytes;
@@ -673,7 +642,6 @@ AdaptWorkspace carve(void *ws, long long n, int m) {
   w.start = take(((size_t)m + 2) * 4);
   w.big = take((size_t)m * 4);
   w.n_big = take(4);
-  w.sign = (int8_t *)take((size_t)n);
   if (m < kSmallGrid) {
     // closed windows <= n / L + m <= n + m; chunks <= (n + m) / kFoldChunk + m
     w.wbase = take(((size_t)m + 1) * 4);
@@ -736,13 +704,11 @@ hipError_t launch_region_adapt(const ramlt_adapt_params &p, const ramlt_region_s
   }
   hipLaunchKernelGGL(region_starts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.keys[cur], n, m,
                      w.start, w.n_big);
-  hipLaunchKernelGGL(window_delta_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w.keys[cur], w.start,
-                     w.vals[cur], n, p, s, w.sign);
   hipLaunchKernelGGL(region_update_kernel, dim3((unsigned)((m + kSortBlock - 1) / kSortBlock)), dim3(kSortBlock), 0,
-                     st, w.start, w.vals[cur], n, w.sign, p, s, w.big, w.n_big);
+                     st, w.start, w.vals[cur], n, p, s, w.big, w.n_big);
   // large regions: at most n / (L kSmallWindows) of them; a fixed grid strides the list
-  hipLaunchKernelGGL(region_update_wave_kernel, dim3(256), dim3(kSortBlock), 0, st, w.start, w.vals[cur], n, w.sign,
-                     p, s, w.big, w.n_big);
+  hipLaunchKernelGGL(region_update_wave_kernel, dim3(256), dim3(kSortBlock), 0, st, w.start, w.vals[cur], n, p, s,
+                     w.big, w.n_big);
   return hipGetLastError();
 }
 
