@@ -218,12 +218,13 @@ class SingleChain:
         return stats_bytes(self.P, self.S, self.feat_bytes) + self.P * FILTER_STEP_BYTES_PER_PX
 
 
-def hbm_roofline(nbytes, ms, note):
+def hbm_roofline(nbytes, ms, note, traffic=None):
     """Roofline object of an operation bound by HBM: algorithmic bytes over the measured
-    time (HIP events around the operation's launches) against 8 TB/s."""
+    time (HIP events around the operation's launches) against 8 TB/s; ``traffic``: the
+    measured HBM bytes of the same launches, when a current record exists."""
     gbs = nbytes / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes": int(nbytes), "covers": note}
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "algorithmic_bytes": int(nbytes), "covers": note}
 
 
 def time_loop(stream, fn, steps):
@@ -413,7 +414,7 @@ ADAPT_PROPOSALS = 1 << 24
 ADAPT_REGION_COUNTS = (20 * 20, 20 * 20 * 50 * 50)  # the 2-D grid N_top^2; the 4-D grid N_top^2 N_bottom^2
 
 
-def measure_adapt(steps, warmup, cpu=True):
+def measure_adapt(steps, warmup, cpu=True, traffic_path=TRAFFIC_RECORDS):
     """region_adapt on 16 M proposals per batch (seeded stream of synth.proposals), for the
     paper's 2-D grid (400 regions) and 4-D grid (10^6 regions); one step = one batch.
     Algorithmic bytes: the proposals (region int32 + alpha float32 = 8 B each) and the
@@ -441,7 +442,9 @@ def measure_adapt(steps, warmup, cpu=True):
         out["grids"].append({"regions": m, "ms_per_batch": round(ms, 4),
                              "mproposals_s": round(n / (ms * 1e-3) / 1e6, 1), "algorithmic_bytes": nbytes,
                              "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                             "roofline": hbm_roofline(nbytes, ms, "all kernels of one region_adapt call")})
+                             "roofline": hbm_roofline(nbytes, ms, "all kernels of one region_adapt call",
+                                                      measured_traffic(traffic_path, f"region_adapt 16M {m}")
+                                                      if n == 1 << 24 else None)})
         del rd, ad_, ad
     if cpu:
         out["cpu_baseline"] = adapt_cpu_baseline()
