@@ -3,14 +3,17 @@ MI355X, at 1920x1080 with 64 spp (fp32 RGB radiance + albedo/normal/depth featur
 window (radius 5), 20x20 region grid.
 
 One step = the whole hot path over one frame already resident in HBM:
-  stats_accumulate -> filter_forward -> filter_backward with the MSE loss seed (vs a
-  4096-spp reference) fused in (gradients for every radiance sample and every region
-  parameter, and the loss).
+  stats_accumulate -> filter_forward forming out, the MSE loss seed U (vs a 4096-spp
+  reference), the loss and dL/dlambda -> filter_backward forming the gradient of every
+  radiance sample from U.
 `value` is filtered Mpixel/s of that fwd+bwd step. Reported beside it: the forward-only
-rate (stats + filter), the step with a separate loss_seed kernel, the 32-frame batch of
-uneven frames replayed as one HIP graph per step, and the 3840x2160 / 256 spp / fp16
-feature frame with a 15x15 window. Inputs are synthetic and seeded (synth/), generated on
-the GPU before timing.
+rate (stats + filter), the step with the seed fused into the adjoint or in a separate
+loss_seed kernel, the 32-frame batch of uneven frames replayed as one HIP graph per step,
+the 3840x2160 / 256 spp / fp16 feature frame with a 15x15 window, and the rows beyond the
+filter. Inputs are synthetic and seeded (synth/), generated on the GPU before timing.
+Timed regions are K back-to-back steps between two synchronisations (defaults K = 200,
+W = 20): a timed region carries a fixed start-up cost of about 1 ms on MI355X, which K
+spreads over the steps.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extra]
 """
@@ -33,8 +36,8 @@ def parse():
 
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--width", type=int, default=HD.W)
     p.add_argument("--height", type=int, default=HD.H)
     p.add_argument("--spp", type=int, default=HD.S)
@@ -159,6 +162,8 @@ class SingleChain:
             # the step, untimed here
             from paper_2402_08273_amd import tune as _tune
 
+            # statistics launch size, then the filter schedule on the frame's statistics
+            _tune.tune_stats(self.tabs)
             self.call0(self.lib.stats_accumulate, self.tabs)
             _tune.tune_table(self.tabf, zero=[self.acc])
             self.tabu[0].flags = self.tabf[0].flags
@@ -216,6 +221,21 @@ class SingleChain:
 
     def algorithmic_bytes(self):
         return stats_bytes(self.P, self.S, self.feat_bytes) + self.P * FILTER_STEP_BYTES_PER_PX
+
+
+def stats_launch_of(flags, table=None):
+    """Name of the statistics launch size held in a descriptor's flags (bits 4-7), and with
+    ``table`` the tuner's median time per candidate for that table's workload."""
+    from paper_2402_08273_amd import _abi
+    from paper_2402_08273_amd import tune as _tune
+
+    v = (flags & _abi.RAMLT_STATS_WG_MASK) >> _abi.RAMLT_STATS_WG_SHIFT
+    name = _tune.stats_launch_name(v) if v else "3 per CU (library default)"
+    if table is None:
+        return name
+    rec = _tune.TuneCache().record(_tune.stats_workload_key(table, _tune.device_arch()))
+    ms = {_tune.stats_launch_name(int(k)): t for k, t in (rec or {}).get("ms", {}).items()}
+    return {"chosen": name, "tuning_ms": ms}
 
 
 def hbm_roofline(nbytes, ms, note, traffic=None):
@@ -276,9 +296,10 @@ def measure_uhd(steps, warmup, tune=True, traffic_path=TRAFFIC_RECORDS):
         "algorithmic_bytes": b,
         "hbm_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "filter_schedule": schedule_name(c.tabl[0].flags),
+        "stats_launch": stats_launch_of(c.tabs[0].flags, c.tabs),
         "stats_ms": round(ms_stats, 4),
         "roofline": stats_roofline(sb, ms_stats, measured_traffic(traffic_path, f"stats {UHD.W}x{UHD.H}x{UHD.S} fp16"),
-                                   "stats_kernel (one launch)"),
+                                   "stats_kernel (the launches of one stats_accumulate call)"),
     }
     del c
     torch.cuda.empty_cache()
@@ -327,6 +348,7 @@ def measure_batch32(steps, warmup, tune=True, traffic_path=TRAFFIC_RECORDS):
         "algorithmic_bytes": nbytes,
         "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "filter_schedule": schedule_name(b.table[0].flags),
+        "stats_launch": stats_launch_of(b.table[0].flags, b.table),
         "stats_ms": round(ms_stats, 4),
         "roofline": stats_roofline(sbytes, ms_stats, measured_traffic(traffic_path, "stats batch32"),
                                    "plan_kernel + stats_batched_kernel (the batch's statistics launch)"),
@@ -843,6 +865,7 @@ def main():
         "radiance_adjoint_ms": round(adj_ms, 4),
         "filter_schedule": schedule_name(c.tabl[0].flags),
         "filter_schedule_fwd_only": schedule_name(c.tabf[0].flags),
+        "stats_launch": stats_launch_of(c.tabs[0].flags, c.tabs),
         "roofline": {
             "kernel": "stats_accumulate",
             "bound": "hbm",

@@ -32,6 +32,11 @@ RAMLT_TILE_64X8 = 3
 RAMLT_TILE_MASK = 3
 RAMLT_SCHED_DIRECT = 4
 RAMLT_LOSS_IN_FORWARD = 8  # the MSE seed and dL/dlambda in filter_forward; filter_backward: G only
+# stats_accumulate launch size: v workgroups per compute unit per launch (1..14), one launch
+# (15), or the default (0), in bits 4-7
+RAMLT_STATS_WG_SHIFT = 4
+RAMLT_STATS_WG_MASK = 15 << RAMLT_STATS_WG_SHIFT
+RAMLT_STATS_ONE_LAUNCH = 15
 TILE_SHAPES = {RAMLT_TILE_32X8: (32, 8), RAMLT_TILE_32X16: (32, 16), RAMLT_TILE_64X8: (64, 8)}
 
 OP_STATS = 0

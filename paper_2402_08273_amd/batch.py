@@ -129,16 +129,21 @@ class FrameBatch:
         self.ws_bytes = max(ws, 256)
 
     def tune(self, **kw):
-        """Choose the filter's launch schedule (tile shape, window schedule) for this batch
-        by timing the candidates on its own frames (:mod:`.tune`, cached by shape), write it
-        into every descriptor and rebuild the device table and workspace. Needs the
-        statistics of the frames (run ``stats()`` first); clears the gradient and loss
-        accumulators. Call before ``capture()``."""
+        """Choose the filter's launch schedule (tile shape, window schedule) and the
+        statistics pass's launch size for this batch by timing the candidates on its own
+        frames (:mod:`.tune`, cached by shape), write them into every descriptor and rebuild
+        the device table and workspace. Needs the statistics of the frames (run ``stats()``
+        first); clears the gradient and loss accumulators. Call before ``capture()``.
+        Returns the filter schedule; the statistics launch size is ``self.stats_launch``."""
         from . import tune as _tune
 
         if self._graph is not None:
             raise RuntimeError("tune() before capture()")
         best = _tune.tune_table(self.table, device=self.device, zero=self._grads + [self.loss], **kw)
+        self._upload()
+        self.stats_launch = _tune.tune_stats(self.table, device=self.device,
+                                             table_dev=self.table_dev if self.n > 1 else None,
+                                             cache=kw.get("cache"), force=kw.get("force", False))
         self._upload()
         return best
 

@@ -22,7 +22,15 @@
 //    compile-time bucket >= K_L and lags beyond K_L are computed but not written;
 //  * the 23 per-pixel results are parked in LDS and written after the pixel's last load,
 //    with the "sc1" store policy. Stores share the in-order outstanding-operation counter
-//    with loads, and measured mixed read/write streams on MI355X run fastest this way.
+//    with loads, and measured mixed read/write streams on MI355X run fastest this way;
+//  * a frame is covered by a series of launches of kStatsWgPerCu workgroups per compute
+//    unit each: every workgroup of a launch is resident from its start, so the launch's
+//    waves move through the sample planes together and read each plane over one
+//    contiguous span at a time. One launch over the whole frame lets resident workgroups
+//    drift apart by whole channels, and the same bytes took 9 % longer on MI355X.
+#include <algorithm>
+#include <atomic>
+
 #include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
@@ -35,6 +43,30 @@ constexpr int kStatsBlock = 256;
 static_assert(kStatsBlock == kStatsTilePixels, "one thread per pixel of a planned tile");
 constexpr int kParked = 9 + 14;  // radiance mean/var/tau x 3, feature mean/var x 7
 constexpr int kStoreSC1 = 16;    // buffer cache-policy operand: sc1
+// Workgroups per compute unit in one launch of the statistics pass (measured on MI355X at
+// 1080p, 64 spp: 2, 3, 4, 5 per CU took 0.893, 0.870, 0.880, 0.894 ms; launches whose
+// size is not a whole number per CU, 0.91-0.95 ms; one launch of the frame, 0.951 ms).
+constexpr int kStatsWgPerCu = 3;
+constexpr int kMaxDevices = 64;
+
+// Workgroups (tiles, or batched units) per launch on the current device for the launch
+// size field of a frame's flags: v per compute unit (kStatsWgPerCu for 0), or no limit
+// for RAMLT_STATS_ONE_LAUNCH. The CU count is read once per device.
+long long stats_launch_size(int32_t flags) {
+  int v = (flags & RAMLT_STATS_WG_MASK) >> RAMLT_STATS_WG_SHIFT;
+  if (v == RAMLT_STATS_ONE_LAUNCH) return 1LL << 40;
+  if (v == 0) v = kStatsWgPerCu;
+  static std::atomic<int> cached[kMaxDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 256LL * v;
+  int cus = cached[dev].load(std::memory_order_relaxed);
+  if (cus <= 0) {
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    cached[dev].store(cus, std::memory_order_relaxed);
+  }
+  return (long long)cus * v;
+}
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)0xFFFFFFFF, 0x00020000);
@@ -232,10 +264,11 @@ __device__ __forceinline__ void stats_tile(const ramlt_frame &f, long long pix0,
   }
 }
 
+// Tiles tile0 .. tile0 + gridDim.x - 1 of the frame.
 template <int KT, int B>
-__global__ __launch_bounds__(kStatsBlock) void stats_kernel(const ramlt_frame f) {
+__global__ __launch_bounds__(kStatsBlock) void stats_kernel(const ramlt_frame f, long long tile0) {
   __shared__ float park[kParked * kStatsBlock];
-  stats_tile<KT, B>(f, (long long)blockIdx.x * kStatsBlock, park);
+  stats_tile<KT, B>(f, (tile0 + blockIdx.x) * kStatsBlock, park);
 }
 
 // Batched form: one workgroup per planned work unit, frames in the plan's order (most
@@ -243,23 +276,23 @@ __global__ __launch_bounds__(kStatsBlock) void stats_kernel(const ramlt_frame f)
 // stats_unit_tiles(S) consecutive 256-pixel tiles, so frames with few samples per pixel
 // still give each workgroup a useful amount of data. (A persistent form popping units
 // from an atomic queue measured 6 % slower than this plain grid on a 32-frame batch.)
+// Units unit0 .. unit0 + gridDim.x - 1 of the plan.
 template <int KT, int B>
 __global__ __launch_bounds__(kStatsBlock) void stats_batched_kernel(const ramlt_frame *__restrict__ frames,
-                                                                    BatchPlan *plan) {
+                                                                    BatchPlan *plan, long long unit0) {
   __shared__ float park[kParked * kStatsBlock];
-  const unsigned long long total = plan->total_tiles;
-  for (unsigned long long t = blockIdx.x; t < total; t += gridDim.x) {  // one pass unless capped
-    int fi;
-    long long local;
-    plan_lookup(plan, t, &fi, &local);
-    const ramlt_frame f = frames[fi];
-    const long long P = (long long)f.W * f.H;
-    const int m = stats_unit_tiles(f.S);
-    for (int j = 0; j < m; ++j) {  // park entries are per thread: no barrier between tiles
-      const long long p0 = (local * m + j) * kStatsBlock;
-      if (p0 >= P) break;
-      stats_tile<KT, B>(f, p0, park);
-    }
+  const unsigned long long t = (unsigned long long)unit0 + blockIdx.x;
+  if (t >= plan->total_tiles) return;
+  int fi;
+  long long local;
+  plan_lookup(plan, t, &fi, &local);
+  const ramlt_frame f = frames[fi];
+  const long long P = (long long)f.W * f.H;
+  const int m = stats_unit_tiles(f.S);
+  for (int j = 0; j < m; ++j) {  // park entries are per thread: no barrier between tiles
+    const long long p0 = (local * m + j) * kStatsBlock;
+    if (p0 >= P) break;
+    stats_tile<KT, B>(f, p0, park);
   }
 }
 
@@ -275,11 +308,18 @@ int lag_bucket(int k) {
 
 template <int KT, int B>
 hipError_t launch_stats_kt(const ramlt_frame *fh, const ramlt_frame *fd, int n, void *ws, hipStream_t st) {
+  // (at most 2^22 workgroups per launch: 2^30 work-items)
+  const long long per_launch = std::min(stats_launch_size(fh[0].flags), 1LL << 22);
   if (n == 1) {
     const long long P = (long long)fh[0].W * fh[0].H;
-    const unsigned grid = (unsigned)((P + kStatsBlock - 1) / kStatsBlock);
-    hipLaunchKernelGGL((stats_kernel<KT, B>), dim3(grid), dim3(kStatsBlock), 0, st, fh[0]);
-    return hipGetLastError();
+    const long long tiles = (P + kStatsBlock - 1) / kStatsBlock;
+    for (long long t0 = 0; t0 < tiles; t0 += per_launch) {
+      const unsigned grid = (unsigned)(tiles - t0 < per_launch ? tiles - t0 : per_launch);
+      hipLaunchKernelGGL((stats_kernel<KT, B>), dim3(grid), dim3(kStatsBlock), 0, st, fh[0], t0);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
   BatchPlan *plan = (BatchPlan *)ws;
   hipError_t e = launch_plan(fd, n, RAMLT_OP_STATS, -1, plan, st);
@@ -289,9 +329,13 @@ hipError_t launch_stats_kt(const ramlt_frame *fh, const ramlt_frame *fd, int n, 
     const long long unit = (long long)kStatsTilePixels * stats_unit_tiles(fh[i].S);
     units += ((long long)fh[i].W * fh[i].H + unit - 1) / unit;
   }
-  const unsigned grid = (unsigned)(units < (1LL << 22) ? units : (1LL << 22));
-  hipLaunchKernelGGL((stats_batched_kernel<KT, B>), dim3(grid), dim3(kStatsBlock), 0, st, fd, plan);
-  return hipGetLastError();
+  for (long long u0 = 0; u0 < units; u0 += per_launch) {
+    const unsigned grid = (unsigned)(units - u0 < per_launch ? units - u0 : per_launch);
+    hipLaunchKernelGGL((stats_batched_kernel<KT, B>), dim3(grid), dim3(kStatsBlock), 0, st, fd, plan, u0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace

@@ -1,5 +1,6 @@
-"""Autotuner for the filter's launch schedule: output tile shape (32x8, 32x16, 64x8) and
-window schedule (separable rows-then-columns, or the direct (2r+1)^2 gather).
+"""Autotuner for the launch schedules: the filter's output tile shape (32x8, 32x16, 64x8)
+and window schedule (separable rows-then-columns, or the direct (2r+1)^2 gather), and the
+statistics pass's launch size (workgroups per compute unit per launch, or one launch).
 
 The schedule is a field of every frame descriptor (``ramlt_frame.flags``); it changes the
 launch, not the result beyond fp32 rounding order. The tuner times each candidate on the
@@ -28,6 +29,8 @@ CANDIDATES = (
     _abi.RAMLT_TILE_32X8 | _abi.RAMLT_SCHED_DIRECT,
 )
 SCHEDULE_BITS = _abi.RAMLT_TILE_MASK | _abi.RAMLT_SCHED_DIRECT
+# statistics launch sizes (workgroups per compute unit per launch; 15 = one launch)
+STATS_CANDIDATES = (2, 3, 4, 5, 6, 8, _abi.RAMLT_STATS_ONE_LAUNCH)
 
 _lock = threading.Lock()
 
@@ -62,8 +65,8 @@ class TuneCache:
     def record(self, key: str) -> Optional[dict]:
         return self._data.get(key)
 
-    def put(self, key: str, schedule: int, timings: Dict[int, float]):
-        self._data[key] = {"schedule": int(schedule), "name": schedule_name(schedule),
+    def put(self, key: str, schedule: int, timings: Dict[int, float], name: Optional[str] = None):
+        self._data[key] = {"schedule": int(schedule), "name": name or schedule_name(schedule),
                            "ms": {str(k): round(v, 5) for k, v in timings.items()}}
         with _lock:
             os.makedirs(os.path.dirname(self.path) or ".", exist_ok=True)
@@ -160,6 +163,65 @@ def _device_state(table, device):
         keep.append(w)
         ws_ptr = (w.data_ptr() + 255) // 256 * 256
     return table_dev, keep, ws_ptr, need
+
+
+def stats_workload_key(descs: Iterable, arch: str) -> str:
+    """Key of the statistics pass over a list of frame descriptors: architecture + each
+    frame's (W, H, S, feature dtype or none, maximum lag), in order."""
+    parts = []
+    for d in descs:
+        feat = "none" if not d.features else ("f16" if d.feat_dtype == _abi.RAMLT_F16 else "f32")
+        parts.append(f"{d.W}x{d.H}x{d.S}/{feat}/L{min(d.max_lag, d.S - 1)}")
+    return "stats|" + arch + "|" + ";".join(parts)
+
+
+def stats_launch_name(v: int) -> str:
+    return "one launch" if v == _abi.RAMLT_STATS_ONE_LAUNCH else f"{v} per CU"
+
+
+def tune_stats(table, stream=None, device=None, candidates: Sequence[int] = STATS_CANDIDATES, reps: int = 10,
+               warmup: int = 3, cache: Optional[TuneCache] = None, force: bool = False, table_dev=None) -> int:
+    """Pick the statistics pass's launch size for the frames of ``table`` (a ctypes array of
+    RamltFrame whose sample planes and statistics outputs are live on the device; for more
+    than one frame ``table_dev`` is the device copy of the table, which is rewritten for each
+    candidate): times stats_accumulate for every candidate, writes the winner into bits
+    4-7 of every descriptor's flags (the library reads the first) and returns it."""
+    device = torch.device(device or torch.cuda.current_device())
+    stream = stream or torch.cuda.current_stream(device)
+    cache = cache if cache is not None else TuneCache()
+    key = stats_workload_key(table, device_arch(device))
+    best = None if force else cache.get(key)
+    n = len(table)
+    if n > 1 and table_dev is None:
+        raise ValueError("a batch needs the device copy of its table")
+
+    def put(v):
+        for d in table:
+            d.flags = (d.flags & ~_abi.RAMLT_STATS_WG_MASK) | (v << _abi.RAMLT_STATS_WG_SHIFT)
+        if n > 1:
+            raw = bytes(ctypes.string_at(ctypes.addressof(table), ctypes.sizeof(table)))
+            table_dev.copy_(torch.frombuffer(bytearray(raw), dtype=torch.uint8))
+
+    if best is None:
+        lib = _abi.load()
+        need = _abi.workspace_size(list(table), _abi.OP_STATS)
+        w = torch.empty(need + 256, device=device, dtype=torch.uint8) if need else None
+        ws_ptr = (w.data_ptr() + 255) // 256 * 256 if need else None
+        dev_ptr = table_dev.data_ptr() if n > 1 else None
+        timings = {}
+        for cand in candidates:
+            put(cand)
+
+            def run():
+                st = lib.stats_accumulate(table, dev_ptr, n, ws_ptr, need, stream.cuda_stream)
+                if st != _abi.RAMLT_OK:
+                    raise _abi.RamltError(st, _abi.last_error())
+
+            timings[cand] = _median_ms(run, stream, reps, warmup)
+        best = min(timings, key=timings.get)
+        cache.put(key, best, timings, name=stats_launch_name(best))
+    put(best)
+    return best
 
 
 def tuned_schedule(W, H, S, radius, n_regions, device=None, cache: Optional[TuneCache] = None) -> int:

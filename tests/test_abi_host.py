@@ -111,7 +111,7 @@ def test_valid_arguments_reach_the_device_check(lib):
         (lambda f: setattr(f, "lag_corr", 0x40003), _abi.RAMLT_EINVAL),
         (lambda f: setattr(f, "rad_stride_y", 7), _abi.RAMLT_EINVAL),
         (lambda f: setattr(f, "rad_stride_s", 0), _abi.RAMLT_EINVAL),
-        (lambda f: setattr(f, "flags", 16), _abi.RAMLT_EINVAL),
+        (lambda f: setattr(f, "flags", 256), _abi.RAMLT_EINVAL),
         (lambda f: setattr(f, "flags", -1), _abi.RAMLT_EINVAL),
         (lambda f: (setattr(f, "H", 1 << 16), setattr(f, "rad_stride_y", 1 << 15)), _abi.RAMLT_EUNSUPPORTED),
         (lambda f: (setattr(f, "features", 0x100000), setattr(f, "feat_dtype", 7),
@@ -242,6 +242,13 @@ def test_schedule_flags(lib):
         f = _valid_filter_frame()
         f.flags = flags
         assert _status("filter_forward", [f]) in (_abi.RAMLT_EHIP, _abi.RAMLT_OK), flags
+    # every statistics launch size (bits 4-7) is valid for every operation; bit 8 is not
+    for v in range(16):
+        f = _valid_filter_frame()
+        f.flags = v << _abi.RAMLT_STATS_WG_SHIFT
+        assert _status("filter_forward", [f]) in (_abi.RAMLT_EHIP, _abi.RAMLT_OK), v
+        f.flags |= 1 << 8
+        assert _status("filter_forward", [f]) == _abi.RAMLT_EINVAL, v
     f = _valid_filter_frame()
     f.W, f.H, f.n_regions = 1920, 1080, 20
     base = _abi.workspace_size([f], _abi.OP_FILTER_BACKWARD)

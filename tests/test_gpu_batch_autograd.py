@@ -115,6 +115,26 @@ def test_batched_matches_single_frames_and_oracle():
     assert abs(_h(b.loss)[0] - loss_total) <= 1e-5 * loss_total
 
 
+def test_batched_stats_launch_sizes_give_the_same_results():
+    # the batch's work units run in launches of v workgroups per compute unit, or in one
+    # launch; the statistics are the same bits either way
+    lam_d = _dev(make_lambda(20, seed=99))
+    frames, _ = _batch_inputs(SPECS, lam_d)
+    b = FrameBatch(frames)
+    got = {}
+    for v in (1, 3, _abi.RAMLT_STATS_ONE_LAUNCH):
+        for d in b.table:
+            d.flags = (d.flags & ~_abi.RAMLT_STATS_WG_MASK) | (v << _abi.RAMLT_STATS_WG_SHIFT)
+        b._upload()
+        b.stats()
+        got[v] = [{k: _h(o[k]) for k in ("mean", "var", "tau", "feat_mean", "feat_var") if o.get(k) is not None}
+                  for o in b.outputs]
+    for v, frames_v in got.items():
+        for i, (a, ref) in enumerate(zip(frames_v, got[1])):
+            for k in ref:
+                assert np.array_equal(a[k], ref[k], equal_nan=True), (v, i, k)
+
+
 def test_batched_loss_in_forward_matches_oracle():
     # the six uneven frames (fp32 / fp16 / no features, S from 1 to 64, shared lambda and
     # gradient) with the loss formed in the forward launch
@@ -253,9 +273,15 @@ def test_tuned_batch_matches_oracle(tmp_path):
     b.stats()
     best = b.tune(cache=cache, reps=3, warmup=1)
     assert best in tune.CANDIDATES
-    assert all(d.flags == best for d in b.table)
+    assert all(d.flags & tune.SCHEDULE_BITS == best for d in b.table)
     key = tune.workload_key(b.table, tune.device_arch())
     assert cache.record(key)["schedule"] == best and len(cache.record(key)["ms"]) == len(tune.CANDIDATES)
+    # the statistics launch size, timed on the same frames, is in bits 4-7 of every descriptor
+    assert b.stats_launch in tune.STATS_CANDIDATES
+    assert all((d.flags & _abi.RAMLT_STATS_WG_MASK) >> _abi.RAMLT_STATS_WG_SHIFT == b.stats_launch for d in b.table)
+    skey = tune.stats_workload_key(b.table, tune.device_arch())
+    assert cache.record(skey)["schedule"] == b.stats_launch
+    assert len(cache.record(skey)["ms"]) == len(tune.STATS_CANDIDATES)
     b.step()
     torch.cuda.synchronize()
     gl_sum, gl_scale, loss_total = np.zeros(400), np.zeros(400), 0.0

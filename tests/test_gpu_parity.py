@@ -89,6 +89,26 @@ def test_stats_without_lag_output_and_features():
     _check_stats(rad, None, 8, st)
 
 
+def test_stats_launch_sizes_give_the_same_results():
+    # the frame's tiles run as a series of launches of v workgroups per compute unit (or one
+    # launch): 1172 tiles, the last one ragged; every launch size gives the same bits, and the
+    # default matches the oracle
+    W, H, S = 1000, 300, 8
+    print(f"stats launch sizes W={W} H={H} S={S}", flush=True)
+    rad, feats = make_frame(W, H, S, seed=21, noise=NOISE_UNIFORM, firefly_p=0.01)
+    rad_d, feat_d = _dev(rad), _dev(feats)
+    results = {}
+    for v in (0, 1, 2, 3, 5, _abi.RAMLT_STATS_ONE_LAUNCH):
+        f, out = ops.stats_frame(rad_d, feat_d, 4)
+        f.flags = v << _abi.RAMLT_STATS_WG_SHIFT
+        _abi.stats_accumulate([f], stream=torch.cuda.current_stream().cuda_stream)
+        results[v] = [_host(t) for t in out]
+    for v, arrs in results.items():
+        for name, a, b in zip(ops.Stats._fields, arrs, results[0]):
+            assert np.array_equal(a, b, equal_nan=True), (v, name)
+    _check_stats(rad, feats, 4, ops.Stats(*[torch.from_numpy(a) for a in results[0]]))
+
+
 def _filter_inputs(W, H, S, N, seed):
     rad, _ = make_frame(W, H, S, seed=seed, with_features=False)
     mean32 = oracle.stats_accumulate(rad, None, 0)["mean"].astype(np.float32)

@@ -35,3 +35,22 @@ def test_keys_and_names():
     # every candidate is a valid flags value and they are distinct
     assert len(set(tune.CANDIDATES)) == len(tune.CANDIDATES)
     assert all(c & ~(_abi.RAMLT_TILE_MASK | _abi.RAMLT_SCHED_DIRECT) == 0 for c in tune.CANDIDATES)
+
+
+def test_stats_keys_and_candidates():
+    a = _abi.RamltFrame()
+    a.W, a.H, a.S, a.max_lag = 3840, 2160, 256, 8
+    a.features, a.feat_dtype = 0x1000, _abi.RAMLT_F16
+    b = _abi.RamltFrame.from_buffer_copy(a)
+    b.features = None
+    assert tune.stats_workload_key([a], "gfx950") == "stats|gfx950|3840x2160x256/f16/L8"
+    assert tune.stats_workload_key([b], "gfx950") == "stats|gfx950|3840x2160x256/none/L8"
+    b.S = 4  # the lag is clipped to S - 1, as the library clips it
+    assert tune.stats_workload_key([b], "gfx950").endswith("/L3")
+    # launch sizes fit the 4-bit field, and none is the library default (0)
+    assert len(set(tune.STATS_CANDIDATES)) == len(tune.STATS_CANDIDATES)
+    assert all(1 <= v <= 15 for v in tune.STATS_CANDIDATES)
+    assert _abi.RAMLT_STATS_ONE_LAUNCH in tune.STATS_CANDIDATES
+    assert tune.stats_launch_name(15) == "one launch" and tune.stats_launch_name(3) == "3 per CU"
+    # the field does not overlap the filter schedule bits or the loss flag
+    assert _abi.RAMLT_STATS_WG_MASK & (tune.SCHEDULE_BITS | _abi.RAMLT_LOSS_IN_FORWARD) == 0
