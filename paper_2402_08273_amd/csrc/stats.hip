@@ -8,8 +8,8 @@
 //    x of one sample plane, so each wave load is a contiguous 256 B (fp32) run. Loads are
 //    non-temporal: the planes are streamed once;
 //  * channels are processed one after another and samples are streamed in register chunks
-//    of B, so the working set per thread stays small and several waves per SIMD keep loads
-//    in flight;
+//    (16 samples of radiance, 8 of an fp32 feature, 16 of an fp16 one), so the working set
+//    per thread stays small and several waves per SIMD keep loads in flight;
 //  * accumulation is fp64 about a shift K0 = the pixel's first sample, d_s = g_s - K0
 //    (exact for fp32 inputs). On CDNA4 fp64 FMA issues at the fp32 (non-packed) rate,
 //    so this costs registers, not time, and makes the one-pass formulas
@@ -43,10 +43,12 @@ constexpr int kStatsBlock = 256;
 static_assert(kStatsBlock == kStatsTilePixels, "one thread per pixel of a planned tile");
 constexpr int kParked = 9 + 14;  // radiance mean/var/tau x 3, feature mean/var x 7
 constexpr int kStoreSC1 = 16;    // buffer cache-policy operand: sc1
-// Workgroups per compute unit in one launch of the statistics pass (measured on MI355X at
-// 1080p, 64 spp: 2, 3, 4, 5 per CU took 0.893, 0.870, 0.880, 0.894 ms; launches whose
-// size is not a whole number per CU, 0.91-0.95 ms; one launch of the frame, 0.951 ms).
-constexpr int kStatsWgPerCu = 3;
+// Workgroups per compute unit in one launch of the statistics pass. Measured on MI355X at
+// 1080p, 64 spp (one box): 3, 4, 5, 8 per CU took 0.888, 0.864, 0.891, 0.891 ms, and one
+// launch of the frame 0.95 ms; launches whose size is not a whole number per CU,
+// 0.91-0.95 ms. With 16-sample chunks for the fp32 features as well, 3 per CU was best
+// (0.879 ms).
+constexpr int kStatsWgPerCu = 4;
 constexpr int kMaxDevices = 64;
 
 // Workgroups (tiles, or batched units) per launch on the current device for the launch
@@ -244,7 +246,7 @@ __device__ __forceinline__ void stats_tile(const ramlt_frame &f, long long pix0,
       const float *fb = (const float *)f.features;
 #pragma unroll 1
       for (int c = 0; c < RAMLT_N_FEATURES; ++c)
-        feature_channel<float, 16>(fb + c * f.feat_stride_c, f.feat_stride_s, foff, f.S, fpark + c * kStatsBlock);
+        feature_channel<float, 8>(fb + c * f.feat_stride_c, f.feat_stride_s, foff, f.S, fpark + c * kStatsBlock);
     }
   }
   // deferred result stores
