@@ -584,13 +584,39 @@ def measure_lens(steps, warmup, cpu=True):
     acc = float(alpha[ok].double().mean())
     nbytes = int(n * (44 + 12 * acc))
     gbs = nbytes / (ms * 1e-3) / 1e9
+
+    # the same chains regrouped by screen tile (lens_chain_sort, 48 B per chain: omega read
+    # twice, density read; omega, density and the old index written), then stepped with their
+    # noise regrouped the same way
+    ms_sort = time_loop(stream, lambda: ops.lens_chain_sort(om, W, H, tx, density=dens), steps)
+    om_s, dens_s, perm = ops.lens_chain_sort(om, W, H, tx, density=dens)
+    noise_s = noise[perm.long()].contiguous()
+
+    def step_sorted():
+        last["ra"] = ops.lens_chain_step(L, tx, ad.lam, N, om_s, noise_s, density=dens_s)
+
+    def loop_sorted():
+        step_sorted()
+        ad.step(*last["ra"])
+
+    for _ in range(warmup):
+        step_sorted()
+    ms_s = time_loop(stream, step_sorted, steps)
+    ms_loop_s = time_loop(stream, loop_sorted, steps)
+    gbs_s = nbytes / (ms_s * 1e-3) / 1e9
     out = {"workload": f"lens-perturbation chains, {n} chains, {W}x{H} luminance, {N}x{N} regions, "
-                       f"tan(fov/2) = {tx}",
-           "chains": n, "ms_per_step": round(ms, 4), "gchains_s": round(n / (ms * 1e-3) / 1e9, 2),
-           "ms_per_adaptive_step": round(ms_loop, 4), "mean_alpha": round(acc, 4), "algorithmic_bytes": nbytes,
-           "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-           "roofline": hbm_roofline(nbytes, ms, "scale_kernel + lens_step_kernel")}
-    del L, om, noise, ad, last, dens
+                       f"tan(fov/2) = {tx}; chains grouped by 256x256-pixel screen tile (lens_chain_sort)",
+           "chains": n, "ms_per_step": round(ms_s, 4), "gchains_s": round(n / (ms_s * 1e-3) / 1e9, 2),
+           "ms_per_adaptive_step": round(ms_loop_s, 4), "mean_alpha": round(acc, 4), "algorithmic_bytes": nbytes,
+           "achieved_gbs": round(gbs_s, 1), "hbm_frac": round(gbs_s / HBM_PEAK_GBS, 4),
+           "roofline": hbm_roofline(nbytes, ms_s, "scale_kernel + lens_step_kernel (chains in tile order)",
+                                    measured_traffic(TRAFFIC_RECORDS, "lens step 16M sorted")),
+           "sort_ms": round(ms_sort, 4), "sort_gbs": round(n * 48 / (ms_sort * 1e-3) / 1e9, 1),
+           "ms_per_step_sorting_every_16": round(ms_s + ms_sort / 16, 4),
+           "index_order": {"ms_per_step": round(ms, 4), "ms_per_adaptive_step": round(ms_loop, 4),
+                           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                           "traffic": measured_traffic(TRAFFIC_RECORDS, "lens step 16M index order")}}
+    del L, om, noise, ad, last, dens, om_s, dens_s, perm, noise_s
     if cpu:
         out["cpu_baseline"] = lens_cpu_baseline()
     torch.cuda.empty_cache()

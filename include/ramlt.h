@@ -27,7 +27,8 @@
  *                     angle of scale sigma_k = sqrt(exp(lambda_k)).
  *   rrmse             Sec. 8.2: relative RMS error map and image value.
  *   lens_chain_step   Sec. 3.3 / 6.1 / Alg. 1: one Metropolis step of screen-space chains
- *                     under the regional adaptive lens perturbation (luminance target).
+ *                     under the regional adaptive lens perturbation (luminance target);
+ *                     lens_chain_sort regroups the chains by screen tile between steps.
  *
  * Conventions shared by every entry point
  *   - All pointers inside ramlt_frame are DEVICE pointers into memory the caller owns
@@ -405,6 +406,31 @@ int lens_chain_step(const float *luminance, int32_t W, int32_t H, float tan_half
 
 /* Workspace bytes of lens_chain_step (0 for an invalid n_regions). */
 size_t ramlt_lens_workspace_size(int32_t n_regions);
+
+/* Reorder of lens chains by screen tile, for the locality of lens_chain_step's luminance
+ * reads. Not an operation of the paper: its chains are independent (Sec. 3.3, Sec. 7), so
+ * their order in memory is free, and chains grouped by where they are on the screen read a
+ * few KB of the image per workgroup instead of a cache line each.
+ * The key of chain i is the T x T pixel tile of its current pixel under lens_chain_step's
+ * raster map (tiles numbered row-major, tile = (iy / T) * ceil(W / T) + ix / T), or the tile
+ * count for a chain outside the frame or NaN; T = 2^s with s the smallest integer >= 4 that
+ * leaves at most 63 tiles (256 at 1920 x 1080, 512 at 3840 x 2160). The chains are written
+ * in key order, stably (chains of one tile keep their index order):
+ *   omega_out[j] = omega[perm[j]], density_out[j] = density[perm[j]], perm[j] = old index.
+ * omega: DEVICE float[n][3] (read); density: DEVICE float[n] or NULL (lens_chain_step's
+ * carried luminance, moved with its chain); omega_out: DEVICE float[n][3]; density_out:
+ * DEVICE float[n], required iff density is given; perm: DEVICE int32[n] or NULL (the old
+ * index of each chain, to reorder any per-chain data the caller keeps). Outputs must not
+ * overlap the inputs. W, H, tan_half_fov_x as for lens_chain_step; n in
+ * 0..RAMLT_MAX_PROPOSALS. workspace: DEVICE, 256-byte aligned, at least
+ * ramlt_lens_sort_workspace_size(n) bytes (64 counters per 4096 chains). Errors:
+ * RAMLT_EINVAL, RAMLT_EWORKSPACE. */
+int lens_chain_sort(int32_t W, int32_t H, float tan_half_fov_x, const float *omega, const float *density, int64_t n,
+                    float *omega_out, float *density_out, int32_t *perm, void *workspace, size_t ws_bytes,
+                    void *stream);
+
+/* Workspace bytes of lens_chain_sort for n chains (0 for n <= 0). */
+size_t ramlt_lens_sort_workspace_size(int64_t n);
 
 /* ------------------------------------------------------------------------------------
  * rRMSE of an image against a reference (Sec. 8.2: the error measure of the paper's

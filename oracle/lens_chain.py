@@ -59,6 +59,28 @@ def raster(omega, W, H, tan_half_x):
     return inside, ix, iy
 
 
+def sort_tile_side(W, H, max_tiles=63):
+    """Side T of the screen tiles of the chain reorder: the smallest power of two >= 16 with
+    ceil(W / T) * ceil(H / T) <= max_tiles."""
+    T = 16
+    while -(-W // T) * -(-H // T) > max_tiles:
+        T *= 2
+    return T
+
+
+def tile_order(omega, W, H, tan_half_x):
+    """The chain reorder (not an operation of the paper: the chains are independent, so their
+    order in memory is free). Key of chain i: the T x T tile of its pixel under the raster map
+    above, row-major, or the tile count for a chain outside the frame; the chains sorted by key,
+    stably. Returns (keys int64 [n], perm int64 [n]) with perm the old index of each chain in
+    the new order."""
+    inside, ix, iy = raster(omega, W, H, tan_half_x)
+    T = sort_tile_side(W, H)
+    ntx, nty = -(-W // T), -(-H // T)
+    keys = np.where(inside, (iy // T) * ntx + ix // T, ntx * nty)
+    return keys, np.argsort(keys, kind="stable")
+
+
 def step(luminance, tan_half_x, lam, n_regions, omega, noise):
     """One step of every chain. luminance [H, W] float32; lam [n_regions^2] (float64);
     omega [n, 3] float32 states; noise [n, 3] = (u, v, u_accept). Returns

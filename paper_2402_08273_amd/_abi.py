@@ -68,6 +68,8 @@ EXPORTED = (
     "ramlt_perturb_workspace_size",
     "lens_chain_step",
     "ramlt_lens_workspace_size",
+    "lens_chain_sort",
+    "ramlt_lens_sort_workspace_size",
     "rrmse",
     "ramlt_rrmse_workspace_size",
 )
@@ -221,6 +223,12 @@ def load():
     lib.lens_chain_step.restype = ctypes.c_int
     lib.ramlt_lens_workspace_size.argtypes = [ctypes.c_int32]
     lib.ramlt_lens_workspace_size.restype = ctypes.c_size_t
+    lib.lens_chain_sort.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.lens_chain_sort.restype = ctypes.c_int
+    lib.ramlt_lens_sort_workspace_size.argtypes = [ctypes.c_int64]
+    lib.ramlt_lens_sort_workspace_size.restype = ctypes.c_size_t
     lib.ramlt_perturb_workspace_size.argtypes = [ctypes.c_int32]
     lib.ramlt_perturb_workspace_size.restype = ctypes.c_size_t
     lib.perturb_directions.restype = ctypes.c_int
@@ -383,6 +391,22 @@ def lens_chain_step(luminance, W, H, tan_half_fov_x, lam, n_regions, omega, nois
 
 def lens_workspace_size(n_regions):
     return int(load().ramlt_lens_workspace_size(n_regions))
+
+
+def lens_chain_sort_status(W, H, tan_half_fov_x, omega, density, n, omega_out, density_out, perm, workspace=None,
+                           ws_bytes=0, stream=None):
+    return load().lens_chain_sort(W, H, tan_half_fov_x, omega, density, n, omega_out, density_out, perm, workspace,
+                                  ws_bytes, stream)
+
+
+def lens_chain_sort(W, H, tan_half_fov_x, omega, density, n, omega_out, density_out, perm, workspace=None,
+                    ws_bytes=0, stream=None):
+    return _check(lens_chain_sort_status(W, H, tan_half_fov_x, omega, density, n, omega_out, density_out, perm,
+                                         workspace, ws_bytes, stream))
+
+
+def lens_sort_workspace_size(n):
+    return int(load().ramlt_lens_sort_workspace_size(n))
 
 
 def rrmse_status(image, reference, W, H, eps, map_, out, workspace=None, ws_bytes=0, stream=None):

@@ -386,6 +386,59 @@ size_t ramlt_lens_workspace_size(int32_t n_regions) {
   return ramlt::perturb_workspace_bytes(n_regions * n_regions);
 }
 
+static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+int lens_chain_sort(int32_t W, int32_t H, float tan_half_fov_x, const float *omega, const float *density, int64_t n,
+                    float *omega_out, float *density_out, int32_t *perm, void *workspace, size_t ws_bytes,
+                    void *stream) {
+  if (W < 1 || H < 1 || W > RAMLT_MAX_SIDE || H > RAMLT_MAX_SIDE || (long long)W * H > RAMLT_MAX_PLANE_ELEMS)
+    return fail(RAMLT_EINVAL, "lens_chain_sort: image size %d x %d out of range", W, H);
+  if (!std::isfinite(tan_half_fov_x) || !(tan_half_fov_x > 0.0f))
+    return fail(RAMLT_EINVAL, "lens_chain_sort: tan_half_fov_x must be finite and > 0");
+  const float ty = (float)((double)tan_half_fov_x * H / W);
+  if (!(ty > 0.0f) || !std::isfinite(ty))
+    return fail(RAMLT_EINVAL, "lens_chain_sort: tan_half_fov_x * H / W is not a positive float");
+  if (n < 0 || n > RAMLT_MAX_PROPOSALS)
+    return fail(RAMLT_EINVAL, "lens_chain_sort: n %lld outside 0..%lld", (long long)n,
+                (long long)RAMLT_MAX_PROPOSALS);
+  if (n > 0) {
+    if (!omega || !aligned(omega, 4) || !omega_out || !aligned(omega_out, 4))
+      return fail(RAMLT_EINVAL, "lens_chain_sort: omega and omega_out must be 4-byte aligned device pointers");
+    if ((density == nullptr) != (density_out == nullptr))
+      return fail(RAMLT_EINVAL, "lens_chain_sort: density and density_out go together");
+    if (density && (!aligned(density, 4) || !aligned(density_out, 4)))
+      return fail(RAMLT_EINVAL, "lens_chain_sort: density and density_out must be 4-byte aligned");
+    if (perm && !aligned(perm, 4)) return fail(RAMLT_EINVAL, "lens_chain_sort: perm is not 4-byte aligned");
+    const size_t n3 = (size_t)n * 3 * sizeof(float), n1 = (size_t)n * sizeof(float);
+    // every output against every input (the outputs are written while the inputs are read)
+    bool bad = overlap(omega_out, n3, omega, n3) || (perm && overlap(perm, n1, omega, n3));
+    if (density)
+      bad = bad || overlap(density_out, n1, omega, n3) || overlap(density_out, n1, density, n1) ||
+            overlap(omega_out, n3, density, n1) || (perm && overlap(perm, n1, density, n1));
+    if (bad) return fail(RAMLT_EINVAL, "lens_chain_sort: outputs overlap the inputs");
+    const size_t need = ramlt::lens_sort_workspace_bytes(n);
+    if (workspace == nullptr || ws_bytes < need)
+      return fail(RAMLT_EWORKSPACE, "lens_chain_sort needs %zu bytes of workspace, got %zu", need,
+                  workspace == nullptr ? (size_t)0 : ws_bytes);
+    if (!aligned(workspace, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
+  }
+  int r = check_device();
+  if (r) return r;
+  const hipError_t e = ramlt::launch_lens_sort(W, H, tan_half_fov_x, ty, omega, density, n, omega_out, density_out,
+                                               perm, workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RAMLT_EHIP, "lens_chain_sort: %s", hipGetErrorString(e));
+  g_last_error.clear();
+  return RAMLT_OK;
+}
+
+size_t ramlt_lens_sort_workspace_size(int64_t n) {
+  if (n <= 0 || n > RAMLT_MAX_PROPOSALS) return 0;
+  return ramlt::lens_sort_workspace_bytes(n);
+}
+
 int rrmse(const float *image, const float *reference, int32_t W, int32_t H, double eps, float *map,
           double *rrmse_out, void *workspace, size_t ws_bytes, void *stream) {
   if (W < 1 || H < 1 || W > RAMLT_MAX_SIDE || H > RAMLT_MAX_SIDE || (long long)W * H > RAMLT_MAX_PLANE_ELEMS)

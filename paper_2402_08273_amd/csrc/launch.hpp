@@ -45,6 +45,13 @@ hipError_t launch_lens_step(const float *lum, int W, int H, float tx, float ty, 
                             float *omega, float *density, const float *noise, int32_t *region, float *alpha,
                             float *omega_prop, long long n, void *ws, hipStream_t st);
 
+// Reorder of lens chains by screen tile (chains.hip): validated arguments; ty as for the
+// step. Tiles are 2^lens_sort_tile_shift(W, H) pixels on a side.
+int lens_sort_tile_shift(int W, int H);
+size_t lens_sort_workspace_bytes(long long n);
+hipError_t launch_lens_sort(int W, int H, float tx, float ty, const float *omega, const float *density, long long n,
+                            float *omega_out, float *density_out, int32_t *perm, void *ws, hipStream_t st);
+
 // rRMSE (rrmse.hip): validated arguments; P = W H pixels.
 hipError_t launch_rrmse(const float *image, const float *reference, long long P, double eps, float *map,
                         double *out, void *ws, hipStream_t st);

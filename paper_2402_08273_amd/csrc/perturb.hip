@@ -13,6 +13,7 @@
 // (t, b) of omega, in fp32.
 #include "erfinv_poly.hpp"
 #include "launch.hpp"
+#include "raster.hpp"
 
 #include <math.h>
 #include <stdint.h>
@@ -129,29 +130,6 @@ __global__ __launch_bounds__(kPerturbBlock) void perturb_kernel(const Scale *__r
 }
 
 // ------------------------------------------------------------------------ lens chains
-// Raster position of a primary ray direction of a pinhole camera looking along +z, in
-// canonical screen space: sx = 1/2 + (1/2) (x / z) / tx, sy likewise with ty; in the frame
-// iff z > 0 and sx, sy in [0, 1). Every operation rounds to nearest on its own (no fused
-// multiply-add), so the pixel and every decision taken from it are reproducible one IEEE
-// operation at a time.
-struct Raster {
-  bool inside;
-  int ix, iy;
-};
-
-__device__ __forceinline__ Raster raster_of(float wx, float wy, float wz, float tx, float ty, int W, int H) {
-  // HIP's *_rn helpers are plain operators here: the pragma keeps the compiler from fusing
-  // a product into the following sum
-#pragma clang fp contract(off)
-  const float sx = __fadd_rn(0.5f, __fmul_rn(0.5f, __fdiv_rn(__fdiv_rn(wx, wz), tx)));
-  const float sy = __fadd_rn(0.5f, __fmul_rn(0.5f, __fdiv_rn(__fdiv_rn(wy, wz), ty)));
-  Raster r;
-  r.inside = wz > 0.0f && sx >= 0.0f && sx < 1.0f && sy >= 0.0f && sy < 1.0f;
-  r.ix = r.inside ? min((int)__fmul_rn(sx, (float)W), W - 1) : 0;
-  r.iy = r.inside ? min((int)__fmul_rn(sy, (float)H), H - 1) : 0;
-  return r;
-}
-
 // One Metropolis step per chain (Alg. 1 lines 8-13 with the lens perturbation of Sec. 3.3):
 // region k of the current state's pixel on the N x N screen grid (Sec. 6.1, the filter's
 // map), proposal by the direction perturbation with sigma_k, alpha = min(1, L' / L) from

@@ -470,6 +470,31 @@ def lens_chain_step(luminance, tan_half_fov_x, lam, n_regions, omega, noise, wan
     return (region, alpha, prop) if want_proposals else (region, alpha)
 
 
+def lens_chain_sort(omega, W, H, tan_half_fov_x, density=None, want_perm=True):
+    """Regroup lens chains by the screen tile of their current pixel (stable; the tile side is
+    the smallest power of two >= 16 leaving at most 63 tiles), so that the next steps'
+    luminance reads stay in cache. omega float32 [n, 3]; density (optional) float32 [n], the
+    carried luminance, moved with its chain. Returns (omega_sorted, density_sorted or None,
+    perm int32 [n] or None) with omega_sorted[j] = omega[perm[j]]."""
+    n = omega.shape[0] if omega.dim() == 2 else -1
+    if omega.dtype != torch.float32 or tuple(omega.shape) != (n, 3) or not omega.is_contiguous() \
+            or not omega.is_cuda:
+        raise ValueError("omega must be a contiguous float32 [n, 3] device tensor")
+    if density is not None and (density.dtype != torch.float32 or tuple(density.shape) != (n,)
+                                or not density.is_contiguous() or density.device != omega.device):
+        raise ValueError("density must be a contiguous float32 [n] tensor on omega's device")
+    om2 = torch.empty_like(omega)
+    d2 = torch.empty_like(density) if density is not None else None
+    perm = torch.empty(n, device=omega.device, dtype=torch.int32) if want_perm else None
+    p = (lambda t: t.data_ptr() if (t is not None and n) else None)
+    need = _abi.lens_sort_workspace_size(n)
+    ws = torch.empty(need + 256, device=omega.device, dtype=torch.uint8) if need else None
+    wp = (ws.data_ptr() + 255) // 256 * 256 if need else None
+    _abi.lens_chain_sort(int(W), int(H), float(tan_half_fov_x), p(omega), p(density), n, p(om2), p(d2), p(perm), wp,
+                         need, _stream())
+    return om2, d2, perm
+
+
 def rrmse(image, reference, eps=1e-2, want_map=True):
     """rRMSE of ``image`` against ``reference`` (float32 [3, H, W] device tensors, Sec. 8.2):
     returns (map float32 [H, W] or None, rRMSE as a float64 device tensor of shape [])."""

@@ -409,6 +409,36 @@ def test_lens_chain_step_validation(lib):
     assert st(n_regions=257, workspace=None, ws_bytes=0) in ok
 
 
+def test_lens_chain_sort_validation(lib):
+    ok = (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
+    need = _abi.lens_sort_workspace_size(1000)
+    # 64 counters per 4096 chains, then the 64 key bases, each 256-byte aligned
+    assert need == 256 + 256 and _abi.lens_sort_workspace_size(4097) == 512 + 256
+    assert _abi.lens_sort_workspace_size(1 << 24) == 64 * 4096 * 4 + 256
+    assert _abi.lens_sort_workspace_size(0) == 0 and _abi.lens_sort_workspace_size((1 << 30) + 1) == 0
+    args = dict(W=1920, H=1080, tan_half_fov_x=0.6, omega=0x300000, density=0x500000, n=1000, omega_out=0x400000,
+                density_out=0x600000, perm=0x700000, workspace=FAKE_WORKSPACE, ws_bytes=need)
+    st = lambda **kw: _abi.lens_chain_sort_status(**{**args, **kw})
+    assert st() in ok, _abi.last_error()
+    assert st(perm=None) in ok and st(density=None, density_out=None) in ok
+    assert st(omega=None, density=None, omega_out=None, density_out=None, perm=None, n=0, workspace=None,
+              ws_bytes=0) in ok
+    bad = [dict(W=0), dict(H=0), dict(H=65537), dict(tan_half_fov_x=0.0), dict(tan_half_fov_x=float("nan")),
+           dict(n=-1), dict(n=(1 << 30) + 1), dict(omega=None), dict(omega=0x300002), dict(omega_out=None),
+           dict(omega_out=0x400001), dict(density_out=None), dict(density=None), dict(density=0x500002),
+           dict(density_out=0x600002), dict(perm=0x700003),
+           # outputs overlapping inputs (12000 B of omega, 4000 B of density)
+           dict(omega_out=0x300000), dict(omega_out=0x300000 + 11996), dict(omega_out=0x300000 - 11996),
+           dict(density_out=0x300000 + 400), dict(density_out=0x500000 + 3996), dict(omega_out=0x500000 - 8),
+           dict(perm=0x300000 + 8), dict(perm=0x500000 - 3996)]
+    for kw in bad:
+        assert st(**kw) == _abi.RAMLT_EINVAL, kw
+    assert st(omega_out=0x300000 + 12000) in ok  # adjacent is not overlapping
+    assert st(workspace=None, ws_bytes=0) == _abi.RAMLT_EWORKSPACE
+    assert st(ws_bytes=need - 1) == _abi.RAMLT_EWORKSPACE
+    assert st(workspace=FAKE_WORKSPACE + 8) == _abi.RAMLT_EWORKSPACE
+
+
 def test_rrmse_validation(lib):
     ok = (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
     need = _abi.rrmse_workspace_size(1920, 1080)

@@ -26,7 +26,8 @@ def test_header_is_c99_and_links(tmp_path):
     out = subprocess.run([exe], check=True, capture_output=True, text=True, timeout=60).stdout
     got = dict(line.split(" ", 1) for line in out.strip().splitlines())
     assert got["abi"] == f"{ctypes.sizeof(_abi.RamltFrame)} {ctypes.sizeof(_abi.RamltFrame)}"
-    for key in ("stats_null", "stats_noptr", "adapt_null", "qt_null", "perturb_bad", "rrmse_bad", "lens_bad"):
+    for key in ("stats_null", "stats_noptr", "adapt_null", "qt_null", "perturb_bad", "rrmse_bad", "lens_bad",
+                "lens_sort_bad"):
         assert int(got[key]) == _abi.RAMLT_EINVAL, key
-    for key in ("last_error_set", "adapt_ws", "qt_ws", "rrmse_ws", "lens_ws"):
+    for key in ("last_error_set", "adapt_ws", "qt_ws", "rrmse_ws", "lens_ws", "lens_sort_ws"):
         assert got[key] == "1", key

@@ -168,3 +168,47 @@ def test_lens_carried_density_gives_the_same_steps():
     iy = np.minimum((np.where(inside, sy, 0) * f32(H)).astype(np.int64), H - 1)
     d = dens.cpu().numpy()
     assert np.array_equal(d[inside], img[iy[inside], ix[inside]]) and np.all(d[~inside] == -1.0)
+
+
+@pytest.mark.parametrize("W,H,n", [(1920, 1080, 300_037), (3840, 2160, 70_001), (100, 40, 4097), (1, 1, 5000),
+                                   (640, 360, 1), (640, 360, 0), (1000, 1000, 4096)])
+def test_lens_chain_sort_matches_the_stable_tile_order(W, H, n):
+    # the reorder groups chains by the screen tile of their pixel (oracle.lens_chain.tile_order:
+    # float32 raster map, stable sort): order, directions and carried luminance bit for bit
+    print(f"lens sort W={W} H={H} n={n}", flush=True)
+    tx = 0.6
+    omega = make_lens_chains(max(n, 1), W, H, tx, seed=n + 1)[:n]
+    rng = np.random.default_rng(n)
+    dens = rng.random(n).astype(np.float32)
+    dens[rng.random(n) < 0.1] = -1.0
+    om2, d2, perm = ops.lens_chain_sort(_dev(omega), W, H, tx, density=_dev(dens))
+    torch.cuda.synchronize()
+    keys, want = olc.tile_order(omega, W, H, tx)
+    assert np.array_equal(perm.cpu().numpy(), want)
+    assert np.array_equal(om2.cpu().numpy(), omega[want], equal_nan=True)
+    assert np.array_equal(d2.cpu().numpy(), dens[want])
+    if n > 1:  # a key per tile, non-decreasing
+        assert np.all(np.diff(keys[want]) >= 0)
+
+
+def test_lens_step_after_the_sort_is_the_permuted_step():
+    # chains are independent: the step of the reordered chains (with their noise reordered
+    # the same way) is the reordered step, bit for bit; the carried luminance moves along
+    W, H, tx, N, n = 640, 360, 0.6, 20, 200_000
+    L = _dev(make_luminance(W, H, seed=4))
+    lam = _dev(make_lambda_table(N * N, seed=6))
+    omega = _dev(make_lens_chains(n, W, H, tx, seed=7))
+    noise = _dev(make_lens_noise(n, seed=8))
+    dens = torch.full((n,), -1.0, device="cuda")
+    ops.lens_chain_step(L, tx, lam, N, omega, noise, density=dens)  # the carried values are set
+    om_s, dens_s, perm = ops.lens_chain_sort(omega, W, H, tx, density=dens)
+    p = perm.long()
+    noise_s = noise[p].contiguous()
+    r1, a1 = ops.lens_chain_step(L, tx, lam, N, omega, noise, density=dens)
+    r2, a2 = ops.lens_chain_step(L, tx, lam, N, om_s, noise_s, density=dens_s)
+    torch.cuda.synchronize()
+    assert torch.equal(r2, r1[p]) and torch.equal(a2.isnan(), a1[p].isnan())
+    assert torch.equal(torch.nan_to_num(a2, 7.0), torch.nan_to_num(a1[p], 7.0))
+    assert torch.equal(om_s.isnan(), omega[p].isnan())
+    assert torch.equal(torch.nan_to_num(om_s, 7.0), torch.nan_to_num(omega[p], 7.0))
+    assert torch.equal(dens_s, dens[p])

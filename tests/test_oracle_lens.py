@@ -118,3 +118,37 @@ def test_closed_loop_pins_the_direction_of_the_update():
     with np.errstate(over="ignore", invalid="ignore"):
         acc_f, lam_f = run(True)
     assert np.all(np.abs(acc_f - 0.5) > 0.4) and np.all(np.abs(lam_f) > 20), (acc_f, lam_f)
+
+
+def test_tile_order_of_the_chain_reorder():
+    # tile side: the smallest power of two >= 16 leaving at most 63 tiles
+    assert lc.sort_tile_side(1920, 1080) == 256  # 8 x 5 = 40 tiles (128: 15 x 9 = 135)
+    assert lc.sort_tile_side(3840, 2160) == 512
+    assert lc.sort_tile_side(16, 16) == 16 and lc.sort_tile_side(1, 1) == 16
+    assert lc.sort_tile_side(65536, 65536) == 16384  # 4 x 4 (8192: 8 x 8 = 64 tiles)
+    assert lc.sort_tile_side(16 * 63, 16) == 16 and lc.sort_tile_side(16 * 64, 16) == 32
+    # chains through known pixel centres, in a shuffled order, with some outside the frame:
+    # the keys are the tiles of those pixels, written out by hand, and the order is the one a
+    # stable insertion sort by key gives
+    W, H, tx = 100, 40, 0.6
+    T = lc.sort_tile_side(W, H)
+    assert T == 16  # 7 x 3 tiles
+    d = lc.pixel_centre_directions(W, H, tx)
+    rng = np.random.default_rng(3)
+    pick = rng.integers(0, W * H, 500)
+    om = d[pick].copy()
+    out = rng.random(500) < 0.05
+    om[out] = [0.0, 0.0, -1.0]
+    om[7] = [np.nan, 0.0, 1.0]
+    out[7] = True
+    keys, perm = lc.tile_order(om, W, H, tx)
+    px, py = pick % W, pick // W
+    want = np.where(out, 7 * 3, (py // 16) * 7 + px // 16)
+    assert np.array_equal(keys, want)
+    order = []  # stable insertion sort
+    for i in range(len(want)):
+        j = len(order)
+        while j > 0 and want[order[j - 1]] > want[i]:
+            j -= 1
+        order.insert(j, i)
+    assert np.array_equal(perm, order)
