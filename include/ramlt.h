@@ -203,6 +203,21 @@ int loss_seed(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
 int filter_backward(const ramlt_frame *frames_host, const ramlt_frame *frames_dev,
                     int32_t n_frames, void *workspace, size_t ws_bytes, void *stream);
 
+/* The whole differentiable step of ONE frame in one call: stats_accumulate, then
+ * filter_forward with RAMLT_LOSS_IN_FORWARD (out, the MSE seed U in grad_out, *loss and
+ * grad_lambda accumulated), then filter_backward (grad_radiance) -- Appendix A and
+ * Sec. 3.1 eq. path_integral with Sec. 5.2-5.3, as for those calls -- enqueued in that
+ * order on `stream`. Every output is bit for bit what the three calls give with the same
+ * descriptor. frame: HOST pointer to one descriptor whose flags include
+ * RAMLT_LOSS_IN_FORWARD, with every field the three calls require (radiance, mean, var,
+ * tau, features => feat_mean / feat_var, lambda, out, reference, grad_out, grad_radiance;
+ * lag_corr, loss and grad_lambda optional; loss and grad_lambda accumulate, the caller
+ * zeroes them). Flags bits 4-7 size the statistics launches as for stats_accumulate.
+ * workspace: DEVICE, 256-byte aligned, at least ramlt_workspace_size(frame, 1,
+ * RAMLT_OP_FILTER_FORWARD) bytes (the per-tile partials). Errors as for the three calls;
+ * all validation precedes the first launch. */
+int stats_filter_step(const ramlt_frame *frame, void *workspace, size_t ws_bytes, void *stream);
+
 /* filter_backward for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same operation and
  * results, with the workspace taken from a device array the library owns, so the caller

@@ -55,6 +55,7 @@ EXPORTED = (
     "loss_seed",
     "filter_backward",
     "filter_backward_noalloc",
+    "stats_filter_step",
     "ramlt_workspace_size",
     "ramlt_last_error",
     "ramlt_abi_version",
@@ -187,6 +188,8 @@ def load():
     lib.filter_backward_noalloc.argtypes = [ctypes.POINTER(RamltFrame), ctypes.c_void_p, ctypes.c_int32,
                                             ctypes.c_void_p]
     lib.filter_backward_noalloc.restype = ctypes.c_int
+    lib.stats_filter_step.argtypes = [ctypes.POINTER(RamltFrame), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.stats_filter_step.restype = ctypes.c_int
     lib.ramlt_workspace_size.argtypes = [ctypes.POINTER(RamltFrame), ctypes.c_int32, ctypes.c_int32]
     lib.ramlt_workspace_size.restype = ctypes.c_size_t
     lib.ramlt_last_error.argtypes = []
@@ -280,6 +283,20 @@ def filter_backward_noalloc(frames, frames_dev=None, stream=None):
     st = lib.filter_backward_noalloc(arr, frames_dev, n, stream)
     if st != RAMLT_OK:
         raise RamltError(st, lib.ramlt_last_error().decode())
+    return st
+
+
+def stats_filter_step_status(frame, workspace=None, ws_bytes=0, stream=None):
+    """Raw status of stats_filter_step on one descriptor (no exception)."""
+    return load().stats_filter_step(ctypes.byref(frame), workspace, ws_bytes, stream)
+
+
+def stats_filter_step(frame, workspace=None, ws_bytes=0, stream=None):
+    """stats_accumulate + filter_forward (loss in the forward pass) + filter_backward of one
+    frame in one call."""
+    st = stats_filter_step_status(frame, workspace, ws_bytes, stream)
+    if st != RAMLT_OK:
+        raise RamltError(st, load().ramlt_last_error().decode())
     return st
 
 

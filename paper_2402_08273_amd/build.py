@@ -11,7 +11,7 @@ PKG_DIR = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG_DIR)
 CSRC = os.path.join(PKG_DIR, "csrc")
 LIB = os.path.join(PKG_DIR, "libramlt.so")
-SOURCES = ["abi.hip", "batch.hip", "stats.hip", "filter.hip", "adapt.hip", "quadtree.hip", "perturb.hip", "chains.hip", "rrmse.hip", "filter_tiles_32x8.hip",
+SOURCES = ["abi.hip", "batch.hip", "stats.hip", "filter.hip", "adapt.hip", "quadtree.hip", "perturb.hip", "chains.hip", "step.hip", "rrmse.hip", "filter_tiles_32x8.hip",
            "filter_tiles_32x16.hip", "filter_tiles_64x8.hip", "noalloc.hip"]
 ARCH = "gfx950"
 

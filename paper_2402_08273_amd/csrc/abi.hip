@@ -530,6 +530,26 @@ int filter_backward(const ramlt_frame *frames_host, const ramlt_frame *frames_de
                 frames_host, frames_dev, n_frames, workspace, ws_bytes, stream);
 }
 
+int stats_filter_step(const ramlt_frame *frame, void *workspace, size_t ws_bytes, void *stream) {
+  int r = check_common(frame, nullptr, 1);
+  if (r) return r;
+  if (!(frame->flags & RAMLT_LOSS_IN_FORWARD))
+    return fail(RAMLT_EINVAL, "stats_filter_step: the frame's flags must include RAMLT_LOSS_IN_FORWARD");
+  if ((r = validate_stats(*frame, 0)) || (r = validate_forward(*frame, 0)) || (r = validate_backward(*frame, 0)))
+    return r;
+  const size_t need = ramlt::workspace_bytes(frame, 1, RAMLT_OP_FILTER_FORWARD);
+  if (workspace == nullptr || ws_bytes < need)
+    return fail(RAMLT_EWORKSPACE, "stats_filter_step needs %zu bytes of workspace, got %zu", need,
+                workspace == nullptr ? (size_t)0 : ws_bytes);
+  if (!aligned(workspace, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
+  r = check_device();
+  if (r) return r;
+  const hipError_t e = ramlt::launch_step(*frame, workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RAMLT_EHIP, "stats_filter_step: %s", hipGetErrorString(e));
+  g_last_error.clear();
+  return RAMLT_OK;
+}
+
 int filter_backward_noalloc(const ramlt_frame *frames_host, const ramlt_frame *frames_dev, int32_t n_frames,
                             void *stream) {
   int r = check_common(frames_host, frames_dev, n_frames);

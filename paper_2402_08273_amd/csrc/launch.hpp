@@ -17,6 +17,10 @@ hipError_t launch_filter_backward(const ramlt_frame *fh, const ramlt_frame *fd, 
                                   hipStream_t st);
 size_t workspace_bytes(const ramlt_frame *fh, int n, int op);
 
+// The whole step of one validated frame (flags with RAMLT_LOSS_IN_FORWARD): statistics,
+// forward with the loss, radiance adjoint, in that order on st (step.hip).
+hipError_t launch_step(const ramlt_frame &f, void *ws, hipStream_t st);
+
 // The library's own device workspace of filter_backward_noalloc (noalloc.hip): this many
 // bytes per GPU; *ptr = the current device's copy (resolved once per device).
 constexpr size_t kNoallocWorkspaceBytes = RAMLT_NOALLOC_WORKSPACE_BYTES;

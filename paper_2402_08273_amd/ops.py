@@ -257,6 +257,47 @@ def filter_backward_radiance(grad_out, lam, radius, S, n_regions=None, lambda_mi
     return grad_radiance
 
 
+class StepResult(NamedTuple):
+    stats: Stats
+    out: torch.Tensor
+    grad_out: torch.Tensor
+    grad_radiance: torch.Tensor
+    loss: torch.Tensor
+    grad_lambda: Optional[torch.Tensor]
+
+
+def step_frame(radiance, features, lam, radius, reference, max_lag=8, n_regions=None,
+               lambda_min=LAMBDA_MIN_DEFAULT, schedule=0, with_lag_corr=False, want_grad_lambda=True):
+    """Descriptor (flags with RAMLT_LOSS_IN_FORWARD) and zeroed / fresh output tensors of one
+    frame's whole step, for :func:`stats_filter_step` or for the three calls in sequence."""
+    f, st = stats_frame(radiance, features, max_lag, None, with_lag_corr)
+    fl = filter_frame(st.mean, lam, radius, n_regions, lambda_min, int(schedule) | _abi.RAMLT_LOSS_IN_FORWARD)
+    hw = st.mean.shape[1:]
+    _check_plane(reference, "reference", 3, hw)
+    out, grad_out, grad_radiance = (torch.empty_like(st.mean) for _ in range(3))
+    loss = torch.zeros(1, device=st.mean.device, dtype=torch.float64)
+    grad_lambda = torch.zeros_like(lam) if want_grad_lambda else None
+    f.lambda_, f.n_regions, f.radius, f.lambda_min = fl.lambda_, fl.n_regions, fl.radius, fl.lambda_min
+    f.flags = fl.flags
+    f.out, f.reference, f.grad_out = out.data_ptr(), reference.data_ptr(), grad_out.data_ptr()
+    f.grad_radiance, f.loss, f.grad_lambda = grad_radiance.data_ptr(), loss.data_ptr(), _ptr(grad_lambda)
+    return f, StepResult(st, out, grad_out, grad_radiance, loss, grad_lambda)
+
+
+def stats_filter_step(radiance, features, lam, radius, reference, max_lag=8, n_regions=None,
+                      lambda_min=LAMBDA_MIN_DEFAULT, schedule=0, with_lag_corr=False, want_grad_lambda=True):
+    """The whole differentiable step of one frame in one library call: statistics, the
+    filter with the MSE seed, the loss and dL/dlambda, and the radiance adjoint G. Same
+    results as :func:`stats`, :func:`filter_forward_loss` and
+    :func:`filter_backward_radiance`."""
+    f, res = step_frame(radiance, features, lam, radius, reference, max_lag, n_regions, lambda_min, schedule,
+                        with_lag_corr, want_grad_lambda)
+    ws, ws_ptr, ws_bytes = workspace_for([f], _abi.OP_FILTER_FORWARD, radiance.device)
+    _abi.stats_filter_step(f, workspace=ws_ptr, ws_bytes=ws_bytes, stream=_stream())
+    del ws
+    return res
+
+
 class RegionalFilter(torch.autograd.Function):
     """out = filter(mean over samples of radiance; lambda). Differentiable in radiance and
     lambda; the statistics outputs and features carry no gradient.

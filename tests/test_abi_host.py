@@ -507,3 +507,46 @@ def test_noalloc_adjoint_validation(lib):
     assert lib.filter_backward_noalloc((_abi.RamltFrame * 1)(big), None, 1, None) == _abi.RAMLT_EWORKSPACE
     assert "workspace" in _abi.last_error()
     assert lib.filter_backward_noalloc(None, None, 1, None) == _abi.RAMLT_EINVAL
+
+
+def test_stats_filter_step_validation(lib):
+    # the pipelined step validates its one descriptor as stats_accumulate, filter_forward
+    # (loss in the forward pass) and filter_backward would, before any device work
+    f = _valid_stats_frame()
+    g = _valid_filter_frame()
+    for name in ("lambda_", "n_regions", "radius", "lambda_min", "out", "grad_out", "grad_radiance", "grad_lambda",
+                 "reference", "loss"):
+        setattr(f, name, getattr(g, name))
+    f.W, f.H, f.n_regions = 64, 48, 2
+    f.rad_stride_c, f.rad_stride_s, f.rad_stride_y = 16 * 64 * 48, 64 * 48, 64
+    f.flags = _abi.RAMLT_LOSS_IN_FORWARD | _abi.RAMLT_TILE_32X16 | (1 << _abi.RAMLT_STATS_WG_SHIFT)
+    need = _abi.workspace_size([f], _abi.OP_FILTER_FORWARD)
+    assert need > 0
+    ok = (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
+    st = lambda h, **kw: _abi.stats_filter_step_status(h, **{"workspace": FAKE_WORKSPACE, "ws_bytes": need, **kw})  # noqa: E731
+    assert st(f) in ok, _abi.last_error()
+    for field, value in (("radiance", None), ("mean", None), ("var", None), ("tau", None), ("lambda_", None),
+                         ("out", None), ("reference", None), ("grad_out", None), ("grad_radiance", None),
+                         ("mean", 0x20002), ("loss", 0xB0004), ("grad_lambda", 0x90002), ("lag_corr", 0x1002),
+                         ("S", 0), ("max_lag", 33), ("radius", 16), ("n_regions", 0), ("W", 0),
+                         ("flags", _abi.RAMLT_TILE_32X16), ("flags", _abi.RAMLT_LOSS_IN_FORWARD | 0x1000),
+                         ("rad_stride_y", 63)):
+        h = _abi.RamltFrame.from_buffer_copy(f)
+        setattr(h, field, value)
+        assert st(h) == _abi.RAMLT_EINVAL, (field, value)
+    h = _abi.RamltFrame.from_buffer_copy(f)
+    h.features = 0x100000
+    assert st(h) == _abi.RAMLT_EINVAL  # feature planes need feat_mean / feat_var
+    h.feat_mean, h.feat_var = 0x110000, 0x120000
+    h.feat_stride_c, h.feat_stride_s, h.feat_stride_y = 16 * 64 * 48, 64 * 48, 64
+    assert st(h) in ok, _abi.last_error()
+    h.feat_dtype = 7
+    assert st(h) == _abi.RAMLT_EUNSUPPORTED
+    # optional outputs may be NULL
+    h = _abi.RamltFrame.from_buffer_copy(f)
+    h.loss = h.grad_lambda = h.lag_corr = None
+    assert st(h) in ok
+    assert st(f, workspace=None, ws_bytes=0) == _abi.RAMLT_EWORKSPACE
+    assert st(f, ws_bytes=need - 1) == _abi.RAMLT_EWORKSPACE
+    assert st(f, workspace=FAKE_WORKSPACE + 64) == _abi.RAMLT_EWORKSPACE
+    assert lib.stats_filter_step(None, None, 0, None) == _abi.RAMLT_EINVAL
