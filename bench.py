@@ -78,22 +78,38 @@ def calibrate_copy(mib):
 TRAFFIC_RECORDS = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
-def measured_traffic(path, key):
+def measured_traffic(path, key, field="bytes_per_launch"):
     """HBM bytes per launch of the kernel of workload ``key`` from the committed rocprofv3
     counts (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration), or None if there is no
-    record for it or a source it names has changed since the counters were taken."""
+    record for it or a source it names has changed since the counters were taken. ``field``
+    picks another counted value of the record (e.g. VALU wave instructions per launch)."""
     import hashlib
 
     if not path or not os.path.exists(path):
         return None
     for rec in json.load(open(path))["records"]:
-        if rec["key"] != key:
+        if rec["key"] != key or field not in rec:
             continue
         h = hashlib.sha256()
         for src in rec["sources"]:
             h.update(open(os.path.join(ROOT, src), "rb").read())
-        return rec["bytes_per_launch"] if h.hexdigest()[:16] == rec["sources_sha256_16"] else None
+        return rec[field] if h.hexdigest()[:16] == rec["sources_sha256_16"] else None
     return None
+
+
+# VALU issue ceiling of MI355X: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD per
+# 4 cycles at 2.4 GHz
+VALU_PEAK_GINST_S = 256 * 4 * 2.4 / 4
+
+
+def valu_roofline(insts, ms, note):
+    """Roofline object of a kernel bound by VALU issue: its counted VALU wave instructions
+    per launch (rocprofv3 SQ_INSTS_VALU, committed record) over the measured time."""
+    if insts is None:
+        return None
+    g = insts / (ms * 1e-3) / 1e9
+    return {"bound": "alu", "achieved": round(g, 1), "peak": VALU_PEAK_GINST_S, "unit": "G VALU wave-instructions/s",
+            "frac": round(g / VALU_PEAK_GINST_S, 4), "valu_insts": int(insts), "covers": note}
 
 
 def stats_bytes(P, S, feat_bytes=4):
@@ -611,6 +627,8 @@ def measure_lens(steps, warmup, cpu=True):
            "achieved_gbs": round(gbs_s, 1), "hbm_frac": round(gbs_s / HBM_PEAK_GBS, 4),
            "roofline": hbm_roofline(nbytes, ms_s, "scale_kernel + lens_step_kernel (chains in tile order)",
                                     measured_traffic(TRAFFIC_RECORDS, "lens step 16M sorted")),
+           "valu_roofline": valu_roofline(measured_traffic(TRAFFIC_RECORDS, "lens step 16M sorted", "valu_insts"),
+                                          ms_s, "lens_step_kernel (chains in tile order): VALU issue"),
            "sort_ms": round(ms_sort, 4), "sort_gbs": round(n * 48 / (ms_sort * 1e-3) / 1e9, 1),
            "ms_per_step_sorting_every_16": round(ms_s + ms_sort / 16, 4),
            "index_order": {"ms_per_step": round(ms, 4), "ms_per_adaptive_step": round(ms_loop, 4),

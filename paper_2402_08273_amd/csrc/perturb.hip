@@ -11,6 +11,7 @@
 // 1e-9, a fraction of the float32 rounding of theta'). phi' = 2 pi v. The new direction is
 // sin theta' (cos phi' t + sin phi' b) + cos theta' omega in the Duff et al. (2017) basis
 // (t, b) of omega, in fp32.
+#include "batch.hpp"
 #include "erfinv_poly.hpp"
 #include "launch.hpp"
 #include "raster.hpp"
@@ -139,9 +140,10 @@ __global__ __launch_bounds__(kPerturbBlock) void perturb_kernel(const Scale *__r
 // at the proposal, instead of twice.
 template <bool kTable>
 __global__ __launch_bounds__(kPerturbBlock) void lens_step_kernel(
-    const Scale *__restrict__ table, const double *__restrict__ lambda, int N, const float *__restrict__ lum, int W,
-    int H, float tx, float ty, float *__restrict__ omega, float *__restrict__ density, const float *__restrict__ noise,
-    int32_t *__restrict__ region, float *__restrict__ alpha, float *__restrict__ omega_prop, long long n) {
+    const Scale *__restrict__ table, const double *__restrict__ lambda, int N, FastDiv d2W, FastDiv d2H,
+    const float *__restrict__ lum, int W, int H, float tx, float ty, float *__restrict__ omega,
+    float *__restrict__ density, const float *__restrict__ noise, int32_t *__restrict__ region,
+    float *__restrict__ alpha, float *__restrict__ omega_prop, long long n) {
   const long long i = (long long)blockIdx.x * kPerturbBlock + threadIdx.x;
   if (i >= n) return;
   const float wx = omega[3 * i], wy = omega[3 * i + 1], wz = omega[3 * i + 2];
@@ -150,8 +152,9 @@ __global__ __launch_bounds__(kPerturbBlock) void lens_step_kernel(
   int k = -1;
   float a = __builtin_nanf(""), ox = a, oy = a, oz = a, dens = -1.0f;
   if (c.inside) {
-    const int kx = ((2 * c.ix + 1) * N) / (2 * W);
-    const int ky = ((2 * c.iy + 1) * N) / (2 * H);
+    // (2 i + 1) N < 2^17 2^12: exact by FastDiv
+    const int kx = (int)fast_div((uint32_t)(2 * c.ix + 1) * (uint32_t)N, d2W);
+    const int ky = (int)fast_div((uint32_t)(2 * c.iy + 1) * (uint32_t)N, d2H);
     k = ky * N + kx;
     const float th = (float)theta_of((double)u, kTable ? table[k] : scale_of(lambda[k]));
     propose(wx, wy, wz, th, v, ox, oy, oz);
@@ -211,14 +214,15 @@ hipError_t launch_lens_step(const float *lum, int W, int H, float tx, float ty, 
   if (n <= 0) return hipSuccess;
   const int m = N * N;
   const long long blocks = (n + kPerturbBlock - 1) / kPerturbBlock;
+  const FastDiv d2W = make_fastdiv(2u * (uint32_t)W), d2H = make_fastdiv(2u * (uint32_t)H);
   if (m <= kMaxTableRegions) {
     Scale *table = (Scale *)ws;
     scale_kernel<<<(m + kPerturbBlock - 1) / kPerturbBlock, kPerturbBlock, 0, st>>>(lambda, m, table);
-    lens_step_kernel<true><<<(unsigned)blocks, kPerturbBlock, 0, st>>>(table, lambda, N, lum, W, H, tx, ty, omega,
-                                                                       density, noise, region, alpha, omega_prop, n);
+    lens_step_kernel<true><<<(unsigned)blocks, kPerturbBlock, 0, st>>>(
+        table, lambda, N, d2W, d2H, lum, W, H, tx, ty, omega, density, noise, region, alpha, omega_prop, n);
   } else {
-    lens_step_kernel<false><<<(unsigned)blocks, kPerturbBlock, 0, st>>>(nullptr, lambda, N, lum, W, H, tx, ty, omega,
-                                                                        density, noise, region, alpha, omega_prop, n);
+    lens_step_kernel<false><<<(unsigned)blocks, kPerturbBlock, 0, st>>>(
+        nullptr, lambda, N, d2W, d2H, lum, W, H, tx, ty, omega, density, noise, region, alpha, omega_prop, n);
   }
   return hipGetLastError();
 }
