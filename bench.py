@@ -567,7 +567,11 @@ def measure_lens(steps, warmup, cpu=True):
     stream). The chains carry the luminance of their pixel between steps. Algorithmic bytes
     per chain of the step: omega 12 + noise 12 + carried luminance 4 read, region 4 + alpha 4
     + carried luminance 4 written, the luminance at the proposal 4, omega 12 written on
-    acceptance (times the batch's mean alpha)."""
+    acceptance (times the batch's mean alpha).
+
+    Order of the launches (the counter records take the timed steps of the first group):
+    `warmup` closed-loop steps, `steps` steps alone (timed), `steps` closed-loop steps (timed);
+    then the chains regrouped by screen tile (lens_chain_sort) and the same three groups."""
     import torch
 
     from paper_2402_08273_amd import ops
@@ -584,56 +588,50 @@ def measure_lens(steps, warmup, cpu=True):
     dens = torch.full((n,), -1.0, dtype=torch.float32, device=om.device)   # carried luminance
     last = {}
 
-    def step():
-        last["ra"] = ops.lens_chain_step(L, tx, ad.lam, N, om, noise, density=dens)
+    def timed(o, nz, d):
+        def step():
+            last["ra"] = ops.lens_chain_step(L, tx, ad.lam, N, o, nz, density=d)
 
-    def loop():
-        step()
-        ad.step(*last["ra"])
+        def loop():
+            step()
+            ad.step(*last["ra"])
 
-    for _ in range(warmup):
-        loop()
-    ms_loop = time_loop(stream, loop, steps)
-    ms = time_loop(stream, step, steps)
-    region, alpha = last["ra"]
-    ok = region >= 0
-    acc = float(alpha[ok].double().mean())
+        for _ in range(warmup):
+            loop()
+        ms = time_loop(stream, step, steps)
+        region, alpha = last["ra"]
+        ok = region >= 0
+        acc = float(alpha[ok].double().mean())
+        return ms, time_loop(stream, loop, steps), acc
+
+    ms, ms_loop, acc = timed(om, noise, dens)
     nbytes = int(n * (44 + 12 * acc))
     gbs = nbytes / (ms * 1e-3) / 1e9
-
     # the same chains regrouped by screen tile (lens_chain_sort, 48 B per chain: omega read
     # twice, density read; omega, density and the old index written), then stepped with their
     # noise regrouped the same way
     ms_sort = time_loop(stream, lambda: ops.lens_chain_sort(om, W, H, tx, density=dens), steps)
     om_s, dens_s, perm = ops.lens_chain_sort(om, W, H, tx, density=dens)
     noise_s = noise[perm.long()].contiguous()
-
-    def step_sorted():
-        last["ra"] = ops.lens_chain_step(L, tx, ad.lam, N, om_s, noise_s, density=dens_s)
-
-    def loop_sorted():
-        step_sorted()
-        ad.step(*last["ra"])
-
-    for _ in range(warmup):
-        step_sorted()
-    ms_s = time_loop(stream, step_sorted, steps)
-    ms_loop_s = time_loop(stream, loop_sorted, steps)
-    gbs_s = nbytes / (ms_s * 1e-3) / 1e9
+    ms_s, ms_loop_s, acc_s = timed(om_s, noise_s, dens_s)
+    nbytes_s = int(n * (44 + 12 * acc_s))
     out = {"workload": f"lens-perturbation chains, {n} chains, {W}x{H} luminance, {N}x{N} regions, "
-                       f"tan(fov/2) = {tx}; chains grouped by 256x256-pixel screen tile (lens_chain_sort)",
-           "chains": n, "ms_per_step": round(ms_s, 4), "gchains_s": round(n / (ms_s * 1e-3) / 1e9, 2),
-           "ms_per_adaptive_step": round(ms_loop_s, 4), "mean_alpha": round(acc, 4), "algorithmic_bytes": nbytes,
-           "achieved_gbs": round(gbs_s, 1), "hbm_frac": round(gbs_s / HBM_PEAK_GBS, 4),
-           "roofline": hbm_roofline(nbytes, ms_s, "scale_kernel + lens_step_kernel (chains in tile order)",
-                                    measured_traffic(TRAFFIC_RECORDS, "lens step 16M sorted")),
-           "valu_roofline": valu_roofline(measured_traffic(TRAFFIC_RECORDS, "lens step 16M sorted", "valu_insts"),
-                                          ms_s, "lens_step_kernel (chains in tile order): VALU issue"),
-           "sort_ms": round(ms_sort, 4), "sort_gbs": round(n * 48 / (ms_sort * 1e-3) / 1e9, 1),
-           "ms_per_step_sorting_every_16": round(ms_s + ms_sort / 16, 4),
-           "index_order": {"ms_per_step": round(ms, 4), "ms_per_adaptive_step": round(ms_loop, 4),
-                           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                           "traffic": measured_traffic(TRAFFIC_RECORDS, "lens step 16M index order")}}
+                       f"tan(fov/2) = {tx}",
+           "chains": n, "ms_per_step": round(ms, 4), "gchains_s": round(n / (ms * 1e-3) / 1e9, 2),
+           "ms_per_adaptive_step": round(ms_loop, 4), "mean_alpha": round(acc, 4), "algorithmic_bytes": nbytes,
+           "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+           "roofline": hbm_roofline(nbytes, ms, "scale_kernel + lens_step_kernel",
+                                    measured_traffic(TRAFFIC_RECORDS, "lens step 16M")),
+           "valu_roofline": valu_roofline(measured_traffic(TRAFFIC_RECORDS, "lens step 16M", "valu_insts"), ms,
+                                          "lens_step_kernel (VALU issue), over the time of scale_kernel + "
+                                          "lens_step_kernel"),
+           "tile_order": {"note": "the chains regrouped by 256x256-pixel screen tile (lens_chain_sort)",
+                          "ms_per_step": round(ms_s, 4), "ms_per_adaptive_step": round(ms_loop_s, 4),
+                          "mean_alpha": round(acc_s, 4),
+                          "hbm_frac": round(nbytes_s / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "traffic": measured_traffic(TRAFFIC_RECORDS, "lens step 16M tile order"),
+                          "sort_ms": round(ms_sort, 4), "sort_gbs": round(n * 48 / (ms_sort * 1e-3) / 1e9, 1),
+                          "ms_per_step_sorting_every_16": round(ms_s + ms_sort / 16, 4)}}
     del L, om, noise, ad, last, dens, om_s, dens_s, perm, noise_s
     if cpu:
         out["cpu_baseline"] = lens_cpu_baseline()
