@@ -564,18 +564,24 @@ def measure_lens(steps, warmup, cpu=True):
     """Screen-space chains under the regional adaptive lens perturbation on a 1920x1080
     luminance image, 20x20 regions, 16 M chains: one Metropolis step per chain
     (lens_chain_step), and the closed loop (step, then region_adapt of its (region, alpha)
-    stream). The chains carry the luminance of their pixel between steps. Algorithmic bytes
-    per chain of the step: omega 12 + noise 12 + carried luminance 4 read, region 4 + alpha 4
-    + carried luminance 4 written, the luminance at the proposal 4, omega 12 written on
-    acceptance (times the batch's mean alpha).
+    stream). The chains carry the luminance and the index of their pixel between steps.
+    Algorithmic bytes per chain of the step: omega 12 + noise 12 + carried luminance 4 +
+    carried pixel 4 read, region 4 + alpha 4 + carried luminance 4 written, the luminance at
+    the proposal 4, omega 12 + pixel 4 written on acceptance (times the batch's mean alpha).
+
+    The steps alone run with a fixed seeded lambda table, so that their time does not depend on
+    where the adaptation has just left lambda (with 16 M chains every region closes thousands
+    of windows per batch, and lambda swings between its floor, where every proposal stays in
+    its pixel and is accepted, and large scales); the closed loop adapts lambda as it goes.
 
     Order of the launches (the counter records take the timed steps of the first group):
-    `warmup` closed-loop steps, `steps` steps alone (timed), `steps` closed-loop steps (timed);
-    then the chains regrouped by screen tile (lens_chain_sort) and the same three groups."""
+    `warmup` steps alone, `steps` steps alone (timed), `steps` closed-loop steps (timed); then
+    the chains regrouped by screen tile (lens_chain_sort) and the same three groups."""
     import torch
 
     from paper_2402_08273_amd import ops
     from paper_2402_08273_amd.ops import RegionAdapter
+    from synth.directions import make_lambda_table
     from synth.lens import make_lens_chains, make_lens_noise, make_luminance
 
     W, H, tx, N = LENS_CAMERA
@@ -586,37 +592,42 @@ def measure_lens(steps, warmup, cpu=True):
     noise = torch.from_numpy(make_lens_noise(n, seed=9)).cuda()
     ad = RegionAdapter(N * N, L=10)
     dens = torch.full((n,), -1.0, dtype=torch.float32, device=om.device)   # carried luminance
+    pix = torch.full((n,), -2, dtype=torch.int32, device=om.device)       # carried pixel
     last = {}
 
-    def timed(o, nz, d):
+    lam_fixed = torch.from_numpy(make_lambda_table(N * N, seed=7)).cuda()
+
+    def timed(o, nz, d, px):
         def step():
-            last["ra"] = ops.lens_chain_step(L, tx, ad.lam, N, o, nz, density=d)
+            last["ra"] = ops.lens_chain_step(L, tx, lam_fixed, N, o, nz, density=d, pixel=px)
 
         def loop():
-            step()
+            last["ra"] = ops.lens_chain_step(L, tx, ad.lam, N, o, nz, density=d, pixel=px)
             ad.step(*last["ra"])
 
         for _ in range(warmup):
-            loop()
+            step()
         ms = time_loop(stream, step, steps)
         region, alpha = last["ra"]
         ok = region >= 0
         acc = float(alpha[ok].double().mean())
         return ms, time_loop(stream, loop, steps), acc
 
-    ms, ms_loop, acc = timed(om, noise, dens)
-    nbytes = int(n * (44 + 12 * acc))
+    ms, ms_loop, acc = timed(om, noise, dens, pix)
+    nbytes = int(n * (48 + 16 * acc))
     gbs = nbytes / (ms * 1e-3) / 1e9
     # the same chains regrouped by screen tile (lens_chain_sort, 48 B per chain: omega read
     # twice, density read; omega, density and the old index written), then stepped with their
-    # noise regrouped the same way
+    # noise and carried pixels regrouped the same way
     ms_sort = time_loop(stream, lambda: ops.lens_chain_sort(om, W, H, tx, density=dens), steps)
     om_s, dens_s, perm = ops.lens_chain_sort(om, W, H, tx, density=dens)
     noise_s = noise[perm.long()].contiguous()
-    ms_s, ms_loop_s, acc_s = timed(om_s, noise_s, dens_s)
-    nbytes_s = int(n * (44 + 12 * acc_s))
+    pix_s = pix[perm.long()].contiguous()
+    ms_s, ms_loop_s, acc_s = timed(om_s, noise_s, dens_s, pix_s)
+    nbytes_s = int(n * (48 + 16 * acc_s))
     out = {"workload": f"lens-perturbation chains, {n} chains, {W}x{H} luminance, {N}x{N} regions, "
-                       f"tan(fov/2) = {tx}",
+                       f"tan(fov/2) = {tx}; steps alone with a fixed seeded lambda table, the adaptive step "
+                       f"with region_adapt's lambda",
            "chains": n, "ms_per_step": round(ms, 4), "gchains_s": round(n / (ms * 1e-3) / 1e9, 2),
            "ms_per_adaptive_step": round(ms_loop, 4), "mean_alpha": round(acc, 4), "algorithmic_bytes": nbytes,
            "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
@@ -630,9 +641,12 @@ def measure_lens(steps, warmup, cpu=True):
                           "mean_alpha": round(acc_s, 4),
                           "hbm_frac": round(nbytes_s / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                           "traffic": measured_traffic(TRAFFIC_RECORDS, "lens step 16M tile order"),
+                          "valu_roofline": valu_roofline(
+                              measured_traffic(TRAFFIC_RECORDS, "lens step 16M tile order", "valu_insts"), ms_s,
+                              "lens_step_kernel (VALU issue), over the time of scale_kernel + lens_step_kernel"),
                           "sort_ms": round(ms_sort, 4), "sort_gbs": round(n * 48 / (ms_sort * 1e-3) / 1e9, 1),
                           "ms_per_step_sorting_every_16": round(ms_s + ms_sort / 16, 4)}}
-    del L, om, noise, ad, last, dens, om_s, dens_s, perm, noise_s
+    del L, om, noise, ad, last, dens, pix, om_s, dens_s, perm, noise_s, pix_s, lam_fixed
     if cpu:
         out["cpu_baseline"] = lens_cpu_baseline()
     torch.cuda.empty_cache()

@@ -407,6 +407,14 @@ size_t ramlt_perturb_workspace_size(int32_t n_regions);
  * step) is read from the image, and after the step every entry holds the luminance of the
  * chain's pixel (-1 for a chain outside the frame). Results equal those without it as long
  * as the image does not change between steps (reset the entries to -1 when it does).
+ * pixel: DEVICE int32[n] or NULL, read and updated in place: each chain's current pixel
+ * iy * W + ix under the raster map above (-1 for a chain outside the frame or NaN), carried
+ * between steps so that a step skips the raster map of its current state; an entry below -1
+ * or >= W * H (e.g. -2 before the first step) is taken from the raster map of omega, and
+ * after the step every entry holds the chain's pixel. Results equal those without it as
+ * long as the entries are the raster map of omega or below -1 (set them to -2 whenever omega
+ * is changed other than by this call; permute them with the chains, as lens_chain_sort's
+ * perm allows).
  * luminance: DEVICE float[H][W] (>= 0; NaN gives alpha NaN, never a move); lambda:
  * DEVICE double[n_regions^2], 8-byte aligned (e.g. ramlt_region_state.lambda); omega: DEVICE
  * float[n][3], read and updated in place; noise: DEVICE float[n][3]; region: DEVICE int32[n];
@@ -416,8 +424,9 @@ size_t ramlt_perturb_workspace_size(int32_t n_regions);
  * ramlt_lens_workspace_size(n_regions) bytes (0, and NULL allowed, above 65536 regions or for
  * n = 0). Errors: RAMLT_EINVAL, RAMLT_EWORKSPACE. */
 int lens_chain_step(const float *luminance, int32_t W, int32_t H, float tan_half_fov_x, const double *lambda,
-                    int32_t n_regions, float *omega, float *density, const float *noise, int32_t *region,
-                    float *alpha, float *omega_prop, int64_t n, void *workspace, size_t ws_bytes, void *stream);
+                    int32_t n_regions, float *omega, float *density, int32_t *pixel, const float *noise,
+                    int32_t *region, float *alpha, float *omega_prop, int64_t n, void *workspace, size_t ws_bytes,
+                    void *stream);
 
 /* Workspace bytes of lens_chain_step (0 for an invalid n_regions). */
 size_t ramlt_lens_workspace_size(int32_t n_regions);

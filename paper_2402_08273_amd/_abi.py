@@ -221,8 +221,8 @@ def load():
     lib.ramlt_rrmse_workspace_size.restype = ctypes.c_size_t
     lib.lens_chain_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p,
                                     ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
-                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.lens_chain_step.restype = ctypes.c_int
     lib.ramlt_lens_workspace_size.argtypes = [ctypes.c_int32]
     lib.ramlt_lens_workspace_size.restype = ctypes.c_size_t
@@ -395,15 +395,15 @@ def perturb_workspace_size(n_regions):
 
 
 def lens_chain_step_status(luminance, W, H, tan_half_fov_x, lam, n_regions, omega, noise, region, alpha,
-                           omega_prop, n, workspace=None, ws_bytes=0, stream=None, density=None):
-    return load().lens_chain_step(luminance, W, H, tan_half_fov_x, lam, n_regions, omega, density, noise, region,
-                                  alpha, omega_prop, n, workspace, ws_bytes, stream)
+                           omega_prop, n, workspace=None, ws_bytes=0, stream=None, density=None, pixel=None):
+    return load().lens_chain_step(luminance, W, H, tan_half_fov_x, lam, n_regions, omega, density, pixel, noise,
+                                  region, alpha, omega_prop, n, workspace, ws_bytes, stream)
 
 
 def lens_chain_step(luminance, W, H, tan_half_fov_x, lam, n_regions, omega, noise, region, alpha, omega_prop, n,
-                    workspace=None, ws_bytes=0, stream=None, density=None):
+                    workspace=None, ws_bytes=0, stream=None, density=None, pixel=None):
     return _check(lens_chain_step_status(luminance, W, H, tan_half_fov_x, lam, n_regions, omega, noise, region,
-                                         alpha, omega_prop, n, workspace, ws_bytes, stream, density))
+                                         alpha, omega_prop, n, workspace, ws_bytes, stream, density, pixel))
 
 
 def lens_workspace_size(n_regions):

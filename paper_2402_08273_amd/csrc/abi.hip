@@ -337,8 +337,9 @@ int perturb_directions(const double *lambda, int32_t n_regions, const int32_t *r
 }
 
 int lens_chain_step(const float *luminance, int32_t W, int32_t H, float tan_half_fov_x, const double *lambda,
-                    int32_t n_regions, float *omega, float *density, const float *noise, int32_t *region,
-                    float *alpha, float *omega_prop, int64_t n, void *workspace, size_t ws_bytes, void *stream) {
+                    int32_t n_regions, float *omega, float *density, int32_t *pixel, const float *noise,
+                    int32_t *region, float *alpha, float *omega_prop, int64_t n, void *workspace, size_t ws_bytes,
+                    void *stream) {
   if (W < 1 || H < 1 || W > RAMLT_MAX_SIDE || H > RAMLT_MAX_SIDE || (long long)W * H > RAMLT_MAX_PLANE_ELEMS)
     return fail(RAMLT_EINVAL, "lens_chain_step: image size %d x %d out of range", W, H);
   if (!std::isfinite(tan_half_fov_x) || !(tan_half_fov_x > 0.0f))
@@ -364,6 +365,7 @@ int lens_chain_step(const float *luminance, int32_t W, int32_t H, float tan_half
       return fail(RAMLT_EINVAL, "lens_chain_step: omega_prop is not 4-byte aligned");
     if (density && !aligned(density, 4))
       return fail(RAMLT_EINVAL, "lens_chain_step: density is not 4-byte aligned");
+    if (pixel && !aligned(pixel, 4)) return fail(RAMLT_EINVAL, "lens_chain_step: pixel is not 4-byte aligned");
     const size_t need = ramlt::perturb_workspace_bytes(n_regions * n_regions);
     if (need > 0) {
       if (workspace == nullptr || ws_bytes < need)
@@ -375,7 +377,8 @@ int lens_chain_step(const float *luminance, int32_t W, int32_t H, float tan_half
   int r = check_device();
   if (r) return r;
   const hipError_t e = ramlt::launch_lens_step(luminance, W, H, tan_half_fov_x, ty, lambda, n_regions, omega, density,
-                                               noise, region, alpha, omega_prop, n, workspace, (hipStream_t)stream);
+                                               pixel, noise, region, alpha, omega_prop, n, workspace,
+                                               (hipStream_t)stream);
   if (e != hipSuccess) return fail(RAMLT_EHIP, "lens_chain_step: %s", hipGetErrorString(e));
   g_last_error.clear();
   return RAMLT_OK;

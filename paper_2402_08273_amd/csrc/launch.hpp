@@ -46,8 +46,8 @@ size_t perturb_workspace_bytes(int m);
 // Lens-perturbation chain step (perturb.hip): validated arguments; ty = tx H / W; the
 // workspace is perturb_workspace_bytes(N * N).
 hipError_t launch_lens_step(const float *lum, int W, int H, float tx, float ty, const double *lambda, int N,
-                            float *omega, float *density, const float *noise, int32_t *region, float *alpha,
-                            float *omega_prop, long long n, void *ws, hipStream_t st);
+                            float *omega, float *density, int32_t *pixel, const float *noise, int32_t *region,
+                            float *alpha, float *omega_prop, long long n, void *ws, hipStream_t st);
 
 // Reorder of lens chains by screen tile (chains.hip): validated arguments; ty as for the
 // step. Tiles are 2^lens_sort_tile_shift(W, H) pixels on a side.

@@ -137,20 +137,33 @@ __global__ __launch_bounds__(kPerturbBlock) void perturb_kernel(const Scale *__r
 // the luminance at both pixels (0 outside the frame), move iff the uniform is below alpha.
 // With `density`, each chain carries the luminance of its current pixel between steps (an
 // entry below 0 or NaN is read from the image), so a step reads the image once per chain,
-// at the proposal, instead of twice.
+// at the proposal, instead of twice. With `pixel`, each chain carries its current pixel
+// (iy W + ix, -1 outside the frame; an entry below -1 or past the image is taken from the
+// raster map of omega), so a step skips the raster map of its current state: its four
+// correctly rounded divisions were an eighth of the step's instructions.
 template <bool kTable>
 __global__ __launch_bounds__(kPerturbBlock) void lens_step_kernel(
-    const Scale *__restrict__ table, const double *__restrict__ lambda, int N, FastDiv d2W, FastDiv d2H,
+    const Scale *__restrict__ table, const double *__restrict__ lambda, int N, FastDiv d2W, FastDiv d2H, FastDiv dW,
     const float *__restrict__ lum, int W, int H, float tx, float ty, float *__restrict__ omega,
-    float *__restrict__ density, const float *__restrict__ noise, int32_t *__restrict__ region,
-    float *__restrict__ alpha, float *__restrict__ omega_prop, long long n) {
+    float *__restrict__ density, int32_t *__restrict__ pixel, const float *__restrict__ noise,
+    int32_t *__restrict__ region, float *__restrict__ alpha, float *__restrict__ omega_prop, long long n) {
   const long long i = (long long)blockIdx.x * kPerturbBlock + threadIdx.x;
   if (i >= n) return;
   const float wx = omega[3 * i], wy = omega[3 * i + 1], wz = omega[3 * i + 2];
   const float u = noise[3 * i], v = noise[3 * i + 1], ua = noise[3 * i + 2];
-  const Raster c = raster_of(wx, wy, wz, tx, ty, W, H);
+  const int carried_pix = pixel ? pixel[i] : -2;
+  const bool known = carried_pix >= -1 && carried_pix < W * H;  // W H <= 2^30
+  Raster c;
+  if (known) {
+    c.inside = carried_pix >= 0;
+    c.iy = c.inside ? (int)fast_div((uint32_t)carried_pix, dW) : 0;
+    c.ix = c.inside ? carried_pix - c.iy * W : 0;
+  } else {
+    c = raster_of(wx, wy, wz, tx, ty, W, H);
+  }
   int k = -1;
   float a = __builtin_nanf(""), ox = a, oy = a, oz = a, dens = -1.0f;
+  int new_pix = -1;
   if (c.inside) {
     // (2 i + 1) N < 2^17 2^12: exact by FastDiv
     const int kx = (int)fast_div((uint32_t)(2 * c.ix + 1) * (uint32_t)N, d2W);
@@ -169,16 +182,19 @@ __global__ __launch_bounds__(kPerturbBlock) void lens_step_kernel(
       a = 0.0f;
     }
     dens = lc;
+    new_pix = c.iy * W + c.ix;
     if (ua < a) {
       omega[3 * i] = ox;
       omega[3 * i + 1] = oy;
       omega[3 * i + 2] = oz;
       dens = lp;
+      new_pix = p.iy * W + p.ix;  // a = 0 outside the frame: p is inside here
     }
   }
   region[i] = k;
   alpha[i] = a;
   if (density) density[i] = dens;
+  if (pixel && new_pix != carried_pix) pixel[i] = new_pix;
   if (omega_prop) {
     omega_prop[3 * i] = ox;
     omega_prop[3 * i + 1] = oy;
@@ -209,20 +225,22 @@ hipError_t launch_perturb(const double *lambda, int m, const int32_t *region, co
 }
 
 hipError_t launch_lens_step(const float *lum, int W, int H, float tx, float ty, const double *lambda, int N,
-                            float *omega, float *density, const float *noise, int32_t *region, float *alpha,
-                            float *omega_prop, long long n, void *ws, hipStream_t st) {
+                            float *omega, float *density, int32_t *pixel, const float *noise, int32_t *region,
+                            float *alpha, float *omega_prop, long long n, void *ws, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int m = N * N;
   const long long blocks = (n + kPerturbBlock - 1) / kPerturbBlock;
   const FastDiv d2W = make_fastdiv(2u * (uint32_t)W), d2H = make_fastdiv(2u * (uint32_t)H);
+  const FastDiv dW = make_fastdiv((uint32_t)W);
   if (m <= kMaxTableRegions) {
     Scale *table = (Scale *)ws;
     scale_kernel<<<(m + kPerturbBlock - 1) / kPerturbBlock, kPerturbBlock, 0, st>>>(lambda, m, table);
     lens_step_kernel<true><<<(unsigned)blocks, kPerturbBlock, 0, st>>>(
-        table, lambda, N, d2W, d2H, lum, W, H, tx, ty, omega, density, noise, region, alpha, omega_prop, n);
+        table, lambda, N, d2W, d2H, dW, lum, W, H, tx, ty, omega, density, pixel, noise, region, alpha, omega_prop, n);
   } else {
     lens_step_kernel<false><<<(unsigned)blocks, kPerturbBlock, 0, st>>>(
-        nullptr, lambda, N, d2W, d2H, lum, W, H, tx, ty, omega, density, noise, region, alpha, omega_prop, n);
+        nullptr, lambda, N, d2W, d2H, dW, lum, W, H, tx, ty, omega, density, pixel, noise, region, alpha, omega_prop,
+        n);
   }
   return hipGetLastError();
 }

@@ -475,13 +475,16 @@ def perturb_directions(lam, region, omega, uv, theta=False):
     return (out, th) if theta else out
 
 
-def lens_chain_step(luminance, tan_half_fov_x, lam, n_regions, omega, noise, want_proposals=False, density=None):
+def lens_chain_step(luminance, tan_half_fov_x, lam, n_regions, omega, noise, want_proposals=False, density=None,
+                    pixel=None):
     """One Metropolis step of screen-space chains under the regional adaptive lens
     perturbation (Sec. 3.3, Sec. 6.1, Alg. 1 lines 8-13) with the luminance image as target:
     luminance float32 [H, W]; lam float64 [n_regions^2] (e.g. ``RegionAdapter.lam``); omega
     float32 [n, 3] primary directions, updated in place; noise float32 [n, 3] = (u, v,
     acceptance uniform); density (optional) float32 [n], the luminance of each chain's pixel
-    carried between steps (start it at -1; updated in place). Returns (region int32 [n],
+    carried between steps (start it at -1; updated in place); pixel (optional) int32 [n], the
+    pixel of each chain carried between steps (start it at -2; updated in place). Returns
+    (region int32 [n],
     alpha float32 [n]) for :class:`RegionAdapter` (and the proposals [n, 3] with
     ``want_proposals=True``)."""
     if luminance.dtype != torch.float32 or luminance.dim() != 2 or not luminance.is_contiguous() \
@@ -498,6 +501,8 @@ def lens_chain_step(luminance, tan_half_fov_x, lam, n_regions, omega, noise, wan
     if density is not None and (density.dtype != torch.float32 or tuple(density.shape) != (n,)
                                 or not density.is_contiguous()):
         raise ValueError("density must be a contiguous float32 [n] tensor")
+    if pixel is not None and (pixel.dtype != torch.int32 or tuple(pixel.shape) != (n,) or not pixel.is_contiguous()):
+        raise ValueError("pixel must be a contiguous int32 [n] tensor")
     H, W = luminance.shape
     region = torch.empty(n, device=omega.device, dtype=torch.int32)
     alpha = torch.empty(n, device=omega.device, dtype=torch.float32)
@@ -507,7 +512,8 @@ def lens_chain_step(luminance, tan_half_fov_x, lam, n_regions, omega, noise, wan
     ws = torch.empty(need + 256, device=omega.device, dtype=torch.uint8) if need else None
     wp = (ws.data_ptr() + 255) // 256 * 256 if need else None
     _abi.lens_chain_step(luminance.data_ptr(), W, H, float(tan_half_fov_x), lam.data_ptr(), n_regions, p(omega),
-                         p(noise), p(region), p(alpha), p(prop), n, wp, need, _stream(), density=p(density))
+                         p(noise), p(region), p(alpha), p(prop), n, wp, need, _stream(), density=p(density),
+                         pixel=p(pixel))
     return (region, alpha, prop) if want_proposals else (region, alpha)
 
 

@@ -21,7 +21,7 @@ int main(void) {
   printf("qt_null %d\n", quadtree_lookup(NULL, NULL, NULL, NULL, NULL, 0, 1, NULL));
   printf("perturb_bad %d\n", perturb_directions(NULL, 0, NULL, NULL, NULL, NULL, NULL, 0, NULL, 0, NULL));
   printf("rrmse_bad %d\n", rrmse(NULL, NULL, 0, 0, 0.01, NULL, NULL, NULL, 0, NULL));
-  printf("lens_bad %d\n", lens_chain_step(NULL, 64, 32, 0.5f, NULL, 4, NULL, NULL, NULL, NULL, NULL, NULL, 0, NULL, 0, NULL));
+  printf("lens_bad %d\n", lens_chain_step(NULL, 64, 32, 0.5f, NULL, 4, NULL, NULL, NULL, NULL, NULL, NULL, NULL, 0, NULL, 0, NULL));
   printf("lens_ws %d\n", ramlt_lens_workspace_size(20) > 0);
   printf("lens_sort_bad %d\n", lens_chain_sort(0, 32, 0.5f, NULL, NULL, 10, NULL, NULL, NULL, NULL, 0, NULL));
   printf("lens_sort_ws %d\n", ramlt_lens_sort_workspace_size(1 << 20) > 0);

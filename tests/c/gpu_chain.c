@@ -311,7 +311,7 @@ int main(int argc, char **argv) {
   float *lprop = dev_alloc(sizeof(float) * 3 * (size_t)n_chains);
   size_t lws = ramlt_lens_workspace_size(N);
   void *lw = dev_alloc(lws);
-  RAMLT_OK_(lens_chain_step(lum, W, H, tan_half, grid.lambda, N, chains, NULL, noise, lregion, lalpha, lprop,
+  RAMLT_OK_(lens_chain_step(lum, W, H, tan_half, grid.lambda, N, chains, NULL, NULL, noise, lregion, lalpha, lprop,
                             n_chains, lw, lws, NULL));
   HIP_OK(hipDeviceSynchronize());
   download("out_lens_region.i32", lregion, sizeof(int32_t) * (size_t)n_chains);

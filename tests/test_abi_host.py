@@ -395,6 +395,7 @@ def test_lens_chain_step_validation(lib):
     assert st() in ok, _abi.last_error()
     assert st(omega_prop=None) in ok
     assert st(density=0x800000) in ok and st(density=0x800002) == _abi.RAMLT_EINVAL
+    assert st(pixel=0x900000) in ok and st(pixel=0x900001) == _abi.RAMLT_EINVAL
     assert st(omega=None, noise=None, region=None, alpha=None, omega_prop=None, n=0) in ok
     bad = [dict(W=0), dict(H=0), dict(W=65537), dict(tan_half_fov_x=0.0), dict(tan_half_fov_x=-1.0),
            dict(tan_half_fov_x=float("inf")), dict(tan_half_fov_x=float("nan")), dict(tan_half_fov_x=1e-45, H=1),

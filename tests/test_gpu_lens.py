@@ -170,6 +170,44 @@ def test_lens_carried_density_gives_the_same_steps():
     assert np.array_equal(d[inside], img[iy[inside], ix[inside]]) and np.all(d[~inside] == -1.0)
 
 
+@pytest.mark.parametrize("W,H,N", [(320, 200, 20), (1920, 1080, 20), (77, 45, 3), (1, 1, 1)])
+def test_lens_carried_pixel_gives_the_same_steps(W, H, N):
+    # carrying each chain's pixel between steps (no raster map of the current state) changes
+    # nothing in the results: five steps with the pixel (and with pixel and luminance) agree
+    # bit for bit with five steps without either, chains outside the frame and NaN states
+    # included; entries below -1 or past the image are taken from the raster map
+    tx, n = 0.6, 100_003
+    print(f"lens carried pixel W={W} H={H} N={N}", flush=True)
+    L = _dev(make_luminance(W, H, seed=12))
+    lam = _dev(make_lambda_table(N * N, seed=13))
+    om0 = make_lens_chains(n, W, H, tx, seed=14)
+    om0[:50] = [0.0, 0.0, -1.0]          # behind the camera
+    om0[50:60] = [np.nan, 0.0, 1.0]
+    om0[60:70] = [5.0, 0.0, 1.0]         # outside the field of view
+    om_a, om_b, om_c = _dev(om0), _dev(om0), _dev(om0)
+    pix_b = torch.full((n,), -2, dtype=torch.int32, device="cuda")
+    pix_b[1::7] = W * H + 5              # past the image: recomputed as well
+    pix_c = torch.full((n,), -2, dtype=torch.int32, device="cuda")
+    dens_c = torch.full((n,), -1.0, dtype=torch.float32, device="cuda")
+    for r in range(5):
+        nz = _dev(make_lens_noise(n, seed=15, batch=r))
+        ra, aa, pa = ops.lens_chain_step(L, tx, lam, N, om_a, nz, want_proposals=True)
+        rb, ab, pb = ops.lens_chain_step(L, tx, lam, N, om_b, nz, want_proposals=True, pixel=pix_b)
+        rc, ac = ops.lens_chain_step(L, tx, lam, N, om_c, nz, density=dens_c, pixel=pix_c)
+        torch.cuda.synchronize()
+        for rr, aa2 in ((rb, ab), (rc, ac)):
+            assert torch.equal(ra, rr), r
+            assert np.array_equal(aa.cpu().numpy(), aa2.cpu().numpy(), equal_nan=True), r
+        assert np.array_equal(pa.cpu().numpy(), pb.cpu().numpy(), equal_nan=True), r
+        for o in (om_b, om_c):
+            assert np.array_equal(om_a.cpu().numpy(), o.cpu().numpy(), equal_nan=True), r
+    # the carried pixel is the oracle's raster map of each final state
+    inside, ix, iy = olc.raster(om_a.cpu().numpy(), W, H, tx)
+    want = np.where(inside, iy * W + ix, -1)
+    assert np.array_equal(pix_b.cpu().numpy(), want) and np.array_equal(pix_c.cpu().numpy(), want)
+    assert (want[:70] == -1).all() and (ra[:70] == -1).all()
+
+
 @pytest.mark.parametrize("W,H,n", [(1920, 1080, 300_037), (3840, 2160, 70_001), (100, 40, 4097), (1, 1, 5000),
                                    (640, 360, 1), (640, 360, 0), (1000, 1000, 4096)])
 def test_lens_chain_sort_matches_the_stable_tile_order(W, H, n):
