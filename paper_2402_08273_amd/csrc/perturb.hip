@@ -139,8 +139,8 @@ __global__ __launch_bounds__(kPerturbBlock) void perturb_kernel(const Scale *__r
 // entry below 0 or NaN is read from the image), so a step reads the image once per chain,
 // at the proposal, instead of twice. With `pixel`, each chain carries its current pixel
 // (iy W + ix, -1 outside the frame; an entry below -1 or past the image is taken from the
-// raster map of omega), so a step skips the raster map of its current state: its four
-// correctly rounded divisions were an eighth of the step's instructions.
+// raster map of omega), so a step skips the raster map of its current state (four correctly
+// rounded divisions and the compares, 8 % of the step's instructions).
 template <bool kTable>
 __global__ __launch_bounds__(kPerturbBlock) void lens_step_kernel(
     const Scale *__restrict__ table, const double *__restrict__ lambda, int N, FastDiv d2W, FastDiv d2H, FastDiv dW,
