@@ -464,6 +464,9 @@ def perturb_directions(lam, region, omega, uv, theta=False):
         raise ValueError("omega must be a contiguous float32 [n, 3] tensor")
     if uv.dtype != torch.float32 or tuple(uv.shape) != (n, 2) or not uv.is_contiguous():
         raise ValueError("uv must be a contiguous float32 [n, 2] tensor")
+    for name, t in (("region", region), ("omega", omega), ("uv", uv)):
+        if t.device != lam.device:
+            raise ValueError(f"{name} must be on lam's device ({lam.device})")
     out = torch.empty_like(omega)
     th = torch.empty(n, device=omega.device, dtype=torch.float32) if theta else None
     p = (lambda t: t.data_ptr() if (t is not None and n) else None)
@@ -503,6 +506,9 @@ def lens_chain_step(luminance, tan_half_fov_x, lam, n_regions, omega, noise, wan
         raise ValueError("density must be a contiguous float32 [n] tensor")
     if pixel is not None and (pixel.dtype != torch.int32 or tuple(pixel.shape) != (n,) or not pixel.is_contiguous()):
         raise ValueError("pixel must be a contiguous int32 [n] tensor")
+    for name, t in (("omega", omega), ("noise", noise), ("lam", lam), ("density", density), ("pixel", pixel)):
+        if t is not None and t.device != luminance.device:
+            raise ValueError(f"{name} must be on the luminance's device ({luminance.device})")
     H, W = luminance.shape
     region = torch.empty(n, device=omega.device, dtype=torch.int32)
     alpha = torch.empty(n, device=omega.device, dtype=torch.float32)

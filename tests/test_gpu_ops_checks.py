@@ -61,3 +61,27 @@ def test_filter_refuses_misshaped_outputs():
     G, gl = ops.filter_backward(U, mean, out, lam, r, S, N)
     torch.cuda.synchronize()
     assert np.all(G.cpu().numpy() == 0) and np.all(gl.cpu().numpy() == 0)
+
+
+def test_lens_step_refuses_state_on_another_device_or_of_another_type():
+    # checked before anything is launched; with no chains nothing would be launched anyway,
+    # so a missing check could not reach the kernel with a host pointer
+    L = _f32(16, 32)
+    lam = torch.zeros(4, dtype=torch.float64, device="cuda")
+    om, nz = _f32(0, 3), _f32(0, 3)
+    cases = {
+        "density on the host": dict(density=torch.zeros(0, dtype=torch.float32)),
+        "pixel on the host": dict(pixel=torch.zeros(0, dtype=torch.int32)),
+        "pixel int64": dict(pixel=torch.zeros(0, dtype=torch.int64, device="cuda")),
+        "pixel of the wrong length": dict(pixel=torch.zeros(3, dtype=torch.int32, device="cuda")),
+    }
+    for name, kw in cases.items():
+        with pytest.raises(ValueError):
+            ops.lens_chain_step(L, 0.5, lam, 2, om, nz, **kw)
+        print("refused:", name, flush=True)
+    with pytest.raises(ValueError):
+        ops.lens_chain_step(L, 0.5, lam, 2, torch.zeros((0, 3), dtype=torch.float32), nz)
+    region, alpha = ops.lens_chain_step(L, 0.5, lam, 2, om, nz, density=_f32(0),
+                                        pixel=torch.zeros(0, dtype=torch.int32, device="cuda"))
+    torch.cuda.synchronize()
+    assert region.numel() == 0 and alpha.numel() == 0
