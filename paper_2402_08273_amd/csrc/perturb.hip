@@ -52,6 +52,36 @@ __device__ __forceinline__ double horner(const double (&c)[N], double t) {
   return p;
 }
 
+// Natural logarithm of v in [0, 1] (v = x (2 - x) below) in fp64, from the series of
+// atanh: v = m 2^e with m in [sqrt(1/2), sqrt(2)), log v = e ln 2 + 2 atanh(f),
+// f = (m - 1) / (m + 1), |f| <= 3 - 2 sqrt(2) < 0.1716, and 2 atanh(f) = 2 f (1 + f^2/3 + f^4/5
+// + ...) cut after f^14/15: the first term left out is below 2 f^16/17 < 3.6e-14 relative
+// to 2 f, so the result is within ~1e-13 relative of log v (a few ulp of rounding besides),
+// far inside what the inverse CDF built on it needs (1e-9). Eight fused steps and one
+// division replace the library's double-double logarithm, ~50 instructions fewer per
+// proposal. log 0 = -inf; NaN gives NaN.
+__device__ __forceinline__ double log_unit(double v) {
+  constexpr double kSqrtHalf = 0.70710678118654752440;
+  constexpr double kLn2 = 0.69314718055994530942;
+  int e;
+  double m = frexp(v, &e);  // m in [1/2, 1) for v > 0
+  const bool lo = m < kSqrtHalf;
+  m = lo ? m + m : m;
+  e = lo ? e - 1 : e;
+  const double f = (m - 1.0) / (m + 1.0);
+  const double f2 = f * f;
+  double p = 1.0 / 15.0;
+  p = fma(p, f2, 1.0 / 13.0);
+  p = fma(p, f2, 1.0 / 11.0);
+  p = fma(p, f2, 1.0 / 9.0);
+  p = fma(p, f2, 1.0 / 7.0);
+  p = fma(p, f2, 1.0 / 5.0);
+  p = fma(p, f2, 1.0 / 3.0);
+  p = fma(p, f2, 1.0);
+  const double r = fma((double)e, kLn2, 2.0 * f * p);
+  return v == 0.0 ? -__builtin_huge_val() : r;
+}
+
 // erfinv(y) for y in [0, 1], given y and its complement x = 1 - y, each to full relative
 // precision: y P(w) with w = -log(x (2 - x)) = -log(1 - y^2) (Giles, GPU Computing Gems Jade
 // Edition, 2011), P a polynomial in w below w = 6.25 and in sqrt(w) on three intervals up to
@@ -60,7 +90,7 @@ __device__ __forceinline__ double horner(const double (&c)[N], double t) {
 // first form: the tail needs x < 0.001 (w >= 6.25).
 __device__ __forceinline__ double erfinv_from_complement(double y, double x) {
   namespace ep = erfinv_poly;
-  const double w = -log(x * (2.0 - x));
+  const double w = -log_unit(x * (2.0 - x));
   if (w < ep::kCentralHi) return y * horner(ep::kCentral, fma(w, ep::kCentralScale, ep::kCentralShift));
   const double s = sqrt(w);
   if (s < ep::kTail1Hi) return y * horner(ep::kTail1, fma(s, ep::kTail1Scale, ep::kTail1Shift));

@@ -1,8 +1,10 @@
 """The inverse-error-function polynomials of the perturbation kernel
 (paper_2402_08273_amd/csrc/erfinv_poly.hpp), evaluated on the CPU in fp64 exactly as the
-kernel composes them (w = -log(x (2 - x)) from the complement x, Horner in the normalised
-variable, y times the polynomial), against mpmath's erfinv at 80 digits: relative error
-below 1e-9 over every piece, its ends, and the smallest complement a float32 u gives.
+kernel composes them (w = -log(x (2 - x)) from the complement x, with the kernel's own
+logarithm from the atanh series, Horner in the normalised variable, y times the
+polynomial), against mpmath's erfinv at 80 digits: relative error below 1e-9 over every
+piece, its ends, and the smallest complement a float32 u gives. The logarithm is also
+checked on its own against mpmath's over (0, 1].
 
 The kernel stores theta' = sigma sqrt 2 erfinv(y) as float32: with erfinv's relative error
 eps, |theta_f32 - theta| <= 2^-24 |theta| (rounding) + eps |theta| (1 + 2^-24), within the
@@ -42,9 +44,50 @@ def _horner(c, t):
     return p
 
 
+SQRT_HALF = 0.70710678118654752440
+LN2 = 0.69314718055994530942
+
+
+def log_unit(v):
+    """The kernel's logarithm of v in [0, 1] (log_unit in perturb.hip), step by step in fp64:
+    v = m 2^e, m in [sqrt(1/2), sqrt(2)), e ln 2 + 2 f (1 + f^2/3 + ... + f^14/15),
+    f = (m - 1) / (m + 1) (the kernel fuses the multiply-adds: <= 1 ulp per step apart)."""
+    if v == 0.0:
+        return -math.inf
+    m, e = math.frexp(v)
+    if m < SQRT_HALF:
+        m, e = m + m, e - 1
+    f = (m - 1.0) / (m + 1.0)
+    f2 = f * f
+    p = 1.0 / 15.0
+    for c in (1.0 / 13.0, 1.0 / 11.0, 1.0 / 9.0, 1.0 / 7.0, 1.0 / 5.0, 1.0 / 3.0, 1.0):
+        p = p * f2 + c
+    return e * LN2 + 2.0 * f * p
+
+
+def test_log_unit_against_mpmath():
+    # relative error of the series logarithm over (0, 1]: near 1 (no cancellation, e = 0), at
+    # and around powers of two and sqrt(1/2) (the ends of the mantissa range), random
+    # points, and the smallest arguments the kernel can form (x (2 - x) >= 2^-147)
+    rng = np.random.default_rng(5)
+    vs = [1.0, 1.0 - 2.0 ** -53, 1.0 - 1e-12, 1.0 - 1e-6, 0.999, 0.75, 0.5, 0.5 + 2.0 ** -53, 0.5 - 2.0 ** -54,
+          SQRT_HALF, math.nextafter(SQRT_HALF, 0.0), math.nextafter(SQRT_HALF, 1.0), 2.0 ** -147, 2.0 ** -1022,
+          2.0 ** -1074, 1e-300, 1e-30, 3e-8]
+    vs += list(rng.random(2000)) + list(2.0 ** -rng.uniform(0, 140, 2000))
+    worst = 0.0
+    with mp.workdps(40):
+        for v in vs:
+            want = mp.log(mp.mpf(v))
+            got = log_unit(v)
+            rel = abs((mp.mpf(got) - want) / want) if want != 0 else abs(mp.mpf(got))
+            worst = max(worst, float(rel))
+    assert worst < 2e-13, worst
+    assert log_unit(0.0) == -math.inf and math.isnan(log_unit(math.nan))
+
+
 def erfinv_kernel(y, x):
     """The kernel's composition, in fp64 (None where the kernel defers to erfcinv)."""
-    w = -math.log(x * (2.0 - x))
+    w = -log_unit(x * (2.0 - x))
     c = PIECES["Central"]
     if w < c["hi"]:
         return y * _horner(c["c"], w * c["scale"] + c["shift"])
