@@ -181,6 +181,8 @@ __global__ __launch_bounds__(kPerturbBlock) void lens_step_kernel(
   if (i >= n) return;
   const float wx = omega[3 * i], wy = omega[3 * i + 1], wz = omega[3 * i + 2];
   const float u = noise[3 * i], v = noise[3 * i + 1], ua = noise[3 * i + 2];
+  // every load of the chain's own state up front: issued together, one round trip
+  const float carried = density ? density[i] : -1.0f;
   const int carried_pix = pixel ? pixel[i] : -2;
   const bool known = carried_pix >= -1 && carried_pix < W * H;  // W H <= 2^30
   Raster c;
@@ -202,7 +204,6 @@ __global__ __launch_bounds__(kPerturbBlock) void lens_step_kernel(
     const float th = (float)theta_of((double)u, kTable ? table[k] : scale_of(lambda[k]));
     propose(wx, wy, wz, th, v, ox, oy, oz);
     const Raster p = raster_of(ox, oy, oz, tx, ty, W, H);
-    const float carried = density ? density[i] : -1.0f;
     const float lc = carried >= 0.0f ? carried : lum[(long long)c.iy * W + c.ix];
     float lp = 0.0f;
     if (p.inside) {
