@@ -533,7 +533,11 @@ def measure_perturb(steps, warmup, cpu=True):
         out["grids"].append({"regions": m, "ms_per_batch": round(ms, 4),
                              "gproposals_s": round(n / (ms * 1e-3) / 1e9, 2), "algorithmic_bytes": nbytes,
                              "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                             "roofline": hbm_roofline(nbytes, ms, "scale_kernel + perturb_kernel")})
+                             "roofline": hbm_roofline(nbytes, ms, "scale_kernel + perturb_kernel",
+                                                      measured_traffic(TRAFFIC_RECORDS, f"perturb 16M {m}")),
+                             "valu_roofline": valu_roofline(
+                                 measured_traffic(TRAFFIC_RECORDS, f"perturb 16M {m}", "valu_insts"), ms,
+                                 "perturb_kernel (VALU issue), over the time of scale_kernel + perturb_kernel")})
         del lam, region, omega, uv
     if cpu:
         out["cpu_baseline"] = perturb_cpu_baseline()
@@ -694,7 +698,8 @@ def measure_rrmse(steps, warmup, cpu=True):
         out["images"].append({"W": W, "H": H, "ms": round(ms, 4), "mpx_s": round(W * H / (ms * 1e-3) / 1e6, 1),
                               "algorithmic_bytes": nbytes, "achieved_gbs": round(gbs, 1),
                               "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                              "roofline": hbm_roofline(nbytes, ms, "rel_error_kernel + finalize")})
+                              "roofline": hbm_roofline(nbytes, ms, "rel_error_kernel + finalize",
+                                                       measured_traffic(TRAFFIC_RECORDS, f"rrmse {W}x{H}"))})
         del I, R
     if cpu:
         from oracle import rrmse as orr
@@ -782,7 +787,11 @@ def measure_quadtree(steps, warmup, cpu=True):
                              "lookup_nocount_ms": round(ms_nc, 4),
                              "bytes_per_point": bpp, "achieved_gbs": round(gbs, 1),
                              "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "refine_ms": round(rms, 4),
-                             "roofline": hbm_roofline(n * bpp, ms, "lookup_kernel (one launch)")})
+                             "roofline": hbm_roofline(n * bpp, ms, "lookup_kernel (one launch)",
+                                                      measured_traffic(TRAFFIC_RECORDS, f"quadtree lookup 16M {name}")),
+                             "valu_roofline": valu_roofline(
+                                 measured_traffic(TRAFFIC_RECORDS, f"quadtree lookup 16M {name}", "valu_insts"), ms,
+                                 "lookup_kernel (VALU issue)")})
         del t, ad, x, y, root, leaf, snap, live
     if cpu:
         out["cpu_baseline"] = quadtree_cpu_baseline()
