@@ -100,7 +100,9 @@ enum ramlt_tile { RAMLT_TILE_DEFAULT = 0, RAMLT_TILE_32X8 = 1, RAMLT_TILE_32X16 
  * v = 1..14: the frame's 256-pixel tiles are covered by a series of launches of v
  * workgroups per compute unit each, so that every workgroup of a launch is resident from
  * its start; v = 15: one launch covers the whole frame; v = 0: the default (4 per compute
- * unit). A batch takes the value of its first frame. Results do not depend on it. */
+ * unit). A batch takes the value of its first frame. A single frame of fewer than 1024
+ * tiles (under 262 144 pixels) ignores it: one launch of a workgroup per (tile, channel).
+ * Results do not depend on it. */
 #define RAMLT_STATS_WG_SHIFT 4
 #define RAMLT_STATS_WG_MASK (15 << RAMLT_STATS_WG_SHIFT)
 #define RAMLT_STATS_ONE_LAUNCH 15

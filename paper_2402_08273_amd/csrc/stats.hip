@@ -49,6 +49,9 @@ constexpr int kStoreSC1 = 16;    // buffer cache-policy operand: sc1
 // 0.91-0.95 ms. With 16-sample chunks for the fp32 features as well, 3 per CU was best
 // (0.879 ms).
 constexpr int kStatsWgPerCu = 4;
+// A single frame of fewer 256-pixel tiles than this (under 262 144 pixels) gets a workgroup per
+// (tile, channel) instead of per tile, and one launch whatever the launch size asks for.
+constexpr long long kChannelSplitTiles = 1024;
 constexpr int kMaxDevices = 64;
 
 // Workgroups (tiles, or batched units) per launch on the current device for the launch
@@ -266,6 +269,46 @@ __device__ __forceinline__ void stats_tile(const ramlt_frame &f, long long pix0,
   }
 }
 
+// One (256-pixel tile, channel) per workgroup, for frames of few tiles: blockIdx.x = tile,
+// blockIdx.y = channel (radiance 0-2, then the features). A workgroup per tile would leave most
+// compute units idle there while each workgroup walks its channels one after another. The
+// channel functions, their order of operations and the result slots are those of stats_tile,
+// so the results are bit for bit the same.
+template <int KT, int B>
+__global__ __launch_bounds__(kStatsBlock) void stats_channel_kernel(const ramlt_frame f) {
+  __shared__ float park_all[kParked * kStatsBlock];
+  const long long P = (long long)f.W * f.H;
+  const int t = threadIdx.x;
+  const long long pix = (long long)blockIdx.x * kStatsBlock + t;
+  if (pix >= P) return;
+  float *park = park_all + t;
+  const int y = (int)((unsigned)pix / (unsigned)f.W);
+  const int x = (int)pix - y * f.W;
+  const uint32_t o = (uint32_t)pix;
+  const int c = blockIdx.y;
+  if (c < RAMLT_N_RADIANCE) {
+    const int K_L = min(f.max_lag, f.S - 1);
+    const uint32_t roff = (uint32_t)((long long)y * f.rad_stride_y + x);
+    float *pk = park + 3 * c * kStatsBlock;
+    radiance_channel<KT, B>(f.radiance + c * f.rad_stride_c, f.rad_stride_s, roff, f.S, K_L, pk,
+                            f.lag_corr ? f.lag_corr + (long long)c * K_L * P + pix : nullptr, P);
+    store_result(f.mean + c * P, o, pk[0]);
+    store_result(f.var + c * P, o, pk[kStatsBlock]);
+    store_result(f.tau + c * P, o, pk[2 * kStatsBlock]);
+    return;
+  }
+  const int fc = c - RAMLT_N_RADIANCE;
+  const uint32_t foff = (uint32_t)((long long)y * f.feat_stride_y + x);
+  float *fpark = park + (9 + fc) * kStatsBlock;
+  if (f.feat_dtype == RAMLT_F16)
+    feature_channel<_Float16, 16>((const _Float16 *)f.features + fc * f.feat_stride_c, f.feat_stride_s, foff, f.S,
+                                  fpark);
+  else
+    feature_channel<float, 8>((const float *)f.features + fc * f.feat_stride_c, f.feat_stride_s, foff, f.S, fpark);
+  store_result(f.feat_mean + fc * P, o, fpark[0]);
+  store_result(f.feat_var + fc * P, o, fpark[RAMLT_N_FEATURES * kStatsBlock]);
+}
+
 // Tiles tile0 .. tile0 + gridDim.x - 1 of the frame.
 template <int KT, int B>
 __global__ __launch_bounds__(kStatsBlock) void stats_kernel(const ramlt_frame f, long long tile0) {
@@ -315,6 +358,12 @@ hipError_t launch_stats_kt(const ramlt_frame *fh, const ramlt_frame *fd, int n, 
   if (n == 1) {
     const long long P = (long long)fh[0].W * fh[0].H;
     const long long tiles = (P + kStatsBlock - 1) / kStatsBlock;
+    if (tiles < kChannelSplitTiles) {
+      const int nch = RAMLT_N_RADIANCE + (fh[0].features ? RAMLT_N_FEATURES : 0);
+      hipLaunchKernelGGL((stats_channel_kernel<KT, B>), dim3((unsigned)tiles, (unsigned)nch), dim3(kStatsBlock), 0,
+                         st, fh[0]);
+      return hipGetLastError();
+    }
     for (long long t0 = 0; t0 < tiles; t0 += per_launch) {
       const unsigned grid = (unsigned)(tiles - t0 < per_launch ? tiles - t0 : per_launch);
       hipLaunchKernelGGL((stats_kernel<KT, B>), dim3(grid), dim3(kStatsBlock), 0, st, fh[0], t0);
