@@ -237,6 +237,27 @@ class SingleChain:
             self.call(self.lib.loss_seed, self.tabu)
             self.call(self.lib.filter_backward, self.tabu)
 
+    def one_call_table(self):
+        """The step's descriptor for stats_filter_step: the statistics fields and launch size of
+        the stats descriptor, the filter fields and schedule of the loss-in-forward one."""
+        from paper_2402_08273_amd import _abi
+
+        f = _abi.RamltFrame.from_buffer_copy(self.tabl[0])
+        s = self.tabs[0]
+        for name in ("S", "max_lag", "radiance", "rad_stride_c", "rad_stride_s", "rad_stride_y", "features",
+                     "feat_stride_c", "feat_stride_s", "feat_stride_y", "feat_dtype", "mean", "var", "tau",
+                     "lag_corr", "feat_mean", "feat_var"):
+            setattr(f, name, getattr(s, name))
+        f.flags = (self.tabl[0].flags & ~_abi.RAMLT_STATS_WG_MASK) | (s.flags & _abi.RAMLT_STATS_WG_MASK)
+        return (_abi.RamltFrame * 1)(f)
+
+    def one_call_step(self, tab):
+        """The same step through stats_filter_step (accumulators zeroed first)."""
+        self.acc.zero_()
+        st = self.lib.stats_filter_step(tab, self.ws_ptr, self.ws_bytes, self.sh)
+        if st != 0:
+            raise RuntimeError(self._abi.last_error())
+
     def algorithmic_bytes(self):
         return stats_bytes(self.P, self.S, self.feat_bytes) + self.P * FILTER_STEP_BYTES_PER_PX
 
@@ -901,6 +922,8 @@ def main():
     fused_ms = time_loop(c.stream, lambda: c.step(form="fused"), args.steps)
     unfused_ms = time_loop(c.stream, lambda: c.step(form="unfused"), args.steps)
     fwd_only_ms = time_loop(c.stream, lambda: (c.stats(), c.forward()), args.steps)
+    tab1 = c.one_call_table()
+    one_call_ms = time_loop(c.stream, lambda: c.one_call_step(tab1), args.steps)
 
     sb = stats_bytes(P, S)
     achieved = sb / (stats_ms * 1e-3) / 1e9
@@ -929,6 +952,7 @@ def main():
         "fwd_mpx_s": round(P / (fwd_only_ms * 1e-3) / 1e6, 2),
         "fused_adjoint_fwd_bwd_mpx_s": round(P / (fused_ms * 1e-3) / 1e6, 2),
         "unfused_fwd_bwd_mpx_s": round(P / (unfused_ms * 1e-3) / 1e6, 2),
+        "one_call_fwd_bwd_mpx_s": round(P / (one_call_ms * 1e-3) / 1e6, 2),
         "fwd_ms": round(fwd_only_ms, 4),
         "stats_ms": round(stats_ms, 4),
         "filter_forward_with_loss_ms": round(fwd_ms - stats_ms, 4),
