@@ -446,8 +446,9 @@ size_t ramlt_lens_workspace_size(int32_t n_regions);
  * omega: DEVICE float[n][3] (read); density: DEVICE float[n] or NULL (lens_chain_step's
  * carried luminance, moved with its chain); omega_out: DEVICE float[n][3]; density_out:
  * DEVICE float[n], required iff density is given; perm: DEVICE int32[n] or NULL (the old
- * index of each chain, to reorder any per-chain data the caller keeps). Outputs must not
- * overlap the inputs. W, H, tan_half_fov_x as for lens_chain_step; n in
+ * index of each chain, to reorder any per-chain data the caller keeps). The outputs and the
+ * workspace must not overlap the inputs or each other. W, H, tan_half_fov_x as for
+ * lens_chain_step; n in
  * 0..RAMLT_MAX_PROPOSALS. workspace: DEVICE, 256-byte aligned, at least
  * ramlt_lens_sort_workspace_size(n) bytes (64 counters per 4096 chains). Errors:
  * RAMLT_EINVAL, RAMLT_EWORKSPACE. */

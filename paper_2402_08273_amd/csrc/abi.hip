@@ -416,17 +416,29 @@ int lens_chain_sort(int32_t W, int32_t H, float tan_half_fov_x, const float *ome
       return fail(RAMLT_EINVAL, "lens_chain_sort: density and density_out must be 4-byte aligned");
     if (perm && !aligned(perm, 4)) return fail(RAMLT_EINVAL, "lens_chain_sort: perm is not 4-byte aligned");
     const size_t n3 = (size_t)n * 3 * sizeof(float), n1 = (size_t)n * sizeof(float);
-    // every output against every input (the outputs are written while the inputs are read)
-    bool bad = overlap(omega_out, n3, omega, n3) || (perm && overlap(perm, n1, omega, n3));
-    if (density)
-      bad = bad || overlap(density_out, n1, omega, n3) || overlap(density_out, n1, density, n1) ||
-            overlap(omega_out, n3, density, n1) || (perm && overlap(perm, n1, density, n1));
-    if (bad) return fail(RAMLT_EINVAL, "lens_chain_sort: outputs overlap the inputs");
     const size_t need = ramlt::lens_sort_workspace_bytes(n);
     if (workspace == nullptr || ws_bytes < need)
       return fail(RAMLT_EWORKSPACE, "lens_chain_sort needs %zu bytes of workspace, got %zu", need,
                   workspace == nullptr ? (size_t)0 : ws_bytes);
     if (!aligned(workspace, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
+    // the outputs are written at other chains' places while the inputs are read, and the
+    // workspace's counters while both are in use: each of them against everything else
+    struct Span {
+      const void *p;
+      size_t bytes;
+    };
+    const Span in[2] = {{omega, n3}, {density, density ? n1 : 0}};
+    const Span out[4] = {{omega_out, n3}, {density_out, density_out ? n1 : 0}, {perm, perm ? n1 : 0},
+                         {workspace, need}};
+    for (int a = 0; a < 4; ++a) {
+      if (!out[a].bytes) continue;
+      for (int b = 0; b < 2; ++b)
+        if (in[b].bytes && overlap(out[a].p, out[a].bytes, in[b].p, in[b].bytes))
+          return fail(RAMLT_EINVAL, "lens_chain_sort: outputs and workspace must not overlap the inputs");
+      for (int b = a + 1; b < 4; ++b)
+        if (out[b].bytes && overlap(out[a].p, out[a].bytes, out[b].p, out[b].bytes))
+          return fail(RAMLT_EINVAL, "lens_chain_sort: outputs and workspace must not overlap each other");
+    }
   }
   int r = check_device();
   if (r) return r;

@@ -431,10 +431,16 @@ def test_lens_chain_sort_validation(lib):
            # outputs overlapping inputs (12000 B of omega, 4000 B of density)
            dict(omega_out=0x300000), dict(omega_out=0x300000 + 11996), dict(omega_out=0x300000 - 11996),
            dict(density_out=0x300000 + 400), dict(density_out=0x500000 + 3996), dict(omega_out=0x500000 - 8),
-           dict(perm=0x300000 + 8), dict(perm=0x500000 - 3996)]
+           dict(perm=0x300000 + 8), dict(perm=0x500000 - 3996),
+           # outputs overlapping each other, and the workspace overlapping an input or an output
+           dict(perm=0x400000 + 11996), dict(density_out=0x400000 + 4000), dict(perm=0x600000 - 3996),
+           dict(workspace=0x300000 + 11776), dict(workspace=0x500000), dict(workspace=0x400000 + 256),
+           dict(workspace=0x600000 - 256), dict(workspace=0x700000 + 3840)]
     for kw in bad:
         assert st(**kw) == _abi.RAMLT_EINVAL, kw
     assert st(omega_out=0x300000 + 12000) in ok  # adjacent is not overlapping
+    assert st(perm=0x600000 + 4000, workspace=0x600000 + 8192) in ok
+    assert st(perm=None, workspace=0x700000) in ok  # spans of absent outputs are empty
     assert st(workspace=None, ws_bytes=0) == _abi.RAMLT_EWORKSPACE
     assert st(ws_bytes=need - 1) == _abi.RAMLT_EWORKSPACE
     assert st(workspace=FAKE_WORKSPACE + 8) == _abi.RAMLT_EWORKSPACE
