@@ -282,7 +282,9 @@ typedef struct ramlt_region_state {
 /* region: DEVICE int32[n]; alpha: DEVICE float[n]; n in 0..RAMLT_MAX_PROPOSALS (0 = no
  * work). params, state: HOST structs. workspace: DEVICE, 256-byte aligned, at least
  * ramlt_adapt_workspace_size(n, n_regions) bytes (proposals sorted by region, stably,
- * and region boundaries). Errors as for the other entry points. */
+ * and region boundaries). The state arrays and the workspace, which the call writes, must
+ * not overlap each other or the proposals (RAMLT_EINVAL). Errors as for the other entry
+ * points. */
 int region_adapt(const ramlt_adapt_params *params, const ramlt_region_state *state, const int32_t *region,
                  const float *alpha, int64_t n_proposals, void *workspace, size_t ws_bytes, void *stream);
 
@@ -346,7 +348,9 @@ int quadtree_lookup(const ramlt_quadtree *tree, const int32_t *root, const float
  * as it is, updates = max(1, floor(parent updates / 4)) (the paper gives n_k / 4; it is
  * rounded down and kept >= 1 so the step size stays finite), and an empty pending window
  * (acc = 0, visits = 0). m_split >= 0. workspace: DEVICE, 256-byte aligned, at least
- * ramlt_quadtree_workspace_size(capacity) bytes. The result is deterministic. */
+ * ramlt_quadtree_workspace_size(capacity) bytes. The tree's arrays, the first capacity
+ * entries of the state's arrays and the workspace must not overlap (RAMLT_EINVAL). The
+ * result is deterministic. */
 int quadtree_refine(const ramlt_quadtree *tree, int32_t m_split, const ramlt_region_state *state,
                     void *workspace, size_t ws_bytes, void *stream);
 

@@ -202,6 +202,30 @@ int run_op(int op, const char *name, Validator v, Launcher l, const ramlt_frame 
   return RAMLT_OK;
 }
 
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+// A device buffer of an entry point: its address and byte length (0 = absent).
+struct Span {
+  const void *p;
+  size_t bytes;
+};
+
+// True if a written buffer overlaps another written buffer or a read one (the kernels of the
+// entry point write some buffers at other elements' places while they read the rest).
+bool writes_overlap(const Span *wr, int nwr, const Span *rd, int nrd) {
+  for (int a = 0; a < nwr; ++a) {
+    if (!wr[a].bytes) continue;
+    for (int b = 0; b < nrd; ++b)
+      if (rd[b].bytes && overlap(wr[a].p, wr[a].bytes, rd[b].p, rd[b].bytes)) return true;
+    for (int b = a + 1; b < nwr; ++b)
+      if (wr[b].bytes && overlap(wr[a].p, wr[a].bytes, wr[b].p, wr[b].bytes)) return true;
+  }
+  return false;
+}
+
 int validate_adapt(const ramlt_adapt_params *p, const ramlt_region_state *s, const int32_t *region,
                    const float *alpha, int64_t n) {
   if (!p) return fail(RAMLT_EINVAL, "region_adapt: params is NULL");
@@ -292,6 +316,24 @@ int quadtree_refine(const ramlt_quadtree *tree, int32_t m_split, const ramlt_reg
     return fail(RAMLT_EWORKSPACE, "quadtree_refine needs %zu bytes of workspace, got %zu", need,
                 workspace == nullptr ? (size_t)0 : ws_bytes);
   if (!aligned(workspace, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
+  {
+    // children are written past the nodes in use while the parents are read, and the state of
+    // every child from its parent's: all of these buffers are written
+    const size_t c = (size_t)tree->capacity;
+    const Span wr[10] = {{tree->child, c * 4},
+                         {tree->depth, c * 4},
+                         {tree->visits, c * 4},
+                         {tree->n_nodes, 4},
+                         {workspace, need},
+                         {state ? state->lambda : nullptr, state ? c * 8 : 0},
+                         {state ? state->acc : nullptr, state ? c * 8 : 0},
+                         {state ? state->visits : nullptr, state ? c * 4 : 0},
+                         {state ? state->updates : nullptr, state ? c * 4 : 0},
+                         {state ? state->lambda_f32 : nullptr, state && state->lambda_f32 ? c * 4 : 0}};
+    if (writes_overlap(wr, 10, nullptr, 0))
+      return fail(RAMLT_EINVAL, "quadtree_refine: the tree's arrays, the state's first capacity entries and the "
+                                "workspace must not overlap");
+  }
   r = check_device();
   if (r) return r;
   const hipError_t e = ramlt::launch_quadtree_refine(*tree, m_split, state, workspace, (hipStream_t)stream);
@@ -389,11 +431,6 @@ size_t ramlt_lens_workspace_size(int32_t n_regions) {
   return ramlt::perturb_workspace_bytes(n_regions * n_regions);
 }
 
-static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
-  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
-  return x < y + nb && y < x + na;
-}
-
 int lens_chain_sort(int32_t W, int32_t H, float tan_half_fov_x, const float *omega, const float *density, int64_t n,
                     float *omega_out, float *density_out, int32_t *perm, void *workspace, size_t ws_bytes,
                     void *stream) {
@@ -422,23 +459,12 @@ int lens_chain_sort(int32_t W, int32_t H, float tan_half_fov_x, const float *ome
                   workspace == nullptr ? (size_t)0 : ws_bytes);
     if (!aligned(workspace, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
     // the outputs are written at other chains' places while the inputs are read, and the
-    // workspace's counters while both are in use: each of them against everything else
-    struct Span {
-      const void *p;
-      size_t bytes;
-    };
+    // workspace's counters while both are in use
     const Span in[2] = {{omega, n3}, {density, density ? n1 : 0}};
     const Span out[4] = {{omega_out, n3}, {density_out, density_out ? n1 : 0}, {perm, perm ? n1 : 0},
                          {workspace, need}};
-    for (int a = 0; a < 4; ++a) {
-      if (!out[a].bytes) continue;
-      for (int b = 0; b < 2; ++b)
-        if (in[b].bytes && overlap(out[a].p, out[a].bytes, in[b].p, in[b].bytes))
-          return fail(RAMLT_EINVAL, "lens_chain_sort: outputs and workspace must not overlap the inputs");
-      for (int b = a + 1; b < 4; ++b)
-        if (out[b].bytes && overlap(out[a].p, out[a].bytes, out[b].p, out[b].bytes))
-          return fail(RAMLT_EINVAL, "lens_chain_sort: outputs and workspace must not overlap each other");
-    }
+    if (writes_overlap(out, 4, in, 2))
+      return fail(RAMLT_EINVAL, "lens_chain_sort: outputs and workspace must not overlap the inputs or each other");
   }
   int r = check_device();
   if (r) return r;
@@ -504,6 +530,18 @@ int region_adapt(const ramlt_adapt_params *params, const ramlt_region_state *sta
       return fail(RAMLT_EWORKSPACE, "region_adapt needs %zu bytes of workspace, got %zu", need,
                   workspace == nullptr ? (size_t)0 : ws_bytes);
     if (!aligned(workspace, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
+  }
+  {
+    // the sorted stream is written to the workspace while the proposals are read, and the state
+    // is updated in place
+    const size_t m = (size_t)params->n_regions, np = (size_t)(n_proposals > 0 ? n_proposals : 0);
+    const Span rd[2] = {{region, np * 4}, {alpha, np * 4}};
+    const Span wr[6] = {{state->lambda, m * 8},  {state->acc, m * 8},
+                        {state->visits, m * 4},  {state->updates, m * 4},
+                        {state->lambda_f32, state->lambda_f32 ? m * 4 : 0}, {workspace, need}};
+    if (writes_overlap(wr, 6, rd, 2))
+      return fail(RAMLT_EINVAL, "region_adapt: the state arrays and the workspace must not overlap each other or "
+                                "the proposals");
   }
   r = check_device();
   if (r) return r;

@@ -303,6 +303,28 @@ def test_region_adapt_validation(lib):
     assert _abi.adapt_status(p, s, 0x500000, 0x600000, 1000, None, 0) == _abi.RAMLT_EWORKSPACE
     assert _abi.adapt_status(p, s, 0x500000, 0x600000, 1000, ws, need - 1) == _abi.RAMLT_EWORKSPACE
     assert _abi.adapt_status(p, s, 0x500000, 0x600000, 1000, ws + 16, need) == _abi.RAMLT_EWORKSPACE
+    # the state arrays (400 regions: 3200 B of lambda and acc, 1600 B of visits and updates)
+    # and the workspace are written: none may overlap another one or the proposals (4000 B each)
+    overlapping = [
+        (lambda p, s: setattr(s, "acc", 0x100000 + 3192), {}),
+        (lambda p, s: setattr(s, "updates", 0x300000 + 1596), {}),
+        (lambda p, s: setattr(s, "lambda_f32", 0x200000 + 8), {}),
+        (lambda p, s: setattr(s, "visits", 0x500000 + 3996), {}),
+        (lambda p, s: setattr(s, "lambda_", 0x600000 - 3192), {}),
+        (lambda p, s: None, dict(region=ws + need - 4)),
+        (lambda p, s: None, dict(alpha=ws - 3996)),
+        (lambda p, s: None, dict(ws=0x300000)),
+    ]
+    for mutate, kw in overlapping:
+        p, s = _adapt_args()
+        mutate(p, s)
+        a = dict(region=0x500000, alpha=0x600000, ws=ws)
+        a.update(kw)
+        assert _abi.adapt_status(p, s, a["region"], a["alpha"], 1000, a["ws"], need) == _abi.RAMLT_EINVAL, kw
+    p, s = _adapt_args()
+    s.acc = 0x100000 + 3200  # adjacent is not overlapping
+    s.lambda_f32 = 0x400000 + 1600
+    assert _abi.adapt_status(p, s, 0x500000, 0x600000, 1000, ws, need) in (_abi.RAMLT_EHIP, _abi.RAMLT_OK)
     assert _abi.adapt_status(None, s, 0x500000, 0x600000, 1000, ws, need) == _abi.RAMLT_EINVAL
     assert _abi.adapt_status(p, None, 0x500000, 0x600000, 1000, ws, need) == _abi.RAMLT_EINVAL
 
@@ -357,6 +379,19 @@ def test_quadtree_validation(lib):
         s = _abi.RamltRegionState(0x900000, 0xA00000, 0xB00000, 0xC00000, None)
         setattr(s, field, val)
         assert _abi.quadtree_refine_status(t, 5000, s, ws, need) == _abi.RAMLT_EINVAL
+    # every buffer of a refinement is written: capacity 1000 gives 4000 B per int32 array and
+    # 8000 B per fp64 one
+    for obj, field, val in (("t", "depth", 0x100000 + 3996), ("t", "n_nodes", 0x300000 + 3996),
+                            ("s", "acc", 0x900000 + 7992), ("s", "visits", 0x200000 + 8),
+                            ("s", "lambda_f32", 0xC00000 + 3996), ("s", "updates", ws + need - 4)):
+        t = _tree()
+        s = _abi.RamltRegionState(0x900000, 0xA00000, 0xB00000, 0xC00000, None)
+        setattr(t if obj == "t" else s, field, val)
+        assert _abi.quadtree_refine_status(t, 5000, s, ws, need) == _abi.RAMLT_EINVAL, field
+    t = _tree()
+    assert _abi.quadtree_refine_status(t, 5000, None, 0x100000 + 3840, need) == _abi.RAMLT_EINVAL
+    s = _abi.RamltRegionState(0x900000, 0x900000 + 8000, 0xB00000, 0xB00000 + 4000, 0xC00000)
+    assert _abi.quadtree_refine_status(t, 5000, s, ws, need) in ok  # adjacent is not overlapping
 
 
 def test_perturb_directions_validation(lib):
