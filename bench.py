@@ -280,10 +280,19 @@ def stats_launch_of(flags, table=None):
 def hbm_roofline(nbytes, ms, note, traffic=None):
     """Roofline object of an operation bound by HBM: algorithmic bytes over the measured
     time (HIP events around the operation's launches) against 8 TB/s; ``traffic``: the
-    measured HBM bytes of the same launches, when a current record exists."""
+    measured HBM bytes of the same launches, when a current record exists, and
+    ``traffic_gbs`` the rate those bytes move at over the same time (set only with them)."""
     gbs = nbytes / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "algorithmic_bytes": int(nbytes), "covers": note}
+    r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "algorithmic_bytes": int(nbytes), "covers": note}
+    if traffic:
+        r["traffic_gbs"] = traffic_gbs(traffic, ms)
+    return r
+
+
+def traffic_gbs(traffic, ms):
+    """GB/s of counted HBM bytes over a measured time, or None without a current record."""
+    return round(traffic / (ms * 1e-3) / 1e9, 1) if traffic else None
 
 
 def time_loop(stream, fn, steps):
@@ -305,9 +314,7 @@ def time_loop(stream, fn, steps):
 def stats_roofline(nbytes, ms, traffic, note):
     """Roofline object of a statistics launch: algorithmic bytes over its duration (HIP
     events on the launch stream) against 8 TB/s, and the committed counter bytes."""
-    r = hbm_roofline(nbytes, ms, note)
-    r["traffic"] = traffic
-    return r
+    return hbm_roofline(nbytes, ms, note, traffic)
 
 
 def measure_uhd(steps, warmup, tune=True, traffic_path=TRAFFIC_RECORDS):
@@ -666,6 +673,8 @@ def measure_lens(steps, warmup, cpu=True):
                           "mean_alpha": round(acc_s, 4),
                           "hbm_frac": round(nbytes_s / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                           "traffic": measured_traffic(TRAFFIC_RECORDS, "lens step 16M tile order"),
+                          "traffic_gbs": traffic_gbs(measured_traffic(TRAFFIC_RECORDS, "lens step 16M tile order"),
+                                                     ms_s),
                           "valu_roofline": valu_roofline(
                               measured_traffic(TRAFFIC_RECORDS, "lens step 16M tile order", "valu_insts"), ms_s,
                               "lens_step_kernel (VALU issue), over the time of scale_kernel + lens_step_kernel"),
@@ -968,6 +977,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "traffic_gbs": traffic_gbs(traffic, stats_ms),
             "algorithmic_bytes": sb,
         },
         # whole step: the statistics pass, the forward with the loss (mean, reference read;
