@@ -103,8 +103,11 @@ VALU_PEAK_GINST_S = 256 * 4 * 2.4 / 4
 
 
 def valu_roofline(insts, ms, note):
-    """Roofline object of a kernel bound by VALU issue: its counted VALU wave instructions
-    per launch (rocprofv3 SQ_INSTS_VALU, committed record) over the measured time."""
+    """Roofline object against the VALU issue ceiling, reported beside a kernel's HBM one:
+    its counted VALU wave instructions per launch (rocprofv3 SQ_INSTS_VALU, committed record)
+    over the measured time. A high fraction says issue could bind; whether it does shows
+    when fewer instructions shorten the kernel (for the lens step and the direction
+    perturbation they did not: their counted bytes already move at a device copy's rate)."""
     if insts is None:
         return None
     g = insts / (ms * 1e-3) / 1e9
