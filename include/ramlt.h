@@ -378,7 +378,9 @@ size_t ramlt_quadtree_workspace_size(int32_t capacity);
  * 8-byte aligned; theta_out: DEVICE float[n] or NULL. n in 0..RAMLT_MAX_PROPOSALS;
  * n_regions in 1..RAMLT_MAX_ADAPT_REGIONS. workspace: DEVICE, 256-byte aligned, at least
  * ramlt_perturb_workspace_size(n_regions) bytes (per-region terms that depend on sigma only,
- * for up to 65536 regions; 0 bytes, and NULL allowed, above that or for n = 0). Errors: RAMLT_EINVAL for bad sizes/pointers, RAMLT_EWORKSPACE. */
+ * for up to 65536 regions; 0 bytes, and NULL allowed, above that or for n = 0). omega_out
+ * may be omega itself; otherwise omega_out, theta_out and the workspace must not overlap
+ * each other or an input. Errors: RAMLT_EINVAL for bad sizes/pointers, RAMLT_EWORKSPACE. */
 int perturb_directions(const double *lambda, int32_t n_regions, const int32_t *region, const float *omega,
                        const float *uv, float *omega_out, float *theta_out, int64_t n, void *workspace,
                        size_t ws_bytes, void *stream);
@@ -428,7 +430,9 @@ size_t ramlt_perturb_workspace_size(int32_t n_regions);
  * rrmse; tan_half_fov_x finite, > 0; n_regions in 1..RAMLT_MAX_REGIONS; n in
  * 0..RAMLT_MAX_PROPOSALS. workspace: DEVICE, 256-byte aligned, at least
  * ramlt_lens_workspace_size(n_regions) bytes (0, and NULL allowed, above 65536 regions or for
- * n = 0). Errors: RAMLT_EINVAL, RAMLT_EWORKSPACE. */
+ * n = 0). The buffers the call writes (omega, density, pixel, region, alpha, omega_prop, the
+ * workspace) must not overlap each other or an input. Errors: RAMLT_EINVAL,
+ * RAMLT_EWORKSPACE. */
 int lens_chain_step(const float *luminance, int32_t W, int32_t H, float tan_half_fov_x, const double *lambda,
                     int32_t n_regions, float *omega, float *density, int32_t *pixel, const float *noise,
                     int32_t *region, float *alpha, float *omega_prop, int64_t n, void *workspace, size_t ws_bytes,

@@ -368,6 +368,16 @@ int perturb_directions(const double *lambda, int32_t n_regions, const int32_t *r
                     workspace == nullptr ? (size_t)0 : ws_bytes);
       if (!aligned(workspace, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
     }
+    // the sigma table is written before the proposals read it, and each proposal's outputs
+    // while the others read their inputs: omega_out may be omega itself (a proposal reads its
+    // direction before it writes the new one), nothing else may overlap
+    const size_t m = (size_t)n_regions, nn = (size_t)n;
+    const bool in_place = (const void *)omega_out == (const void *)omega;
+    const Span rd[4] = {{lambda, m * 8}, {region, nn * 4}, {omega, in_place ? 0 : nn * 12}, {uv, nn * 8}};
+    const Span wr[3] = {{omega_out, nn * 12}, {theta_out, theta_out ? nn * 4 : 0}, {workspace, need}};
+    if (writes_overlap(wr, 3, rd, 4))
+      return fail(RAMLT_EINVAL, "perturb_directions: omega_out, theta_out and the workspace must not overlap each "
+                                "other or the inputs (omega_out may be omega itself)");
   }
   int r = check_device();
   if (r) return r;
@@ -415,6 +425,16 @@ int lens_chain_step(const float *luminance, int32_t W, int32_t H, float tan_half
                     workspace == nullptr ? (size_t)0 : ws_bytes);
       if (!aligned(workspace, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
     }
+    // the sigma table is written before the chains read it, and each chain's state and
+    // outputs while the others read theirs: every written buffer stands alone
+    const size_t nn = (size_t)n, m = (size_t)n_regions * (size_t)n_regions, P = (size_t)W * (size_t)H;
+    const Span rd[3] = {{luminance, P * 4}, {lambda, m * 8}, {noise, nn * 12}};
+    const Span wr[7] = {{omega, nn * 12},      {density, density ? nn * 4 : 0}, {pixel, pixel ? nn * 4 : 0},
+                        {region, nn * 4},      {alpha, nn * 4},                 {omega_prop, omega_prop ? nn * 12 : 0},
+                        {workspace, need}};
+    if (writes_overlap(wr, 7, rd, 3))
+      return fail(RAMLT_EINVAL, "lens_chain_step: the chains' state, the outputs and the workspace must not overlap "
+                                "each other or the inputs");
   }
   int r = check_device();
   if (r) return r;

@@ -416,6 +416,13 @@ def test_perturb_directions_validation(lib):
     # many regions: no table, no workspace
     assert _abi.perturb_workspace_size(65537) == 0
     assert st(n_regions=65537, workspace=None, ws_bytes=0) in ok
+    # written buffers (omega_out 12000 B, theta_out 4000 B, the sigma table) against each
+    # other and the inputs; omega_out may be omega itself
+    assert st(omega_out=0x300000) in ok
+    for kw in [dict(omega_out=0x300000 + 12), dict(omega_out=0x400000 - 4), dict(theta_out=0x200000 + 3996),
+               dict(theta_out=0x500000 + 11996), dict(theta_out=0x100000 + 3196), dict(workspace=0x500000),
+               dict(workspace=0x300000 - 256), dict(omega_out=0x300000, theta_out=0x300000 + 8)]:
+        assert st(**kw) == _abi.RAMLT_EINVAL, kw
 
 
 def test_lens_chain_step_validation(lib):
@@ -423,7 +430,7 @@ def test_lens_chain_step_validation(lib):
     need = _abi.lens_workspace_size(20)
     assert need == _abi.perturb_workspace_size(400) and _abi.lens_workspace_size(0) == 0
     assert _abi.lens_workspace_size(4097) == 0 and _abi.lens_workspace_size(257) == 0   # 66049 regions: no table
-    args = dict(luminance=0x100000, W=1920, H=1080, tan_half_fov_x=0.6, lam=0x200000, n_regions=20,
+    args = dict(luminance=0x10000000, W=1920, H=1080, tan_half_fov_x=0.6, lam=0x200000, n_regions=20,
                 omega=0x300000, noise=0x400000, region=0x500000, alpha=0x600000, omega_prop=0x700000, n=1000,
                 workspace=FAKE_WORKSPACE, ws_bytes=need)
     st = lambda **kw: _abi.lens_chain_step_status(**{**args, **kw})
@@ -434,7 +441,7 @@ def test_lens_chain_step_validation(lib):
     assert st(omega=None, noise=None, region=None, alpha=None, omega_prop=None, n=0) in ok
     bad = [dict(W=0), dict(H=0), dict(W=65537), dict(tan_half_fov_x=0.0), dict(tan_half_fov_x=-1.0),
            dict(tan_half_fov_x=float("inf")), dict(tan_half_fov_x=float("nan")), dict(tan_half_fov_x=1e-45, H=1),
-           dict(n_regions=0), dict(n_regions=4097), dict(luminance=None), dict(luminance=0x100002), dict(lam=None),
+           dict(n_regions=0), dict(n_regions=4097), dict(luminance=None), dict(luminance=0x10000002), dict(lam=None),
            dict(lam=0x200004), dict(n=-1), dict(n=(1 << 30) + 1), dict(omega=None), dict(omega=0x300001),
            dict(noise=None), dict(region=None), dict(alpha=0x600002), dict(omega_prop=0x700001)]
     for kw in bad:
@@ -443,6 +450,14 @@ def test_lens_chain_step_validation(lib):
     assert st(ws_bytes=need - 1) == _abi.RAMLT_EWORKSPACE
     assert st(workspace=FAKE_WORKSPACE + 8) == _abi.RAMLT_EWORKSPACE
     assert st(n_regions=257, workspace=None, ws_bytes=0) in ok
+    # the chains' state and outputs (12000 B of omega, 4000 B per int / float array) and the
+    # sigma table are written: none may overlap another one or an input (the 8.3 MB image, the
+    # 3200 B of lambda, 12000 B of noise)
+    for kw in [dict(omega=0x400000 - 12), dict(region=0x600000 + 3996), dict(alpha=0x300000 + 11996),
+               dict(omega_prop=0x600000 - 11996), dict(density=0x500000), dict(pixel=0x200000 + 3196),
+               dict(density=0x10000000 + 8294396), dict(workspace=0x400000 + 11776), dict(noise=0x700000 + 8)]:
+        assert st(**kw) == _abi.RAMLT_EINVAL, kw
+    assert st(density=0x800000, pixel=0x800000 + 4000) in ok  # adjacent is not overlapping
 
 
 def test_lens_chain_sort_validation(lib):
