@@ -334,7 +334,9 @@ int quadtree_init(const ramlt_quadtree *tree, void *stream);
  * so the counts do not depend on the order; int32, so more than 2^31 - 1 visits of one
  * leaf between refinements wrap).
  * root: DEVICE int32[n] or NULL; x, y: DEVICE float[n]; leaf: DEVICE int32[n]; n in
- * 0..RAMLT_MAX_QT_POINTS. Errors: RAMLT_EINVAL for bad sizes or pointers. */
+ * 0..RAMLT_MAX_QT_POINTS. leaf, and the tree's visits when counting, must not overlap each
+ * other, the points or the tree's other arrays. Errors: RAMLT_EINVAL for bad sizes or
+ * pointers. */
 int quadtree_lookup(const ramlt_quadtree *tree, const int32_t *root, const float *x, const float *y,
                     int32_t *leaf, int64_t n_points, int32_t count, void *stream);
 
@@ -478,7 +480,8 @@ size_t ramlt_lens_sort_workspace_size(int64_t n);
  * image, reference: DEVICE float[3][H][W] (dense planes, e.g. filter_forward's out and the
  * frame's reference); map: DEVICE float[H][W] or NULL; rrmse_out: DEVICE double or NULL
  * (not both NULL); W, H in 1..RAMLT_MAX_SIDE with W H <= RAMLT_MAX_PLANE_ELEMS; eps finite,
- * >= 0. workspace: DEVICE, 256-byte aligned, >= ramlt_rrmse_workspace_size(W, H) bytes. */
+ * >= 0. workspace: DEVICE, 256-byte aligned, >= ramlt_rrmse_workspace_size(W, H) bytes.
+ * map, rrmse_out and the workspace must not overlap each other or the images. */
 int rrmse(const float *image, const float *reference, int32_t W, int32_t H, double eps, float *map,
           double *rrmse_out, void *workspace, size_t ws_bytes, void *stream);
 

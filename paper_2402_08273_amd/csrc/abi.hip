@@ -288,6 +288,17 @@ int quadtree_lookup(const ramlt_quadtree *tree, const int32_t *root, const float
   if (n_points > 0 && (!x || !aligned(x, 4) || !y || !aligned(y, 4) || !leaf || !aligned(leaf, 4)))
     return fail(RAMLT_EINVAL, "quadtree_lookup: x, y and leaf must be 4-byte aligned device pointers");
   if (root && !aligned(root, 4)) return fail(RAMLT_EINVAL, "quadtree_lookup: root is not 4-byte aligned");
+  if (n_points > 0) {
+    // leaf is written, and the tree's visit counts with count, while the points and the
+    // tree's links are read
+    const size_t np = (size_t)n_points, c = (size_t)tree->capacity;
+    const Span rd[6] = {{x, np * 4},           {y, np * 4},           {root, root ? np * 4 : 0},
+                        {tree->child, c * 4},  {tree->depth, c * 4},  {tree->n_nodes, 4}};
+    const Span wr[2] = {{leaf, np * 4}, {tree->visits, count ? c * 4 : 0}};
+    if (writes_overlap(wr, 2, rd, 6))
+      return fail(RAMLT_EINVAL, "quadtree_lookup: leaf (and the visit counts when counting) must not overlap each "
+                                "other, the points or the tree's links");
+  }
   r = check_device();
   if (r) return r;
   const hipError_t e =
@@ -515,6 +526,13 @@ int rrmse(const float *image, const float *reference, int32_t W, int32_t H, doub
     return fail(RAMLT_EWORKSPACE, "rrmse needs %zu bytes of workspace, got %zu", need,
                 workspace == nullptr ? (size_t)0 : ws_bytes);
   if (!aligned(workspace, 256)) return fail(RAMLT_EWORKSPACE, "workspace must be 256-byte aligned");
+  {
+    const size_t P = (size_t)W * (size_t)H;
+    const Span rd[2] = {{image, P * 12}, {reference, P * 12}};
+    const Span wr[3] = {{map, map ? P * 4 : 0}, {rrmse_out, rrmse_out ? (size_t)8 : 0}, {workspace, need}};
+    if (writes_overlap(wr, 3, rd, 2))
+      return fail(RAMLT_EINVAL, "rrmse: map, rrmse_out and the workspace must not overlap each other or the images");
+  }
   int r = check_device();
   if (r) return r;
   const hipError_t e =

@@ -371,6 +371,13 @@ def test_quadtree_validation(lib):
     assert _abi.quadtree_lookup_status(t, None, 0x600000, 0x700000, 0x800000, -1, 1) == _abi.RAMLT_EINVAL
     assert _abi.quadtree_lookup_status(t, None, 0x600000, 0x700000, 0x800000, (1 << 30) + 1, 1) == \
         _abi.RAMLT_EINVAL
+    # leaf (400 B) and, when counting, the visit counts (4000 B) are written
+    assert _abi.quadtree_lookup_status(t, None, 0x600000, 0x700000, 0x600000 + 396, 100, 1) == _abi.RAMLT_EINVAL
+    assert _abi.quadtree_lookup_status(t, 0x800000 - 396, 0x600000, 0x700000, 0x800000, 100, 1) == _abi.RAMLT_EINVAL
+    assert _abi.quadtree_lookup_status(t, None, 0x600000, 0x700000, 0x100000 + 8, 100, 1) == _abi.RAMLT_EINVAL
+    assert _abi.quadtree_lookup_status(t, None, 0x300000 + 8, 0x700000, 0x800000, 100, 1) == _abi.RAMLT_EINVAL
+    assert _abi.quadtree_lookup_status(t, None, 0x300000 + 8, 0x700000, 0x800000, 100, 0) in ok  # visits unused
+    assert _abi.quadtree_lookup_status(t, None, 0x600000, 0x700000, 0x300000 + 3996, 100, 1) == _abi.RAMLT_EINVAL
     assert _abi.quadtree_refine_status(t, -1, None, ws, need) == _abi.RAMLT_EINVAL
     assert _abi.quadtree_refine_status(t, 5000, None, None, 0) == _abi.RAMLT_EWORKSPACE
     assert _abi.quadtree_refine_status(t, 5000, None, ws, need - 1) == _abi.RAMLT_EWORKSPACE
@@ -501,18 +508,23 @@ def test_rrmse_validation(lib):
     need = _abi.rrmse_workspace_size(1920, 1080)
     assert need >= 8 * (1920 * 1080 // 2048) and need % 256 == 0   # one fp64 partial per 2048 px
     assert _abi.rrmse_workspace_size(0, 5) == 0 and _abi.rrmse_workspace_size(65537, 1) == 0
-    args = dict(image=0x100000, reference=0x200000, W=1920, H=1080, eps=1e-2, map_=0x300000, out=0x400000,
+    # 1920 x 1080: 24.9 MB per image, 8.3 MB of map
+    args = dict(image=0x10000000, reference=0x20000000, W=1920, H=1080, eps=1e-2, map_=0x30000000, out=0x38000000,
                 workspace=FAKE_WORKSPACE, ws_bytes=need)
     st = lambda **kw: _abi.rrmse_status(**{**args, **kw})
     assert st() in ok, _abi.last_error()
     assert st(map_=None) in ok and st(out=None) in ok and st(eps=0.0) in ok
     for kw in (dict(W=0), dict(H=-1), dict(W=65537), dict(W=40000, H=40000), dict(eps=-1.0),
-               dict(eps=float("nan")), dict(eps=float("inf")), dict(image=None), dict(reference=0x200002),
-               dict(map_=None, out=None), dict(map_=0x300001), dict(out=0x400004)):
+               dict(eps=float("nan")), dict(eps=float("inf")), dict(image=None), dict(reference=0x20000002),
+               dict(map_=None, out=None), dict(map_=0x30000001), dict(out=0x38000004),
+               # written buffers overlapping each other or an image
+               dict(map_=0x20000000 + 24883196), dict(out=0x10000000 + 8), dict(out=0x30000000 + 8294392),
+               dict(workspace=0x30000000), dict(map_=0x10000000 - 8294396), dict(image=0x38000000 - 24883196)):
         assert st(**kw) == _abi.RAMLT_EINVAL, kw
     assert st(workspace=None, ws_bytes=0) == _abi.RAMLT_EWORKSPACE
     assert st(ws_bytes=need - 1) == _abi.RAMLT_EWORKSPACE
     assert st(workspace=FAKE_WORKSPACE + 64) == _abi.RAMLT_EWORKSPACE
+    assert st(out=0x30000000 + 8294400) in ok  # adjacent is not overlapping
 
 
 def test_loss_in_forward_flag(lib):
